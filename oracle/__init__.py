@@ -1,0 +1,260 @@
+"""FP64 CPU oracle for the MAC-projection solve.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package; the product path (the
+HIP library and its Python binding) never does, and shares no code with it.
+
+The arithmetic lives in `mproj_oracle.c` (plain C, FP64, OpenMP over z planes);
+this module builds it with gcc and wraps it for numpy arrays.  Each wrapper
+names the passage of the paper it follows; see the C file's header for the
+discretisation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mproj_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile the oracle with gcc (FP64, -O2, OpenMP)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.c_int
+_F = ctypes.c_double
+_GRID = [_I, _I, _I, _F, _I, _I, _I]
+
+
+def _declare(lib):
+    lib.or_cell_radius.argtypes = _GRID + [_D, _D]
+    lib.or_fill_beta0.argtypes = _GRID + [_I, _D, _I, _F, _D, _D]
+    lib.or_fill_beta0.restype = _I
+    lib.or_face_coefs.argtypes = _GRID + [_D, _D, _D, _D, _D]
+    lib.or_gradient.argtypes = _GRID + [_D, _D, _D, _D]
+    lib.or_divergence.argtypes = _GRID + [_D, _D, _D, _D]
+    lib.or_apply.argtypes = _GRID + [_D, _D, _D, _D, _D]
+    lib.or_beta0_divergence.argtypes = _GRID + [_D, _D, _D, _D, _D]
+    lib.or_mac_rhs.argtypes = _GRID + [_D, _D, _D, _D, _D, _D]
+    lib.or_mac_rhs.restype = _F
+    lib.or_velocity_correct.argtypes = _GRID + [_D, _D, _D, _D, _D, _D, _D, _D]
+    lib.or_coef_grad.argtypes = _GRID + [_D, _D, _D, _D, _D]
+    lib.or_solve.argtypes = _GRID + [_D, _D, _D, _D, _D, _F, _I, _I, _I, ctypes.POINTER(_I), _D]
+    lib.or_solve.restype = _I
+    lib.or_sum.argtypes = [_I, _I, _I, _D]
+    lib.or_sum.restype = _F
+    lib.or_dot.argtypes = [_I, _I, _I, _D, _D]
+    lib.or_dot.restype = _F
+    lib.or_num_threads.restype = _I
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    _lib = _declare(ctypes.CDLL(_LIB))
+    return _lib
+
+
+class use_library:
+    """Context manager that routes every wrapper in this module through another
+    build of the oracle source (the mutation tests compile planted mistakes
+    into copies of it)."""
+
+    def __init__(self, path):
+        self.lib = _declare(ctypes.CDLL(path))
+
+    def __enter__(self):
+        global _lib
+        self.saved = _load()
+        _lib = self.lib
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def compile_variant(src_text, out_path):
+    """Compile a (modified) copy of the oracle source to `out_path`."""
+    c_path = out_path + ".c"
+    with open(c_path, "w") as f:
+        f.write(src_text)
+    subprocess.check_call(["gcc", "-O1", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", out_path, c_path, "-lm"])
+    return out_path
+
+
+def source_text():
+    with open(_SRC) as f:
+        return f.read()
+
+
+def _p(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous, "oracle arrays must be C-contiguous float64"
+    return a.ctypes.data_as(_D)
+
+
+class Grid:
+    """Uniform cell-centred grid: nx, ny, nz cells of spacing h; bc per axis
+    (0 periodic, 1 Neumann wall)."""
+
+    def __init__(self, nx, ny, nz, h, bc):
+        self.nx, self.ny, self.nz, self.h = int(nx), int(ny), int(nz), float(h)
+        self.bc = tuple(int(b) for b in bc)
+
+    @classmethod
+    def of(cls, prob):
+        return cls(prob.nx, prob.ny, prob.nz, prob.h, prob.bc)
+
+    def args(self):
+        return [self.nx, self.ny, self.nz, self.h, *self.bc]
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def face_shapes(self):
+        bx, by, bz = self.bc
+        n = (self.nz, self.ny, self.nx)
+        return (n[0], n[1], n[2] + bx), (n[0], n[1] + by, n[2]), (n[0] + bz, n[1], n[2])
+
+    def cells(self):
+        return np.zeros(self.shape)
+
+    def faces(self):
+        return tuple(np.zeros(s) for s in self.face_shapes())
+
+
+def num_threads():
+    return _load().or_num_threads()
+
+
+def cell_radius(g, center):
+    """Distance of each cell centre from `center` (radius used by fill, Sec. 3.1)."""
+    r = g.cells()
+    c = np.ascontiguousarray(center, dtype=np.float64)
+    _load().or_cell_radius(*g.args(), _p(c), _p(r))
+    return r
+
+
+def fill_beta0(g, geometry, beta0_1d, dr, center):
+    """Fill module of Sec. 3.1: direct injection (planar, table per z cell) or
+    interpolation in r (spherical, table on (j+1/2) dr, linear)."""
+    out = g.cells()
+    b = np.ascontiguousarray(beta0_1d, dtype=np.float64)
+    c = np.ascontiguousarray(center, dtype=np.float64)
+    st = _load().or_fill_beta0(*g.args(), int(geometry), _p(b), len(b), float(dr), _p(c), _p(out))
+    if st:
+        raise ValueError("bad base-state table for this geometry")
+    return out
+
+
+def face_coefs(g, beta0_cc, rho):
+    """beta0/rho at faces: harmonic mean of the two cells; walls 0 (momentum
+    equation of Sec. 2 carries beta0/rho in front of the pressure gradient)."""
+    cx, cy, cz = g.faces()
+    _load().or_face_coefs(*g.args(), _p(beta0_cc), _p(rho), _p(cx), _p(cy), _p(cz))
+    return cx, cy, cz
+
+
+def map_base_state(g, geometry, beta0_1d, dr, center, rho):
+    """beta0 on cells and the three face-coefficient arrays."""
+    b = fill_beta0(g, geometry, beta0_1d, dr, center)
+    return b, face_coefs(g, b, rho)
+
+
+def gradient(g, phi):
+    gx, gy, gz = g.faces()
+    _load().or_gradient(*g.args(), _p(phi), _p(gx), _p(gy), _p(gz))
+    return gx, gy, gz
+
+
+def divergence(g, fx, fy, fz):
+    out = g.cells()
+    _load().or_divergence(*g.args(), _p(fx), _p(fy), _p(fz), _p(out))
+    return out
+
+
+def apply(g, cx, cy, cz, phi):
+    """M phi = D(C G phi)."""
+    out = g.cells()
+    _load().or_apply(*g.args(), _p(cx), _p(cy), _p(cz), _p(phi), _p(out))
+    return out
+
+
+def beta0_divergence(g, beta0_cc, ux, uy, uz):
+    """D(beta0_f U) with beta0_f the mean of the two cells."""
+    out = g.cells()
+    _load().or_beta0_divergence(*g.args(), _p(beta0_cc), _p(ux), _p(uy), _p(uz), _p(out))
+    return out
+
+
+def mac_rhs(g, beta0_cc, ux, uy, uz, S):
+    """rhs = D(beta0 U) - beta0 S made mean-zero (constraints div1/div2 of
+    Sec. 3.2 with the dp0/dt term folded into S).  Returns (rhs, removed mean)."""
+    out = g.cells()
+    m = _load().or_mac_rhs(*g.args(), _p(beta0_cc), _p(ux), _p(uy), _p(uz), _p(S), _p(out))
+    return out, m
+
+
+def solve(g, cx, cy, cz, rhs, tol=1e-12, maxcycles=200, nu1=2, nu2=2, phi0=None):
+    """Mean-zero phi with M phi = rhs - mean(rhs), to ||r||/||rhs|| <= tol."""
+    phi = g.cells() if phi0 is None else np.array(phi0, dtype=np.float64, order="C")
+    cyc = _I(0)
+    rel = _F(0.0)
+    rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+    st = _load().or_solve(*g.args(), _p(cx), _p(cy), _p(cz), _p(rhs), _p(phi), float(tol), int(maxcycles),
+                          int(nu1), int(nu2), ctypes.byref(cyc), ctypes.byref(rel))
+    return phi, dict(converged=(st == 0), cycles=cyc.value, rel_resid=rel.value)
+
+
+def velocity_correct(g, cx, cy, cz, beta0_cc, phi, ux, uy, uz):
+    """U - (c_f/beta0_f) G phi (Appendix A: remove the gradient part).  Returns copies."""
+    ux, uy, uz = (np.array(a, dtype=np.float64, order="C") for a in (ux, uy, uz))
+    _load().or_velocity_correct(*g.args(), _p(cx), _p(cy), _p(cz), _p(beta0_cc), _p(phi), _p(ux), _p(uy), _p(uz))
+    return ux, uy, uz
+
+
+def coef_grad(g, lam, phi):
+    """(G lam)_f (G phi)_f: gradient of <w, phi> with respect to c_f when lam
+    solves M lam = w - mean(w)."""
+    gx, gy, gz = g.faces()
+    _load().or_coef_grad(*g.args(), _p(lam), _p(phi), _p(gx), _p(gy), _p(gz))
+    return gx, gy, gz
+
+
+def residual_norm(g, cx, cy, cz, rhs, phi):
+    """||rhs - M phi||_2 / ||rhs||_2 in FP64 (rhs taken as given)."""
+    r = rhs - apply(g, cx, cy, cz, phi)
+    lib = _load()
+    r = np.ascontiguousarray(r)
+    rhs = np.ascontiguousarray(rhs)
+    return float(np.sqrt(lib.or_dot(g.nx, g.ny, g.nz, _p(r), _p(r)) / lib.or_dot(g.nx, g.ny, g.nz, _p(rhs), _p(rhs))))
+
+
+def mac_project(prob, tol=1e-12, maxcycles=200):
+    """Whole projection on a workloads.Problem: map, rhs, solve, correct.
+    Returns a dict of every intermediate."""
+    g = Grid.of(prob)
+    beta0_cc, (cx, cy, cz) = map_base_state(g, prob.geometry, prob.beta0_1d, prob.dr, prob.center, prob.rho)
+    rhs, m = mac_rhs(g, beta0_cc, prob.ux, prob.uy, prob.uz, prob.S)
+    phi, info = solve(g, cx, cy, cz, rhs, tol=tol, maxcycles=maxcycles)
+    ux, uy, uz = velocity_correct(g, cx, cy, cz, beta0_cc, phi, prob.ux, prob.uy, prob.uz)
+    return dict(grid=g, beta0_cc=beta0_cc, cx=cx, cy=cy, cz=cz, rhs=rhs, mean=m, phi=phi, info=info,
+                ux=ux, uy=uy, uz=uz)

@@ -1,0 +1,694 @@
+/*
+ * mproj_oracle.c -- plain FP64 CPU reference for the MAC-projection solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the oracle the GPU library is checked
+ * against.  Only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark load it; the product path never does.  It shares no source,
+ * header, table or helper with the HIP library.
+ *
+ * What it computes (Fan, Nonaka, Almgren, Harpole, Zingale, "MAESTROeX: A
+ * Massively Parallel Low Mach Number Astrophysical Solver"):
+ *
+ *  - fill (Sec. 3.1): the 1D base state beta0 mapped onto the Cartesian cells,
+ *    by direct injection in planar geometry and by interpolation in the radius
+ *    r = |x - centre| in spherical geometry (linear here, on the uniform radial
+ *    grid r_j = (j + 1/2) dr);
+ *  - the MAC projection of Sec. 3.2 Steps 3 and 7 (the constraints div1/div2,
+ *    i.e. the velocity constraint of Sec. 2 with the dp0/dt term folded into
+ *    S) and Appendix A: find phi with
+ *        div((beta0/rho) grad phi) = div(beta0 U) - beta0 S,
+ *    then U <- U - (beta0/rho)/beta0 grad phi, so div(beta0 U) = beta0 S.
+ *
+ * Discretisation (cell-centred finite volume on a uniform grid of spacing h):
+ *    (G phi)_f = (phi_R - phi_L)/h                 cell -> face
+ *    (D F)_i   = sum_d (F_{i+1/2 e_d} - F_{i-1/2 e_d})/h   face -> cell
+ *    M phi     = D (C (G phi)),   C = diag(face coefficients c_f)
+ *  with c_f the harmonic mean of the cell values beta0/rho on the two sides,
+ *  beta0 on a face the arithmetic mean of the two cells, periodic faces
+ *  wrapping, and Neumann boundary faces being walls (c_f = 0, U_f = 0).
+ *  The right-hand side is made mean-zero and the solution is the unique
+ *  mean-zero phi.
+ *
+ * The solver is a geometric multigrid V-cycle iteration (red-black Gauss-Seidel,
+ * 8-cell average restriction, 4-face average coefficient restriction,
+ * piecewise-constant prolongation, conjugate gradients on the coarsest grid),
+ * iterated until ||rhs - M phi||_2 / ||rhs||_2 <= tol.  Only the converged
+ * answer matters; it is the definition above, reached iteratively.
+ *
+ * Layouts (C order, x fastest):  cells [nz][ny][nx];  x faces [nz][ny][nx+bx];
+ * y faces [nz][ny+by][nx]; z faces [nz+bz][ny][nx]; b* = 0 periodic (n faces,
+ * face i is the low face of cell i) or 1 Neumann (n+1 faces, 0 and n walls).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int nx, ny, nz;
+    double h;
+    int bx, by, bz; /* 0 periodic, 1 Neumann */
+} grid_t;
+
+static grid_t mkgrid(int nx, int ny, int nz, double h, int bx, int by, int bz)
+{
+    grid_t g = {nx, ny, nz, h, bx, by, bz};
+    return g;
+}
+
+static long ncell(const grid_t *g) { return (long)g->nx * g->ny * g->nz; }
+static long cell(const grid_t *g, int i, int j, int k) { return ((long)k * g->ny + j) * g->nx + i; }
+static long xface(const grid_t *g, int f, int j, int k) { return ((long)k * g->ny + j) * (g->nx + g->bx) + f; }
+static long yface(const grid_t *g, int i, int f, int k) { return ((long)k * (g->ny + g->by) + f) * g->nx + i; }
+static long zface(const grid_t *g, int i, int j, int f) { return ((long)f * g->ny + j) * g->nx + i; }
+static long nxface(const grid_t *g) { return (long)g->nz * g->ny * (g->nx + g->bx); }
+static long nyface(const grid_t *g) { return (long)g->nz * (g->ny + g->by) * g->nx; }
+static long nzface(const grid_t *g) { return (long)(g->nz + g->bz) * g->ny * g->nx; }
+
+/* Cells on the two sides of face f along an axis of n cells.  Returns 0 for a
+ * Neumann wall (no cell on one side). */
+static int face_sides(int f, int n, int b, int *L, int *R)
+{
+    if (b) {
+        if (f == 0 || f == n) return 0;
+        *L = f - 1;
+        *R = f;
+        return 1;
+    }
+    *L = (f + n - 1) % n;
+    *R = f % n;
+    return 1;
+}
+
+/* Index of the high face of cell i along an axis of n cells. */
+static int high_face(int i, int n, int b) { return b ? i + 1 : (i + 1) % n; }
+
+/* ---------------------------------------------------------------------- */
+/* fill: base state -> cells (Sec. 3.1)                                    */
+/* ---------------------------------------------------------------------- */
+
+/* Distance from the centre of cell (i,j,k) to `center`. */
+static double cell_radius(const grid_t *g, const double *center, int i, int j, int k)
+{
+    double x = (i + 0.5) * g->h - center[0];
+    double y = (j + 0.5) * g->h - center[1];
+    double z = (k + 0.5) * g->h - center[2];
+    return sqrt(x * x + y * y + z * z);
+}
+
+/* Linear interpolation of a table given at r_j = (j + 1/2) dr; the end values
+ * are held beyond the first and last table points. */
+static double radial_lookup(const double *tab, int n1d, double dr, double r)
+{
+    double t = r / dr - 0.5;
+    if (t <= 0.0) return tab[0];
+    if (t >= (double)(n1d - 1)) return tab[n1d - 1];
+    int j = (int)floor(t);
+    double w = t - j;
+    return (1.0 - w) * tab[j] + w * tab[j + 1];
+}
+
+void or_cell_radius(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *center, double *r)
+{
+    grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) r[cell(&g, i, j, k)] = cell_radius(&g, center, i, j, k);
+}
+
+/* geometry 0: planar, table indexed by the z cell (n1d == nz, direct injection).
+ * geometry 1: spherical, table on r_j = (j + 1/2) dr about `center`. */
+int or_fill_beta0(int nx, int ny, int nz, double h, int bx, int by, int bz, int geometry, const double *b1d, int n1d,
+                  double dr, const double *center, double *beta0_cc)
+{
+    grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
+    if (geometry == 0 && n1d != nz) return 1;
+    if (geometry == 1 && (n1d < 2 || !(dr > 0.0))) return 1;
+#pragma omp parallel for
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                double v;
+                if (geometry == 0)
+                    v = b1d[k];
+                else
+                    v = radial_lookup(b1d, n1d, dr, cell_radius(&g, center, i, j, k));
+                beta0_cc[cell(&g, i, j, k)] = v;
+            }
+    return 0;
+}
+
+/* Face coefficients: harmonic mean of beta0/rho on the two sides; walls 0. */
+void or_face_coefs(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *beta0_cc, const double *rho,
+                   double *cx, double *cy, double *cz)
+{
+    grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
+    long n = ncell(&g);
+    double *c = (double *)malloc(sizeof(double) * n);
+    for (long q = 0; q < n; q++) c[q] = beta0_cc[q] / rho[q];
+    int L, R;
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int f = 0; f < nx + bx; f++) {
+                double v = 0.0;
+                if (face_sides(f, nx, bx, &L, &R)) {
+                    double a = c[cell(&g, L, j, k)], b = c[cell(&g, R, j, k)];
+                    v = 2.0 * a * b / (a + b);
+                }
+                cx[xface(&g, f, j, k)] = v;
+            }
+    for (int k = 0; k < nz; k++)
+        for (int f = 0; f < ny + by; f++)
+            for (int i = 0; i < nx; i++) {
+                double v = 0.0;
+                if (face_sides(f, ny, by, &L, &R)) {
+                    double a = c[cell(&g, i, L, k)], b = c[cell(&g, i, R, k)];
+                    v = 2.0 * a * b / (a + b);
+                }
+                cy[yface(&g, i, f, k)] = v;
+            }
+    for (int f = 0; f < nz + bz; f++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                double v = 0.0;
+                if (face_sides(f, nz, bz, &L, &R)) {
+                    double a = c[cell(&g, i, j, L)], b = c[cell(&g, i, j, R)];
+                    v = 2.0 * a * b / (a + b);
+                }
+                cz[zface(&g, i, j, f)] = v;
+            }
+    free(c);
+}
+
+/* ---------------------------------------------------------------------- */
+/* G, D and M = D C G                                                      */
+/* ---------------------------------------------------------------------- */
+
+/* (G phi)_f = (phi_R - phi_L)/h on every face with two sides; 0 on walls. */
+void or_gradient(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *phi, double *gx, double *gy,
+                 double *gz)
+{
+    grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
+    int L, R;
+#pragma omp parallel for private(L, R)
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int f = 0; f < nx + bx; f++)
+                gx[xface(&g, f, j, k)] =
+                    face_sides(f, nx, bx, &L, &R) ? (phi[cell(&g, R, j, k)] - phi[cell(&g, L, j, k)]) / h : 0.0;
+#pragma omp parallel for private(L, R)
+    for (int k = 0; k < nz; k++)
+        for (int f = 0; f < ny + by; f++)
+            for (int i = 0; i < nx; i++)
+                gy[yface(&g, i, f, k)] =
+                    face_sides(f, ny, by, &L, &R) ? (phi[cell(&g, i, R, k)] - phi[cell(&g, i, L, k)]) / h : 0.0;
+#pragma omp parallel for private(L, R)
+    for (int f = 0; f < nz + bz; f++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++)
+                gz[zface(&g, i, j, f)] =
+                    face_sides(f, nz, bz, &L, &R) ? (phi[cell(&g, i, j, R)] - phi[cell(&g, i, j, L)]) / h : 0.0;
+}
+
+/* (D F)_i = sum_d (F_high - F_low)/h; wall faces carry no flux. */
+void or_divergence(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *fx, const double *fy,
+                   const double *fz, double *out)
+{
+    grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
+#pragma omp parallel for
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                int ih = high_face(i, nx, bx), jh = high_face(j, ny, by), kh = high_face(k, nz, bz);
+                double xl = (bx && i == 0) ? 0.0 : fx[xface(&g, i, j, k)];
+                double xh = (bx && ih == nx) ? 0.0 : fx[xface(&g, ih, j, k)];
+                double yl = (by && j == 0) ? 0.0 : fy[yface(&g, i, j, k)];
+                double yh = (by && jh == ny) ? 0.0 : fy[yface(&g, i, jh, k)];
+                double zl = (bz && k == 0) ? 0.0 : fz[zface(&g, i, j, k)];
+                double zh = (bz && kh == nz) ? 0.0 : fz[zface(&g, i, j, kh)];
+                out[cell(&g, i, j, k)] = ((xh - xl) + (yh - yl) + (zh - zl)) / h;
+            }
+}
+
+static void face_product(long n, const double *a, const double *b, double *out)
+{
+    for (long q = 0; q < n; q++) out[q] = a[q] * b[q];
+}
+
+/* out = M phi = D (C (G phi)), written as the three steps of its definition. */
+void or_apply(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *cx, const double *cy,
+              const double *cz, const double *phi, double *out)
+{
+    grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
+    long mx = nxface(&g), my = nyface(&g), mz = nzface(&g);
+    double *gx = (double *)malloc(sizeof(double) * mx);
+    double *gy = (double *)malloc(sizeof(double) * my);
+    double *gz = (double *)malloc(sizeof(double) * mz);
+    or_gradient(nx, ny, nz, h, bx, by, bz, phi, gx, gy, gz);
+    face_product(mx, cx, gx, gx);
+    face_product(my, cy, gy, gy);
+    face_product(mz, cz, gz, gz);
+    or_divergence(nx, ny, nz, h, bx, by, bz, gx, gy, gz, out);
+    free(gx);
+    free(gy);
+    free(gz);
+}
+
+/* beta0 on faces (arithmetic mean of the two cells) times U; walls 0. */
+static void beta0_flux(const grid_t *g, const double *beta0_cc, const double *ux, const double *uy, const double *uz,
+                       double *fx, double *fy, double *fz)
+{
+    int L, R;
+    for (int k = 0; k < g->nz; k++)
+        for (int j = 0; j < g->ny; j++)
+            for (int f = 0; f < g->nx + g->bx; f++) {
+                long q = xface(g, f, j, k);
+                fx[q] = face_sides(f, g->nx, g->bx, &L, &R)
+                            ? 0.5 * (beta0_cc[cell(g, L, j, k)] + beta0_cc[cell(g, R, j, k)]) * ux[q]
+                            : 0.0;
+            }
+    for (int k = 0; k < g->nz; k++)
+        for (int f = 0; f < g->ny + g->by; f++)
+            for (int i = 0; i < g->nx; i++) {
+                long q = yface(g, i, f, k);
+                fy[q] = face_sides(f, g->ny, g->by, &L, &R)
+                            ? 0.5 * (beta0_cc[cell(g, i, L, k)] + beta0_cc[cell(g, i, R, k)]) * uy[q]
+                            : 0.0;
+            }
+    for (int f = 0; f < g->nz + g->bz; f++)
+        for (int j = 0; j < g->ny; j++)
+            for (int i = 0; i < g->nx; i++) {
+                long q = zface(g, i, j, f);
+                fz[q] = face_sides(f, g->nz, g->bz, &L, &R)
+                            ? 0.5 * (beta0_cc[cell(g, i, j, L)] + beta0_cc[cell(g, i, j, R)]) * uz[q]
+                            : 0.0;
+            }
+}
+
+/* out = D(beta0 U). */
+void or_beta0_divergence(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *beta0_cc,
+                         const double *ux, const double *uy, const double *uz, double *out)
+{
+    grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
+    long mx = nxface(&g), my = nyface(&g), mz = nzface(&g);
+    double *fx = (double *)malloc(sizeof(double) * mx);
+    double *fy = (double *)malloc(sizeof(double) * my);
+    double *fz = (double *)malloc(sizeof(double) * mz);
+    beta0_flux(&g, beta0_cc, ux, uy, uz, fx, fy, fz);
+    or_divergence(nx, ny, nz, h, bx, by, bz, fx, fy, fz, out);
+    free(fx);
+    free(fy);
+    free(fz);
+}
+
+static double plane_ordered_sum(const grid_t *g, const double *a)
+{
+    /* sum each z plane, then the planes in order: independent of threads */
+    double *ps = (double *)malloc(sizeof(double) * g->nz);
+    long plane = (long)g->nx * g->ny;
+#pragma omp parallel for
+    for (int k = 0; k < g->nz; k++) {
+        double s = 0.0;
+        for (long q = 0; q < plane; q++) s += a[(long)k * plane + q];
+        ps[k] = s;
+    }
+    double s = 0.0;
+    for (int k = 0; k < g->nz; k++) s += ps[k];
+    free(ps);
+    return s;
+}
+
+static double plane_ordered_dot(const grid_t *g, const double *a, const double *b)
+{
+    double *ps = (double *)malloc(sizeof(double) * g->nz);
+    long plane = (long)g->nx * g->ny;
+#pragma omp parallel for
+    for (int k = 0; k < g->nz; k++) {
+        double s = 0.0;
+        for (long q = 0; q < plane; q++) s += a[(long)k * plane + q] * b[(long)k * plane + q];
+        ps[k] = s;
+    }
+    double s = 0.0;
+    for (int k = 0; k < g->nz; k++) s += ps[k];
+    free(ps);
+    return s;
+}
+
+double or_sum(int nx, int ny, int nz, const double *a)
+{
+    grid_t g = mkgrid(nx, ny, nz, 1.0, 0, 0, 0);
+    return plane_ordered_sum(&g, a);
+}
+
+double or_dot(int nx, int ny, int nz, const double *a, const double *b)
+{
+    grid_t g = mkgrid(nx, ny, nz, 1.0, 0, 0, 0);
+    return plane_ordered_dot(&g, a, b);
+}
+
+/* MAC right-hand side: rhs = D(beta0 U) - beta0 S, then its mean removed.
+ * Returns the removed mean. */
+double or_mac_rhs(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *beta0_cc, const double *ux,
+                  const double *uy, const double *uz, const double *S, double *rhs)
+{
+    grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
+    long n = ncell(&g);
+    or_beta0_divergence(nx, ny, nz, h, bx, by, bz, beta0_cc, ux, uy, uz, rhs);
+    for (long q = 0; q < n; q++) rhs[q] -= beta0_cc[q] * S[q];
+    double m = plane_ordered_sum(&g, rhs) / (double)n;
+    for (long q = 0; q < n; q++) rhs[q] -= m;
+    return m;
+}
+
+/* U <- U - (c_f / beta0_f) (G phi)_f on every face with two sides. */
+void or_velocity_correct(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *cx, const double *cy,
+                         const double *cz, const double *beta0_cc, const double *phi, double *ux, double *uy,
+                         double *uz)
+{
+    grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
+    int L, R;
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int f = 0; f < nx + bx; f++)
+                if (face_sides(f, nx, bx, &L, &R)) {
+                    long a = cell(&g, L, j, k), b = cell(&g, R, j, k), q = xface(&g, f, j, k);
+                    ux[q] -= cx[q] / (0.5 * (beta0_cc[a] + beta0_cc[b])) * (phi[b] - phi[a]) / h;
+                }
+    for (int k = 0; k < nz; k++)
+        for (int f = 0; f < ny + by; f++)
+            for (int i = 0; i < nx; i++)
+                if (face_sides(f, ny, by, &L, &R)) {
+                    long a = cell(&g, i, L, k), b = cell(&g, i, R, k), q = yface(&g, i, f, k);
+                    uy[q] -= cy[q] / (0.5 * (beta0_cc[a] + beta0_cc[b])) * (phi[b] - phi[a]) / h;
+                }
+    for (int f = 0; f < nz + bz; f++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++)
+                if (face_sides(f, nz, bz, &L, &R)) {
+                    long a = cell(&g, i, j, L), b = cell(&g, i, j, R), q = zface(&g, i, j, f);
+                    uz[q] -= cz[q] / (0.5 * (beta0_cc[a] + beta0_cc[b])) * (phi[b] - phi[a]) / h;
+                }
+}
+
+/* dL/dc_f = (G lam)_f (G phi)_f for L = <w, phi>, where lam solves M lam = w
+ * (mean-zero).  Walls get 0. */
+void or_coef_grad(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *lam, const double *phi,
+                  double *gx, double *gy, double *gz)
+{
+    grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
+    long mx = nxface(&g), my = nyface(&g), mz = nzface(&g);
+    double *px = (double *)malloc(sizeof(double) * mx);
+    double *py = (double *)malloc(sizeof(double) * my);
+    double *pz = (double *)malloc(sizeof(double) * mz);
+    or_gradient(nx, ny, nz, h, bx, by, bz, lam, gx, gy, gz);
+    or_gradient(nx, ny, nz, h, bx, by, bz, phi, px, py, pz);
+    face_product(mx, gx, px, gx);
+    face_product(my, gy, py, gy);
+    face_product(mz, gz, pz, gz);
+    free(px);
+    free(py);
+    free(pz);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Multigrid                                                               */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    grid_t g;
+    double *cx, *cy, *cz; /* external face layout */
+    double *phi, *rhs, *res;
+} level_t;
+
+#define MAX_LEVELS 24
+
+/* One Gauss-Seidel update of cell (i,j,k) for M phi = rhs:
+ *   phi_i = (sum_f c_f phi_nb(f) - h^2 rhs_i) / sum_f c_f. */
+static void relax_cell(const level_t *lv, int i, int j, int k)
+{
+    const grid_t *g = &lv->g;
+    int nx = g->nx, ny = g->ny, nz = g->nz;
+    double num = 0.0, den = 0.0, c;
+    int n_;
+    /* x low / high */
+    if (!(g->bx && i == 0)) {
+        c = lv->cx[xface(g, i, j, k)];
+        n_ = (i + nx - 1) % nx;
+        num += c * lv->phi[cell(g, n_, j, k)];
+        den += c;
+    }
+    if (!(g->bx && i == nx - 1)) {
+        c = lv->cx[xface(g, high_face(i, nx, g->bx), j, k)];
+        n_ = (i + 1) % nx;
+        num += c * lv->phi[cell(g, n_, j, k)];
+        den += c;
+    }
+    if (!(g->by && j == 0)) {
+        c = lv->cy[yface(g, i, j, k)];
+        n_ = (j + ny - 1) % ny;
+        num += c * lv->phi[cell(g, i, n_, k)];
+        den += c;
+    }
+    if (!(g->by && j == ny - 1)) {
+        c = lv->cy[yface(g, i, high_face(j, ny, g->by), k)];
+        n_ = (j + 1) % ny;
+        num += c * lv->phi[cell(g, i, n_, k)];
+        den += c;
+    }
+    if (!(g->bz && k == 0)) {
+        c = lv->cz[zface(g, i, j, k)];
+        n_ = (k + nz - 1) % nz;
+        num += c * lv->phi[cell(g, i, j, n_)];
+        den += c;
+    }
+    if (!(g->bz && k == nz - 1)) {
+        c = lv->cz[zface(g, i, j, high_face(k, nz, g->bz))];
+        n_ = (k + 1) % nz;
+        num += c * lv->phi[cell(g, i, j, n_)];
+        den += c;
+    }
+    long q = cell(g, i, j, k);
+    if (den > 0.0) lv->phi[q] = (num - g->h * g->h * lv->rhs[q]) / den;
+}
+
+static void rbgs(level_t *lv)
+{
+    const grid_t *g = &lv->g;
+    /* With an odd periodic extent, cells of one colour can touch across the
+     * wrap; then the sweep runs serially so the result does not depend on the
+     * thread count. */
+    int par = !((g->bx == 0 && g->nx % 2) || (g->by == 0 && g->ny % 2) || (g->bz == 0 && g->nz % 2));
+    for (int colour = 0; colour < 2; colour++) {
+#pragma omp parallel for if (par)
+        for (int k = 0; k < g->nz; k++)
+            for (int j = 0; j < g->ny; j++)
+                for (int i = (j + k + colour) & 1; i < g->nx; i += 2) relax_cell(lv, i, j, k);
+    }
+}
+
+static void residual(level_t *lv)
+{
+    const grid_t *g = &lv->g;
+    long n = ncell(g);
+    or_apply(g->nx, g->ny, g->nz, g->h, g->bx, g->by, g->bz, lv->cx, lv->cy, lv->cz, lv->phi, lv->res);
+    for (long q = 0; q < n; q++) lv->res[q] = lv->rhs[q] - lv->res[q];
+}
+
+/* coarse face = mean of the 4 fine faces that cover it */
+static void restrict_coefs(const level_t *f, level_t *c)
+{
+    const grid_t *gf = &f->g, *gc = &c->g;
+    for (int K = 0; K < gc->nz; K++)
+        for (int J = 0; J < gc->ny; J++)
+            for (int F = 0; F < gc->nx + gc->bx; F++) {
+                double s = 0.0;
+                for (int b = 0; b < 2; b++)
+                    for (int a = 0; a < 2; a++) s += f->cx[xface(gf, 2 * F, 2 * J + a, 2 * K + b)];
+                c->cx[xface(gc, F, J, K)] = 0.25 * s;
+            }
+    for (int K = 0; K < gc->nz; K++)
+        for (int F = 0; F < gc->ny + gc->by; F++)
+            for (int I = 0; I < gc->nx; I++) {
+                double s = 0.0;
+                for (int b = 0; b < 2; b++)
+                    for (int a = 0; a < 2; a++) s += f->cy[yface(gf, 2 * I + a, 2 * F, 2 * K + b)];
+                c->cy[yface(gc, I, F, K)] = 0.25 * s;
+            }
+    for (int F = 0; F < gc->nz + gc->bz; F++)
+        for (int J = 0; J < gc->ny; J++)
+            for (int I = 0; I < gc->nx; I++) {
+                double s = 0.0;
+                for (int b = 0; b < 2; b++)
+                    for (int a = 0; a < 2; a++) s += f->cz[zface(gf, 2 * I + a, 2 * J + b, 2 * F)];
+                c->cz[zface(gc, I, J, F)] = 0.25 * s;
+            }
+}
+
+/* coarse rhs = mean of the 8 fine residuals */
+static void restrict_residual(const level_t *f, level_t *c)
+{
+    const grid_t *gf = &f->g, *gc = &c->g;
+#pragma omp parallel for
+    for (int K = 0; K < gc->nz; K++)
+        for (int J = 0; J < gc->ny; J++)
+            for (int I = 0; I < gc->nx; I++) {
+                double s = 0.0;
+                for (int c_ = 0; c_ < 2; c_++)
+                    for (int b = 0; b < 2; b++)
+                        for (int a = 0; a < 2; a++) s += f->res[cell(gf, 2 * I + a, 2 * J + b, 2 * K + c_)];
+                c->rhs[cell(gc, I, J, K)] = 0.125 * s;
+            }
+}
+
+/* fine phi += coarse phi of the parent cell */
+static void prolong_add(level_t *f, const level_t *c)
+{
+    const grid_t *gf = &f->g, *gc = &c->g;
+#pragma omp parallel for
+    for (int k = 0; k < gf->nz; k++)
+        for (int j = 0; j < gf->ny; j++)
+            for (int i = 0; i < gf->nx; i++) f->phi[cell(gf, i, j, k)] += c->phi[cell(gc, i / 2, j / 2, k / 2)];
+}
+
+static void remove_mean(const grid_t *g, double *a)
+{
+    long n = ncell(g);
+    double m = plane_ordered_sum(g, a) / (double)n;
+    for (long q = 0; q < n; q++) a[q] -= m;
+}
+
+/* Conjugate gradients on A = -M (symmetric, positive on mean-zero vectors)
+ * for the coarsest grid; rhs is made mean-zero first. */
+static void bottom_cg(level_t *lv)
+{
+    const grid_t *g = &lv->g;
+    long n = ncell(g);
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *p = (double *)malloc(sizeof(double) * n);
+    double *Ap = (double *)malloc(sizeof(double) * n);
+    remove_mean(g, lv->rhs);
+    for (long q = 0; q < n; q++) {
+        lv->phi[q] = 0.0;
+        r[q] = -lv->rhs[q]; /* A x = -rhs */
+        p[q] = r[q];
+    }
+    double rr = plane_ordered_dot(g, r, r), rr0 = rr;
+    long maxit = 20 * n + 100;
+    for (long it = 0; it < maxit && rr > 1e-30 * rr0 && rr > 0.0; it++) {
+        or_apply(g->nx, g->ny, g->nz, g->h, g->bx, g->by, g->bz, lv->cx, lv->cy, lv->cz, p, Ap);
+        for (long q = 0; q < n; q++) Ap[q] = -Ap[q];
+        double pAp = plane_ordered_dot(g, p, Ap);
+        if (!(pAp > 0.0)) break;
+        double alpha = rr / pAp;
+        for (long q = 0; q < n; q++) {
+            lv->phi[q] += alpha * p[q];
+            r[q] -= alpha * Ap[q];
+        }
+        remove_mean(g, r);
+        double rr1 = plane_ordered_dot(g, r, r);
+        double beta = rr1 / rr;
+        rr = rr1;
+        for (long q = 0; q < n; q++) p[q] = r[q] + beta * p[q];
+    }
+    remove_mean(g, lv->phi);
+    free(r);
+    free(p);
+    free(Ap);
+}
+
+static void vcycle(level_t *lv, int l, int nlev, int nu1, int nu2)
+{
+    if (l == nlev - 1) {
+        bottom_cg(&lv[l]);
+        return;
+    }
+    for (int s = 0; s < nu1; s++) rbgs(&lv[l]);
+    residual(&lv[l]);
+    restrict_residual(&lv[l], &lv[l + 1]);
+    memset(lv[l + 1].phi, 0, sizeof(double) * ncell(&lv[l + 1].g));
+    vcycle(lv, l + 1, nlev, nu1, nu2);
+    prolong_add(&lv[l], &lv[l + 1]);
+    for (int s = 0; s < nu2; s++) rbgs(&lv[l]);
+}
+
+static double norm2(const grid_t *g, const double *a) { return sqrt(plane_ordered_dot(g, a, a)); }
+
+/* Solve M phi = rhs (rhs made mean-zero; phi returned mean-zero).
+ * phi is the initial guess on entry.  Returns 0 on convergence, 1 otherwise. */
+int or_solve(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *cx, const double *cy,
+             const double *cz, const double *rhs, double *phi, double tol, int maxcycles, int nu1, int nu2,
+             int *cycles_out, double *relres_out)
+{
+    level_t lv[MAX_LEVELS];
+    int nlev = 0;
+    grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
+    for (;;) {
+        level_t *L = &lv[nlev];
+        L->g = g;
+        long n = ncell(&g);
+        L->phi = (double *)calloc(n, sizeof(double));
+        L->rhs = (double *)malloc(sizeof(double) * n);
+        L->res = (double *)malloc(sizeof(double) * n);
+        if (nlev == 0) {
+            L->cx = (double *)cx;
+            L->cy = (double *)cy;
+            L->cz = (double *)cz;
+        } else {
+            L->cx = (double *)malloc(sizeof(double) * nxface(&g));
+            L->cy = (double *)malloc(sizeof(double) * nyface(&g));
+            L->cz = (double *)malloc(sizeof(double) * nzface(&g));
+            restrict_coefs(&lv[nlev - 1], L);
+        }
+        nlev++;
+        int can = g.nx % 2 == 0 && g.ny % 2 == 0 && g.nz % 2 == 0 && g.nx >= 8 && g.ny >= 8 && g.nz >= 8;
+        if (!can || nlev == MAX_LEVELS) break;
+        g = mkgrid(g.nx / 2, g.ny / 2, g.nz / 2, 2.0 * g.h, bx, by, bz);
+    }
+    long n = ncell(&lv[0].g);
+    memcpy(lv[0].rhs, rhs, sizeof(double) * n);
+    remove_mean(&lv[0].g, lv[0].rhs);
+    memcpy(lv[0].phi, phi, sizeof(double) * n);
+    double nb = norm2(&lv[0].g, lv[0].rhs);
+    int cyc = 0;
+    double rel = 0.0;
+    int status = 0;
+    if (nb > 0.0) {
+        for (;;) {
+            residual(&lv[0]);
+            rel = norm2(&lv[0].g, lv[0].res) / nb;
+            if (rel <= tol) break;
+            if (cyc >= maxcycles) {
+                status = 1;
+                break;
+            }
+            vcycle(lv, 0, nlev, nu1, nu2);
+            cyc++;
+        }
+    } else {
+        memset(lv[0].phi, 0, sizeof(double) * n);
+    }
+    remove_mean(&lv[0].g, lv[0].phi);
+    memcpy(phi, lv[0].phi, sizeof(double) * n);
+    for (int l = 0; l < nlev; l++) {
+        free(lv[l].phi);
+        free(lv[l].rhs);
+        free(lv[l].res);
+        if (l > 0) {
+            free(lv[l].cx);
+            free(lv[l].cy);
+            free(lv[l].cz);
+        }
+    }
+    if (cycles_out) *cycles_out = cyc;
+    if (relres_out) *relres_out = rel;
+    return status;
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,145 @@
+"""Planted mistakes in copies of the oracle must fail at least one pin.
+
+Each case copies `oracle/mproj_oracle.c`, replaces one exact piece of text by a
+plausible mistake (a dropped term, a flipped sign, a wrong index, a wrong
+constant), compiles the copy with gcc on the CPU, routes the oracle wrappers
+through it and checks that the named pin now fails.  The oracle source itself
+is never modified.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_03634_amd import workloads as W
+from tests import pins
+
+
+def pin_series_conductance():
+    g = oracle.Grid(2, 1, 1, 0.25, (1, 0, 0))
+    cx, _, _ = oracle.face_coefs(g, np.array([[[3.0, 3.0]]]), np.array([[[1.5, 0.2]]]))
+    a, b, h = 2.0, 15.0, 0.25
+    return abs(cx[0, 0, 1] / h - 1.0 / (h / (2 * a) + h / (2 * b))) < 1e-12
+
+
+def pin_apply_incidence():
+    ok = True
+    for bc, shape in (((1, 0, 1), (6, 4, 10)), ((0, 1, 0), (5, 7, 3))):
+        nx, ny, nz = shape
+        cx, cy, cz = W.random_coefs(nx, ny, nz, bc, 11)
+        cy *= 3.0
+        cz *= 7.0
+        g = oracle.Grid(nx, ny, nz, 1.0 / nz, bc)
+        phi = W.random_cells(nx, ny, nz, 12)
+        ref = pins.operator(nx, ny, nz, 1.0 / nz, bc, cx, cy, cz) @ phi.ravel()
+        got = oracle.apply(g, cx, cy, cz, phi).ravel()
+        ok &= bool(np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max())
+    return ok
+
+
+def pin_injection():
+    p = W.planar_problem(12, nx=6, ny=5, contrast=1e3, seed=5)
+    b = oracle.fill_beta0(oracle.Grid.of(p), 0, p.beta0_1d, p.dr, p.center)
+    return bool(np.array_equal(b, np.broadcast_to(p.beta0_1d[:, None, None], b.shape)))
+
+
+def pin_linear_profile():
+    n, h = 8, 1.0 / 8
+    dr = h / 5
+    rj = (np.arange(W.spherical_n1d(n)) + 0.5) * dr
+    b = oracle.fill_beta0(oracle.Grid(n, n, n, h, (1, 1, 1)), 1, 2.0 + 3.0 * rj, dr, (0.5, 0.5, 0.5))
+    x = (np.arange(n) + 0.5) * h - 0.5
+    r = np.sqrt(x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2)
+    return bool(np.allclose(b, 2.0 + 3.0 * r, rtol=1e-13, atol=0))
+
+
+def pin_constraint():
+    p = W.planar_problem(8, contrast=1e3, seed=8)
+    res = oracle.mac_project(p, tol=1e-13)
+    g = res["grid"]
+    d = oracle.beta0_divergence(g, res["beta0_cc"], res["ux"], res["uy"], res["uz"])
+    # the constraint as stated (beta0 at faces = mean of the two cells), assembled here
+    b0 = res["beta0_cc"]
+    bz = 0.5 * (b0[1:] + b0[:-1])
+    fx = b0 * res["ux"]
+    fy = b0 * res["uy"]
+    fz = np.zeros_like(res["uz"])
+    fz[1:-1] = bz * res["uz"][1:-1]
+    D = pins.divergence_matrix(g.nx, g.ny, g.nz, g.h, g.bc)
+    d_ind = (D @ np.concatenate([fx.ravel(), fy.ravel(), fz.ravel()])).reshape(d.shape)
+    target = b0 * p.S - (b0 * p.S).mean()
+    scale = np.abs(oracle.beta0_divergence(g, b0, p.ux, p.uy, p.uz)).max()
+    return bool(np.abs(d_ind - target).max() < 1e-9 * scale and np.abs(d - target).max() < 1e-9 * scale)
+
+
+def pin_sparse_lu():
+    nx, ny, nz = 8, 8, 8
+    bc = (0, 0, 1)
+    cx, cy, cz = W.random_coefs(nx, ny, nz, bc, 31)
+    rhs = W.random_cells(nx, ny, nz, 32)
+    g = oracle.Grid(nx, ny, nz, 1.0 / nz, bc)
+    phi, _ = oracle.solve(g, cx, cy, cz, rhs, tol=1e-13)
+    ref = pins.bordered_solve(pins.operator(nx, ny, nz, 1.0 / nz, bc, cx, cy, cz), rhs)
+    return bool(np.linalg.norm(phi.ravel() - ref) <= 1e-10 * np.linalg.norm(ref))
+
+
+def pin_coef_grad_fd():
+    n = 6
+    bc = (0, 0, 1)
+    g = oracle.Grid(n, n, n, 1.0 / n, bc)
+    cx, cy, cz = W.random_coefs(n, n, n, bc, 61)
+    rhs = W.random_cells(n, n, n, 62, mean_zero=True)
+    w = W.random_cells(n, n, n, 63)
+    phi, _ = oracle.solve(g, cx, cy, cz, rhs, tol=1e-13)
+    lam, _ = oracle.solve(g, cx, cy, cz, w, tol=1e-13)
+    gx, gy, gz = oracle.coef_grad(g, lam, phi)
+    rng = np.random.default_rng(2)
+    vx, vy, vz = (rng.uniform(-1, 1, a.shape) * (a != 0) for a in (cx, cy, cz))
+
+    def L(s):
+        M = pins.operator(n, n, n, 1.0 / n, bc, cx * (1 + s * vx), cy * (1 + s * vy), cz * (1 + s * vz))
+        return float((w.ravel() * pins.bordered_solve(M, rhs)).sum())
+
+    fd = (L(1e-6) - L(-1e-6)) / 2e-6
+    dd = float((gx * cx * vx).sum() + (gy * cy * vy).sum() + (gz * cz * vz).sum())
+    return abs(fd - dd) <= 1e-6 * abs(dd)
+
+
+MUTANTS = [
+    ("harmonic mean replaced by arithmetic mean", "v = 2.0 * a * b / (a + b);", "v = 0.5 * (a + b);",
+     pin_series_conductance),
+    ("gradient sign flipped on x faces",
+     "(phi[cell(&g, R, j, k)] - phi[cell(&g, L, j, k)]) / h", "(phi[cell(&g, L, j, k)] - phi[cell(&g, R, j, k)]) / h",
+     pin_apply_incidence),
+    ("z term dropped from the divergence", "((xh - xl) + (yh - yl) + (zh - zl)) / h", "((xh - xl) + (yh - yl)) / h",
+     pin_apply_incidence),
+    ("y wall flag read from the x axis", "double yl = (by && j == 0)", "double yl = (bx && j == 0)",
+     pin_apply_incidence),
+    ("planar table indexed by y", "v = b1d[k];", "v = b1d[j];", pin_injection),
+    ("radial table offset by half a cell", "double t = r / dr - 0.5;", "double t = r / dr;", pin_linear_profile),
+    ("sign of beta0 S in the right-hand side", "rhs[q] -= beta0_cc[q] * S[q];", "rhs[q] += beta0_cc[q] * S[q];",
+     pin_constraint),
+    ("z-face beta0 taken from one side",
+     "0.5 * (beta0_cc[cell(g, i, j, L)] + beta0_cc[cell(g, i, j, R)]) * uz[q]", "beta0_cc[cell(g, i, j, L)] * uz[q]",
+     pin_constraint),
+    ("velocity correction multiplies by beta0",
+     "ux[q] -= cx[q] / (0.5 * (beta0_cc[a] + beta0_cc[b]))", "ux[q] -= cx[q] * (0.5 * (beta0_cc[a] + beta0_cc[b]))",
+     pin_constraint),
+    ("convergence test on a mis-scaled norm", "rel = norm2(&lv[0].g, lv[0].res) / nb;",
+     "rel = norm2(&lv[0].g, lv[0].res) / (1e6 * nb);", pin_sparse_lu),
+    ("z factor dropped from the coefficient gradient", "    face_product(mz, gz, pz, gz);\n", "\n", pin_coef_grad_fd),
+]
+
+
+def test_pins_pass_on_the_oracle():
+    for _, _, _, pin in MUTANTS:
+        assert pin(), pin.__name__
+
+
+@pytest.mark.parametrize("case", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(case, tmp_path):
+    name, old, new, pin = case
+    src = oracle.source_text()
+    assert old in src, f"mutation site for '{name}' not found in the oracle source"
+    lib = oracle.compile_variant(src.replace(old, new), str(tmp_path / "mutant.so"))
+    with oracle.use_library(lib):
+        assert not pin(), f"pin {pin.__name__} did not catch: {name}"
