@@ -1,0 +1,166 @@
+/*
+ * mproj.h -- C ABI of the MI355X (gfx950) MAC-projection library libmproj.so.
+ *
+ * The operation is the MAC projection of the low Mach number method of Fan,
+ * Nonaka, Almgren, Harpole and Zingale ("MAESTROeX: A Massively Parallel Low
+ * Mach Number Astrophysical Solver"): Sec. 3.2, Steps 3 and 7, enforce the
+ * velocity constraint of Sec. 2,
+ *        div(beta0 U) = beta0 (S - (1/(Gamma1 p0)) dp0/dt),
+ * on face-centred velocities by a variable-coefficient Poisson solve (Appendix
+ * A).  With the dp0/dt term folded into S by the caller, the library solves
+ *        div((beta0/rho) grad phi) = div(beta0 U) - beta0 S       (mean removed)
+ * and sets U <- U - (beta0/rho)/beta0 grad phi, so that div(beta0 U) = beta0 S
+ * up to the solve residual and the mean.  beta0 comes from a 1D base state
+ * mapped onto the cells by the fill module of Sec. 3.1.
+ *
+ * Discretisation: uniform cell-centred grid of spacing h; for a face f between
+ * cells L and R, (G phi)_f = (phi_R - phi_L)/h; (D F)_i = sum over the three
+ * axes of (F_high - F_low)/h; the operator is M = D C G with C the face
+ * coefficients (harmonic mean of beta0/rho of the two cells); beta0 on a face
+ * is the arithmetic mean of the two cells.  Periodic axes wrap; Neumann axes
+ * end in walls (c = 0 and U = 0 on the two boundary faces).  M is symmetric
+ * negative semi-definite with the constants as null space: right-hand sides
+ * are made mean-zero and solutions are returned mean-zero.
+ *
+ * Layouts: every array is C order with x fastest.
+ *   cells    [nz][ny][nx]
+ *   x faces  [nz][ny][nx + bx]      b = 0 (periodic): n faces per row, face i
+ *   y faces  [nz][ny + by][nx]      is the low face of cell i; b = 1 (Neumann):
+ *   z faces  [nz + bz][ny][nx]      n + 1 faces, faces 0 and n are walls.
+ * Entries of U on wall faces are ignored on input and left unchanged; wall
+ * coefficients are ignored on input and written as 0 on output.
+ *
+ * Pointers: every array argument is a DEVICE pointer (HIP global memory on the
+ * context's device), owned by the caller, float64, contiguous, and must not
+ * alias another argument of the same call unless stated.  Scalars and the
+ * small structs below live in host memory.  Calls enqueue work on the
+ * context's stream and return after the last device->host read that the call
+ * needs, so outputs are ready in stream order when the call returns.
+ *
+ * Errors: every call returns an mp_status; no call aborts or throws.  Argument
+ * checks that need no device run before any HIP call.  mp_last_error() gives a
+ * text for the last failure on a context.  A context is not thread-safe; use
+ * one per host thread and stream.
+ */
+#ifndef MPROJ_H
+#define MPROJ_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MP_OK = 0,
+    MP_ERR_ARG = 1,            /* bad argument (null pointer, size, enum, table) */
+    MP_ERR_DEVICE = 2,         /* no usable HIP device, or a HIP call failed */
+    MP_ERR_NOMEM = 3,          /* device allocation failed */
+    MP_ERR_NOT_CONVERGED = 4,  /* max_outer reached; outputs hold the best iterate */
+    MP_ERR_NONFINITE = 5,      /* NaN/Inf found in an input or a norm */
+    MP_ERR_SINGULAR_RHS = 6,   /* demean == 0 and the right-hand side has a mean */
+    MP_ERR_STATE = 7           /* call order: coefficients or base state missing */
+} mp_status;
+
+enum { MP_BC_PERIODIC = 0, MP_BC_NEUMANN = 1 };
+enum { MP_PLANAR = 0, MP_SPHERICAL = 1 };
+enum { MP_FP64 = 0, MP_MIXED = 1 };
+
+/* Solver configuration, fixed for the life of a context. */
+typedef struct mp_config {
+    int nx, ny, nz;          /* cells per axis, each >= 1 */
+    double h;                /* cell size, > 0 */
+    int bc[3];               /* MP_BC_PERIODIC or MP_BC_NEUMANN for x, y, z */
+    int precision;           /* MP_FP64: FP64 V-cycles; MP_MIXED: FP32 V-cycles
+                                inside FP64 iterative refinement */
+    double rtol;             /* stop when ||rhs - M phi||_2 <= rtol ||rhs||_2 (FP64) */
+    int max_outer;           /* max V-cycles (FP64) or refinement steps (MIXED) */
+    int nu1, nu2;            /* red-black Gauss-Seidel sweeps before / after */
+    int cycles_per_outer;    /* FP32 V-cycles per refinement step (MIXED) */
+    double bottom_rtol;      /* BiCGStab tolerance on the coarsest grid */
+    int bottom_max_iter;     /* BiCGStab iteration cap */
+    int demean;              /* 1: remove the mean of the rhs; 0: require mean ~ 0 */
+    int kernel_timing;       /* 1: time the finest-level smoother launches with
+                                HIP events (mp_info.smooth_*) */
+    void *stream;            /* hipStream_t for every launch; NULL = null stream */
+    int device;              /* HIP device ordinal */
+} mp_config;
+
+/* Per-call report, filled by mp_mac_project and mp_solve. */
+typedef struct mp_info {
+    int outer_iters;         /* refinement steps (MIXED) or V-cycles (FP64) */
+    int vcycles;             /* V-cycles run */
+    int bottom_iters_total;  /* reserved (BiCGStab counts stay on the device) */
+    int levels;              /* multigrid levels, finest included */
+    double rel_resid;        /* final ||rhs - M phi||_2 / ||rhs||_2 in FP64 */
+    double div_defect;       /* ||D(beta0 U_new) - beta0 S - m||_2 / ||rhs||_2 */
+    double rhs_norm;         /* ||rhs||_2 after the mean is removed */
+    double rhs_mean;         /* mean removed from div(beta0 U) - beta0 S */
+    double resid_hist[64];   /* relative residual before each step */
+    double ms_rhs, ms_solve, ms_correct;   /* phase times (HIP events) */
+    double smooth_ms_total;  /* summed finest-level smoother time (kernel_timing) */
+    int smooth_launches;     /* number of launches summed above */
+    int flags;               /* bit 0: stagnation detected */
+} mp_info;
+
+typedef struct mp_ctx mp_ctx;
+
+/* Fill *cfg with defaults for an nx x ny x nz grid: h = 1/nz, periodic x/y,
+ * Neumann z, MIXED, rtol 1e-10, max_outer 100, V(2,2), 1 cycle per step,
+ * bottom 1e-10 / 400 iterations, demean 1, null stream, device 0. */
+void mp_config_default(mp_config *cfg, int nx, int ny, int nz);
+
+/* Create a context: validates cfg, selects the device, allocates the
+ * multigrid hierarchy (levels halve every axis while all extents stay even
+ * and >= 4 after halving; the coarsest grid must hold <= 4096 cells).
+ * Errors: MP_ERR_ARG (cfg), MP_ERR_DEVICE (no device), MP_ERR_NOMEM. */
+int mp_init(const mp_config *cfg, mp_ctx **out);
+
+/* Fill (Sec. 3.1) and face coefficients.
+ * geometry MP_PLANAR: beta0_1d has n1d == nz entries, one per z cell (direct
+ *   injection); dr and center are ignored (may be NULL).
+ * geometry MP_SPHERICAL: beta0_1d[j] is beta0 at radius (j + 1/2) dr about the
+ *   point center[3] (host array, physical units); each cell takes the linear
+ *   interpolation at the distance of its centre, holding the end values beyond
+ *   the table.
+ * rho: cell density (> 0).  cx, cy, cz: output face coefficients beta0/rho
+ * (harmonic mean, walls 0), FP64, face layouts above; any of them may be NULL.
+ * Rebuilds the coefficient hierarchy.  Errors: MP_ERR_ARG (sizes, dr, n1d),
+ * MP_ERR_NONFINITE (rho <= 0 or non-finite values). */
+int mp_map_base_state(mp_ctx *ctx, int geometry, const double *beta0_1d, int n1d, double dr, const double *center,
+                      const double *rho, double *cx, double *cy, double *cz);
+
+/* Use caller face coefficients (>= 0, finite; walls ignored) instead of the
+ * mapped ones; keeps any mapped beta0.  Rebuilds the coefficient hierarchy. */
+int mp_set_coefs(mp_ctx *ctx, const double *cx, const double *cy, const double *cz);
+
+/* MAC projection (Sec. 3.2 Steps 3/7, Appendix A).  In: ux, uy, uz (U before
+ * projection), S (cells), phi (initial guess when use_initial_guess != 0).
+ * Out: ux, uy, uz projected in place, phi (mean-zero), *info (may be NULL).
+ * Needs mp_map_base_state first (MP_ERR_STATE otherwise).  On
+ * MP_ERR_NOT_CONVERGED the outputs hold the last iterate and its projection. */
+int mp_mac_project(mp_ctx *ctx, double *ux, double *uy, double *uz, const double *S, double *phi,
+                   int use_initial_guess, mp_info *info);
+
+/* Solve M x = rhs (rhs mean removed when demean = 1); x mean-zero.  This is
+ * also the adjoint solve, M being symmetric. */
+int mp_solve(mp_ctx *ctx, const double *rhs, double *x, int use_initial_guess, mp_info *info);
+
+/* y = M x with the context's FP64 level-0 coefficients. */
+int mp_apply(mp_ctx *ctx, const double *x, double *y);
+
+/* Face-coefficient gradient of L = <w, phi>: g_f = (G lam)_f (G phi)_f, where
+ * lam = mp_solve(w) and phi = mp_solve(rhs); walls 0.  Face layouts above. */
+int mp_coef_grad(mp_ctx *ctx, const double *lam, const double *phi, double *gx, double *gy, double *gz);
+
+/* Release a context and its device memory; NULL is accepted. */
+int mp_free(mp_ctx *ctx);
+
+/* Text of the last failure on ctx (never NULL; "" if none). */
+const char *mp_last_error(const mp_ctx *ctx);
+
+/* Library version string. */
+const char *mp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPROJ_H */

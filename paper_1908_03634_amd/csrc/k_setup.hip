@@ -1,0 +1,451 @@
+// k_setup.hip -- gfx950 kernels for the base-state mapping, the face
+// coefficients, the MAC right-hand side, the velocity correction, the
+// coefficient gradient and the FP64 reductions.
+//
+// All of these are HBM-bound elementwise or 7-point passes: one thread per
+// cell, x fastest across the 64 lanes of a wavefront so every array access is
+// a contiguous 512-byte (FP64) row segment; neighbour reads hit L2.
+#include "mp_device.h"
+#include "mp_kernels.h"
+
+#include <math.h>
+
+namespace mp {
+
+int red_blocks(long long n)
+{
+    long long b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > kMaxRedBlocks) b = kMaxRedBlocks;
+    return (int)b;
+}
+
+static inline unsigned grid1(long long n)
+{
+    long long b = (n + kBlock - 1) / kBlock;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+// ---------------------------------------------------------------- reductions
+
+__global__ __launch_bounds__(1024) void k_final_sum(const double* __restrict__ part, int nb, double* out, double scale,
+                                                    double* rms_out, double count)
+{
+    __shared__ double sh[16];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) v += part[b];
+    double s = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        out[0] = scale * s;
+        if (rms_out) {
+            double r = sqrt(s / count);
+            rms_out[0] = r > 0.0 ? r : 1.0;
+            rms_out[1] = r > 0.0 ? 1.0 / r : 1.0;
+        }
+    }
+}
+
+void launch_final_sum(const double* partials, int nb, double* out, double scale, double* rms_out, double count,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(1024), 0, s, partials, nb, out, scale, rms_out, count);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum(const double* __restrict__ x, long long n, double* part)
+{
+    __shared__ double sh[kBlock / kWave];
+    double v = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        v += x[q];
+    double s = block_sum(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_sum(const double* x, long long n, double* partials, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum, dim3(nb), dim3(kBlock), 0, s, x, n, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sub_mean_sumsq(double* __restrict__ x, long long n,
+                                                           const double* __restrict__ mean, double* part)
+{
+    __shared__ double sh[kBlock / kWave];
+    const double m = mean[0];
+    double v = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        double a = x[q] - m;
+        x[q] = a;
+        v = fma(a, a, v);
+    }
+    double s = block_sum(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_sub_mean_sumsq(double* x, long long n, const double* mean, double* partials, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sub_mean_sumsq, dim3(nb), dim3(kBlock), 0, s, x, n, mean, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sub_mean(double* __restrict__ x, long long n,
+                                                     const double* __restrict__ mean)
+{
+    long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q < n) x[q] -= mean[0];
+}
+
+void launch_sub_mean(double* x, long long n, const double* mean, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sub_mean, dim3(grid1(n)), dim3(kBlock), 0, s, x, n, mean);
+}
+
+__global__ __launch_bounds__(kBlock) void k_neg_copy_sum(const double* __restrict__ rhs, double* __restrict__ b,
+                                                         long long n, double* part)
+{
+    __shared__ double sh[kBlock / kWave];
+    double v = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        double a = -rhs[q];
+        b[q] = a;
+        v += a;
+    }
+    double s = block_sum(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_neg_copy_sum(const double* rhs, double* b, long long n, double* partials, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_neg_copy_sum, dim3(nb), dim3(kBlock), 0, s, rhs, b, n, partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy(const double* __restrict__ src, double* __restrict__ dst, long long n)
+{
+    long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q < n) dst[q] = src[q];
+}
+
+void launch_copy(const double* src, double* dst, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy, dim3(grid1(n)), dim3(kBlock), 0, s, src, dst, n);
+}
+
+// ------------------------------------------------------------------- fill
+
+// Fill (Sec. 3.1): planar direct injection of the z table; spherical linear
+// interpolation in r on r_j = (j + 1/2) dr, end values held beyond the table.
+__global__ __launch_bounds__(kBlock) void k_fill(Dims d, double h, int geometry, const double* __restrict__ tab,
+                                                 int n1d, double dr, double cx0, double cy0, double cz0,
+                                                 const double* __restrict__ rho, double* __restrict__ beta0,
+                                                 double* __restrict__ ccell, double* part)
+{
+    __shared__ double sh[kBlock / kWave];
+    const long long n = d.n();
+    double bad = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        cell_ijk(d, q, i, j, k);
+        double b;
+        if (geometry == 0) {
+            b = tab[k];
+        } else {
+            const double x = (i + 0.5) * h - cx0, y = (j + 0.5) * h - cy0, z = (k + 0.5) * h - cz0;
+            const double r = sqrt(x * x + y * y + z * z);
+            const double t = r / dr - 0.5;
+            if (t <= 0.0) {
+                b = tab[0];
+            } else if (t >= (double)(n1d - 1)) {
+                b = tab[n1d - 1];
+            } else {
+                const int jj = (int)floor(t);
+                const double w = t - jj;
+                b = (1.0 - w) * tab[jj] + w * tab[jj + 1];
+            }
+        }
+        const double rq = rho[q];
+        const double c = b / rq;
+        beta0[q] = b;
+        ccell[q] = c;
+        if (!(rq > 0.0) || !isfinite(rq) || !isfinite(c) || !(b > 0.0)) bad += 1.0;
+    }
+    double s = block_sum(bad, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_fill(const Dims& d, double h, int geometry, const double* tab, int n1d, double dr, double cx0, double cy0,
+                 double cz0, const double* rho, double* beta0, double* ccell, double* partials, int nb,
+                 hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(kBlock), 0, s, d, h, geometry, tab, n1d, dr, cx0, cy0, cz0, rho, beta0,
+                       ccell, partials);
+}
+
+__device__ __forceinline__ double harmonic(double a, double b) { return 2.0 * a * b / (a + b); }
+
+// External face indices of the low faces of cell (i,j,k) and of the Neumann
+// high walls.
+struct ExtIdx {
+    long long xl, yl, zl;
+};
+
+__device__ __forceinline__ ExtIdx ext_low(const Dims& d, int i, int j, int k)
+{
+    const int bx = !d.px, by = !d.py;
+    ExtIdx e;
+    e.xl = ((long long)k * d.ny + j) * (d.nx + bx) + i;
+    e.yl = ((long long)k * (d.ny + by) + j) * d.nx + i;
+    e.zl = ((long long)k * d.ny + j) * d.nx + i;
+    return e;
+}
+
+__global__ __launch_bounds__(kBlock) void k_faces_from_cells(Dims d, const double* __restrict__ cc,
+                                                             double* __restrict__ c64x, double* __restrict__ c64y,
+                                                             double* __restrict__ c64z, float* __restrict__ c32x,
+                                                             float* __restrict__ c32y, float* __restrict__ c32z,
+                                                             double* __restrict__ ex, double* __restrict__ ey,
+                                                             double* __restrict__ ez)
+{
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= d.n()) return;
+    int i, j, k;
+    cell_ijk(d, q, i, j, k);
+    const Nbr b = neighbours(d, q, i, j, k);
+    const double c0 = cc[q];
+    const double fx = (i > 0 || d.px) ? harmonic(cc[b.xm], c0) : 0.0;
+    const double fy = (j > 0 || d.py) ? harmonic(cc[b.ym], c0) : 0.0;
+    const double fz = (k > 0 || d.pz) ? harmonic(cc[b.zm], c0) : 0.0;
+    c64x[q] = fx;
+    c64y[q] = fy;
+    c64z[q] = fz;
+    if (c32x) {
+        c32x[q] = (float)fx;
+        c32y[q] = (float)fy;
+        c32z[q] = (float)fz;
+    }
+    if (ex) {
+        const ExtIdx e = ext_low(d, i, j, k);
+        ex[e.xl] = fx;
+        ey[e.yl] = fy;
+        ez[e.zl] = fz;
+        if (!d.px && i == d.nx - 1) ex[e.xl + 1] = 0.0;
+        if (!d.py && j == d.ny - 1) ey[e.yl + d.nx] = 0.0;
+        if (!d.pz && k == d.nz - 1) ez[e.zl + (long long)d.nx * d.ny] = 0.0;
+    }
+}
+
+void launch_faces_from_cells(const Dims& d, const double* ccell, double* c64x, double* c64y, double* c64z,
+                             float* c32x, float* c32y, float* c32z, double* ex, double* ey, double* ez,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_faces_from_cells, dim3(grid1(d.n())), dim3(kBlock), 0, s, d, ccell, c64x, c64y, c64z, c32x,
+                       c32y, c32z, ex, ey, ez);
+}
+
+__global__ __launch_bounds__(kBlock) void k_import_faces(Dims d, const double* __restrict__ ex,
+                                                         const double* __restrict__ ey, const double* __restrict__ ez,
+                                                         double* __restrict__ c64x, double* __restrict__ c64y,
+                                                         double* __restrict__ c64z, float* __restrict__ c32x,
+                                                         float* __restrict__ c32y, float* __restrict__ c32z,
+                                                         double* part)
+{
+    __shared__ double sh[kBlock / kWave];
+    const long long n = d.n();
+    double bad = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        cell_ijk(d, q, i, j, k);
+        const ExtIdx e = ext_low(d, i, j, k);
+        const double fx = (i > 0 || d.px) ? ex[e.xl] : 0.0;
+        const double fy = (j > 0 || d.py) ? ey[e.yl] : 0.0;
+        const double fz = (k > 0 || d.pz) ? ez[e.zl] : 0.0;
+        if (!(fx >= 0.0) || !(fy >= 0.0) || !(fz >= 0.0) || !isfinite(fx) || !isfinite(fy) || !isfinite(fz))
+            bad += 1.0;
+        c64x[q] = fx;
+        c64y[q] = fy;
+        c64z[q] = fz;
+        if (c32x) {
+            c32x[q] = (float)fx;
+            c32y[q] = (float)fy;
+            c32z[q] = (float)fz;
+        }
+    }
+    double s = block_sum(bad, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_import_faces(const Dims& d, const double* ex, const double* ey, const double* ez, double* c64x,
+                         double* c64y, double* c64z, float* c32x, float* c32y, float* c32z, double* partials, int nb,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_import_faces, dim3(nb), dim3(kBlock), 0, s, d, ex, ey, ez, c64x, c64y, c64z, c32x, c32y,
+                       c32z, partials);
+}
+
+// Coarse low face of coarse cell (I,J,K) = mean of the 4 fine low faces of the
+// fine cells that touch it.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kBlock) void k_coef_restrict(Dims f, const Tin* __restrict__ fx,
+                                                          const Tin* __restrict__ fy, const Tin* __restrict__ fz,
+                                                          Tout* __restrict__ cx, Tout* __restrict__ cy,
+                                                          Tout* __restrict__ cz)
+{
+    const int nxc = f.nx / 2, nyc = f.ny / 2, nzc = f.nz / 2;
+    const long long nc = (long long)nxc * nyc * nzc;
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= nc) return;
+    const long long t = q / nxc;
+    const int I = (int)(q - t * nxc), K = (int)(t / nyc), J = (int)(t - (long long)K * nyc);
+    const long long sy = f.nx, sz = (long long)f.nx * f.ny;
+    const long long base = (long long)(2 * K) * sz + (long long)(2 * J) * sy + 2 * I;
+    const double ax = (double)fx[base] + (double)fx[base + sy] + (double)fx[base + sz] + (double)fx[base + sy + sz];
+    const double ay = (double)fy[base] + (double)fy[base + 1] + (double)fy[base + sz] + (double)fy[base + 1 + sz];
+    const double az = (double)fz[base] + (double)fz[base + 1] + (double)fz[base + sy] + (double)fz[base + 1 + sy];
+    cx[q] = (Tout)(0.25 * ax);
+    cy[q] = (Tout)(0.25 * ay);
+    cz[q] = (Tout)(0.25 * az);
+}
+
+template <typename Tin, typename Tout>
+void launch_coef_restrict(const Dims& fine, const Tin* fx, const Tin* fy, const Tin* fz, Tout* cx, Tout* cy,
+                          Tout* cz, hipStream_t s)
+{
+    const long long nc = (long long)(fine.nx / 2) * (fine.ny / 2) * (fine.nz / 2);
+    hipLaunchKernelGGL((k_coef_restrict<Tin, Tout>), dim3(grid1(nc)), dim3(kBlock), 0, s, fine, fx, fy, fz, cx, cy,
+                       cz);
+}
+
+template void launch_coef_restrict<double, double>(const Dims&, const double*, const double*, const double*, double*,
+                                                   double*, double*, hipStream_t);
+template void launch_coef_restrict<double, float>(const Dims&, const double*, const double*, const double*, float*,
+                                                  float*, float*, hipStream_t);
+template void launch_coef_restrict<float, float>(const Dims&, const float*, const float*, const float*, float*,
+                                                 float*, float*, hipStream_t);
+
+// ---------------------------------------------------------------- projection
+
+// beta0 on a face: arithmetic mean of the two cells.
+// b = beta0 S - D(beta0 U): minus the MAC right-hand side of Sec. 3.2 Steps 3/7.
+__global__ __launch_bounds__(kBlock) void k_mac_rhs(Dims d, double inv_h, const double* __restrict__ beta0,
+                                                    const double* __restrict__ ux, const double* __restrict__ uy,
+                                                    const double* __restrict__ uz, const double* __restrict__ S,
+                                                    double* __restrict__ b, double* part,
+                                                    const double* __restrict__ shift)
+{
+    // shift == nullptr: write b, partials = sum b.
+    // shift != nullptr: no write, partials = sum (b - shift[0])^2.
+    const double sh0 = shift ? shift[0] : 0.0;
+    __shared__ double sh[kBlock / kWave];
+    const long long n = d.n();
+    double acc = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
+         q += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        cell_ijk(d, q, i, j, k);
+        const Nbr nb = neighbours(d, q, i, j, k);
+        const ExtIdx e = ext_low(d, i, j, k);
+        const double b0 = beta0[q];
+        // low faces
+        const double fxl = (i > 0 || d.px) ? 0.5 * (beta0[nb.xm] + b0) * ux[e.xl] : 0.0;
+        const double fyl = (j > 0 || d.py) ? 0.5 * (beta0[nb.ym] + b0) * uy[e.yl] : 0.0;
+        const double fzl = (k > 0 || d.pz) ? 0.5 * (beta0[nb.zm] + b0) * uz[e.zl] : 0.0;
+        // high faces
+        double fxh = 0.0, fyh = 0.0, fzh = 0.0;
+        if (i < d.nx - 1) fxh = 0.5 * (b0 + beta0[nb.xp]) * ux[e.xl + 1];
+        else if (d.px) fxh = 0.5 * (b0 + beta0[nb.xp]) * ux[e.xl - (d.nx - 1)];
+        if (j < d.ny - 1) fyh = 0.5 * (b0 + beta0[nb.yp]) * uy[e.yl + d.nx];
+        else if (d.py) fyh = 0.5 * (b0 + beta0[nb.yp]) * uy[e.yl - (long long)(d.ny - 1) * d.nx];
+        if (k < d.nz - 1) fzh = 0.5 * (b0 + beta0[nb.zp]) * uz[e.zl + (long long)d.nx * d.ny];
+        else if (d.pz) fzh = 0.5 * (b0 + beta0[nb.zp]) * uz[e.zl - (long long)(d.nz - 1) * d.nx * d.ny];
+        const double div = ((fxh - fxl) + (fyh - fyl) + (fzh - fzl)) * inv_h;
+        const double v = b0 * S[q] - div;
+        if (shift) {
+            const double e2 = v - sh0;
+            acc = fma(e2, e2, acc);
+        } else {
+            b[q] = v;
+            acc += v;
+        }
+    }
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_mac_rhs(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
+                    const double* uz, const double* S, double* b, double* partials, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mac_rhs, dim3(nb), dim3(kBlock), 0, s, d, inv_h, beta0, ux, uy, uz, S, b, partials,
+                       (const double*)nullptr);
+}
+
+void launch_rhs_defect(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
+                       const double* uz, const double* S, const double* shift, double* partials, int nb,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mac_rhs, dim3(nb), dim3(kBlock), 0, s, d, inv_h, beta0, ux, uy, uz, S, (double*)nullptr,
+                       partials, shift);
+}
+
+// Velocity correction of one face: U - (c / beta0_f) (phi_R - phi_L) / h.
+__device__ __forceinline__ double corrected(double u, double c, double bl, double br, double pl, double pr,
+                                            double inv_h)
+{
+    return u - c / (0.5 * (bl + br)) * ((pr - pl) * inv_h);
+}
+
+// Each thread owns the low faces of its cell: it alone reads and writes them,
+// so the update is race-free in place.  Neumann walls are left unchanged.
+__global__ __launch_bounds__(kBlock) void k_vel_correct(Dims d, double inv_h, const double* __restrict__ c64x,
+                                                        const double* __restrict__ c64y,
+                                                        const double* __restrict__ c64z,
+                                                        const double* __restrict__ beta0,
+                                                        const double* __restrict__ phi, double* __restrict__ ux,
+                                                        double* __restrict__ uy, double* __restrict__ uz)
+{
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= d.n()) return;
+    int i, j, k;
+    cell_ijk(d, q, i, j, k);
+    const Nbr nb = neighbours(d, q, i, j, k);
+    const ExtIdx e = ext_low(d, i, j, k);
+    const double b0 = beta0[q], p0 = phi[q];
+    if (i > 0 || d.px) ux[e.xl] = corrected(ux[e.xl], c64x[q], beta0[nb.xm], b0, phi[nb.xm], p0, inv_h);
+    if (j > 0 || d.py) uy[e.yl] = corrected(uy[e.yl], c64y[q], beta0[nb.ym], b0, phi[nb.ym], p0, inv_h);
+    if (k > 0 || d.pz) uz[e.zl] = corrected(uz[e.zl], c64z[q], beta0[nb.zm], b0, phi[nb.zm], p0, inv_h);
+}
+
+void launch_vel_correct(const Dims& d, double inv_h, const double* c64x, const double* c64y, const double* c64z,
+                        const double* beta0, const double* phi, double* ux, double* uy, double* uz, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vel_correct, dim3(grid1(d.n())), dim3(kBlock), 0, s, d, inv_h, c64x, c64y, c64z, beta0,
+                       phi, ux, uy, uz);
+}
+
+// Coefficient gradient on the low faces of each cell; Neumann high walls 0.
+__global__ __launch_bounds__(kBlock) void k_coef_grad(Dims d, double inv_h2, const double* __restrict__ lam,
+                                                      const double* __restrict__ phi, double* __restrict__ gx,
+                                                      double* __restrict__ gy, double* __restrict__ gz)
+{
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q >= d.n()) return;
+    int i, j, k;
+    cell_ijk(d, q, i, j, k);
+    const Nbr nb = neighbours(d, q, i, j, k);
+    const ExtIdx e = ext_low(d, i, j, k);
+    const double l0 = lam[q], p0 = phi[q];
+    gx[e.xl] = (i > 0 || d.px) ? (l0 - lam[nb.xm]) * (p0 - phi[nb.xm]) * inv_h2 : 0.0;
+    gy[e.yl] = (j > 0 || d.py) ? (l0 - lam[nb.ym]) * (p0 - phi[nb.ym]) * inv_h2 : 0.0;
+    gz[e.zl] = (k > 0 || d.pz) ? (l0 - lam[nb.zm]) * (p0 - phi[nb.zm]) * inv_h2 : 0.0;
+    if (!d.px && i == d.nx - 1) gx[e.xl + 1] = 0.0;
+    if (!d.py && j == d.ny - 1) gy[e.yl + d.nx] = 0.0;
+    if (!d.pz && k == d.nz - 1) gz[e.zl + (long long)d.nx * d.ny] = 0.0;
+}
+
+void launch_coef_grad(const Dims& d, double inv_h2, const double* lam, const double* phi, double* gx, double* gy,
+                      double* gz, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_coef_grad, dim3(grid1(d.n())), dim3(kBlock), 0, s, d, inv_h2, lam, phi, gx, gy, gz);
+}
+
+}  // namespace mp

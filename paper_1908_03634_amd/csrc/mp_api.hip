@@ -1,0 +1,639 @@
+// mp_api.hip -- host driver and C ABI of libmproj (declared in include/mproj.h).
+//
+// Owns the multigrid hierarchy and workspace of one context, runs the V-cycle,
+// the FP64 iterative refinement around FP32 V-cycles, and the projection
+// phases (right-hand side, solve, velocity correction) as kernel sequences on
+// the caller's stream.  The only device->host transfers are small scalar
+// read-backs (norms, counts) into pinned memory.
+#include "../../include/mproj.h"
+#include "mp_device.h"
+#include "mp_kernels.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+namespace {
+
+using mp::Dims;
+
+constexpr int kMaxBottomCells = 16384;
+constexpr int kScal = 64;  // device scalar slots
+// scalar slots
+enum { S_MEAN = 0, S_NB2 = 1, S_RR = 2, S_DEF = 3, S_BAD = 4, S_GAUGE = 5, S_ZERO = 6, S_PAIR0 = 8 };
+
+struct Level {
+    Dims d;
+    double h;
+    void* x = nullptr;  // iterate (T)
+    void* b = nullptr;  // right-hand side (T)
+    void* cx = nullptr;
+    void* cy = nullptr;
+    void* cz = nullptr;
+    bool own_x = false, own_b = false, own_c = false;
+};
+
+}  // namespace
+
+struct mp_ctx {
+    mp_config cfg;
+    Dims d0;
+    long long n0 = 0;
+    hipStream_t stream = nullptr;
+    std::vector<Level> lv;
+    double *c64x = nullptr, *c64y = nullptr, *c64z = nullptr;
+    double *beta0 = nullptr, *ccell = nullptr, *b64 = nullptr;
+    double *partials = nullptr, *dscal = nullptr, *bottom_work = nullptr;
+    double* hscal = nullptr;  // pinned host
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> kev;
+    int kev_used = 0;
+    bool have_coefs = false, have_base = false;
+    std::string err;
+};
+
+namespace {
+
+int fail(mp_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(mp_ctx* c, int code, const char* fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                                            \
+    do {                                                                                                             \
+        hipError_t e_ = (call);                                                                                      \
+        if (e_ != hipSuccess) return fail((ctx), MP_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+bool log_on() { return getenv("MP_LOG") && getenv("MP_LOG")[0] == '1'; }
+
+template <typename T>
+T* dalloc(long long n, hipError_t& e)
+{
+    void* p = nullptr;
+    e = hipMalloc(&p, (size_t)(n > 0 ? n : 1) * sizeof(T));
+    return (T*)p;
+}
+
+int check_config(const mp_config* c, mp_ctx* ctx)
+{
+    if (!c) return fail(ctx, MP_ERR_ARG, "config is NULL");
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(ctx, MP_ERR_ARG, "grid extents must be >= 1");
+    if ((long long)c->nx * c->ny * c->nz > (1LL << 34)) return fail(ctx, MP_ERR_ARG, "grid too large");
+    if (!(c->h > 0.0) || !isfinite(c->h)) return fail(ctx, MP_ERR_ARG, "h must be positive");
+    for (int a = 0; a < 3; a++)
+        if (c->bc[a] != MP_BC_PERIODIC && c->bc[a] != MP_BC_NEUMANN) return fail(ctx, MP_ERR_ARG, "bad bc[%d]", a);
+    if (c->precision != MP_FP64 && c->precision != MP_MIXED) return fail(ctx, MP_ERR_ARG, "bad precision");
+    if (!(c->rtol > 0.0) || c->rtol >= 1.0) return fail(ctx, MP_ERR_ARG, "rtol must be in (0, 1)");
+    if (c->max_outer < 0 || c->max_outer > 10000) return fail(ctx, MP_ERR_ARG, "bad max_outer");
+    if (c->nu1 < 0 || c->nu2 < 0 || c->nu1 + c->nu2 < 1 || c->nu1 > 16 || c->nu2 > 16)
+        return fail(ctx, MP_ERR_ARG, "nu1/nu2 out of range");
+    if (c->cycles_per_outer < 1 || c->cycles_per_outer > 16) return fail(ctx, MP_ERR_ARG, "bad cycles_per_outer");
+    if (!(c->bottom_rtol > 0.0) || c->bottom_max_iter < 1) return fail(ctx, MP_ERR_ARG, "bad bottom settings");
+    if (c->demean != 0 && c->demean != 1) return fail(ctx, MP_ERR_ARG, "demean must be 0 or 1");
+    return MP_OK;
+}
+
+void free_all(mp_ctx* c)
+{
+    for (auto& L : c->lv) {
+        if (L.own_x) (void)hipFree(L.x);
+        if (L.own_b) (void)hipFree(L.b);
+        if (L.own_c) {
+            (void)hipFree(L.cx);
+            (void)hipFree(L.cy);
+            (void)hipFree(L.cz);
+        }
+    }
+    c->lv.clear();
+    double* bufs[] = {c->c64x, c->c64y, c->c64z, c->beta0, c->ccell, c->b64, c->partials, c->dscal, c->bottom_work};
+    for (double* p : bufs)
+        if (p) (void)hipFree(p);
+    if (c->hscal) (void)hipHostFree(c->hscal);
+    for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : c->kev) (void)hipEventDestroy(e);
+    c->kev.clear();
+}
+
+bool mixed(const mp_ctx* c) { return c->cfg.precision == MP_MIXED; }
+
+int sync_read(mp_ctx* c, int first, int count)
+{
+    HIPCHK(c, hipMemcpyAsync(c->hscal + first, c->dscal + first, sizeof(double) * count, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    return MP_OK;
+}
+
+int nblk(const mp_ctx* c) { return mp::red_blocks(c->n0); }
+
+// Coefficients of levels 1.. from level 0.
+void build_pyramid(mp_ctx* c)
+{
+    for (size_t l = 1; l < c->lv.size(); l++) {
+        Level& F = c->lv[l - 1];
+        Level& C = c->lv[l];
+        if (mixed(c)) {
+            if (l == 1)
+                mp::launch_coef_restrict<double, float>(F.d, c->c64x, c->c64y, c->c64z, (float*)C.cx, (float*)C.cy,
+                                                        (float*)C.cz, c->stream);
+            else
+                mp::launch_coef_restrict<float, float>(F.d, (float*)F.cx, (float*)F.cy, (float*)F.cz, (float*)C.cx,
+                                                       (float*)C.cy, (float*)C.cz, c->stream);
+        } else {
+            mp::launch_coef_restrict<double, double>(F.d, (double*)F.cx, (double*)F.cy, (double*)F.cz,
+                                                     (double*)C.cx, (double*)C.cy, (double*)C.cz, c->stream);
+        }
+    }
+}
+
+void timed_begin(mp_ctx* c, bool on)
+{
+    if (on && c->kev_used + 1 < (int)c->kev.size()) (void)hipEventRecord(c->kev[c->kev_used], c->stream);
+}
+
+void timed_end(mp_ctx* c, bool on)
+{
+    if (on && c->kev_used + 1 < (int)c->kev.size()) {
+        (void)hipEventRecord(c->kev[c->kev_used + 1], c->stream);
+        c->kev_used += 2;
+    }
+}
+
+template <typename T>
+void smooth(mp_ctx* c, int l, bool zero_init)
+{
+    Level& L = c->lv[l];
+    const T h2 = (T)(L.h * L.h);
+    const bool tm = c->cfg.kernel_timing && l == 0;
+    for (int colour = 0; colour < 2; colour++) {
+        timed_begin(c, tm);
+        mp::launch_rbgs<T>(L.d, (T*)L.x, (const T*)L.b, (const T*)L.cx, (const T*)L.cy, (const T*)L.cz, h2, colour,
+                           (zero_init && colour == 0) ? 1 : 0, c->stream);
+        timed_end(c, tm);
+    }
+}
+
+template <typename T>
+void vcycle(mp_ctx* c, int l, bool zero_init)
+{
+    Level& L = c->lv[l];
+    const int nlev = (int)c->lv.size();
+    if (l == nlev - 1) {
+        mp::launch_bottom<T>(L.d, (const T*)L.b, (T*)L.x, (const T*)L.cx, (const T*)L.cy, (const T*)L.cz, L.h * L.h,
+                             c->cfg.bottom_rtol, c->cfg.bottom_max_iter, c->bottom_work, c->stream);
+        return;
+    }
+    if (zero_init && c->cfg.nu1 == 0) (void)hipMemsetAsync(L.x, 0, sizeof(T) * L.d.n(), c->stream);
+    for (int s = 0; s < c->cfg.nu1; s++) smooth<T>(c, l, zero_init && s == 0);
+    Level& C = c->lv[l + 1];
+    mp::launch_resid_restrict<T>(L.d, (const T*)L.x, (const T*)L.b, (const T*)L.cx, (const T*)L.cy, (const T*)L.cz,
+                                 (T)(1.0 / (L.h * L.h)), (T*)C.b, c->stream);
+    vcycle<T>(c, l + 1, true);
+    mp::launch_prolong<T>(L.d, (T*)L.x, (const T*)C.x, c->stream);
+    for (int s = 0; s < c->cfg.nu2; s++) smooth<T>(c, l, false);
+}
+
+// Solve A phi = b64 (b64 mean-zero, ||b64||^2 = nb2 in hscal[S_NB2]).
+int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
+{
+    const long long n = c->n0;
+    const int nb = nblk(c);
+    const double nb2 = c->hscal[S_NB2];
+    const double inv_h2 = 1.0 / (c->cfg.h * c->cfg.h);
+    if (info) info->levels = (int)c->lv.size();
+    if (!isfinite(nb2)) return fail(c, MP_ERR_NONFINITE, "right-hand side is not finite");
+    if (nb2 == 0.0) {
+        HIPCHK(c, hipMemsetAsync(phi, 0, sizeof(double) * n, c->stream));
+        if (info) info->rel_resid = 0.0;
+        return MP_OK;
+    }
+    if (!use_guess) HIPCHK(c, hipMemsetAsync(phi, 0, sizeof(double) * n, c->stream));
+    const bool mx = mixed(c);
+    if (!mx) c->lv[0].x = phi;
+    int status = MP_ERR_NOT_CONVERGED;
+    double rel = 1.0;
+    double hist[64];
+    int vc = 0, it = 0;
+    for (it = 0;; it++) {
+        const int p = it & 1;
+        double* sp = c->dscal + S_PAIR0 + 2 * p;
+        double* sq = c->dscal + S_PAIR0 + 2 * (1 - p);
+        mp::launch_resid64(c->d0, phi, c->b64, c->c64x, c->c64y, c->c64z, inv_h2, mx ? (float*)c->lv[0].b : nullptr,
+                           sp + 1, c->partials, nb, c->stream);
+        mp::launch_final_sum(c->partials, nb, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
+        int st = sync_read(c, S_RR, 1);
+        if (st) return st;
+        rel = sqrt(c->hscal[S_RR] / nb2);
+        if (it < 64) {
+            hist[it] = rel;
+            if (info) info->resid_hist[it] = rel;
+        }
+        if (log_on()) fprintf(stderr, "[mproj] step %d rel_resid %.3e\n", it, rel);
+        if (!isfinite(rel)) {
+            status = MP_ERR_NONFINITE;
+            fail(c, status, "residual became non-finite at step %d", it);
+            break;
+        }
+        if (rel <= c->cfg.rtol) {
+            status = MP_OK;
+            break;
+        }
+        if (it >= c->cfg.max_outer) {
+            fail(c, MP_ERR_NOT_CONVERGED, "not converged after %d steps (rel. residual %.3e)", it, rel);
+            break;
+        }
+        if (it >= 6 && it < 64 && rel > 0.9 * hist[it - 6]) {
+            if (info) info->flags |= 1;
+            fail(c, MP_ERR_NOT_CONVERGED, "stagnated at step %d (rel. residual %.3e)", it, rel);
+            break;
+        }
+        if (mx) {
+            for (int k = 0; k < c->cfg.cycles_per_outer; k++) {
+                vcycle<float>(c, 0, k == 0);
+                vc++;
+            }
+            mp::launch_ir_update(n, phi, (const float*)c->lv[0].x, sp, c->stream);
+        } else {
+            vcycle<double>(c, 0, it == 0 && !use_guess);
+            vc++;
+        }
+    }
+    // gauge: mean(phi) = 0
+    mp::launch_sum(phi, n, c->partials, nb, c->stream);
+    mp::launch_final_sum(c->partials, nb, c->dscal + S_GAUGE, 1.0 / (double)n, nullptr, 0.0, c->stream);
+    mp::launch_sub_mean(phi, n, c->dscal + S_GAUGE, c->stream);
+    if (info) {
+        info->outer_iters = it;
+        info->vcycles = vc;
+        info->rel_resid = rel;
+    }
+    return status;
+}
+
+void finish_timing(mp_ctx* c, mp_info* info)
+{
+    if (!info) return;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) info->ms_rhs = ms;
+    if (hipEventElapsedTime(&ms, c->ev[1], c->ev[2]) == hipSuccess) info->ms_solve = ms;
+    if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) info->ms_correct = ms;
+    if (c->cfg.kernel_timing) {
+        double tot = 0.0;
+        int cnt = 0;
+        for (int q = 0; q + 1 < c->kev_used; q += 2) {
+            if (hipEventElapsedTime(&ms, c->kev[q], c->kev[q + 1]) == hipSuccess) {
+                tot += ms;
+                cnt++;
+            }
+        }
+        info->smooth_ms_total = tot;
+        info->smooth_launches = cnt;
+    }
+}
+
+void reset_info(mp_info* info)
+{
+    if (info) memset(info, 0, sizeof(*info));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mp_version(void) { return "mproj 0.1 (gfx950)"; }
+
+void mp_config_default(mp_config* cfg, int nx, int ny, int nz)
+{
+    if (!cfg) return;
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->nx = nx;
+    cfg->ny = ny;
+    cfg->nz = nz;
+    cfg->h = nz > 0 ? 1.0 / nz : 1.0;
+    cfg->bc[0] = MP_BC_PERIODIC;
+    cfg->bc[1] = MP_BC_PERIODIC;
+    cfg->bc[2] = MP_BC_NEUMANN;
+    cfg->precision = MP_MIXED;
+    cfg->rtol = 1e-10;
+    cfg->max_outer = 100;
+    cfg->nu1 = 2;
+    cfg->nu2 = 2;
+    cfg->cycles_per_outer = 1;
+    cfg->bottom_rtol = 1e-10;
+    cfg->bottom_max_iter = 400;
+    cfg->demean = 1;
+    cfg->kernel_timing = 0;
+    cfg->stream = nullptr;
+    cfg->device = 0;
+}
+
+int mp_init(const mp_config* cfg, mp_ctx** out)
+{
+    if (!out) return MP_ERR_ARG;
+    *out = nullptr;
+    mp_ctx tmp;
+    int st = check_config(cfg, &tmp);
+    if (st) return st;
+    // bottom size check (host only)
+    {
+        int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
+        while (nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0 && nx >= 8 && ny >= 8 && nz >= 8) {
+            nx /= 2;
+            ny /= 2;
+            nz /= 2;
+        }
+        if ((long long)nx * ny * nz > kMaxBottomCells) return MP_ERR_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return MP_ERR_DEVICE;
+    if (cfg->device < 0 || cfg->device >= ndev) return MP_ERR_ARG;
+    if (hipSetDevice(cfg->device) != hipSuccess) return MP_ERR_DEVICE;
+
+    mp_ctx* c = new mp_ctx();
+    c->cfg = *cfg;
+    c->stream = (hipStream_t)cfg->stream;
+    c->d0 = Dims{cfg->nx, cfg->ny, cfg->nz, cfg->bc[0] == MP_BC_PERIODIC, cfg->bc[1] == MP_BC_PERIODIC,
+                 cfg->bc[2] == MP_BC_PERIODIC};
+    c->n0 = c->d0.n();
+    const bool mx = mixed(c);
+    const size_t tsz = mx ? sizeof(float) : sizeof(double);
+    hipError_t e = hipSuccess;
+    auto ok = [&](void* p) { return p != nullptr && e == hipSuccess; };
+    bool good = true;
+    c->c64x = dalloc<double>(c->n0, e), good &= ok(c->c64x);
+    c->c64y = dalloc<double>(c->n0, e), good &= ok(c->c64y);
+    c->c64z = dalloc<double>(c->n0, e), good &= ok(c->c64z);
+    c->beta0 = dalloc<double>(c->n0, e), good &= ok(c->beta0);
+    c->ccell = dalloc<double>(c->n0, e), good &= ok(c->ccell);
+    c->b64 = dalloc<double>(c->n0, e), good &= ok(c->b64);
+    c->partials = dalloc<double>(4 * mp::kMaxRedBlocks, e), good &= ok(c->partials);
+    c->dscal = dalloc<double>(kScal, e), good &= ok(c->dscal);
+    // levels
+    Dims d = c->d0;
+    double h = cfg->h;
+    for (int l = 0;; l++) {
+        Level L;
+        L.d = d;
+        L.h = h;
+        if (mx || l > 0) {
+            void* p = nullptr;
+            e = hipMalloc(&p, tsz * d.n());
+            good &= e == hipSuccess;
+            L.x = p;
+            L.own_x = true;
+            p = nullptr;
+            e = hipMalloc(&p, tsz * d.n());
+            good &= e == hipSuccess;
+            L.b = p;
+            L.own_b = true;
+        } else {
+            L.b = c->b64;
+        }
+        if (mx || l > 0) {
+            void* p[3] = {nullptr, nullptr, nullptr};
+            for (int a = 0; a < 3; a++) {
+                e = hipMalloc(&p[a], tsz * d.n());
+                good &= e == hipSuccess;
+            }
+            L.cx = p[0];
+            L.cy = p[1];
+            L.cz = p[2];
+            L.own_c = true;
+        } else {
+            L.cx = c->c64x;
+            L.cy = c->c64y;
+            L.cz = c->c64z;
+        }
+        c->lv.push_back(L);
+        if (!(d.nx % 2 == 0 && d.ny % 2 == 0 && d.nz % 2 == 0 && d.nx >= 8 && d.ny >= 8 && d.nz >= 8)) break;
+        d = Dims{d.nx / 2, d.ny / 2, d.nz / 2, d.px, d.py, d.pz};
+        h *= 2.0;
+    }
+    c->bottom_work = dalloc<double>(7 * c->lv.back().d.n(), e), good &= ok(c->bottom_work);
+    if (good && hipHostMalloc((void**)&c->hscal, sizeof(double) * kScal, hipHostMallocDefault) != hipSuccess)
+        good = false;
+    for (auto& ev : c->ev)
+        if (good && hipEventCreate(&ev) != hipSuccess) good = false;
+    if (good && cfg->kernel_timing) {
+        c->kev.resize(2048);
+        for (auto& ev : c->kev)
+            if (good && hipEventCreate(&ev) != hipSuccess) good = false;
+    }
+    if (!good) {
+        free_all(c);
+        delete c;
+        (void)hipGetLastError();
+        return MP_ERR_NOMEM;
+    }
+    if (hipMemsetAsync(c->dscal, 0, sizeof(double) * kScal, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return MP_ERR_DEVICE;
+    }
+    if (log_on())
+        fprintf(stderr, "[mproj] init %dx%dx%d levels=%zu precision=%s\n", cfg->nx, cfg->ny, cfg->nz, c->lv.size(),
+                mx ? "mixed" : "fp64");
+    *out = c;
+    return MP_OK;
+}
+
+int mp_free(mp_ctx* c)
+{
+    if (!c) return MP_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    free_all(c);
+    delete c;
+    return MP_OK;
+}
+
+const char* mp_last_error(const mp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int mp_map_base_state(mp_ctx* c, int geometry, const double* beta0_1d, int n1d, double dr, const double* center,
+                      const double* rho, double* cx, double* cy, double* cz)
+{
+    if (!c) return MP_ERR_ARG;
+    if (geometry != MP_PLANAR && geometry != MP_SPHERICAL) return fail(c, MP_ERR_ARG, "bad geometry");
+    if (!beta0_1d || !rho) return fail(c, MP_ERR_ARG, "beta0_1d and rho are required");
+    if ((cx == nullptr) != (cy == nullptr) || (cx == nullptr) != (cz == nullptr))
+        return fail(c, MP_ERR_ARG, "cx, cy, cz must be all given or all NULL");
+    double c0 = 0, c1 = 0, c2 = 0;
+    if (geometry == MP_PLANAR) {
+        if (n1d != c->cfg.nz) return fail(c, MP_ERR_ARG, "planar table needs n1d == nz (%d != %d)", n1d, c->cfg.nz);
+    } else {
+        if (n1d < 2) return fail(c, MP_ERR_ARG, "spherical table needs n1d >= 2");
+        if (!(dr > 0.0) || !isfinite(dr)) return fail(c, MP_ERR_ARG, "dr must be positive");
+        if (!center) return fail(c, MP_ERR_ARG, "center is required for spherical geometry");
+        c0 = center[0];
+        c1 = center[1];
+        c2 = center[2];
+        if (!isfinite(c0) || !isfinite(c1) || !isfinite(c2)) return fail(c, MP_ERR_ARG, "center must be finite");
+    }
+    (void)hipSetDevice(c->cfg.device);
+    const int nb = nblk(c);
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    mp::launch_fill(c->d0, c->cfg.h, geometry, beta0_1d, n1d, dr, c0, c1, c2, rho, c->beta0, c->ccell, c->partials,
+                    nb, c->stream);
+    mp::launch_final_sum(c->partials, nb, c->dscal + S_BAD, 1.0, nullptr, 0.0, c->stream);
+    Level& L0 = c->lv[0];
+    const bool mx = mixed(c);
+    mp::launch_faces_from_cells(c->d0, c->ccell, c->c64x, c->c64y, c->c64z, mx ? (float*)L0.cx : nullptr,
+                                mx ? (float*)L0.cy : nullptr, mx ? (float*)L0.cz : nullptr, cx, cy, cz, c->stream);
+    build_pyramid(c);
+    int st = sync_read(c, S_BAD, 1);
+    if (st) return st;
+    if (c->hscal[S_BAD] != 0.0) {
+        c->have_base = c->have_coefs = false;
+        return fail(c, MP_ERR_NONFINITE, "%.0f cells with rho <= 0, beta0 <= 0 or non-finite values",
+                    c->hscal[S_BAD]);
+    }
+    c->have_base = c->have_coefs = true;
+    return MP_OK;
+}
+
+int mp_set_coefs(mp_ctx* c, const double* cx, const double* cy, const double* cz)
+{
+    if (!c) return MP_ERR_ARG;
+    if (!cx || !cy || !cz) return fail(c, MP_ERR_ARG, "cx, cy, cz are required");
+    (void)hipSetDevice(c->cfg.device);
+    const int nb = nblk(c);
+    Level& L0 = c->lv[0];
+    const bool mx = mixed(c);
+    mp::launch_import_faces(c->d0, cx, cy, cz, c->c64x, c->c64y, c->c64z, mx ? (float*)L0.cx : nullptr,
+                            mx ? (float*)L0.cy : nullptr, mx ? (float*)L0.cz : nullptr, c->partials, nb, c->stream);
+    mp::launch_final_sum(c->partials, nb, c->dscal + S_BAD, 1.0, nullptr, 0.0, c->stream);
+    build_pyramid(c);
+    int st = sync_read(c, S_BAD, 1);
+    if (st) return st;
+    if (c->hscal[S_BAD] != 0.0) {
+        c->have_coefs = false;
+        return fail(c, MP_ERR_NONFINITE, "%.0f negative or non-finite face coefficients", c->hscal[S_BAD]);
+    }
+    c->have_coefs = true;
+    return MP_OK;
+}
+
+// Prepare b64 from its raw form already in b64 (sum in partials): mean -> S_MEAN,
+// remove it (demean) and ||b||^2 -> S_NB2, rms -> first scale pair.
+static int finish_rhs(mp_ctx* c, int nb)
+{
+    const long long n = c->n0;
+    mp::launch_final_sum(c->partials, nb, c->dscal + S_MEAN, 1.0 / (double)n, nullptr, 0.0, c->stream);
+    mp::launch_sub_mean_sumsq(c->b64, n, c->dscal + S_MEAN, c->partials, nb, c->stream);
+    mp::launch_final_sum(c->partials, nb, c->dscal + S_NB2, 1.0, c->dscal + S_PAIR0, (double)n, c->stream);
+    int st = sync_read(c, S_MEAN, 2);
+    if (st) return st;
+    if (!isfinite(c->hscal[S_MEAN]) || !isfinite(c->hscal[S_NB2]))
+        return fail(c, MP_ERR_NONFINITE, "non-finite right-hand side");
+    if (!c->cfg.demean) {
+        const double m = c->hscal[S_MEAN], nb2 = c->hscal[S_NB2];
+        if (fabs(m) * sqrt((double)n) > 1e-12 * sqrt(nb2 + (double)n * m * m))
+            return fail(c, MP_ERR_SINGULAR_RHS, "right-hand side has mean %.3e (demean is off)", m);
+    }
+    return MP_OK;
+}
+
+int mp_mac_project(mp_ctx* c, double* ux, double* uy, double* uz, const double* S, double* phi,
+                   int use_initial_guess, mp_info* info)
+{
+    if (!c) return MP_ERR_ARG;
+    reset_info(info);
+    if (!ux || !uy || !uz || !S || !phi) return fail(c, MP_ERR_ARG, "ux, uy, uz, S and phi are required");
+    if (!c->have_base) return fail(c, MP_ERR_STATE, "mp_map_base_state has not succeeded on this context");
+    if (!c->have_coefs) return fail(c, MP_ERR_STATE, "face coefficients missing");
+    (void)hipSetDevice(c->cfg.device);
+    c->kev_used = 0;
+    const int nb = nblk(c);
+    const double inv_h = 1.0 / c->cfg.h;
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    mp::launch_mac_rhs(c->d0, inv_h, c->beta0, ux, uy, uz, S, c->b64, c->partials, nb, c->stream);
+    int st = finish_rhs(c, nb);
+    if (st) return st;
+    if (info) {
+        info->rhs_norm = sqrt(c->hscal[S_NB2]);
+        info->rhs_mean = -c->hscal[S_MEAN];
+    }
+    HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+    int solve_st = run_solve(c, phi, use_initial_guess, info);
+    if (solve_st != MP_OK && solve_st != MP_ERR_NOT_CONVERGED) return solve_st;
+    HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+    mp::launch_vel_correct(c->d0, inv_h, c->c64x, c->c64y, c->c64z, c->beta0, phi, ux, uy, uz, c->stream);
+    mp::launch_rhs_defect(c->d0, inv_h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, c->partials, nb, c->stream);
+    mp::launch_final_sum(c->partials, nb, c->dscal + S_DEF, 1.0, nullptr, 0.0, c->stream);
+    HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
+    st = sync_read(c, S_DEF, 1);
+    if (st) return st;
+    if (info) {
+        const double nb2 = c->hscal[S_NB2];
+        info->div_defect = nb2 > 0.0 ? sqrt(c->hscal[S_DEF] / nb2) : sqrt(c->hscal[S_DEF]);
+        finish_timing(c, info);
+    }
+    return solve_st;
+}
+
+int mp_solve(mp_ctx* c, const double* rhs, double* x, int use_initial_guess, mp_info* info)
+{
+    if (!c) return MP_ERR_ARG;
+    reset_info(info);
+    if (!rhs || !x) return fail(c, MP_ERR_ARG, "rhs and x are required");
+    if (!c->have_coefs) return fail(c, MP_ERR_STATE, "no face coefficients (call mp_map_base_state or mp_set_coefs)");
+    (void)hipSetDevice(c->cfg.device);
+    c->kev_used = 0;
+    const int nb = nblk(c);
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    mp::launch_neg_copy_sum(rhs, c->b64, c->n0, c->partials, nb, c->stream);
+    int st = finish_rhs(c, nb);
+    if (st) return st;
+    if (info) {
+        info->rhs_norm = sqrt(c->hscal[S_NB2]);
+        info->rhs_mean = -c->hscal[S_MEAN];
+    }
+    HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+    int solve_st = run_solve(c, x, use_initial_guess, info);
+    HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+    HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    finish_timing(c, info);
+    return solve_st;
+}
+
+int mp_apply(mp_ctx* c, const double* x, double* y)
+{
+    if (!c) return MP_ERR_ARG;
+    if (!x || !y) return fail(c, MP_ERR_ARG, "x and y are required");
+    if (!c->have_coefs) return fail(c, MP_ERR_STATE, "no face coefficients");
+    (void)hipSetDevice(c->cfg.device);
+    mp::launch_apply64(c->d0, x, c->c64x, c->c64y, c->c64z, 1.0 / (c->cfg.h * c->cfg.h), y, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MP_OK;
+}
+
+int mp_coef_grad(mp_ctx* c, const double* lam, const double* phi, double* gx, double* gy, double* gz)
+{
+    if (!c) return MP_ERR_ARG;
+    if (!lam || !phi || !gx || !gy || !gz) return fail(c, MP_ERR_ARG, "lam, phi, gx, gy, gz are required");
+    (void)hipSetDevice(c->cfg.device);
+    mp::launch_coef_grad(c->d0, 1.0 / (c->cfg.h * c->cfg.h), lam, phi, gx, gy, gz, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// mp_kernels.h -- host-side launchers of the gfx950 kernels (no HIP types
+// beyond hipStream_t).  Every launcher enqueues on `s` and does not synchronise.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mp {
+
+struct Dims;
+
+// Largest number of blocks a reduction kernel uses (size of a partials slot).
+constexpr int kMaxRedBlocks = 2048;
+constexpr int kBlock = 256;
+
+int red_blocks(long long n);
+
+// ---- reductions ---------------------------------------------------------
+// out[0] = scale * sum(partials[0..nb)); when rms_out != nullptr also
+// rms_out[0] = sqrt(sum / count), rms_out[1] = 1 / rms_out[0] (1 if the sum is 0).
+void launch_final_sum(const double* partials, int nb, double* out, double scale, double* rms_out, double count,
+                      hipStream_t s);
+// partials[b] = per-block sum of x (grid-stride, fixed order).
+void launch_sum(const double* x, long long n, double* partials, int nb, hipStream_t s);
+// x[q] -= mean[0]; partials = per-block sum of x^2 after the update.
+void launch_sub_mean_sumsq(double* x, long long n, const double* mean, double* partials, int nb, hipStream_t s);
+// x[q] -= mean[0].
+void launch_sub_mean(double* x, long long n, const double* mean, hipStream_t s);
+// b[q] = -rhs[q]; partials = per-block sum of b.
+void launch_neg_copy_sum(const double* rhs, double* b, long long n, double* partials, int nb, hipStream_t s);
+
+// ---- mapping and coefficients ---------------------------------------------
+// beta0 on cells (planar injection or spherical linear interpolation) and
+// ccell = beta0 / rho; partials = per-block count of invalid cells.
+void launch_fill(const Dims& d, double h, int geometry, const double* tab, int n1d, double dr, double cx0, double cy0,
+                 double cz0, const double* rho, double* beta0, double* ccell, double* partials, int nb,
+                 hipStream_t s);
+// Internal low-face coefficients from cell values (harmonic mean), FP64 and
+// optionally FP32; optional external FP64 face arrays (nullptr to skip).
+void launch_faces_from_cells(const Dims& d, const double* ccell, double* c64x, double* c64y, double* c64z,
+                             float* c32x, float* c32y, float* c32z, double* ex, double* ey, double* ez,
+                             hipStream_t s);
+// Internal low-face coefficients from external face arrays; partials counts
+// invalid (negative or non-finite) entries.
+void launch_import_faces(const Dims& d, const double* ex, const double* ey, const double* ez, double* c64x,
+                         double* c64y, double* c64z, float* c32x, float* c32y, float* c32z, double* partials, int nb,
+                         hipStream_t s);
+// Coarse low-face coefficients: mean of the 4 fine faces covering each face.
+template <typename Tin, typename Tout>
+void launch_coef_restrict(const Dims& fine, const Tin* fx, const Tin* fy, const Tin* fz, Tout* cx, Tout* cy,
+                          Tout* cz, hipStream_t s);
+
+// ---- projection ------------------------------------------------------------
+// b = beta0 S - D(beta0 U) (= minus the MAC right-hand side); partials = sum b.
+void launch_mac_rhs(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
+                    const double* uz, const double* S, double* b, double* partials, int nb, hipStream_t s);
+// partials = per-block sum of (beta0 S - D(beta0 U) - shift[0])^2 (no write):
+// the divergence defect of a projected velocity.
+void launch_rhs_defect(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
+                       const double* uz, const double* S, const double* shift, double* partials, int nb,
+                       hipStream_t s);
+// U <- U - (c/beta0_f) G phi on every non-wall face (in place).
+void launch_vel_correct(const Dims& d, double inv_h, const double* c64x, const double* c64y, const double* c64z,
+                        const double* beta0, const double* phi, double* ux, double* uy, double* uz, hipStream_t s);
+// g = (G lam)(G phi) on every non-wall face, external layout; walls 0.
+void launch_coef_grad(const Dims& d, double inv_h2, const double* lam, const double* phi, double* gx, double* gy,
+                      double* gz, hipStream_t s);
+
+// ---- multigrid -----------------------------------------------------------
+template <typename T>
+void launch_rbgs(const Dims& d, T* phi, const T* rhs, const T* cx, const T* cy, const T* cz, T h2, int colour,
+                 int zero_init, hipStream_t s);
+template <typename T>
+void launch_resid_restrict(const Dims& fine, const T* phi, const T* rhs, const T* cx, const T* cy, const T* cz,
+                           T inv_h2, T* coarse_rhs, hipStream_t s);
+template <typename T>
+void launch_prolong(const Dims& fine, T* phi, const T* coarse_phi, hipStream_t s);
+// BiCGStab in FP64 on the coarsest grid (one workgroup); work = 7 * n doubles.
+template <typename T>
+void launch_bottom(const Dims& d, const T* rhs, T* phi, const T* cx, const T* cy, const T* cz, double h2, double rtol,
+                   int maxit, double* work, hipStream_t s);
+
+// ---- FP64 level-0 operations --------------------------------------------
+// y = M x = -(A x).
+void launch_apply64(const Dims& d, const double* x, const double* cx, const double* cy, const double* cz,
+                    double inv_h2, double* y, hipStream_t s);
+// r = b - A phi; partials = per-block sum r^2; when r32 != nullptr,
+// r32 = float(r * inv_s[0]).
+void launch_resid64(const Dims& d, const double* phi, const double* b, const double* cx, const double* cy,
+                    const double* cz, double inv_h2, float* r32, const double* inv_s, double* partials, int nb,
+                    hipStream_t s);
+// phi += s[0] * e.
+void launch_ir_update(long long n, double* phi, const float* e, const double* s, hipStream_t st);
+
+// Plain device copy (bandwidth calibration of the traffic counters).
+void launch_copy(const double* src, double* dst, long long n, hipStream_t s);
+
+}  // namespace mp

@@ -1,0 +1,293 @@
+"""Python binding of libmproj (the C ABI in include/mproj.h).
+
+Argument marshalling only: tensors are checked (device, dtype, shape,
+contiguity) and their device pointers handed to the library, which runs every
+step on the GPU.  There is no CPU fallback; a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmproj.so")
+
+MP_OK = 0
+STATUS = {
+    0: "MP_OK",
+    1: "MP_ERR_ARG",
+    2: "MP_ERR_DEVICE",
+    3: "MP_ERR_NOMEM",
+    4: "MP_ERR_NOT_CONVERGED",
+    5: "MP_ERR_NONFINITE",
+    6: "MP_ERR_SINGULAR_RHS",
+    7: "MP_ERR_STATE",
+}
+MP_ERR_NOT_CONVERGED = 4
+PERIODIC, NEUMANN = 0, 1
+PLANAR, SPHERICAL = 0, 1
+FP64, MIXED = 0, 1
+
+
+class MprojError(RuntimeError):
+    def __init__(self, code, msg, info=None):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.msg = msg
+        self.info = info
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("h", ctypes.c_double),
+        ("bc", ctypes.c_int * 3),
+        ("precision", ctypes.c_int),
+        ("rtol", ctypes.c_double),
+        ("max_outer", ctypes.c_int),
+        ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
+        ("cycles_per_outer", ctypes.c_int),
+        ("bottom_rtol", ctypes.c_double),
+        ("bottom_max_iter", ctypes.c_int),
+        ("demean", ctypes.c_int),
+        ("kernel_timing", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("device", ctypes.c_int),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("outer_iters", ctypes.c_int),
+        ("vcycles", ctypes.c_int),
+        ("bottom_iters_total", ctypes.c_int),
+        ("levels", ctypes.c_int),
+        ("rel_resid", ctypes.c_double),
+        ("div_defect", ctypes.c_double),
+        ("rhs_norm", ctypes.c_double),
+        ("rhs_mean", ctypes.c_double),
+        ("resid_hist", ctypes.c_double * 64),
+        ("ms_rhs", ctypes.c_double), ("ms_solve", ctypes.c_double), ("ms_correct", ctypes.c_double),
+        ("smooth_ms_total", ctypes.c_double),
+        ("smooth_launches", ctypes.c_int),
+        ("flags", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        n = min(max(self.outer_iters + 1, 0), 64)
+        return dict(outer_iters=self.outer_iters, vcycles=self.vcycles, levels=self.levels,
+                    rel_resid=self.rel_resid, div_defect=self.div_defect, rhs_norm=self.rhs_norm,
+                    rhs_mean=self.rhs_mean, resid_hist=list(self.resid_hist[:n]), ms_rhs=self.ms_rhs,
+                    ms_solve=self.ms_solve, ms_correct=self.ms_correct, smooth_ms_total=self.smooth_ms_total,
+                    smooth_launches=self.smooth_launches, flags=self.flags)
+
+
+# Every exported symbol of include/mproj.h.
+EXPORTS = ["mp_config_default", "mp_init", "mp_map_base_state", "mp_set_coefs", "mp_mac_project", "mp_solve",
+           "mp_apply", "mp_coef_grad", "mp_free", "mp_last_error", "mp_version"]
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libmproj.so (built by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libmproj.so not found at {p}: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    D = ctypes.c_double
+    lib.mp_config_default.argtypes = [ctypes.POINTER(Config), I, I, I]
+    lib.mp_config_default.restype = None
+    lib.mp_init.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(P)]
+    lib.mp_init.restype = I
+    lib.mp_map_base_state.argtypes = [P, I, P, I, D, ctypes.POINTER(D), P, P, P, P]
+    lib.mp_map_base_state.restype = I
+    lib.mp_set_coefs.argtypes = [P, P, P, P]
+    lib.mp_set_coefs.restype = I
+    lib.mp_mac_project.argtypes = [P, P, P, P, P, P, I, ctypes.POINTER(Info)]
+    lib.mp_mac_project.restype = I
+    lib.mp_solve.argtypes = [P, P, P, I, ctypes.POINTER(Info)]
+    lib.mp_solve.restype = I
+    lib.mp_apply.argtypes = [P, P, P]
+    lib.mp_apply.restype = I
+    lib.mp_coef_grad.argtypes = [P, P, P, P, P, P]
+    lib.mp_coef_grad.restype = I
+    lib.mp_free.argtypes = [P]
+    lib.mp_free.restype = I
+    lib.mp_last_error.argtypes = [P]
+    lib.mp_last_error.restype = ctypes.c_char_p
+    lib.mp_version.argtypes = []
+    lib.mp_version.restype = ctypes.c_char_p
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def face_shapes(nx, ny, nz, bc):
+    bx, by, bz = bc
+    return (nz, ny, nx + bx), (nz, ny + by, nx), (nz + bz, ny, nx)
+
+
+class Context:
+    """One solver context: grid, boundary kinds, precision and the multigrid
+    hierarchy on one device and stream."""
+
+    def __init__(self, nx, ny, nz, h=None, bc=(PERIODIC, PERIODIC, NEUMANN), precision="mixed", rtol=1e-10,
+                 max_outer=100, nu1=2, nu2=2, cycles_per_outer=1, bottom_rtol=1e-10, bottom_max_iter=400,
+                 demean=True, kernel_timing=False, device=None, stream=None):
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise MprojError(2, "no GPU visible to torch")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        cfg = Config()
+        self.lib.mp_config_default(ctypes.byref(cfg), nx, ny, nz)
+        cfg.h = float(h) if h is not None else 1.0 / nz
+        for a in range(3):
+            cfg.bc[a] = int(bc[a])
+        cfg.precision = {"mixed": MIXED, "fp64": FP64}[precision]
+        cfg.rtol = rtol
+        cfg.max_outer = max_outer
+        cfg.nu1, cfg.nu2 = nu1, nu2
+        cfg.cycles_per_outer = cycles_per_outer
+        cfg.bottom_rtol = bottom_rtol
+        cfg.bottom_max_iter = bottom_max_iter
+        cfg.demean = 1 if demean else 0
+        cfg.kernel_timing = 1 if kernel_timing else 0
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = st
+        cfg.stream = ctypes.c_void_p(st.cuda_stream)
+        cfg.device = self.device.index
+        self.cfg = cfg
+        self.nx, self.ny, self.nz, self.h, self.bc = nx, ny, nz, cfg.h, tuple(int(b) for b in bc)
+        self.precision = precision
+        handle = ctypes.c_void_p()
+        code = self.lib.mp_init(ctypes.byref(cfg), ctypes.byref(handle))
+        if code != MP_OK:
+            raise MprojError(code, "mp_init failed")
+        self._h = handle
+
+    # -- helpers ---------------------------------------------------------
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    def face_shapes(self):
+        return face_shapes(self.nx, self.ny, self.nz, self.bc)
+
+    def _ptr(self, t, shape, name):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device != self.device or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor on {self.device}")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _check(self, code, what, info=None):
+        if code != MP_OK:
+            msg = self.lib.mp_last_error(self._h).decode()
+            raise MprojError(code, f"{what}: {msg}", info)
+
+    def empty_cells(self):
+        return torch.empty(self.shape, dtype=torch.float64, device=self.device)
+
+    def empty_faces(self):
+        return tuple(torch.empty(s, dtype=torch.float64, device=self.device) for s in self.face_shapes())
+
+    # -- API -------------------------------------------------------------
+    def map_base_state(self, geometry, beta0_1d, rho, dr=0.0, center=None, out=None, want_coefs=True):
+        """Fill beta0 (planar injection / spherical linear interpolation) and
+        build the face coefficients; returns (cx, cy, cz) or None."""
+        n1d = int(beta0_1d.shape[0])
+        tab = self._ptr(beta0_1d, (n1d,), "beta0_1d")
+        rp = self._ptr(rho, self.shape, "rho")
+        faces = None
+        if want_coefs:
+            faces = out if out is not None else self.empty_faces()
+            ptrs = [self._ptr(f, s, "coef") for f, s in zip(faces, self.face_shapes())]
+        else:
+            ptrs = [None, None, None]
+        c = (ctypes.c_double * 3)(*(center if center is not None else (0.0, 0.0, 0.0)))
+        code = self.lib.mp_map_base_state(self._h, int(geometry), tab, n1d, float(dr), c, rp, *ptrs)
+        self._check(code, "mp_map_base_state")
+        return faces
+
+    def set_coefs(self, cx, cy, cz):
+        ps = [self._ptr(f, s, n) for f, s, n in zip((cx, cy, cz), self.face_shapes(), ("cx", "cy", "cz"))]
+        self._check(self.lib.mp_set_coefs(self._h, *ps), "mp_set_coefs")
+
+    def mac_project(self, ux, uy, uz, S, phi=None, use_initial_guess=False, allow_not_converged=False):
+        """Project (ux, uy, uz) in place; returns (phi, info dict)."""
+        sx, sy, sz = self.face_shapes()
+        pu = [self._ptr(ux, sx, "ux"), self._ptr(uy, sy, "uy"), self._ptr(uz, sz, "uz")]
+        ps = self._ptr(S, self.shape, "S")
+        if phi is None:
+            phi = self.empty_cells()
+            use_initial_guess = False
+        pp = self._ptr(phi, self.shape, "phi")
+        info = Info()
+        code = self.lib.mp_mac_project(self._h, *pu, ps, pp, int(bool(use_initial_guess)), ctypes.byref(info))
+        d = info.as_dict()
+        if not (allow_not_converged and code == MP_ERR_NOT_CONVERGED):
+            self._check(code, "mp_mac_project", d)
+        d["status"] = code
+        return phi, d
+
+    def solve(self, rhs, x=None, use_initial_guess=False, allow_not_converged=False):
+        """Mean-zero x with div(c grad x) = rhs (mean of rhs removed)."""
+        pr = self._ptr(rhs, self.shape, "rhs")
+        if x is None:
+            x = self.empty_cells()
+            use_initial_guess = False
+        px = self._ptr(x, self.shape, "x")
+        info = Info()
+        code = self.lib.mp_solve(self._h, pr, px, int(bool(use_initial_guess)), ctypes.byref(info))
+        d = info.as_dict()
+        if not (allow_not_converged and code == MP_ERR_NOT_CONVERGED):
+            self._check(code, "mp_solve", d)
+        d["status"] = code
+        return x, d
+
+    def apply(self, x, out=None):
+        """M x = div(c grad x) with the FP64 finest-level coefficients."""
+        y = out if out is not None else self.empty_cells()
+        self._check(self.lib.mp_apply(self._h, self._ptr(x, self.shape, "x"), self._ptr(y, self.shape, "y")),
+                    "mp_apply")
+        return y
+
+    def coef_grad(self, lam, phi, out=None):
+        """(G lam)(G phi) on every face (walls 0)."""
+        g = out if out is not None else self.empty_faces()
+        ps = [self._ptr(f, s, "g") for f, s in zip(g, self.face_shapes())]
+        self._check(self.lib.mp_coef_grad(self._h, self._ptr(lam, self.shape, "lam"),
+                                          self._ptr(phi, self.shape, "phi"), *ps), "mp_coef_grad")
+        return g
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.mp_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+
+def version():
+    return load_library().mp_version().decode()

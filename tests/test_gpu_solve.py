@@ -1,0 +1,167 @@
+"""GPU solves and projections against the FP64 oracle (small and odd grids,
+every boundary combination, both precisions), plus error paths."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1908_03634_amd import mproj, workloads as W
+from tests import pins
+from tests.gpu_util import N, T, context_for, gpu_project, rel, say
+
+pytestmark = pytest.mark.gpu
+
+BCS = [(0, 0, 1), (1, 1, 1), (0, 0, 0), (1, 0, 1)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c1_projection_matches_oracle(precision):
+    """32^3, periodic x/y, Neumann z, 1e2 contrast: phi within 1e-9 (both sides
+    solved to 1e-12), corrected U and the divergence constraint."""
+    say("c1", precision)
+    p = W.config_problem("c1")
+    ref = oracle.mac_project(p, tol=1e-12)
+    r = gpu_project(p, precision, rtol=1e-12)
+    g = ref["grid"]
+    phi = N(r["phi"])
+    assert rel(phi, ref["phi"]) < 1e-9
+    assert abs(phi.mean()) < 1e-14 * np.abs(phi).max()
+    # the oracle's operator on the GPU's phi
+    assert oracle.residual_norm(g, ref["cx"], ref["cy"], ref["cz"], ref["rhs"], phi) <= 1.01e-12
+    # the corrected velocity equals the oracle's correction applied to the GPU phi
+    ux, uy, uz = oracle.velocity_correct(g, ref["cx"], ref["cy"], ref["cz"], ref["beta0_cc"], phi, p.ux, p.uy, p.uz)
+    for a, b in ((r["ux"], ux), (r["uy"], uy), (r["uz"], uz)):
+        assert np.abs(N(a) - b).max() <= 1e-12 * np.abs(b).max()
+    info = r["info"]
+    assert info["rel_resid"] <= 1e-12
+    assert info["div_defect"] <= 2e-12
+    assert info["rhs_mean"] == pytest.approx(ref["mean"], rel=1e-9, abs=1e-14)
+    r["ctx"].close()
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(8, 8, 8), (16, 16, 16), (6, 4, 10), (9, 5, 7), (24, 40, 16), (33, 17, 9)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_matches_sparse_lu(bc, shape, precision):
+    nx, ny, nz = shape
+    say("solve", shape, bc, precision)
+    h = 1.0 / nz
+    cx, cy, cz = W.random_coefs(nx, ny, nz, bc, 201)
+    rhs = W.random_cells(nx, ny, nz, 202)
+    ctx = mproj.Context(nx, ny, nz, h=h, bc=bc, precision=precision, rtol=1e-12)
+    ctx.set_coefs(T(cx), T(cy), T(cz))
+    x, info = ctx.solve(T(rhs))
+    x = N(x)
+    if nx * ny * nz <= 4096:
+        ref = pins.bordered_solve(pins.operator(nx, ny, nz, h, bc, cx, cy, cz), rhs).reshape(x.shape)
+    else:
+        ref, _ = oracle.solve(oracle.Grid(nx, ny, nz, h, bc), cx, cy, cz, rhs, tol=1e-13)
+    assert rel(x, ref) < 1e-9
+    assert info["rel_resid"] <= 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_spherical_projection_small(precision):
+    say("spherical small", precision)
+    p = W.spherical_problem(32, seed=303)
+    ref = oracle.mac_project(p, tol=1e-12)
+    r = gpu_project(p, precision, rtol=1e-12)
+    assert rel(N(r["phi"]), ref["phi"]) < 1e-9
+    for a, b in ((r["ux"], ref["ux"]), (r["uy"], ref["uy"]), (r["uz"], ref["uz"])):
+        assert np.abs(N(a) - b).max() <= 1e-9 * np.abs(b).max()
+    r["ctx"].close()
+
+
+def test_results_are_bitwise_reproducible():
+    p = W.config_problem("c1")
+    outs = []
+    for _ in range(2):
+        r = gpu_project(p, "mixed", rtol=1e-10)
+        outs.append((N(r["phi"]), N(r["uz"]), r["info"]["rel_resid"]))
+        r["ctx"].close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+
+
+def test_mixed_and_fp64_agree_and_reach_tolerance():
+    p = W.planar_problem(64, contrast=1e4, seed=404)
+    a = gpu_project(p, "mixed", rtol=1e-10)
+    b = gpu_project(p, "fp64", rtol=1e-10)
+    say("mixed", a["info"]["outer_iters"], a["info"]["resid_hist"][:4], "fp64", b["info"]["outer_iters"])
+    assert a["info"]["rel_resid"] <= 1e-10 and b["info"]["rel_resid"] <= 1e-10
+    assert rel(N(a["phi"]), N(b["phi"])) < 1e-7
+    a["ctx"].close()
+    b["ctx"].close()
+
+
+def test_warm_start_and_idempotence():
+    p = W.planar_problem(32, contrast=1e3, seed=505)
+    r = gpu_project(p, "fp64", rtol=1e-12)
+    ctx = r["ctx"]
+    # projecting the projected velocity again gives phi ~ 0 and leaves U unchanged
+    ux2, uy2, uz2 = r["ux"].clone(), r["uy"].clone(), r["uz"].clone()
+    phi2, info2 = ctx.mac_project(ux2, uy2, uz2, T(p.S))
+    assert np.linalg.norm(N(phi2)) <= 1e-9 * np.linalg.norm(N(r["phi"]))
+    assert np.abs(N(uz2) - N(r["uz"])).max() <= 1e-11 * np.abs(N(r["uz"])).max()
+    # a converged initial guess needs no further step
+    ux3, uy3, uz3 = T(p.ux), T(p.uy), T(p.uz)
+    phi3, info3 = ctx.mac_project(ux3, uy3, uz3, T(p.S), phi=r["phi"].clone(), use_initial_guess=True)
+    assert info3["outer_iters"] == 0
+    ctx.close()
+
+
+def test_not_converged_reports_and_fills_info():
+    p = W.config_problem("c1")
+    ctx = context_for(p, "mixed", rtol=1e-12, max_outer=1)
+    ctx.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center)
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.mac_project(T(p.ux), T(p.uy), T(p.uz), T(p.S))
+    assert e.value.code == 4
+    assert e.value.info["outer_iters"] == 1 and 0 < e.value.info["rel_resid"] < 1
+    ctx.close()
+
+
+def test_nonfinite_source_is_reported():
+    p = W.config_problem("c1")
+    S = p.S.copy()
+    S[3, 3, 3] = np.nan
+    ctx = context_for(p, "mixed")
+    ctx.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center)
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.mac_project(T(p.ux), T(p.uy), T(p.uz), T(S))
+    assert e.value.code == 5
+    ctx.close()
+
+
+def test_singular_rhs_without_demean():
+    n = 8
+    cx, cy, cz = W.random_coefs(n, n, n, (0, 0, 1), 7)
+    ctx = mproj.Context(n, n, n, precision="fp64", demean=False)
+    ctx.set_coefs(T(cx), T(cy), T(cz))
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.solve(T(np.ones((n, n, n))))
+    assert e.value.code == 6
+    x, info = ctx.solve(T(W.random_cells(n, n, n, 8, mean_zero=True)))
+    assert info["rel_resid"] <= 1e-10
+    ctx.close()
+
+
+def test_zero_rhs_gives_zero():
+    n = 16
+    ctx = mproj.Context(n, n, n, precision="mixed")
+    cx, cy, cz = W.random_coefs(n, n, n, (0, 0, 1), 9)
+    ctx.set_coefs(T(cx), T(cy), T(cz))
+    x, info = ctx.solve(T(np.zeros((n, n, n))))
+    assert not N(x).any() and info["rel_resid"] == 0.0
+    ctx.close()
+
+
+def test_wrong_shapes_are_rejected():
+    ctx = mproj.Context(8, 8, 8, precision="fp64")
+    with pytest.raises(ValueError):
+        ctx.solve(T(np.zeros((8, 8, 9))))
+    with pytest.raises(ValueError):
+        ctx.solve(T(np.zeros((8, 8, 8))).float())
+    ctx.close()
