@@ -1,0 +1,223 @@
+"""Benchmark: MAC solves per second to a 1e-10 relative residual on one MI355X.
+
+One step = one whole MAC projection as a time step of the method performs it
+(Sec. 3.2 Steps 3/7): map the base state to face coefficients (fill + harmonic
+faces + coefficient hierarchy), assemble the right-hand side, solve to
+||r||/||b|| <= 1e-10, and correct the face velocity, on device-resident inputs
+of the 256^3 plane-parallel workload (periodic x/y, Neumann z, 1e4 density
+contrast, seeded).  `value` is the mixed-precision rate (FP32 V(2,2) cycles in
+FP64 iterative refinement); the plain FP64 V-cycle rate is reported beside it.
+
+The JSON line also carries the roofline of the dominant kernel (the finest-
+level smoother, timed per launch with HIP events on the library's stream) and
+the FP64 CPU oracle timed on the host for a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "MAC solves/sec to 1e-10 residual (mixed vs FP64) + stencil HBM GB/s"
+WORKLOAD = "c2"
+
+
+def _parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=WORKLOAD, choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--fp64-steps", type=int, default=None, help="steps of the FP64 comparison (default: steps)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-samples", type=int, default=1, help="oracle projections timed on the host")
+    ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one precision only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for the HBM traffic counters)")
+    return ap.parse_args()
+
+
+def _dominant_kernel_bytes_per_cell():
+    """Algorithmic bytes per finest-level cell for one launch of the smoother.
+
+    Red-black Gauss-Seidel, one colour per launch, FP32: per cell the launch
+    reads the iterate (both colours share every line), the three face
+    coefficients and the right-hand side of its colour, and writes its colour:
+    1 + 3 + 1/2 + 1/2 = 5 words = 20 bytes.
+    """
+    return 20.0
+
+
+def _traffic_record(kernel):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec:
+        return None
+    # the counters belong to the kernel source they were taken on
+    import hashlib
+
+    src = os.path.join(ROOT, rec.get("source", ""))
+    if not os.path.exists(src):
+        return None
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if digest != rec.get("sha256"):
+        return None
+    return rec
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the solve is not sharded across GPUs",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1908_03634_amd import mproj, workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    p = W.config_problem(args.workload)
+    n = p.ncell
+    print(f"[bench] workload {p.name}: {p.nx}x{p.ny}x{p.nz}, bc {p.bc}", file=sys.stderr, flush=True)
+
+    def T(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    beta0_1d, rho, S = T(p.beta0_1d), T(p.rho), T(p.S)
+    U0 = [T(p.ux), T(p.uy), T(p.uz)]
+    K, Wm = args.steps, args.warmup
+
+    def run(precision, steps, warmup, kernel_timing):
+        ctx = mproj.Context(p.nx, p.ny, p.nz, h=p.h, bc=p.bc, precision=precision, rtol=1e-10,
+                            kernel_timing=kernel_timing)
+        total = steps + warmup
+        # every step projects its own copy of the unprojected velocity
+        copies = [[u.clone() for u in U0] for _ in range(total)]
+        phi = ctx.empty_cells()
+        infos = []
+        torch.cuda.synchronize()
+        t0 = None
+        for s in range(total):
+            if s == warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            ctx.map_base_state(p.geometry, beta0_1d, rho, p.dr, p.center, want_coefs=False)
+            _, info = ctx.mac_project(*copies[s], S, phi=phi)
+            if s >= warmup:
+                infos.append(info)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.close()
+        del copies
+        return dt, infos
+
+    if args.copy_calibration:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 3 copies of {nbytes} bytes", file=sys.stderr, flush=True)
+        del src, dst
+
+    res = {}
+    for prec in ("mixed", "fp64"):
+        if args.only and prec != args.only:
+            continue
+        steps = K if prec == "mixed" else (args.fp64_steps or K)
+        dt, infos = run(prec, steps, Wm, kernel_timing=True)
+        res[prec] = (dt, steps, infos)
+        print(f"[bench] {prec}: {steps / dt:.2f} solves/s, {1e3 * dt / steps:.3f} ms/step, "
+              f"steps {infos[-1]['outer_iters']}, rel {infos[-1]['rel_resid']:.2e}", file=sys.stderr, flush=True)
+
+    main_prec = args.only or "mixed"
+    dt, steps, infos = res[main_prec]
+    value = steps / dt
+    # dominant kernel: finest-level smoother launches, HIP events on the library stream
+    tot_ms = sum(i["smooth_ms_total"] for i in infos)
+    cnt = sum(i["smooth_launches"] for i in infos)
+    avg_s = tot_ms / cnt / 1e3 if cnt else float("nan")
+    bytes_per_launch = _dominant_kernel_bytes_per_cell() * n * (2.0 if main_prec == "fp64" else 1.0)
+    achieved = bytes_per_launch / avg_s / 1e9
+    kname = "k_rbgs<float>" if main_prec == "mixed" else "k_rbgs<double>"
+    rec = _traffic_record(kname)
+    traffic = None
+    if rec:
+        traffic = {"fetch_bytes": rec["fetch_bytes"], "write_bytes": rec["write_bytes"],
+                   "algorithmic_bytes": bytes_per_launch, "scale": rec.get("scale")}
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "avg_launch_us": round(avg_s * 1e6, 2), "launches": cnt,
+                "bytes_per_launch": bytes_per_launch}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build(force=False)
+        t0 = time.perf_counter()
+        for _ in range(args.cpu_samples):
+            r = oracle.mac_project(p, tol=1e-10)
+        cdt = time.perf_counter() - t0
+        cpu = {"value": round(args.cpu_samples / cdt, 4), "unit": "solves/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{args.cpu_samples} full {p.nx}x{p.ny}x{p.nz} projection(s) (fill, faces, rhs, FP64 "
+                         f"V(2,2) multigrid to 1e-10 in {r['info']['cycles']} cycles, correction)"}
+        print(f"[bench] cpu oracle: {cpu['value']} solves/s on {cpu['cores']} threads", file=sys.stderr, flush=True)
+
+    last = infos[-1]
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": Wm,
+        "ms_per_step": round(1e3 * dt / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if main_prec == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {p.nx}^3 plane-parallel, periodic x/y, Neumann z, "
+                               f"{p.meta.get('contrast'):.0e} density contrast; map + rhs + solve to 1e-10 + "
+                               f"velocity correction per step",
+                   "precision": main_prec, "smoother": "red-black Gauss-Seidel V(2,2)",
+                   "outer_steps": last["outer_iters"], "rel_resid": last["rel_resid"],
+                   "levels": last["levels"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if "fp64" in res and main_prec != "fp64":
+        fdt, fsteps, finfos = res["fp64"]
+        line["fp64_value"] = round(fsteps / fdt, 3)
+        line["fp64_ms_per_step"] = round(1e3 * fdt / fsteps, 4)
+        line["fp64_cycles"] = finfos[-1]["outer_iters"]
+        line["mixed_over_fp64"] = round(value / (fsteps / fdt), 3)
+    line["phase_ms"] = {"rhs": round(last["ms_rhs"], 4), "solve": round(last["ms_solve"], 4),
+                        "correct": round(last["ms_correct"], 4)}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

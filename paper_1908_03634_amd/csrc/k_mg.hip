@@ -134,12 +134,14 @@ void launch_prolong(const Dims& fine, T* phi, const T* coarse_phi, hipStream_t s
 
 // BiCGStab in FP64 for A x = b on the coarsest grid, run by one workgroup.
 // b is made mean-zero first (the system is singular with the constants as
-// null space); the result is returned mean-zero.  work holds 7 n doubles.
+// null space); the result is returned mean-zero.  With use_x0 the iteration
+// starts from the x passed in and stops at rtol times the initial residual;
+// otherwise it starts from zero.  work holds 7 n doubles.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ bin, T* __restrict__ xout,
                                                  const T* __restrict__ cx, const T* __restrict__ cy,
                                                  const T* __restrict__ cz, double h2, double rtol, int maxit,
-                                                 double* __restrict__ work)
+                                                 int use_x0, double* __restrict__ work)
 {
     __shared__ double sh[16];
     const int n = (int)d.n();
@@ -156,19 +158,7 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
     double part = 0.0;
     for (int q = tid; q < n; q += nt) part += (double)bin[q];
     const double mean = block_sum(part, sh) / n;
-    part = 0.0;
-    for (int q = tid; q < n; q += nt) {
-        const double bq = (double)bin[q] - mean;
-        x[q] = 0.0;
-        r[q] = bq;
-        rh[q] = bq;
-        p[q] = 0.0;
-        v[q] = 0.0;
-        part = fma(bq, bq, part);
-    }
-    const double bnorm2 = block_sum(part, sh);
-    const double tol2 = rtol * rtol * bnorm2;
-    double rho = 1.0, alpha = 1.0, omega = 1.0;
+    for (int q = tid; q < n; q += nt) x[q] = use_x0 ? (double)xout[q] : 0.0;
 
     // A y for y in work (FP64), coefficients in T.
     auto apply = [&](const double* y, double* out) {
@@ -183,6 +173,20 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
         }
         __syncthreads();
     };
+
+    if (use_x0) apply(x, tv);
+    part = 0.0;
+    for (int q = tid; q < n; q += nt) {
+        const double rq = ((double)bin[q] - mean) - (use_x0 ? tv[q] : 0.0);
+        r[q] = rq;
+        rh[q] = rq;
+        p[q] = 0.0;
+        v[q] = 0.0;
+        part = fma(rq, rq, part);
+    }
+    const double bnorm2 = block_sum(part, sh);
+    const double tol2 = rtol * rtol * bnorm2;
+    double rho = 1.0, alpha = 1.0, omega = 1.0;
 
     if (bnorm2 > 0.0) {
         for (int it = 0; it < maxit; it++) {
@@ -242,12 +246,13 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
 
 template <typename T>
 void launch_bottom(const Dims& d, const T* rhs, T* phi, const T* cx, const T* cy, const T* cz, double h2, double rtol,
-                   int maxit, double* work, hipStream_t s)
+                   int maxit, int use_x0, double* work, hipStream_t s)
 {
     long long n = d.n();
     int nt = (int)((n + 63) / 64) * 64;
     if (nt > 1024) nt = 1024;
-    hipLaunchKernelGGL((k_bottom<T>), dim3(1), dim3(nt), 0, s, d, rhs, phi, cx, cy, cz, h2, rtol, maxit, work);
+    hipLaunchKernelGGL((k_bottom<T>), dim3(1), dim3(nt), 0, s, d, rhs, phi, cx, cy, cz, h2, rtol, maxit, use_x0,
+                       work);
 }
 
 // --------------------------------------------------------- FP64 level 0
@@ -324,7 +329,7 @@ void launch_ir_update(long long n, double* phi, const float* e, const double* s,
     template void launch_resid_restrict<T>(const Dims&, const T*, const T*, const T*, const T*, const T*, T, T*,      \
                                            hipStream_t);                                                              \
     template void launch_prolong<T>(const Dims&, T*, const T*, hipStream_t);                                          \
-    template void launch_bottom<T>(const Dims&, const T*, T*, const T*, const T*, const T*, double, double, int,      \
+    template void launch_bottom<T>(const Dims&, const T*, T*, const T*, const T*, const T*, double, double, int, int, \
                                    double*, hipStream_t);
 MP_INST(float)
 MP_INST(double)

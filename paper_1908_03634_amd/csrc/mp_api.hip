@@ -197,7 +197,8 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
     const int nlev = (int)c->lv.size();
     if (l == nlev - 1) {
         mp::launch_bottom<T>(L.d, (const T*)L.b, (T*)L.x, (const T*)L.cx, (const T*)L.cy, (const T*)L.cz, L.h * L.h,
-                             c->cfg.bottom_rtol, c->cfg.bottom_max_iter, c->bottom_work, c->stream);
+                             c->cfg.bottom_rtol, c->cfg.bottom_max_iter, zero_init ? 0 : 1, c->bottom_work,
+                             c->stream);
         return;
     }
     if (zero_init && c->cfg.nu1 == 0) (void)hipMemsetAsync(L.x, 0, sizeof(T) * L.d.n(), c->stream);

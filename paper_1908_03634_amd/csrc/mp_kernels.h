@@ -74,9 +74,10 @@ void launch_resid_restrict(const Dims& fine, const T* phi, const T* rhs, const T
 template <typename T>
 void launch_prolong(const Dims& fine, T* phi, const T* coarse_phi, hipStream_t s);
 // BiCGStab in FP64 on the coarsest grid (one workgroup); work = 7 * n doubles.
+// use_x0: start from phi (tolerance relative to the initial residual).
 template <typename T>
 void launch_bottom(const Dims& d, const T* rhs, T* phi, const T* cx, const T* cy, const T* cz, double h2, double rtol,
-                   int maxit, double* work, hipStream_t s);
+                   int maxit, int use_x0, double* work, hipStream_t s);
 
 // ---- FP64 level-0 operations --------------------------------------------
 // y = M x = -(A x).

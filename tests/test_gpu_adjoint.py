@@ -1,0 +1,125 @@
+"""The differentiable solve (hand-written adjoint behind torch.autograd)
+against the FP64 oracle gradient and central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1908_03634_amd import mproj, workloads as W
+from paper_1908_03634_amd.autograd import mac_solve
+from tests import pins
+from tests.gpu_util import N, T, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(p):
+    g = oracle.Grid.of(p)
+    b0, (cx, cy, cz) = oracle.map_base_state(g, p.geometry, p.beta0_1d, p.dr, p.center, p.rho)
+    rhs, _ = oracle.mac_rhs(g, b0, p.ux, p.uy, p.uz, p.S)
+    return g, rhs, (cx, cy, cz)
+
+
+def _gpu_grads(p, rhs, coefs, precision, rtol):
+    ctx = mproj.Context(p.nx, p.ny, p.nz, h=p.h, bc=p.bc, precision=precision, rtol=rtol)
+    r = T(rhs).requires_grad_(True)
+    cs = [T(c).requires_grad_(True) for c in coefs]
+    phi = mac_solve(ctx, r, *cs)
+    loss = (phi * T(p.w)).sum()
+    loss.backward()
+    out = dict(phi=N(phi), grad_rhs=N(r.grad), grad_c=[N(c.grad) for c in cs], loss=float(loss), ctx=ctx)
+    return out
+
+
+def test_c4_gradients_match_oracle():
+    """128^3, 1e3 contrast, FP64: grad_rhs = lam and grad_c = (G lam)(G phi)
+    within 1e-6 of the oracle's (both sides solved to 1e-12)."""
+    p = W.config_problem("c4")
+    g, rhs, coefs = _setup(p)
+    say("c4 oracle solves")
+    phi_o, _ = oracle.solve(g, *coefs, rhs, tol=1e-12)
+    lam_o, _ = oracle.solve(g, *coefs, p.w, tol=1e-12)
+    gx, gy, gz = oracle.coef_grad(g, lam_o, phi_o)
+    say("c4 gpu")
+    r = _gpu_grads(p, rhs, coefs, "fp64", 1e-12)
+    assert rel(r["phi"], phi_o) < 1e-9
+    assert rel(r["grad_rhs"], lam_o) < 1e-9
+    for a, b in zip(r["grad_c"], (gx, gy, gz)):
+        assert rel(a, b) < 1e-6
+    # walls carry no gradient
+    assert not r["grad_c"][2][0].any() and not r["grad_c"][2][-1].any()
+    r["ctx"].close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fd_copy_gradients_match_central_differences(precision):
+    """16^3 copy: GPU gradients against central differences (h = 1e-6) of
+    sparse-LU solves on the CPU."""
+    p = W.fd_copy_problem()
+    g, rhs, (cx, cy, cz) = _setup(p)
+    r = _gpu_grads(p, rhs, (cx, cy, cz), precision, 1e-12)
+    w = p.w
+
+    def L(cx_, cy_, cz_, rhs_):
+        M = pins.operator(g.nx, g.ny, g.nz, g.h, g.bc, cx_, cy_, cz_)
+        return float((w.ravel() * pins.bordered_solve(M, rhs_)).sum())
+
+    rng = np.random.default_rng(11)
+    vx, vy, vz = (rng.uniform(-1, 1, a.shape) * (a != 0) for a in (cx, cy, cz))
+    eps = 1e-6
+    fd = (L(cx * (1 + eps * vx), cy * (1 + eps * vy), cz * (1 + eps * vz), rhs)
+          - L(cx * (1 - eps * vx), cy * (1 - eps * vy), cz * (1 - eps * vz), rhs)) / (2 * eps)
+    gxx, gyy, gzz = r["grad_c"]
+    dd = float((gxx * cx * vx).sum() + (gyy * cy * vy).sum() + (gzz * cz * vz).sum())
+    assert dd == pytest.approx(fd, rel=1e-6)
+    vr = rng.standard_normal(rhs.shape)
+    fdr = (L(cx, cy, cz, rhs + 1e-6 * vr) - L(cx, cy, cz, rhs - 1e-6 * vr)) / 2e-6
+    assert float((r["grad_rhs"] * vr).sum()) == pytest.approx(fdr, rel=1e-6)
+    r["ctx"].close()
+
+
+def test_c5_adjoint_properties_at_full_size():
+    """512^3 mixed: forward + backward through the autograd function.  The
+    adjoint solve's residual under the oracle's operator, the gradient kernel
+    on sampled faces, and the dot-product identity <w, S b> = <S w, b>."""
+    p = W.config_problem("c5")
+    ctx = mproj.Context(p.nx, p.ny, p.nz, h=p.h, bc=p.bc, precision="mixed", rtol=1e-10)
+    say("c5 map")
+    cx, cy, cz = ctx.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center)
+    ux, uy, uz = T(p.ux), T(p.uy), T(p.uz)
+    # rhs of the projection as the solve input
+    _, info = ctx.mac_project(ux, uy, uz, T(p.S))
+    del ux, uy, uz
+    g = oracle.Grid.of(p)
+    b0 = oracle.fill_beta0(g, p.geometry, p.beta0_1d, p.dr, p.center)
+    rhs, _ = oracle.mac_rhs(g, b0, p.ux, p.uy, p.uz, p.S)
+    r = T(rhs).requires_grad_(True)
+    cs = [c.clone().requires_grad_(True) for c in (cx, cy, cz)]
+    say("c5 forward/backward")
+    phi = mac_solve(ctx, r, *cs)
+    wt = T(p.w)
+    (phi * wt).sum().backward()
+    lam = N(r.grad)
+    wm = p.w - p.w.mean()
+    coefs = [N(c) for c in (cx, cy, cz)]
+    say("c5 oracle residual of lam")
+    res = oracle.residual_norm(g, *coefs, wm, lam)
+    say(f"  adjoint residual {res:.3e}")
+    assert res <= 1.01e-10
+    # dot-product identity
+    phin = N(phi)
+    a1 = float(np.dot(p.w.ravel(), phin.ravel()))
+    a2 = float(np.dot(lam.ravel(), (rhs - rhs.mean()).ravel()))
+    scale = float(np.linalg.norm(p.w) * np.linalg.norm(phin))
+    say(f"  <w,phi> {a1:.6e}  <lam,b> {a2:.6e}  scale {scale:.3e}")
+    assert abs(a1 - a2) <= 1e-7 * scale
+    # sampled face gradients from lam and phi
+    gz = N(cs[2].grad)
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        k = int(rng.integers(1, p.nz))
+        j = int(rng.integers(0, p.ny))
+        i = int(rng.integers(0, p.nx))
+        ref = (lam[k, j, i] - lam[k - 1, j, i]) * (phin[k, j, i] - phin[k - 1, j, i]) / p.h ** 2
+        assert gz[k, j, i] == pytest.approx(ref, rel=1e-12, abs=1e-300)
+    ctx.close()

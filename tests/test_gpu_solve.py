@@ -101,8 +101,10 @@ def test_warm_start_and_idempotence():
     r = gpu_project(p, "fp64", rtol=1e-12)
     ctx = r["ctx"]
     # projecting the projected velocity again gives phi ~ 0 and leaves U unchanged
+    # (its right-hand side is rounding noise, so no relative tolerance is
+    # reachable; the stagnation exit is expected)
     ux2, uy2, uz2 = r["ux"].clone(), r["uy"].clone(), r["uz"].clone()
-    phi2, info2 = ctx.mac_project(ux2, uy2, uz2, T(p.S))
+    phi2, info2 = ctx.mac_project(ux2, uy2, uz2, T(p.S), allow_not_converged=True)
     assert np.linalg.norm(N(phi2)) <= 1e-9 * np.linalg.norm(N(r["phi"]))
     assert np.abs(N(uz2) - N(r["uz"])).max() <= 1e-11 * np.abs(N(r["uz"])).max()
     # a converged initial guess needs no further step
