@@ -44,17 +44,6 @@ def _parse():
     return ap.parse_args()
 
 
-def _dominant_kernel_bytes_per_cell():
-    """Algorithmic bytes per finest-level cell for one launch of the smoother.
-
-    Red-black Gauss-Seidel, one colour per launch, FP32: per cell the launch
-    reads the iterate (both colours share every line), the three face
-    coefficients and the right-hand side of its colour, and writes its colour:
-    1 + 3 + 1/2 + 1/2 = 5 words = 20 bytes.
-    """
-    return 20.0
-
-
 def _traffic_record(kernel):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -153,22 +142,29 @@ def main():
     main_prec = args.only or "mixed"
     dt, steps, infos = res[main_prec]
     value = steps / dt
-    # dominant kernel: finest-level smoother launches, HIP events on the library stream
+    # dominant kernel: the finest-level smoother.  The library records HIP
+    # events around each of its launches on its own stream and the
+    # algorithmic bytes of each launch (x_old unless zero, b, three face
+    # coefficients, x_new, plus 1/8 word of coarse correction when the
+    # prolongation is folded in).
     tot_ms = sum(i["smooth_ms_total"] for i in infos)
     cnt = sum(i["smooth_launches"] for i in infos)
+    tot_bytes = sum(i["smooth_bytes"] for i in infos)
     avg_s = tot_ms / cnt / 1e3 if cnt else float("nan")
-    bytes_per_launch = _dominant_kernel_bytes_per_cell() * n * (2.0 if main_prec == "fp64" else 1.0)
+    bytes_per_launch = tot_bytes / cnt if cnt else float("nan")
     achieved = bytes_per_launch / avg_s / 1e9
-    kname = "k_rbgs<float>" if main_prec == "mixed" else "k_rbgs<double>"
+    kname = "k_sweep<float>" if main_prec == "mixed" else "k_sweep<double>"
     rec = _traffic_record(kname)
     traffic = None
     if rec:
         traffic = {"fetch_bytes": rec["fetch_bytes"], "write_bytes": rec["write_bytes"],
-                   "algorithmic_bytes": bytes_per_launch, "scale": rec.get("scale")}
+                   "total_bytes": rec["fetch_bytes"] + rec["write_bytes"],
+                   "algorithmic_bytes": rec.get("algorithmic_bytes"), "calibration": rec.get("calibration")}
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": traffic["total_bytes"] if traffic else None, "traffic_detail": traffic,
                 "avg_launch_us": round(avg_s * 1e6, 2), "launches": cnt,
-                "bytes_per_launch": bytes_per_launch}
+                "bytes_per_launch": round(bytes_per_launch)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -63,6 +63,7 @@ typedef enum {
 enum { MP_BC_PERIODIC = 0, MP_BC_NEUMANN = 1 };
 enum { MP_PLANAR = 0, MP_SPHERICAL = 1 };
 enum { MP_FP64 = 0, MP_MIXED = 1 };
+enum { MP_SMOOTH_AUTO = 0, MP_SMOOTH_PER_COLOUR = 1, MP_SMOOTH_FUSED = 2 };
 
 /* Solver configuration, fixed for the life of a context. */
 typedef struct mp_config {
@@ -80,6 +81,15 @@ typedef struct mp_config {
     int demean;              /* 1: remove the mean of the rhs; 0: require mean ~ 0 */
     int kernel_timing;       /* 1: time the finest-level smoother launches with
                                 HIP events (mp_info.smooth_*) */
+    int smoother;            /* MP_SMOOTH_AUTO: both colours in one launch on the
+                                large levels, one launch per colour elsewhere;
+                                MP_SMOOTH_PER_COLOUR: one launch per colour on
+                                every level; MP_SMOOTH_FUSED: both colours in one
+                                launch wherever the grid allows.  All three give
+                                the same bits. */
+    int coarse_cycle;        /* 1: run levels of <= 32768 cells in one workgroup
+                                (bottom <= 256 cells by one wavefront); 0: one
+                                launch per operation on every level */
     void *stream;            /* hipStream_t for every launch; NULL = null stream */
     int device;              /* HIP device ordinal */
 } mp_config;
@@ -98,6 +108,7 @@ typedef struct mp_info {
     double ms_rhs, ms_solve, ms_correct;   /* phase times (HIP events) */
     double smooth_ms_total;  /* summed finest-level smoother time (kernel_timing) */
     int smooth_launches;     /* number of launches summed above */
+    double smooth_bytes;     /* algorithmic HBM bytes of those launches */
     int flags;               /* bit 0: stagnation detected */
 } mp_info;
 
@@ -105,12 +116,14 @@ typedef struct mp_ctx mp_ctx;
 
 /* Fill *cfg with defaults for an nx x ny x nz grid: h = 1/nz, periodic x/y,
  * Neumann z, MIXED, rtol 1e-10, max_outer 100, V(2,2), 1 cycle per step,
- * bottom 1e-10 / 400 iterations, demean 1, null stream, device 0. */
+ * bottom 1e-8 / 400 iterations, demean 1, automatic smoother, coarse cycle on,
+ * null stream, device 0. */
 void mp_config_default(mp_config *cfg, int nx, int ny, int nz);
 
 /* Create a context: validates cfg, selects the device, allocates the
- * multigrid hierarchy (levels halve every axis while all extents stay even
- * and >= 4 after halving; the coarsest grid must hold <= 4096 cells).
+ * multigrid hierarchy (levels halve every axis while all extents are even and
+ * >= 4, so the coarsest grid keeps >= 2 cells per axis; it must hold <= 16384
+ * cells).
  * Errors: MP_ERR_ARG (cfg), MP_ERR_DEVICE (no device), MP_ERR_NOMEM. */
 int mp_init(const mp_config *cfg, mp_ctx **out);
 
@@ -122,7 +135,8 @@ int mp_init(const mp_config *cfg, mp_ctx **out);
  *   interpolation at the distance of its centre, holding the end values beyond
  *   the table.
  * rho: cell density (> 0).  cx, cy, cz: output face coefficients beta0/rho
- * (harmonic mean, walls 0), FP64, face layouts above; any of them may be NULL.
+ * (harmonic mean, walls 0), FP64, face layouts above; all three or none may be
+ * NULL (the solver keeps its own copy either way).
  * Rebuilds the coefficient hierarchy.  Errors: MP_ERR_ARG (sizes, dr, n1d),
  * MP_ERR_NONFINITE (rho <= 0 or non-finite values). */
 int mp_map_base_state(mp_ctx *ctx, int geometry, const double *beta0_1d, int n1d, double dr, const double *center,

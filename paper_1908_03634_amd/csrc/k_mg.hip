@@ -1,142 +1,95 @@
-// k_mg.hip -- gfx950 multigrid kernels: red-black Gauss-Seidel smoother,
-// fused residual + 8-cell restriction, piecewise-constant prolongation,
-// FP64 BiCGStab on the coarsest grid, and the FP64 level-0 residual and
-// update of the iterative refinement.
+// k_mg.hip -- gfx950 multigrid kernels launched one per operation: one colour
+// of red-black Gauss-Seidel (the reference the fused sweep is checked
+// against, and the fallback for odd periodic extents), residual + 8-cell
+// restriction, piecewise-constant prolongation, the workgroup BiCGStab
+// bottom solve for coarsest grids too large for one wavefront, and the FP64
+// finest-level operator, residual and update of the iterative refinement.
 //
 // The stencils are bandwidth-bound (about 20 flops per 24-48 bytes), so no
-// matrix cores are involved; the design goals are contiguous x-fastest rows
-// per wavefront and as few passes over HBM as possible.
+// matrix cores are involved.  Launches are 3D (x fastest, 64 lanes along x)
+// so no thread divides a 64-bit index; the FP64 residual marches along z
+// keeping the z-neighbours of its column in registers.
 #include "mp_device.h"
 #include "mp_kernels.h"
+#include "mp_launch.h"
 
 #include <math.h>
 
 namespace mp {
 
-static inline unsigned grid1(long long n)
-{
-    long long b = (n + kBlock - 1) / kBlock;
-    return (unsigned)(b < 1 ? 1 : b);
-}
-
 // ------------------------------------------------------------------ smoother
 
-// One colour of a red-black Gauss-Seidel sweep on A x = b (in place).
-// Colour of cell (i,j,k) is (i+j+k) mod 2; thread t owns the pair of x
-// cells (2p, 2p+1) of one row and updates the one of the requested colour:
-//     x_i = (h^2 b_i + sum_f c_f x_nb(f)) / sum_f c_f.
-// zero_init: the iterate is zero on entry -- the neighbours are not read and
-// the other cell of the pair is set to zero (so no separate clear is needed).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_rbgs(Dims d, T* __restrict__ x, const T* __restrict__ b,
-                                                 const T* __restrict__ cx, const T* __restrict__ cy,
-                                                 const T* __restrict__ cz, T h2, int colour, int zero_init)
+__global__ __launch_bounds__(256) void k_rbgs(Dims d, T* __restrict__ x, const T* __restrict__ b,
+                                              const T* __restrict__ cx, const T* __restrict__ cy,
+                                              const T* __restrict__ cz, T h2, int colour, int zero_init)
 {
-    const int nxh = (d.nx + 1) >> 1;
-    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const long long total = (long long)nxh * d.ny * d.nz;
-    if (t >= total) return;
-    const long long row = t / nxh;
-    const int p = (int)(t - row * nxh);
-    const int k = (int)(row / d.ny);
-    const int j = (int)(row - (long long)k * d.ny);
-    const int par = (j + k + colour) & 1;
-    const int i = 2 * p + par;
-    const long long rbase = row * d.nx;
-    if (zero_init) {
-        const int io = 2 * p + (1 - par);
-        if (io < d.nx) x[rbase + io] = T(0);
-    }
-    if (i >= d.nx) return;
-    const long long q = rbase + i;
-    const Nbr nb = neighbours(d, q, i, j, k);
-    T csum, cv;
-    if (zero_init) {
-        const T c0 = cx[q], c1 = ld_or0(cx, nb.cxp), c2 = cy[q], c3 = ld_or0(cy, nb.cyp), c4 = cz[q],
-                c5 = ld_or0(cz, nb.czp);
-        csum = ((((c0 + c1) + c2) + c3) + c4) + c5;
-        cv = T(0);
-    } else {
-        stencil_sums<T>(cx, cy, cz, x, q, nb, csum, cv);
-    }
-    x[q] = csum > T(0) ? fma(h2, b[q], cv) / csum : (zero_init ? T(0) : x[q]);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (p >= (d.nx + 1) / 2 || j >= d.ny || k >= d.nz) return;
+    rbgs_cell<T>(d, x, b, cx, cy, cz, h2, colour, zero_init, p, j, k);
 }
 
 template <typename T>
 void launch_rbgs(const Dims& d, T* phi, const T* rhs, const T* cx, const T* cy, const T* cz, T h2, int colour,
                  int zero_init, hipStream_t s)
 {
-    const long long total = (long long)((d.nx + 1) / 2) * d.ny * d.nz;
-    hipLaunchKernelGGL((k_rbgs<T>), dim3(grid1(total)), dim3(kBlock), 0, s, d, phi, rhs, cx, cy, cz, h2, colour,
-                       zero_init);
+    const Shape3 sh = cells3((d.nx + 1) / 2, d.ny, d.nz);
+    hipLaunchKernelGGL((k_rbgs<T>), sh.grid, sh.block, 0, s, d, phi, rhs, cx, cy, cz, h2, colour, zero_init);
 }
 
 // --------------------------------------------------------- transfer operators
 
-// Coarse rhs = mean of the 8 fine residuals r = b - A x (one thread per
-// coarse cell; lanes read adjacent fine pairs, so rows stay contiguous).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_resid_restrict(Dims d, const T* __restrict__ x, const T* __restrict__ b,
-                                                           const T* __restrict__ cx, const T* __restrict__ cy,
-                                                           const T* __restrict__ cz, T inv_h2, T* __restrict__ bc)
+__global__ __launch_bounds__(256) void k_resid_restrict(Dims d, const T* __restrict__ x, const T* __restrict__ b,
+                                                        const T* __restrict__ cx, const T* __restrict__ cy,
+                                                        const T* __restrict__ cz, T inv_h2, T* __restrict__ bc)
 {
     const int nxc = d.nx / 2, nyc = d.ny / 2, nzc = d.nz / 2;
-    const long long qc = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (qc >= (long long)nxc * nyc * nzc) return;
-    const long long t = qc / nxc;
-    const int I = (int)(qc - t * nxc), K = (int)(t / nyc), J = (int)(t - (long long)K * nyc);
-    T acc = T(0);
-#pragma unroll
-    for (int c = 0; c < 2; c++)
-#pragma unroll
-        for (int bb = 0; bb < 2; bb++)
-#pragma unroll
-            for (int a = 0; a < 2; a++) {
-                const int i = 2 * I + a, j = 2 * J + bb, k = 2 * K + c;
-                const long long q = ((long long)k * d.ny + j) * d.nx + i;
-                const Nbr nb = neighbours(d, q, i, j, k);
-                T csum, cvs;
-                stencil_sums<T>(cx, cy, cz, x, q, nb, csum, cvs);
-                const T r = b[q] - (csum * x[q] - cvs) * inv_h2;
-                acc += r;
-            }
-    bc[qc] = T(0.125) * acc;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (I >= nxc || J >= nyc || K >= nzc) return;
+    bc[((long long)K * nyc + J) * nxc + I] = restrict_cell<T>(d, x, b, cx, cy, cz, inv_h2, I, J, K);
 }
 
 template <typename T>
 void launch_resid_restrict(const Dims& fine, const T* phi, const T* rhs, const T* cx, const T* cy, const T* cz,
                            T inv_h2, T* coarse_rhs, hipStream_t s)
 {
-    const long long nc = (long long)(fine.nx / 2) * (fine.ny / 2) * (fine.nz / 2);
-    hipLaunchKernelGGL((k_resid_restrict<T>), dim3(grid1(nc)), dim3(kBlock), 0, s, fine, phi, rhs, cx, cy, cz, inv_h2,
+    const Shape3 sh = cells3(fine.nx / 2, fine.ny / 2, fine.nz / 2);
+    hipLaunchKernelGGL((k_resid_restrict<T>), sh.grid, sh.block, 0, s, fine, phi, rhs, cx, cy, cz, inv_h2,
                        coarse_rhs);
 }
 
 // Fine x += coarse e of the parent cell.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong(Dims d, T* __restrict__ x, const T* __restrict__ e)
+__global__ __launch_bounds__(256) void k_prolong(Dims d, T* __restrict__ x, const T* __restrict__ e)
 {
-    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (q >= d.n()) return;
-    int i, j, k;
-    cell_ijk(d, q, i, j, k);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= d.nx || j >= d.ny || k >= d.nz) return;
     const int nxc = d.nx / 2, nyc = d.ny / 2;
-    x[q] += e[((long long)(k >> 1) * nyc + (j >> 1)) * nxc + (i >> 1)];
+    x[((long long)k * d.ny + j) * d.nx + i] += e[((long long)(k >> 1) * nyc + (j >> 1)) * nxc + (i >> 1)];
 }
 
 template <typename T>
 void launch_prolong(const Dims& fine, T* phi, const T* coarse_phi, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_prolong<T>), dim3(grid1(fine.n())), dim3(kBlock), 0, s, fine, phi, coarse_phi);
+    const Shape3 sh = cells3(fine.nx, fine.ny, fine.nz);
+    hipLaunchKernelGGL((k_prolong<T>), sh.grid, sh.block, 0, s, fine, phi, coarse_phi);
 }
 
 // ------------------------------------------------------------ bottom solve
 
-// BiCGStab in FP64 for A x = b on the coarsest grid, run by one workgroup.
-// b is made mean-zero first (the system is singular with the constants as
-// null space); the result is returned mean-zero.  With use_x0 the iteration
-// starts from the x passed in and stops at rtol times the initial residual;
-// otherwise it starts from zero.  work holds 7 n doubles.
+// BiCGStab in FP64 for A x = b on the coarsest grid, run by one workgroup
+// (used when that grid holds more cells than one wavefront solves in
+// registers).  b is made mean-zero first (the system is singular with the
+// constants as null space); the result is returned mean-zero.  With use_x0
+// the iteration starts from the x passed in and stops at rtol times the
+// initial residual; otherwise it starts from zero.  work holds 7 n doubles.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ bin, T* __restrict__ xout,
                                                  const T* __restrict__ cx, const T* __restrict__ cy,
@@ -257,15 +210,15 @@ void launch_bottom(const Dims& d, const T* rhs, T* phi, const T* cx, const T* cy
 
 // --------------------------------------------------------- FP64 level 0
 
-__global__ __launch_bounds__(kBlock) void k_apply64(Dims d, const double* __restrict__ x,
-                                                    const double* __restrict__ cx, const double* __restrict__ cy,
-                                                    const double* __restrict__ cz, double inv_h2,
-                                                    double* __restrict__ y)
+__global__ __launch_bounds__(256) void k_apply64(Dims d, const double* __restrict__ x, const double* __restrict__ cx,
+                                                 const double* __restrict__ cy, const double* __restrict__ cz,
+                                                 double inv_h2, double* __restrict__ y)
 {
-    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (q >= d.n()) return;
-    int i, j, k;
-    cell_ijk(d, q, i, j, k);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= d.nx || j >= d.ny || k >= d.nz) return;
+    const long long q = ((long long)k * d.ny + j) * d.nx + i;
     const Nbr nb = neighbours(d, q, i, j, k);
     double csum, cv;
     stencil_sums<double>(cx, cy, cz, x, q, nb, csum, cv);
@@ -275,43 +228,80 @@ __global__ __launch_bounds__(kBlock) void k_apply64(Dims d, const double* __rest
 void launch_apply64(const Dims& d, const double* x, const double* cx, const double* cy, const double* cz,
                     double inv_h2, double* y, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_apply64, dim3(grid1(d.n())), dim3(kBlock), 0, s, d, x, cx, cy, cz, inv_h2, y);
+    const Shape3 sh = cells3(d.nx, d.ny, d.nz);
+    hipLaunchKernelGGL(k_apply64, sh.grid, sh.block, 0, s, d, x, cx, cy, cz, inv_h2, y);
 }
 
-__global__ __launch_bounds__(kBlock) void k_resid64(Dims d, const double* __restrict__ x,
-                                                    const double* __restrict__ b, const double* __restrict__ cx,
-                                                    const double* __restrict__ cy, const double* __restrict__ cz,
-                                                    double inv_h2, float* __restrict__ r32,
-                                                    const double* __restrict__ inv_s, double* part)
+// r = b - A x for a column of lz cells per thread; the column's z-neighbours
+// and z-face coefficients stay in registers.  Same arithmetic, in the same
+// order, as stencil_sums.
+__global__ __launch_bounds__(256) void k_resid64(Dims d, int lz, const double* __restrict__ x,
+                                                 const double* __restrict__ b, const double* __restrict__ cx,
+                                                 const double* __restrict__ cy, const double* __restrict__ cz,
+                                                 double inv_h2, float* __restrict__ r32,
+                                                 const double* __restrict__ inv_s, double* part)
 {
-    __shared__ double sh[kBlock / kWave];
-    const long long n = d.n();
-    const double is = r32 ? inv_s[0] : 0.0;
+    __shared__ double sh[4];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z0 = blockIdx.z * lz;
+    const int z1 = min(z0 + lz, d.nz);
     double acc = 0.0;
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
-         q += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_ijk(d, q, i, j, k);
-        const Nbr nb = neighbours(d, q, i, j, k);
-        double csum, cv;
-        stencil_sums<double>(cx, cy, cz, x, q, nb, csum, cv);
-        const double r = b[q] - (csum * x[q] - cv) * inv_h2;
-        acc = fma(r, r, acc);
-        if (r32) r32[q] = (float)(r * is);
+    if (i < d.nx && j < d.ny) {
+        const double is = r32 ? inv_s[0] : 0.0;
+        const long long sy = d.nx, sz = (long long)d.nx * d.ny;
+        const long long oxm = i > 0 ? -1 : (d.px ? d.nx - 1 : 0);
+        const long long oxp = i < d.nx - 1 ? 1 : (d.px ? -(long long)(d.nx - 1) : 0);
+        const bool hxp = i < d.nx - 1 || d.px;
+        const long long oym = j > 0 ? -sy : (d.py ? (long long)(d.ny - 1) * sy : 0);
+        const long long oyp = j < d.ny - 1 ? sy : (d.py ? -(long long)(d.ny - 1) * sy : 0);
+        const bool hyp = j < d.ny - 1 || d.py;
+        long long q = (long long)z0 * sz + (long long)j * d.nx + i;
+        double xzm = z0 > 0 ? x[q - sz] : (d.pz ? x[q + (long long)(d.nz - 1) * sz] : x[q]);
+        double x0 = x[q];
+        double czl = cz[q];
+        for (int k = z0; k < z1; k++) {
+            const bool last = k == d.nz - 1;
+            const long long qp = !last ? q + sz : (d.pz ? q - (long long)(d.nz - 1) * sz : q);
+            const double xzp = x[qp];
+            const double czh = (!last || d.pz) ? cz[qp] : 0.0;
+            const double c0 = cx[q], c1 = hxp ? cx[q + oxp] : 0.0;
+            const double c2 = cy[q], c3 = hyp ? cy[q + oyp] : 0.0;
+            const double csum = ((((c0 + c1) + c2) + c3) + czl) + czh;
+            double s = c0 * x[q + oxm];
+            s = fma(c1, x[q + oxp], s);
+            s = fma(c2, x[q + oym], s);
+            s = fma(c3, x[q + oyp], s);
+            s = fma(czl, xzm, s);
+            s = fma(czh, xzp, s);
+            const double r = b[q] - (csum * x0 - s) * inv_h2;
+            acc = fma(r, r, acc);
+            if (r32) r32[q] = (float)(r * is);
+            xzm = x0;
+            x0 = xzp;
+            czl = czh;
+            q += sz;
+        }
     }
     const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+        part[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
 }
+
+
 
 void launch_resid64(const Dims& d, const double* phi, const double* b, const double* cx, const double* cy,
-                    const double* cz, double inv_h2, float* r32, const double* inv_s, double* partials, int nb,
+                    const double* cz, double inv_h2, float* r32, const double* inv_s, double* partials, int* nb_out,
                     hipStream_t s)
 {
-    hipLaunchKernelGGL(k_resid64, dim3(nb), dim3(kBlock), 0, s, d, phi, b, cx, cy, cz, inv_h2, r32, inv_s, partials);
+    const ShapeZ sh = zmarch(d.nx, d.ny, d.nz, kZBlocks);
+    *nb_out = (int)sh.blocks();
+    hipLaunchKernelGGL(k_resid64, sh.grid, sh.block, 0, s, d, sh.lz, phi, b, cx, cy, cz, inv_h2, r32, inv_s,
+                       partials);
 }
 
-__global__ __launch_bounds__(kBlock) void k_ir_update(long long n, double* __restrict__ x,
-                                                      const float* __restrict__ e, const double* __restrict__ s)
+__global__ __launch_bounds__(256) void k_ir_update(long long n, double* __restrict__ x, const float* __restrict__ e,
+                                                   const double* __restrict__ s)
 {
     const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (q < n) x[q] = fma(s[0], (double)e[q], x[q]);
@@ -319,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_update(long long n, double* __res
 
 void launch_ir_update(long long n, double* phi, const float* e, const double* s, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ir_update, dim3(grid1(n)), dim3(kBlock), 0, st, n, phi, e, s);
+    hipLaunchKernelGGL(k_ir_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, phi, e, s);
 }
 
 // ------------------------------------------------------------ instantiations

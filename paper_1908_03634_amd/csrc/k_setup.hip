@@ -7,6 +7,7 @@
 // a contiguous 512-byte (FP64) row segment; neighbour reads hit L2.
 #include "mp_device.h"
 #include "mp_kernels.h"
+#include "mp_launch.h"
 
 #include <math.h>
 
@@ -24,6 +25,28 @@ static inline unsigned grid1(long long n)
 {
     long long b = (n + kBlock - 1) / kBlock;
     return (unsigned)(b < 1 ? 1 : b);
+}
+
+int zred_blocks(const Dims& d) { return (int)zmarch(d.nx, d.ny, d.nz, kZBlocks).blocks(); }
+
+// Index helpers of the 3D launches.
+#define MP_IJK3                                                                                                       \
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;                                                             \
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;                                                             \
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+
+// Column (i, j) and z range [z0, z1) of a z-marching launch.
+#define MP_ZCOL                                                                                                       \
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;                                                             \
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;                                                             \
+    const int z0 = blockIdx.z * lz;                                                                                   \
+    const int z1 = min(z0 + lz, d.nz);                                                                                \
+    const bool col = i < d.nx && j < d.ny;
+
+__device__ __forceinline__ void zpart_store(double* part, double s)
+{
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+        part[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
 }
 
 // ---------------------------------------------------------------- reductions
@@ -134,18 +157,16 @@ void launch_copy(const double* src, double* dst, long long n, hipStream_t s)
 
 // Fill (Sec. 3.1): planar direct injection of the z table; spherical linear
 // interpolation in r on r_j = (j + 1/2) dr, end values held beyond the table.
-__global__ __launch_bounds__(kBlock) void k_fill(Dims d, double h, int geometry, const double* __restrict__ tab,
-                                                 int n1d, double dr, double cx0, double cy0, double cz0,
-                                                 const double* __restrict__ rho, double* __restrict__ beta0,
-                                                 double* __restrict__ ccell, double* part)
+__global__ __launch_bounds__(kBlock) void k_fill(Dims d, int lz, double h, int geometry,
+                                                 const double* __restrict__ tab, int n1d, double dr, double cx0,
+                                                 double cy0, double cz0, const double* __restrict__ rho,
+                                                 double* __restrict__ beta0, double* __restrict__ ccell, double* part)
 {
     __shared__ double sh[kBlock / kWave];
-    const long long n = d.n();
+    MP_ZCOL
     double bad = 0.0;
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
-         q += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_ijk(d, q, i, j, k);
+    for (int k = z0; col && k < z1; k++) {
+        const long long q = ((long long)k * d.ny + j) * d.nx + i;
         double b;
         if (geometry == 0) {
             b = tab[k];
@@ -169,16 +190,15 @@ __global__ __launch_bounds__(kBlock) void k_fill(Dims d, double h, int geometry,
         ccell[q] = c;
         if (!(rq > 0.0) || !isfinite(rq) || !isfinite(c) || !(b > 0.0)) bad += 1.0;
     }
-    double s = block_sum(bad, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    zpart_store(part, block_sum(bad, sh));
 }
 
 void launch_fill(const Dims& d, double h, int geometry, const double* tab, int n1d, double dr, double cx0, double cy0,
-                 double cz0, const double* rho, double* beta0, double* ccell, double* partials, int nb,
-                 hipStream_t s)
+                 double cz0, const double* rho, double* beta0, double* ccell, double* partials, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(kBlock), 0, s, d, h, geometry, tab, n1d, dr, cx0, cy0, cz0, rho, beta0,
-                       ccell, partials);
+    const ShapeZ sh = zmarch(d.nx, d.ny, d.nz, kZBlocks);
+    hipLaunchKernelGGL(k_fill, sh.grid, sh.block, 0, s, d, sh.lz, h, geometry, tab, n1d, dr, cx0, cy0, cz0, rho,
+                       beta0, ccell, partials);
 }
 
 __device__ __forceinline__ double harmonic(double a, double b) { return 2.0 * a * b / (a + b); }
@@ -206,10 +226,9 @@ __global__ __launch_bounds__(kBlock) void k_faces_from_cells(Dims d, const doubl
                                                              double* __restrict__ ex, double* __restrict__ ey,
                                                              double* __restrict__ ez)
 {
-    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (q >= d.n()) return;
-    int i, j, k;
-    cell_ijk(d, q, i, j, k);
+    MP_IJK3
+    if (i >= d.nx || j >= d.ny || k >= d.nz) return;
+    const long long q = ((long long)k * d.ny + j) * d.nx + i;
     const Nbr b = neighbours(d, q, i, j, k);
     const double c0 = cc[q];
     const double fx = (i > 0 || d.px) ? harmonic(cc[b.xm], c0) : 0.0;
@@ -238,11 +257,12 @@ void launch_faces_from_cells(const Dims& d, const double* ccell, double* c64x, d
                              float* c32x, float* c32y, float* c32z, double* ex, double* ey, double* ez,
                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_faces_from_cells, dim3(grid1(d.n())), dim3(kBlock), 0, s, d, ccell, c64x, c64y, c64z, c32x,
-                       c32y, c32z, ex, ey, ez);
+    const Shape3 sh = cells3(d.nx, d.ny, d.nz);
+    hipLaunchKernelGGL(k_faces_from_cells, sh.grid, sh.block, 0, s, d, ccell, c64x, c64y, c64z, c32x, c32y, c32z, ex,
+                       ey, ez);
 }
 
-__global__ __launch_bounds__(kBlock) void k_import_faces(Dims d, const double* __restrict__ ex,
+__global__ __launch_bounds__(kBlock) void k_import_faces(Dims d, int lz, const double* __restrict__ ex,
                                                          const double* __restrict__ ey, const double* __restrict__ ez,
                                                          double* __restrict__ c64x, double* __restrict__ c64y,
                                                          double* __restrict__ c64z, float* __restrict__ c32x,
@@ -250,12 +270,10 @@ __global__ __launch_bounds__(kBlock) void k_import_faces(Dims d, const double* _
                                                          double* part)
 {
     __shared__ double sh[kBlock / kWave];
-    const long long n = d.n();
+    MP_ZCOL
     double bad = 0.0;
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
-         q += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_ijk(d, q, i, j, k);
+    for (int k = z0; col && k < z1; k++) {
+        const long long q = ((long long)k * d.ny + j) * d.nx + i;
         const ExtIdx e = ext_low(d, i, j, k);
         const double fx = (i > 0 || d.px) ? ex[e.xl] : 0.0;
         const double fy = (j > 0 || d.py) ? ey[e.yl] : 0.0;
@@ -271,15 +289,15 @@ __global__ __launch_bounds__(kBlock) void k_import_faces(Dims d, const double* _
             c32z[q] = (float)fz;
         }
     }
-    double s = block_sum(bad, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    zpart_store(part, block_sum(bad, sh));
 }
 
 void launch_import_faces(const Dims& d, const double* ex, const double* ey, const double* ez, double* c64x,
-                         double* c64y, double* c64z, float* c32x, float* c32y, float* c32z, double* partials, int nb,
+                         double* c64y, double* c64z, float* c32x, float* c32y, float* c32z, double* partials,
                          hipStream_t s)
 {
-    hipLaunchKernelGGL(k_import_faces, dim3(nb), dim3(kBlock), 0, s, d, ex, ey, ez, c64x, c64y, c64z, c32x, c32y,
+    const ShapeZ sh = zmarch(d.nx, d.ny, d.nz, kZBlocks);
+    hipLaunchKernelGGL(k_import_faces, sh.grid, sh.block, 0, s, d, sh.lz, ex, ey, ez, c64x, c64y, c64z, c32x, c32y,
                        c32z, partials);
 }
 
@@ -292,11 +310,11 @@ __global__ __launch_bounds__(kBlock) void k_coef_restrict(Dims f, const Tin* __r
                                                           Tout* __restrict__ cz)
 {
     const int nxc = f.nx / 2, nyc = f.ny / 2, nzc = f.nz / 2;
-    const long long nc = (long long)nxc * nyc * nzc;
-    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (q >= nc) return;
-    const long long t = q / nxc;
-    const int I = (int)(q - t * nxc), K = (int)(t / nyc), J = (int)(t - (long long)K * nyc);
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (I >= nxc || J >= nyc || K >= nzc) return;
+    const long long q = ((long long)K * nyc + J) * nxc + I;
     const long long sy = f.nx, sz = (long long)f.nx * f.ny;
     const long long base = (long long)(2 * K) * sz + (long long)(2 * J) * sy + 2 * I;
     const double ax = (double)fx[base] + (double)fx[base + sy] + (double)fx[base + sz] + (double)fx[base + sy + sz];
@@ -311,9 +329,8 @@ template <typename Tin, typename Tout>
 void launch_coef_restrict(const Dims& fine, const Tin* fx, const Tin* fy, const Tin* fz, Tout* cx, Tout* cy,
                           Tout* cz, hipStream_t s)
 {
-    const long long nc = (long long)(fine.nx / 2) * (fine.ny / 2) * (fine.nz / 2);
-    hipLaunchKernelGGL((k_coef_restrict<Tin, Tout>), dim3(grid1(nc)), dim3(kBlock), 0, s, fine, fx, fy, fz, cx, cy,
-                       cz);
+    const Shape3 sh = cells3(fine.nx / 2, fine.ny / 2, fine.nz / 2);
+    hipLaunchKernelGGL((k_coef_restrict<Tin, Tout>), sh.grid, sh.block, 0, s, fine, fx, fy, fz, cx, cy, cz);
 }
 
 template void launch_coef_restrict<double, double>(const Dims&, const double*, const double*, const double*, double*,
@@ -327,7 +344,7 @@ template void launch_coef_restrict<float, float>(const Dims&, const float*, cons
 
 // beta0 on a face: arithmetic mean of the two cells.
 // b = beta0 S - D(beta0 U): minus the MAC right-hand side of Sec. 3.2 Steps 3/7.
-__global__ __launch_bounds__(kBlock) void k_mac_rhs(Dims d, double inv_h, const double* __restrict__ beta0,
+__global__ __launch_bounds__(kBlock) void k_mac_rhs(Dims d, int lz, double inv_h, const double* __restrict__ beta0,
                                                     const double* __restrict__ ux, const double* __restrict__ uy,
                                                     const double* __restrict__ uz, const double* __restrict__ S,
                                                     double* __restrict__ b, double* part,
@@ -337,12 +354,10 @@ __global__ __launch_bounds__(kBlock) void k_mac_rhs(Dims d, double inv_h, const 
     // shift != nullptr: no write, partials = sum (b - shift[0])^2.
     const double sh0 = shift ? shift[0] : 0.0;
     __shared__ double sh[kBlock / kWave];
-    const long long n = d.n();
+    MP_ZCOL
     double acc = 0.0;
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
-         q += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_ijk(d, q, i, j, k);
+    for (int k = z0; col && k < z1; k++) {
+        const long long q = ((long long)k * d.ny + j) * d.nx + i;
         const Nbr nb = neighbours(d, q, i, j, k);
         const ExtIdx e = ext_low(d, i, j, k);
         const double b0 = beta0[q];
@@ -368,22 +383,22 @@ __global__ __launch_bounds__(kBlock) void k_mac_rhs(Dims d, double inv_h, const 
             acc += v;
         }
     }
-    double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    zpart_store(part, block_sum(acc, sh));
 }
 
 void launch_mac_rhs(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
-                    const double* uz, const double* S, double* b, double* partials, int nb, hipStream_t s)
+                    const double* uz, const double* S, double* b, double* partials, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mac_rhs, dim3(nb), dim3(kBlock), 0, s, d, inv_h, beta0, ux, uy, uz, S, b, partials,
+    const ShapeZ sh = zmarch(d.nx, d.ny, d.nz, kZBlocks);
+    hipLaunchKernelGGL(k_mac_rhs, sh.grid, sh.block, 0, s, d, sh.lz, inv_h, beta0, ux, uy, uz, S, b, partials,
                        (const double*)nullptr);
 }
 
 void launch_rhs_defect(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
-                       const double* uz, const double* S, const double* shift, double* partials, int nb,
-                       hipStream_t s)
+                       const double* uz, const double* S, const double* shift, double* partials, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_mac_rhs, dim3(nb), dim3(kBlock), 0, s, d, inv_h, beta0, ux, uy, uz, S, (double*)nullptr,
+    const ShapeZ sh = zmarch(d.nx, d.ny, d.nz, kZBlocks);
+    hipLaunchKernelGGL(k_mac_rhs, sh.grid, sh.block, 0, s, d, sh.lz, inv_h, beta0, ux, uy, uz, S, (double*)nullptr,
                        partials, shift);
 }
 
@@ -403,10 +418,9 @@ __global__ __launch_bounds__(kBlock) void k_vel_correct(Dims d, double inv_h, co
                                                         const double* __restrict__ phi, double* __restrict__ ux,
                                                         double* __restrict__ uy, double* __restrict__ uz)
 {
-    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (q >= d.n()) return;
-    int i, j, k;
-    cell_ijk(d, q, i, j, k);
+    MP_IJK3
+    if (i >= d.nx || j >= d.ny || k >= d.nz) return;
+    const long long q = ((long long)k * d.ny + j) * d.nx + i;
     const Nbr nb = neighbours(d, q, i, j, k);
     const ExtIdx e = ext_low(d, i, j, k);
     const double b0 = beta0[q], p0 = phi[q];
@@ -418,8 +432,8 @@ __global__ __launch_bounds__(kBlock) void k_vel_correct(Dims d, double inv_h, co
 void launch_vel_correct(const Dims& d, double inv_h, const double* c64x, const double* c64y, const double* c64z,
                         const double* beta0, const double* phi, double* ux, double* uy, double* uz, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_vel_correct, dim3(grid1(d.n())), dim3(kBlock), 0, s, d, inv_h, c64x, c64y, c64z, beta0,
-                       phi, ux, uy, uz);
+    const Shape3 sh = cells3(d.nx, d.ny, d.nz);
+    hipLaunchKernelGGL(k_vel_correct, sh.grid, sh.block, 0, s, d, inv_h, c64x, c64y, c64z, beta0, phi, ux, uy, uz);
 }
 
 // Coefficient gradient on the low faces of each cell; Neumann high walls 0.
@@ -427,10 +441,9 @@ __global__ __launch_bounds__(kBlock) void k_coef_grad(Dims d, double inv_h2, con
                                                       const double* __restrict__ phi, double* __restrict__ gx,
                                                       double* __restrict__ gy, double* __restrict__ gz)
 {
-    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (q >= d.n()) return;
-    int i, j, k;
-    cell_ijk(d, q, i, j, k);
+    MP_IJK3
+    if (i >= d.nx || j >= d.ny || k >= d.nz) return;
+    const long long q = ((long long)k * d.ny + j) * d.nx + i;
     const Nbr nb = neighbours(d, q, i, j, k);
     const ExtIdx e = ext_low(d, i, j, k);
     const double l0 = lam[q], p0 = phi[q];
@@ -445,7 +458,8 @@ __global__ __launch_bounds__(kBlock) void k_coef_grad(Dims d, double inv_h2, con
 void launch_coef_grad(const Dims& d, double inv_h2, const double* lam, const double* phi, double* gx, double* gy,
                       double* gz, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_coef_grad, dim3(grid1(d.n())), dim3(kBlock), 0, s, d, inv_h2, lam, phi, gx, gy, gz);
+    const Shape3 sh = cells3(d.nx, d.ny, d.nz);
+    hipLaunchKernelGGL(k_coef_grad, sh.grid, sh.block, 0, s, d, inv_h2, lam, phi, gx, gy, gz);
 }
 
 }  // namespace mp

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace {
@@ -30,13 +31,26 @@ enum { S_MEAN = 0, S_NB2 = 1, S_RR = 2, S_DEF = 3, S_BAD = 4, S_GAUGE = 5, S_ZER
 struct Level {
     Dims d;
     double h;
-    void* x = nullptr;  // iterate (T)
-    void* b = nullptr;  // right-hand side (T)
+    void* x = nullptr;   // current iterate (T)
+    void* x2 = nullptr;  // second iterate buffer for out-of-place sweeps
+    void* b = nullptr;   // right-hand side (T)
     void* cx = nullptr;
     void* cy = nullptr;
     void* cz = nullptr;
-    bool own_x = false, own_b = false, own_c = false;
+    bool own_x = false, own_b = false, own_c = false, own_x2 = false;
+    bool fused = false;  // both colours in one launch on this level
 };
+
+constexpr long long kCoarseCells = 32768;  // levels at or below run in one workgroup
+constexpr long long kWaveBottomCells = 256;
+constexpr long long kFusedMinCells = 1LL << 22;  // fused sweeps on levels at least this large
+
+// Multigrid coarsening: halve every axis while all extents are even and
+// at least 4 (the coarsest grid keeps >= 2 cells per axis).
+inline bool can_coarsen(int nx, int ny, int nz)
+{
+    return nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0 && nx >= 4 && ny >= 4 && nz >= 4;
+}
 
 }  // namespace
 
@@ -52,7 +66,10 @@ struct mp_ctx {
     double* hscal = nullptr;  // pinned host
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> kev;
+    std::vector<double> kev_bytes;
     int kev_used = 0;
+    int nbz = 1;            // partials written by the z-marching reductions
+    int coarse_start = -1;  // first level of the single-workgroup coarse cycle, -1 = off
     bool have_coefs = false, have_base = false;
     std::string err;
 };
@@ -105,6 +122,9 @@ int check_config(const mp_config* c, mp_ctx* ctx)
     if (c->cycles_per_outer < 1 || c->cycles_per_outer > 16) return fail(ctx, MP_ERR_ARG, "bad cycles_per_outer");
     if (!(c->bottom_rtol > 0.0) || c->bottom_max_iter < 1) return fail(ctx, MP_ERR_ARG, "bad bottom settings");
     if (c->demean != 0 && c->demean != 1) return fail(ctx, MP_ERR_ARG, "demean must be 0 or 1");
+    if (c->smoother != MP_SMOOTH_AUTO && c->smoother != MP_SMOOTH_PER_COLOUR && c->smoother != MP_SMOOTH_FUSED)
+        return fail(ctx, MP_ERR_ARG, "bad smoother");
+    if (c->coarse_cycle != 0 && c->coarse_cycle != 1) return fail(ctx, MP_ERR_ARG, "coarse_cycle must be 0 or 1");
     return MP_OK;
 }
 
@@ -112,6 +132,7 @@ void free_all(mp_ctx* c)
 {
     for (auto& L : c->lv) {
         if (L.own_x) (void)hipFree(L.x);
+        if (L.own_x2) (void)hipFree(L.x2);
         if (L.own_b) (void)hipFree(L.b);
         if (L.own_c) {
             (void)hipFree(L.cx);
@@ -168,26 +189,75 @@ void timed_begin(mp_ctx* c, bool on)
     if (on && c->kev_used + 1 < (int)c->kev.size()) (void)hipEventRecord(c->kev[c->kev_used], c->stream);
 }
 
-void timed_end(mp_ctx* c, bool on)
+void timed_end(mp_ctx* c, bool on, double bytes)
 {
     if (on && c->kev_used + 1 < (int)c->kev.size()) {
         (void)hipEventRecord(c->kev[c->kev_used + 1], c->stream);
+        c->kev_bytes[c->kev_used / 2] = bytes;
         c->kev_used += 2;
     }
 }
 
+// One smoothing sweep on level l.  ec: coarse correction to add first
+// (prolongation), or nullptr.
 template <typename T>
-void smooth(mp_ctx* c, int l, bool zero_init)
+void smooth(mp_ctx* c, int l, bool zero_init, const T* ec)
 {
     Level& L = c->lv[l];
     const T h2 = (T)(L.h * L.h);
     const bool tm = c->cfg.kernel_timing && l == 0;
+    const double cells = (double)L.d.n();
+    if (L.fused) {
+        // words per cell: x_old (unless zero), b, 3 coefficients, x_new, 1/8 coarse e
+        const double words = (zero_init ? 0.0 : 1.0) + 1.0 + 3.0 + 1.0 + (ec ? 0.125 : 0.0);
+        timed_begin(c, tm);
+        mp::launch_sweep<T>(L.d, (const T*)L.x, (T*)L.x2, (const T*)L.b, (const T*)L.cx, (const T*)L.cy,
+                            (const T*)L.cz, h2, zero_init ? 1 : 0, ec, c->stream);
+        timed_end(c, tm, words * sizeof(T) * cells);
+        std::swap(L.x, L.x2);
+        return;
+    }
+    if (ec) mp::launch_prolong<T>(L.d, (T*)L.x, ec, c->stream);
     for (int colour = 0; colour < 2; colour++) {
+        // per colour: x (both colours share every line), 3 coefficients, b and x of one colour
         timed_begin(c, tm);
         mp::launch_rbgs<T>(L.d, (T*)L.x, (const T*)L.b, (const T*)L.cx, (const T*)L.cy, (const T*)L.cz, h2, colour,
                            (zero_init && colour == 0) ? 1 : 0, c->stream);
-        timed_end(c, tm);
+        timed_end(c, tm, 5.0 * sizeof(T) * cells);
     }
+}
+
+template <typename T>
+void coarse_cycle(mp_ctx* c, bool zero_init)
+{
+    mp::CoarseArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    const int l0 = c->coarse_start;
+    a.nlev = (int)c->lv.size() - l0;
+    a.px = c->d0.px;
+    a.py = c->d0.py;
+    a.pz = c->d0.pz;
+    a.nu1 = c->cfg.nu1;
+    a.nu2 = c->cfg.nu2;
+    a.zero_init = zero_init ? 1 : 0;
+    a.bottom_rtol = c->cfg.bottom_rtol;
+    a.bottom_maxit = c->cfg.bottom_max_iter;
+    for (int q = 0; q < a.nlev; q++) {
+        const Level& L = c->lv[l0 + q];
+        mp::CoarseLevel<T>& C = a.lv[q];
+        C.nx = L.d.nx;
+        C.ny = L.d.ny;
+        C.nz = L.d.nz;
+        C.h2 = (T)(L.h * L.h);
+        C.inv_h2 = (T)(1.0 / (L.h * L.h));
+        C.h2d = L.h * L.h;
+        C.x = (T*)L.x;
+        C.b = (T*)L.b;
+        C.cx = (const T*)L.cx;
+        C.cy = (const T*)L.cy;
+        C.cz = (const T*)L.cz;
+    }
+    mp::launch_coarse_cycle<T>(a, c->stream);
 }
 
 template <typename T>
@@ -195,6 +265,10 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
 {
     Level& L = c->lv[l];
     const int nlev = (int)c->lv.size();
+    if (l == c->coarse_start) {
+        coarse_cycle<T>(c, zero_init);
+        return;
+    }
     if (l == nlev - 1) {
         mp::launch_bottom<T>(L.d, (const T*)L.b, (T*)L.x, (const T*)L.cx, (const T*)L.cy, (const T*)L.cz, L.h * L.h,
                              c->cfg.bottom_rtol, c->cfg.bottom_max_iter, zero_init ? 0 : 1, c->bottom_work,
@@ -202,13 +276,16 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
         return;
     }
     if (zero_init && c->cfg.nu1 == 0) (void)hipMemsetAsync(L.x, 0, sizeof(T) * L.d.n(), c->stream);
-    for (int s = 0; s < c->cfg.nu1; s++) smooth<T>(c, l, zero_init && s == 0);
+    for (int s = 0; s < c->cfg.nu1; s++) smooth<T>(c, l, zero_init && s == 0, (const T*)nullptr);
     Level& C = c->lv[l + 1];
     mp::launch_resid_restrict<T>(L.d, (const T*)L.x, (const T*)L.b, (const T*)L.cx, (const T*)L.cy, (const T*)L.cz,
                                  (T)(1.0 / (L.h * L.h)), (T*)C.b, c->stream);
     vcycle<T>(c, l + 1, true);
-    mp::launch_prolong<T>(L.d, (T*)L.x, (const T*)C.x, c->stream);
-    for (int s = 0; s < c->cfg.nu2; s++) smooth<T>(c, l, false);
+    if (c->cfg.nu2 == 0) {
+        mp::launch_prolong<T>(L.d, (T*)L.x, (const T*)C.x, c->stream);
+        return;
+    }
+    for (int s = 0; s < c->cfg.nu2; s++) smooth<T>(c, l, false, s == 0 ? (const T*)C.x : (const T*)nullptr);
 }
 
 // Solve A phi = b64 (b64 mean-zero, ||b64||^2 = nb2 in hscal[S_NB2]).
@@ -227,7 +304,7 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
     }
     if (!use_guess) HIPCHK(c, hipMemsetAsync(phi, 0, sizeof(double) * n, c->stream));
     const bool mx = mixed(c);
-    if (!mx) c->lv[0].x = phi;
+    if (!mx) c->lv[0].x = phi;  // x2 stays the internal second buffer
     int status = MP_ERR_NOT_CONVERGED;
     double rel = 1.0;
     double hist[64];
@@ -236,9 +313,10 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
         const int p = it & 1;
         double* sp = c->dscal + S_PAIR0 + 2 * p;
         double* sq = c->dscal + S_PAIR0 + 2 * (1 - p);
+        int nbr = 0;
         mp::launch_resid64(c->d0, phi, c->b64, c->c64x, c->c64y, c->c64z, inv_h2, mx ? (float*)c->lv[0].b : nullptr,
-                           sp + 1, c->partials, nb, c->stream);
-        mp::launch_final_sum(c->partials, nb, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
+                           sp + 1, c->partials, &nbr, c->stream);
+        mp::launch_final_sum(c->partials, nbr, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
         int st = sync_read(c, S_RR, 1);
         if (st) return st;
         rel = sqrt(c->hscal[S_RR] / nb2);
@@ -274,6 +352,11 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
         } else {
             vcycle<double>(c, 0, it == 0 && !use_guess);
             vc++;
+            // out-of-place sweeps may leave the iterate in the second buffer
+            if (c->lv[0].x != (void*)phi) {
+                HIPCHK(c, hipMemcpyAsync(phi, c->lv[0].x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+                std::swap(c->lv[0].x, c->lv[0].x2);
+            }
         }
     }
     // gauge: mean(phi) = 0
@@ -296,16 +379,18 @@ void finish_timing(mp_ctx* c, mp_info* info)
     if (hipEventElapsedTime(&ms, c->ev[1], c->ev[2]) == hipSuccess) info->ms_solve = ms;
     if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) info->ms_correct = ms;
     if (c->cfg.kernel_timing) {
-        double tot = 0.0;
+        double tot = 0.0, bytes = 0.0;
         int cnt = 0;
         for (int q = 0; q + 1 < c->kev_used; q += 2) {
             if (hipEventElapsedTime(&ms, c->kev[q], c->kev[q + 1]) == hipSuccess) {
                 tot += ms;
+                bytes += c->kev_bytes[q / 2];
                 cnt++;
             }
         }
         info->smooth_ms_total = tot;
         info->smooth_launches = cnt;
+        info->smooth_bytes = bytes;
     }
 }
 
@@ -337,10 +422,12 @@ void mp_config_default(mp_config* cfg, int nx, int ny, int nz)
     cfg->nu1 = 2;
     cfg->nu2 = 2;
     cfg->cycles_per_outer = 1;
-    cfg->bottom_rtol = 1e-10;
+    cfg->bottom_rtol = 1e-8;
     cfg->bottom_max_iter = 400;
     cfg->demean = 1;
     cfg->kernel_timing = 0;
+    cfg->smoother = MP_SMOOTH_AUTO;
+    cfg->coarse_cycle = 1;
     cfg->stream = nullptr;
     cfg->device = 0;
 }
@@ -355,7 +442,7 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
     // bottom size check (host only)
     {
         int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
-        while (nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0 && nx >= 8 && ny >= 8 && nz >= 8) {
+        while (can_coarsen(nx, ny, nz)) {
             nx /= 2;
             ny /= 2;
             nz /= 2;
@@ -384,7 +471,8 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
     c->beta0 = dalloc<double>(c->n0, e), good &= ok(c->beta0);
     c->ccell = dalloc<double>(c->n0, e), good &= ok(c->ccell);
     c->b64 = dalloc<double>(c->n0, e), good &= ok(c->b64);
-    c->partials = dalloc<double>(4 * mp::kMaxRedBlocks, e), good &= ok(c->partials);
+    c->nbz = mp::zred_blocks(c->d0);
+    c->partials = dalloc<double>(c->nbz > mp::kMaxRedBlocks ? c->nbz : mp::kMaxRedBlocks, e), good &= ok(c->partials);
     c->dscal = dalloc<double>(kScal, e), good &= ok(c->dscal);
     // levels
     Dims d = c->d0;
@@ -423,17 +511,44 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
             L.cz = c->c64z;
         }
         c->lv.push_back(L);
-        if (!(d.nx % 2 == 0 && d.ny % 2 == 0 && d.nz % 2 == 0 && d.nx >= 8 && d.ny >= 8 && d.nz >= 8)) break;
+        if (!can_coarsen(d.nx, d.ny, d.nz)) break;
         d = Dims{d.nx / 2, d.ny / 2, d.nz / 2, d.px, d.py, d.pz};
         h *= 2.0;
     }
     c->bottom_work = dalloc<double>(7 * c->lv.back().d.n(), e), good &= ok(c->bottom_work);
+    // single-workgroup coarse cycle: trailing levels of <= kCoarseCells cells,
+    // when the bottom fits one wavefront and there is more than one level
+    {
+        const int nlev = (int)c->lv.size();
+        c->coarse_start = -1;
+        if (cfg->coarse_cycle && nlev >= 2 && c->lv.back().d.n() <= kWaveBottomCells) {
+            int lc = nlev - 1;
+            while (lc > 0 && c->lv[lc - 1].d.n() <= kCoarseCells && nlev - (lc - 1) <= mp::kMaxCoarse) lc--;
+            if (lc == 0) lc = 1;  // the finest level keeps its own launches (its iterate may be the caller's)
+            c->coarse_start = lc;
+        }
+        for (int l = 0; l < nlev - 1; l++) {
+            Level& L = c->lv[l];
+            if (c->coarse_start >= 0 && l >= c->coarse_start) break;
+            L.fused = mp::sweep_supported(L.d) &&
+                      (cfg->smoother == MP_SMOOTH_FUSED ||
+                       (cfg->smoother == MP_SMOOTH_AUTO && L.d.n() >= kFusedMinCells));
+            if (L.fused) {
+                void* p = nullptr;
+                e = hipMalloc(&p, tsz * L.d.n());
+                good &= e == hipSuccess;
+                L.x2 = p;
+                L.own_x2 = true;
+            }
+        }
+    }
     if (good && hipHostMalloc((void**)&c->hscal, sizeof(double) * kScal, hipHostMallocDefault) != hipSuccess)
         good = false;
     for (auto& ev : c->ev)
         if (good && hipEventCreate(&ev) != hipSuccess) good = false;
     if (good && cfg->kernel_timing) {
         c->kev.resize(2048);
+        c->kev_bytes.assign(1024, 0.0);
         for (auto& ev : c->kev)
             if (good && hipEventCreate(&ev) != hipSuccess) good = false;
     }
@@ -489,11 +604,11 @@ int mp_map_base_state(mp_ctx* c, int geometry, const double* beta0_1d, int n1d, 
         if (!isfinite(c0) || !isfinite(c1) || !isfinite(c2)) return fail(c, MP_ERR_ARG, "center must be finite");
     }
     (void)hipSetDevice(c->cfg.device);
-    const int nb = nblk(c);
+
     HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
     mp::launch_fill(c->d0, c->cfg.h, geometry, beta0_1d, n1d, dr, c0, c1, c2, rho, c->beta0, c->ccell, c->partials,
-                    nb, c->stream);
-    mp::launch_final_sum(c->partials, nb, c->dscal + S_BAD, 1.0, nullptr, 0.0, c->stream);
+                    c->stream);
+    mp::launch_final_sum(c->partials, c->nbz, c->dscal + S_BAD, 1.0, nullptr, 0.0, c->stream);
     Level& L0 = c->lv[0];
     const bool mx = mixed(c);
     mp::launch_faces_from_cells(c->d0, c->ccell, c->c64x, c->c64y, c->c64z, mx ? (float*)L0.cx : nullptr,
@@ -515,12 +630,12 @@ int mp_set_coefs(mp_ctx* c, const double* cx, const double* cy, const double* cz
     if (!c) return MP_ERR_ARG;
     if (!cx || !cy || !cz) return fail(c, MP_ERR_ARG, "cx, cy, cz are required");
     (void)hipSetDevice(c->cfg.device);
-    const int nb = nblk(c);
+
     Level& L0 = c->lv[0];
     const bool mx = mixed(c);
     mp::launch_import_faces(c->d0, cx, cy, cz, c->c64x, c->c64y, c->c64z, mx ? (float*)L0.cx : nullptr,
-                            mx ? (float*)L0.cy : nullptr, mx ? (float*)L0.cz : nullptr, c->partials, nb, c->stream);
-    mp::launch_final_sum(c->partials, nb, c->dscal + S_BAD, 1.0, nullptr, 0.0, c->stream);
+                            mx ? (float*)L0.cy : nullptr, mx ? (float*)L0.cz : nullptr, c->partials, c->stream);
+    mp::launch_final_sum(c->partials, c->nbz, c->dscal + S_BAD, 1.0, nullptr, 0.0, c->stream);
     build_pyramid(c);
     int st = sync_read(c, S_BAD, 1);
     if (st) return st;
@@ -532,12 +647,13 @@ int mp_set_coefs(mp_ctx* c, const double* cx, const double* cy, const double* cz
     return MP_OK;
 }
 
-// Prepare b64 from its raw form already in b64 (sum in partials): mean -> S_MEAN,
-// remove it (demean) and ||b||^2 -> S_NB2, rms -> first scale pair.
-static int finish_rhs(mp_ctx* c, int nb)
+// Prepare b64 from its raw form already in b64 (nb_sum partial sums in
+// partials): mean -> S_MEAN, remove it and ||b||^2 -> S_NB2, rms -> first
+// scale pair (nb: blocks of the grid-stride pass).
+static int finish_rhs(mp_ctx* c, int nb_sum, int nb)
 {
     const long long n = c->n0;
-    mp::launch_final_sum(c->partials, nb, c->dscal + S_MEAN, 1.0 / (double)n, nullptr, 0.0, c->stream);
+    mp::launch_final_sum(c->partials, nb_sum, c->dscal + S_MEAN, 1.0 / (double)n, nullptr, 0.0, c->stream);
     mp::launch_sub_mean_sumsq(c->b64, n, c->dscal + S_MEAN, c->partials, nb, c->stream);
     mp::launch_final_sum(c->partials, nb, c->dscal + S_NB2, 1.0, c->dscal + S_PAIR0, (double)n, c->stream);
     int st = sync_read(c, S_MEAN, 2);
@@ -565,8 +681,8 @@ int mp_mac_project(mp_ctx* c, double* ux, double* uy, double* uz, const double* 
     const int nb = nblk(c);
     const double inv_h = 1.0 / c->cfg.h;
     HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-    mp::launch_mac_rhs(c->d0, inv_h, c->beta0, ux, uy, uz, S, c->b64, c->partials, nb, c->stream);
-    int st = finish_rhs(c, nb);
+    mp::launch_mac_rhs(c->d0, inv_h, c->beta0, ux, uy, uz, S, c->b64, c->partials, c->stream);
+    int st = finish_rhs(c, c->nbz, nb);
     if (st) return st;
     if (info) {
         info->rhs_norm = sqrt(c->hscal[S_NB2]);
@@ -577,8 +693,8 @@ int mp_mac_project(mp_ctx* c, double* ux, double* uy, double* uz, const double* 
     if (solve_st != MP_OK && solve_st != MP_ERR_NOT_CONVERGED) return solve_st;
     HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
     mp::launch_vel_correct(c->d0, inv_h, c->c64x, c->c64y, c->c64z, c->beta0, phi, ux, uy, uz, c->stream);
-    mp::launch_rhs_defect(c->d0, inv_h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, c->partials, nb, c->stream);
-    mp::launch_final_sum(c->partials, nb, c->dscal + S_DEF, 1.0, nullptr, 0.0, c->stream);
+    mp::launch_rhs_defect(c->d0, inv_h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, c->partials, c->stream);
+    mp::launch_final_sum(c->partials, c->nbz, c->dscal + S_DEF, 1.0, nullptr, 0.0, c->stream);
     HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
     st = sync_read(c, S_DEF, 1);
     if (st) return st;
@@ -601,7 +717,7 @@ int mp_solve(mp_ctx* c, const double* rhs, double* x, int use_initial_guess, mp_
     const int nb = nblk(c);
     HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
     mp::launch_neg_copy_sum(rhs, c->b64, c->n0, c->partials, nb, c->stream);
-    int st = finish_rhs(c, nb);
+    int st = finish_rhs(c, nb, nb);
     if (st) return st;
     if (info) {
         info->rhs_norm = sqrt(c->hscal[S_NB2]);

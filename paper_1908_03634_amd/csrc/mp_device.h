@@ -100,19 +100,110 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Block sum in a fixed order; every thread receives the same value.
-// `sh` must hold blockDim.x / 64 doubles.
+// Wavefront sum whose value is lane 0's result broadcast to every lane, so all
+// lanes take identical branches on it.
+__device__ __forceinline__ double wave_sum_bcast(double v)
+{
+    v = wave_sum(v);
+    return __shfl(v, 0, kWave);
+}
+
+// Block sum in a fixed order; every thread receives the same value.  Works
+// for 1D, 2D and 3D blocks whose thread count is a multiple of 64 (full
+// wavefronts).  `sh` must hold (threads per block) / 64 doubles.
 __device__ __forceinline__ double block_sum(double v, double* sh)
 {
     v = wave_sum(v);
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int nw = (blockDim.x + kWave - 1) / kWave;
+    const int t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const int nthr = blockDim.x * blockDim.y * blockDim.z;
+    const int lane = t & (kWave - 1), w = t / kWave;
+    const int nw = (nthr + kWave - 1) / kWave;
     __syncthreads();
     if (lane == 0) sh[w] = v;
     __syncthreads();
     double s = 0.0;
     for (int q = 0; q < nw; q++) s += sh[q];
     return s;
+}
+
+// ---------------------------------------------------------------------------
+// Per-cell multigrid operations.  Every kernel variant (one launch per colour,
+// the single-workgroup coarse cycle, the fused sweep) evaluates a cell with
+// exactly this arithmetic, so the variants agree bit for bit.
+
+// Gauss-Seidel value of cell q from its neighbours in x:
+//   (h^2 b_q + sum_f c_f x_nb(f)) / sum_f c_f,
+// or the old value when the cell has no coupling.
+template <typename T>
+__device__ __forceinline__ T gs_value(T c0, T c1, T c2, T c3, T c4, T c5, T xm, T xp, T ym, T yp, T zm, T zp, T bq,
+                                      T h2, T old)
+{
+    const T csum = ((((c0 + c1) + c2) + c3) + c4) + c5;
+    T s = c0 * xm;
+    s = fma(c1, xp, s);
+    s = fma(c2, ym, s);
+    s = fma(c3, yp, s);
+    s = fma(c4, zm, s);
+    s = fma(c5, zp, s);
+    return csum > T(0) ? fma(h2, bq, s) / csum : old;
+}
+
+// One cell of one colour of red-black Gauss-Seidel on A x = b, in place.
+// (p, j, k): pair index along x, row, plane; the cell updated is the one of
+// the pair with (i + j + k) % 2 == colour.  zero_init: x is zero on entry;
+// neighbours are not read and the other cell of the pair is cleared.
+template <typename T>
+__device__ __forceinline__ void rbgs_cell(const Dims& d, T* __restrict__ x, const T* __restrict__ b,
+                                          const T* __restrict__ cx, const T* __restrict__ cy,
+                                          const T* __restrict__ cz, T h2, int colour, int zero_init, int p, int j,
+                                          int k)
+{
+    const int par = (j + k + colour) & 1;
+    const int i = 2 * p + par;
+    const long long rbase = ((long long)k * d.ny + j) * d.nx;
+    if (zero_init) {
+        const int io = 2 * p + (1 - par);
+        if (io < d.nx) x[rbase + io] = T(0);
+    }
+    if (i >= d.nx) return;
+    const long long q = rbase + i;
+    const Nbr nb = neighbours(d, q, i, j, k);
+    const T c0 = cx[q], c1 = ld_or0(cx, nb.cxp), c2 = cy[q], c3 = ld_or0(cy, nb.cyp), c4 = cz[q],
+            c5 = ld_or0(cz, nb.czp);
+    if (zero_init)
+        x[q] = gs_value<T>(c0, c1, c2, c3, c4, c5, T(0), T(0), T(0), T(0), T(0), T(0), b[q], h2, T(0));
+    else
+        x[q] = gs_value<T>(c0, c1, c2, c3, c4, c5, x[nb.xm], x[nb.xp], x[nb.ym], x[nb.yp], x[nb.zm], x[nb.zp], b[q],
+                           h2, x[q]);
+}
+
+// Residual r = b - A x at one cell.
+template <typename T>
+__device__ __forceinline__ T resid_cell(const Dims& d, const T* __restrict__ x, const T* __restrict__ b,
+                                        const T* __restrict__ cx, const T* __restrict__ cy, const T* __restrict__ cz,
+                                        T inv_h2, int i, int j, int k)
+{
+    const long long q = ((long long)k * d.ny + j) * d.nx + i;
+    const Nbr nb = neighbours(d, q, i, j, k);
+    T csum, cv;
+    stencil_sums<T>(cx, cy, cz, x, q, nb, csum, cv);
+    return b[q] - (csum * x[q] - cv) * inv_h2;
+}
+
+// Coarse right-hand side of coarse cell (I,J,K): mean of the 8 fine residuals.
+template <typename T>
+__device__ __forceinline__ T restrict_cell(const Dims& d, const T* __restrict__ x, const T* __restrict__ b,
+                                           const T* __restrict__ cx, const T* __restrict__ cy,
+                                           const T* __restrict__ cz, T inv_h2, int I, int J, int K)
+{
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int bb = 0; bb < 2; bb++)
+#pragma unroll
+            for (int a = 0; a < 2; a++) acc += resid_cell<T>(d, x, b, cx, cy, cz, inv_h2, 2 * I + a, 2 * J + bb, 2 * K + c);
+    return T(0.125) * acc;
 }
 
 }  // namespace mp

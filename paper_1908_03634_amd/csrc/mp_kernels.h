@@ -7,11 +7,16 @@ namespace mp {
 
 struct Dims;
 
-// Largest number of blocks a reduction kernel uses (size of a partials slot).
-constexpr int kMaxRedBlocks = 2048;
 constexpr int kBlock = 256;
+// Reductions write one partial per block; z-marching launches are shaped to
+// stay near this many blocks (see mp_launch.h).
+constexpr long long kZBlocks = 8192;
+// Partial sums of 1D grid-stride reductions use at most this many blocks.
+constexpr int kMaxRedBlocks = 2048;
 
 int red_blocks(long long n);
+// Number of partials written by the z-marching reductions on these dims.
+int zred_blocks(const Dims& d);
 
 // ---- reductions ---------------------------------------------------------
 // out[0] = scale * sum(partials[0..nb)); when rms_out != nullptr also
@@ -29,19 +34,18 @@ void launch_neg_copy_sum(const double* rhs, double* b, long long n, double* part
 
 // ---- mapping and coefficients ---------------------------------------------
 // beta0 on cells (planar injection or spherical linear interpolation) and
-// ccell = beta0 / rho; partials = per-block count of invalid cells.
+// ccell = beta0 / rho; partials (zred_blocks) = per-block count of invalid cells.
 void launch_fill(const Dims& d, double h, int geometry, const double* tab, int n1d, double dr, double cx0, double cy0,
-                 double cz0, const double* rho, double* beta0, double* ccell, double* partials, int nb,
-                 hipStream_t s);
+                 double cz0, const double* rho, double* beta0, double* ccell, double* partials, hipStream_t s);
 // Internal low-face coefficients from cell values (harmonic mean), FP64 and
 // optionally FP32; optional external FP64 face arrays (nullptr to skip).
 void launch_faces_from_cells(const Dims& d, const double* ccell, double* c64x, double* c64y, double* c64z,
                              float* c32x, float* c32y, float* c32z, double* ex, double* ey, double* ez,
                              hipStream_t s);
-// Internal low-face coefficients from external face arrays; partials counts
-// invalid (negative or non-finite) entries.
+// Internal low-face coefficients from external face arrays; partials
+// (zred_blocks) counts invalid (negative or non-finite) entries.
 void launch_import_faces(const Dims& d, const double* ex, const double* ey, const double* ez, double* c64x,
-                         double* c64y, double* c64z, float* c32x, float* c32y, float* c32z, double* partials, int nb,
+                         double* c64y, double* c64z, float* c32x, float* c32y, float* c32z, double* partials,
                          hipStream_t s);
 // Coarse low-face coefficients: mean of the 4 fine faces covering each face.
 template <typename Tin, typename Tout>
@@ -49,14 +53,14 @@ void launch_coef_restrict(const Dims& fine, const Tin* fx, const Tin* fy, const 
                           Tout* cz, hipStream_t s);
 
 // ---- projection ------------------------------------------------------------
-// b = beta0 S - D(beta0 U) (= minus the MAC right-hand side); partials = sum b.
+// b = beta0 S - D(beta0 U) (= minus the MAC right-hand side); partials
+// (zred_blocks) = sum b.
 void launch_mac_rhs(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
-                    const double* uz, const double* S, double* b, double* partials, int nb, hipStream_t s);
-// partials = per-block sum of (beta0 S - D(beta0 U) - shift[0])^2 (no write):
-// the divergence defect of a projected velocity.
+                    const double* uz, const double* S, double* b, double* partials, hipStream_t s);
+// partials (zred_blocks) = per-block sum of (beta0 S - D(beta0 U) - shift[0])^2
+// (no write): the divergence defect of a projected velocity.
 void launch_rhs_defect(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
-                       const double* uz, const double* S, const double* shift, double* partials, int nb,
-                       hipStream_t s);
+                       const double* uz, const double* S, const double* shift, double* partials, hipStream_t s);
 // U <- U - (c/beta0_f) G phi on every non-wall face (in place).
 void launch_vel_correct(const Dims& d, double inv_h, const double* c64x, const double* c64y, const double* c64z,
                         const double* beta0, const double* phi, double* ux, double* uy, double* uz, hipStream_t s);
@@ -65,9 +69,17 @@ void launch_coef_grad(const Dims& d, double inv_h2, const double* lam, const dou
                       double* gz, hipStream_t s);
 
 // ---- multigrid -----------------------------------------------------------
+// One colour of red-black Gauss-Seidel, in place (reference / fallback).
 template <typename T>
 void launch_rbgs(const Dims& d, T* phi, const T* rhs, const T* cx, const T* cy, const T* cz, T h2, int colour,
                  int zero_init, hipStream_t s);
+// Both colours in one launch, out of place (xo -> xn).  zero_init: xo is
+// taken as zero.  ec: coarse correction added to xo while reading
+// (prolongation fused into the sweep), or nullptr.
+template <typename T>
+void launch_sweep(const Dims& d, const T* xo, T* xn, const T* b, const T* cx, const T* cy, const T* cz, T h2,
+                  int zero_init, const T* ec, hipStream_t s);
+bool sweep_supported(const Dims& d);
 template <typename T>
 void launch_resid_restrict(const Dims& fine, const T* phi, const T* rhs, const T* cx, const T* cy, const T* cz,
                            T inv_h2, T* coarse_rhs, hipStream_t s);
@@ -79,14 +91,41 @@ template <typename T>
 void launch_bottom(const Dims& d, const T* rhs, T* phi, const T* cx, const T* cy, const T* cz, double h2, double rtol,
                    int maxit, int use_x0, double* work, hipStream_t s);
 
+// The coarse end of a V-cycle in one workgroup (levels lv[0..nlev), the last
+// one solved by one-wavefront BiCGStab; it must hold <= 256 cells).
+constexpr int kMaxCoarse = 8;
+template <typename T>
+struct CoarseLevel {
+    int nx, ny, nz;
+    T h2, inv_h2;  // smoother / residual scalars in the level's precision
+    double h2d;    // h^2 for the FP64 bottom solve
+    T* x;
+    T* b;
+    const T* cx;
+    const T* cy;
+    const T* cz;
+};
+template <typename T>
+struct CoarseArgs {
+    int nlev;
+    int px, py, pz;
+    int nu1, nu2;
+    int zero_init;  // x of lv[0] is zero on entry
+    double bottom_rtol;
+    int bottom_maxit;
+    CoarseLevel<T> lv[kMaxCoarse];
+};
+template <typename T>
+void launch_coarse_cycle(const CoarseArgs<T>& a, hipStream_t s);
+
 // ---- FP64 level-0 operations --------------------------------------------
 // y = M x = -(A x).
 void launch_apply64(const Dims& d, const double* x, const double* cx, const double* cy, const double* cz,
                     double inv_h2, double* y, hipStream_t s);
-// r = b - A phi; partials = per-block sum r^2; when r32 != nullptr,
-// r32 = float(r * inv_s[0]).
+// r = b - A phi; partials (*nb_out of them) = per-block sum r^2; when
+// r32 != nullptr, r32 = float(r * inv_s[0]).
 void launch_resid64(const Dims& d, const double* phi, const double* b, const double* cx, const double* cy,
-                    const double* cz, double inv_h2, float* r32, const double* inv_s, double* partials, int nb,
+                    const double* cz, double inv_h2, float* r32, const double* inv_s, double* partials, int* nb_out,
                     hipStream_t s);
 // phi += s[0] * e.
 void launch_ir_update(long long n, double* phi, const float* e, const double* s, hipStream_t st);

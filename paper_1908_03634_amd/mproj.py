@@ -53,6 +53,8 @@ class Config(ctypes.Structure):
         ("bottom_max_iter", ctypes.c_int),
         ("demean", ctypes.c_int),
         ("kernel_timing", ctypes.c_int),
+        ("smoother", ctypes.c_int),
+        ("coarse_cycle", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("device", ctypes.c_int),
     ]
@@ -72,6 +74,7 @@ class Info(ctypes.Structure):
         ("ms_rhs", ctypes.c_double), ("ms_solve", ctypes.c_double), ("ms_correct", ctypes.c_double),
         ("smooth_ms_total", ctypes.c_double),
         ("smooth_launches", ctypes.c_int),
+        ("smooth_bytes", ctypes.c_double),
         ("flags", ctypes.c_int),
     ]
 
@@ -81,7 +84,7 @@ class Info(ctypes.Structure):
                     rel_resid=self.rel_resid, div_defect=self.div_defect, rhs_norm=self.rhs_norm,
                     rhs_mean=self.rhs_mean, resid_hist=list(self.resid_hist[:n]), ms_rhs=self.ms_rhs,
                     ms_solve=self.ms_solve, ms_correct=self.ms_correct, smooth_ms_total=self.smooth_ms_total,
-                    smooth_launches=self.smooth_launches, flags=self.flags)
+                    smooth_launches=self.smooth_launches, smooth_bytes=self.smooth_bytes, flags=self.flags)
 
 
 # Every exported symbol of include/mproj.h.
@@ -140,8 +143,8 @@ class Context:
     hierarchy on one device and stream."""
 
     def __init__(self, nx, ny, nz, h=None, bc=(PERIODIC, PERIODIC, NEUMANN), precision="mixed", rtol=1e-10,
-                 max_outer=100, nu1=2, nu2=2, cycles_per_outer=1, bottom_rtol=1e-10, bottom_max_iter=400,
-                 demean=True, kernel_timing=False, device=None, stream=None):
+                 max_outer=100, nu1=2, nu2=2, cycles_per_outer=1, bottom_rtol=1e-8, bottom_max_iter=400,
+                 demean=True, kernel_timing=False, smoother="auto", coarse_cycle=True, device=None, stream=None):
         self.lib = load_library()
         if not torch.cuda.is_available():
             raise MprojError(2, "no GPU visible to torch")
@@ -160,6 +163,8 @@ class Context:
         cfg.bottom_max_iter = bottom_max_iter
         cfg.demean = 1 if demean else 0
         cfg.kernel_timing = 1 if kernel_timing else 0
+        cfg.smoother = {"auto": 0, "per_colour": 1, "fused": 2}[smoother]
+        cfg.coarse_cycle = 1 if coarse_cycle else 0
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = st
         cfg.stream = ctypes.c_void_p(st.cuda_stream)

@@ -167,3 +167,40 @@ def test_wrong_shapes_are_rejected():
     with pytest.raises(ValueError):
         ctx.solve(T(np.zeros((8, 8, 8))).float())
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("shape,bc", [((32, 32, 32), (0, 0, 1)), ((40, 24, 16), (0, 0, 1)), ((48, 48, 48), (1, 1, 1)),
+                                      ((128, 64, 64), (0, 0, 1)), ((24, 40, 32), (0, 1, 0))])
+def test_fused_sweep_is_bitwise_equal_to_per_colour_launches(precision, shape, bc):
+    """Both colours in one launch (x_old staged in LDS, red recomputed on a
+    halo ring, prolongation folded into the first post-smoothing sweep) give
+    exactly the bits of one launch per colour."""
+    nx, ny, nz = shape
+    say("fused vs per-colour", shape, bc, precision)
+    p = W.planar_problem(nz, nx=nx, ny=ny, bc=bc, contrast=1e3, seed=606)
+    outs = []
+    for sm in ("fused", "per_colour"):
+        r = gpu_project(p, precision, rtol=1e-10, smoother=sm)
+        outs.append((N(r["phi"]), N(r["uz"]), r["info"]["outer_iters"], r["info"]["resid_hist"]))
+        r["ctx"].close()
+    assert outs[0][2] == outs[1][2]
+    assert outs[0][3] == outs[1][3]
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_coarse_cycle_kernel_matches_per_level_launches(precision):
+    """The single-workgroup coarse cycle (one-wavefront BiCGStab bottom) against
+    one launch per operation on every level: same answer to the tolerance."""
+    p = W.planar_problem(64, contrast=1e4, seed=707)
+    outs = []
+    for cc in (True, False):
+        r = gpu_project(p, precision, rtol=1e-12, coarse_cycle=cc)
+        outs.append((N(r["phi"]), r["info"]))
+        r["ctx"].close()
+    say("coarse cycle steps", outs[0][1]["outer_iters"], "per-level steps", outs[1][1]["outer_iters"])
+    assert outs[0][1]["rel_resid"] <= 1e-12 and outs[1][1]["rel_resid"] <= 1e-12
+    assert rel(outs[0][0], outs[1][0]) < 1e-9
+    assert abs(outs[0][1]["outer_iters"] - outs[1][1]["outer_iters"]) <= 1
