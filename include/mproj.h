@@ -87,7 +87,7 @@ typedef struct mp_config {
                                 every level; MP_SMOOTH_FUSED: both colours in one
                                 launch wherever the grid allows.  All three give
                                 the same bits. */
-    int coarse_cycle;        /* 1: run levels of <= 32768 cells in one workgroup
+    int coarse_cycle;        /* 1: run levels of <= 4096 cells in one workgroup
                                 (bottom <= 256 cells by one wavefront); 0: one
                                 launch per operation on every level */
     void *stream;            /* hipStream_t for every launch; NULL = null stream */

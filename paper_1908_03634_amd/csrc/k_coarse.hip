@@ -157,7 +157,8 @@ __device__ void cg_smooth(const CoarseLevel<T>& L, const Dims& d, int zero_init)
     for (int colour = 0; colour < 2; colour++) {
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
             const int p = e % nxh, t = e / nxh, j = t % d.ny, k = t / d.ny;
-            rbgs_cell<T>(d, L.x, L.b, L.cx, L.cy, L.cz, L.h2, colour, zero_init && colour == 0, p, j, k);
+            rbgs_cell<T, false>(d, L.x, L.b, Coef<T>{L.cx, L.cy, L.cz, nullptr}, L.h2, colour,
+                                zero_init && colour == 0, p, j, k);
         }
         __syncthreads();
     }
@@ -184,7 +185,8 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(CoarseArgs<T> a)
         const int cnt = nxc * nyc * nzc;
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
             const int I = e % nxc, t = e / nxc, J = t % nyc, K = t / nyc;
-            a.lv[l + 1].b[e] = restrict_cell<T>(f, L.x, L.b, L.cx, L.cy, L.cz, L.inv_h2, I, J, K);
+            a.lv[l + 1].b[e] = restrict_cell<T, false>(f, L.x, L.b, Coef<T>{L.cx, L.cy, L.cz, nullptr}, L.inv_h2, I, J,
+                                                       K);
         }
         __syncthreads();
     }

@@ -19,48 +19,53 @@ namespace mp {
 
 // ------------------------------------------------------------------ smoother
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_rbgs(Dims d, T* __restrict__ x, const T* __restrict__ b,
-                                              const T* __restrict__ cx, const T* __restrict__ cy,
-                                              const T* __restrict__ cz, T h2, int colour, int zero_init)
+template <typename T, bool CELL>
+__global__ __launch_bounds__(256) void k_rbgs(Dims d, T* __restrict__ x, const T* __restrict__ b, Coef<T> C, T h2,
+                                              int colour, int zero_init)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     const int k = blockIdx.z * blockDim.z + threadIdx.z;
     if (p >= (d.nx + 1) / 2 || j >= d.ny || k >= d.nz) return;
-    rbgs_cell<T>(d, x, b, cx, cy, cz, h2, colour, zero_init, p, j, k);
+    rbgs_cell<T, CELL>(d, x, b, C, h2, colour, zero_init, p, j, k);
 }
 
 template <typename T>
-void launch_rbgs(const Dims& d, T* phi, const T* rhs, const T* cx, const T* cy, const T* cz, T h2, int colour,
-                 int zero_init, hipStream_t s)
+void launch_rbgs(const Dims& d, T* phi, const T* rhs, const Coef<T>& c, T h2, int colour, int zero_init,
+                 hipStream_t s)
 {
     const Shape3 sh = cells3((d.nx + 1) / 2, d.ny, d.nz);
-    hipLaunchKernelGGL((k_rbgs<T>), sh.grid, sh.block, 0, s, d, phi, rhs, cx, cy, cz, h2, colour, zero_init);
+    if (c.cell)
+        hipLaunchKernelGGL((k_rbgs<T, true>), sh.grid, sh.block, 0, s, d, phi, rhs, c, h2, colour, zero_init);
+    else
+        hipLaunchKernelGGL((k_rbgs<T, false>), sh.grid, sh.block, 0, s, d, phi, rhs, c, h2, colour, zero_init);
 }
 
 // --------------------------------------------------------- transfer operators
 
-template <typename T>
+template <typename T, bool CELL>
 __global__ __launch_bounds__(256) void k_resid_restrict(Dims d, const T* __restrict__ x, const T* __restrict__ b,
-                                                        const T* __restrict__ cx, const T* __restrict__ cy,
-                                                        const T* __restrict__ cz, T inv_h2, T* __restrict__ bc)
+                                                        Coef<T> C, T inv_h2, T* __restrict__ bc)
 {
     const int nxc = d.nx / 2, nyc = d.ny / 2, nzc = d.nz / 2;
     const int I = blockIdx.x * blockDim.x + threadIdx.x;
     const int J = blockIdx.y * blockDim.y + threadIdx.y;
     const int K = blockIdx.z * blockDim.z + threadIdx.z;
     if (I >= nxc || J >= nyc || K >= nzc) return;
-    bc[((long long)K * nyc + J) * nxc + I] = restrict_cell<T>(d, x, b, cx, cy, cz, inv_h2, I, J, K);
+    bc[((long long)K * nyc + J) * nxc + I] = restrict_cell<T, CELL>(d, x, b, C, inv_h2, I, J, K);
 }
 
 template <typename T>
-void launch_resid_restrict(const Dims& fine, const T* phi, const T* rhs, const T* cx, const T* cy, const T* cz,
-                           T inv_h2, T* coarse_rhs, hipStream_t s)
+void launch_resid_restrict(const Dims& fine, const T* phi, const T* rhs, const Coef<T>& c, T inv_h2, T* coarse_rhs,
+                           hipStream_t s)
 {
     const Shape3 sh = cells3(fine.nx / 2, fine.ny / 2, fine.nz / 2);
-    hipLaunchKernelGGL((k_resid_restrict<T>), sh.grid, sh.block, 0, s, fine, phi, rhs, cx, cy, cz, inv_h2,
-                       coarse_rhs);
+    if (c.cell)
+        hipLaunchKernelGGL((k_resid_restrict<T, true>), sh.grid, sh.block, 0, s, fine, phi, rhs, c, inv_h2,
+                           coarse_rhs);
+    else
+        hipLaunchKernelGGL((k_resid_restrict<T, false>), sh.grid, sh.block, 0, s, fine, phi, rhs, c, inv_h2,
+                           coarse_rhs);
 }
 
 // Fine x += coarse e of the parent cell.
@@ -210,9 +215,9 @@ void launch_bottom(const Dims& d, const T* rhs, T* phi, const T* cx, const T* cy
 
 // --------------------------------------------------------- FP64 level 0
 
-__global__ __launch_bounds__(256) void k_apply64(Dims d, const double* __restrict__ x, const double* __restrict__ cx,
-                                                 const double* __restrict__ cy, const double* __restrict__ cz,
-                                                 double inv_h2, double* __restrict__ y)
+template <bool CELL>
+__global__ __launch_bounds__(256) void k_apply64(Dims d, const double* __restrict__ x, Coef<double> C, double inv_h2,
+                                                 double* __restrict__ y)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
@@ -220,26 +225,31 @@ __global__ __launch_bounds__(256) void k_apply64(Dims d, const double* __restric
     if (i >= d.nx || j >= d.ny || k >= d.nz) return;
     const long long q = ((long long)k * d.ny + j) * d.nx + i;
     const Nbr nb = neighbours(d, q, i, j, k);
-    double csum, cv;
-    stencil_sums<double>(cx, cy, cz, x, q, nb, csum, cv);
-    y[q] = (cv - csum * x[q]) * inv_h2;
+    double c0, c1, c2, c3, c4, c5;
+    coef6<double, CELL>(C, d, q, nb, i, j, k, c0, c1, c2, c3, c4, c5);
+    // M x = -(A x) = the residual of a zero right-hand side
+    y[q] = resid_value<double>(c0, c1, c2, c3, c4, c5, x[nb.xm], x[nb.xp], x[nb.ym], x[nb.yp], x[nb.zm], x[nb.zp],
+                                x[q], 0.0, inv_h2);
 }
 
-void launch_apply64(const Dims& d, const double* x, const double* cx, const double* cy, const double* cz,
-                    double inv_h2, double* y, hipStream_t s)
+void launch_apply64(const Dims& d, const double* x, const Coef<double>& c, double inv_h2, double* y, hipStream_t s)
 {
     const Shape3 sh = cells3(d.nx, d.ny, d.nz);
-    hipLaunchKernelGGL(k_apply64, sh.grid, sh.block, 0, s, d, x, cx, cy, cz, inv_h2, y);
+    if (c.cell)
+        hipLaunchKernelGGL(k_apply64<true>, sh.grid, sh.block, 0, s, d, x, c, inv_h2, y);
+    else
+        hipLaunchKernelGGL(k_apply64<false>, sh.grid, sh.block, 0, s, d, x, c, inv_h2, y);
 }
 
 // r = b - A x for a column of lz cells per thread; the column's z-neighbours
-// and z-face coefficients stay in registers.  Same arithmetic, in the same
-// order, as stencil_sums.
+// and z-face coefficients stay in registers (in cell mode the z-face value
+// formed for the high face of one plane is the low face of the next).  Same
+// arithmetic, in the same order, as resid_cell.
+template <bool CELL>
 __global__ __launch_bounds__(256) void k_resid64(Dims d, int lz, const double* __restrict__ x,
-                                                 const double* __restrict__ b, const double* __restrict__ cx,
-                                                 const double* __restrict__ cy, const double* __restrict__ cz,
-                                                 double inv_h2, float* __restrict__ r32,
-                                                 const double* __restrict__ inv_s, double* part)
+                                                 const double* __restrict__ b, Coef<double> C, double inv_h2,
+                                                 float* __restrict__ r32, const double* __restrict__ inv_s,
+                                                 double* part)
 {
     __shared__ double sh[4];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -252,34 +262,50 @@ __global__ __launch_bounds__(256) void k_resid64(Dims d, int lz, const double* _
         const long long sy = d.nx, sz = (long long)d.nx * d.ny;
         const long long oxm = i > 0 ? -1 : (d.px ? d.nx - 1 : 0);
         const long long oxp = i < d.nx - 1 ? 1 : (d.px ? -(long long)(d.nx - 1) : 0);
-        const bool hxp = i < d.nx - 1 || d.px;
+        const bool hxm = i > 0 || d.px, hxp = i < d.nx - 1 || d.px;
         const long long oym = j > 0 ? -sy : (d.py ? (long long)(d.ny - 1) * sy : 0);
         const long long oyp = j < d.ny - 1 ? sy : (d.py ? -(long long)(d.ny - 1) * sy : 0);
-        const bool hyp = j < d.ny - 1 || d.py;
+        const bool hym = j > 0 || d.py, hyp = j < d.ny - 1 || d.py;
         long long q = (long long)z0 * sz + (long long)j * d.nx + i;
-        double xzm = z0 > 0 ? x[q - sz] : (d.pz ? x[q + (long long)(d.nz - 1) * sz] : x[q]);
+        const long long qm = z0 > 0 ? q - sz : (d.pz ? q + (long long)(d.nz - 1) * sz : q);
+        double xzm = x[qm];
         double x0 = x[q];
-        double czl = cz[q];
+        double cc0 = 0.0, czl;
+        if constexpr (CELL) {
+            cc0 = C.cell[q];
+            czl = (z0 > 0 || d.pz) ? harm(C.cell[qm], cc0) : 0.0;
+        } else {
+            czl = C.z[q];
+        }
         for (int k = z0; k < z1; k++) {
             const bool last = k == d.nz - 1;
+            const bool hzp = !last || d.pz;
             const long long qp = !last ? q + sz : (d.pz ? q - (long long)(d.nz - 1) * sz : q);
             const double xzp = x[qp];
-            const double czh = (!last || d.pz) ? cz[qp] : 0.0;
-            const double c0 = cx[q], c1 = hxp ? cx[q + oxp] : 0.0;
-            const double c2 = cy[q], c3 = hyp ? cy[q + oyp] : 0.0;
-            const double csum = ((((c0 + c1) + c2) + c3) + czl) + czh;
-            double s = c0 * x[q + oxm];
-            s = fma(c1, x[q + oxp], s);
-            s = fma(c2, x[q + oym], s);
-            s = fma(c3, x[q + oyp], s);
-            s = fma(czl, xzm, s);
-            s = fma(czh, xzp, s);
-            const double r = b[q] - (csum * x0 - s) * inv_h2;
+            double c0, c1, c2, c3, czh, ccp = 0.0;
+            if constexpr (CELL) {
+                const double* cc = C.cell;
+                ccp = cc[qp];
+                czh = hzp ? harm(cc0, ccp) : 0.0;
+                c0 = hxm ? harm(cc[q + oxm], cc0) : 0.0;
+                c1 = hxp ? harm(cc0, cc[q + oxp]) : 0.0;
+                c2 = hym ? harm(cc[q + oym], cc0) : 0.0;
+                c3 = hyp ? harm(cc0, cc[q + oyp]) : 0.0;
+            } else {
+                czh = hzp ? C.z[qp] : 0.0;
+                c0 = C.x[q];
+                c1 = hxp ? C.x[q + oxp] : 0.0;
+                c2 = C.y[q];
+                c3 = hyp ? C.y[q + oyp] : 0.0;
+            }
+            const double r = resid_value<double>(c0, c1, c2, c3, czl, czh, x[q + oxm], x[q + oxp], x[q + oym],
+                                                 x[q + oyp], xzm, xzp, x0, b[q], inv_h2);
             acc = fma(r, r, acc);
             if (r32) r32[q] = (float)(r * is);
             xzm = x0;
             x0 = xzp;
             czl = czh;
+            cc0 = ccp;
             q += sz;
         }
     }
@@ -288,16 +314,17 @@ __global__ __launch_bounds__(256) void k_resid64(Dims d, int lz, const double* _
         part[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
 }
 
-
-
-void launch_resid64(const Dims& d, const double* phi, const double* b, const double* cx, const double* cy,
-                    const double* cz, double inv_h2, float* r32, const double* inv_s, double* partials, int* nb_out,
-                    hipStream_t s)
+void launch_resid64(const Dims& d, const double* phi, const double* b, const Coef<double>& c, double inv_h2,
+                    float* r32, const double* inv_s, double* partials, int* nb_out, hipStream_t s)
 {
     const ShapeZ sh = zmarch(d.nx, d.ny, d.nz, kZBlocks);
     *nb_out = (int)sh.blocks();
-    hipLaunchKernelGGL(k_resid64, sh.grid, sh.block, 0, s, d, sh.lz, phi, b, cx, cy, cz, inv_h2, r32, inv_s,
-                       partials);
+    if (c.cell)
+        hipLaunchKernelGGL(k_resid64<true>, sh.grid, sh.block, 0, s, d, sh.lz, phi, b, c, inv_h2, r32, inv_s,
+                           partials);
+    else
+        hipLaunchKernelGGL(k_resid64<false>, sh.grid, sh.block, 0, s, d, sh.lz, phi, b, c, inv_h2, r32, inv_s,
+                           partials);
 }
 
 __global__ __launch_bounds__(256) void k_ir_update(long long n, double* __restrict__ x, const float* __restrict__ e,
@@ -315,9 +342,8 @@ void launch_ir_update(long long n, double* phi, const float* e, const double* s,
 // ------------------------------------------------------------ instantiations
 
 #define MP_INST(T)                                                                                                    \
-    template void launch_rbgs<T>(const Dims&, T*, const T*, const T*, const T*, const T*, T, int, int, hipStream_t);  \
-    template void launch_resid_restrict<T>(const Dims&, const T*, const T*, const T*, const T*, const T*, T, T*,      \
-                                           hipStream_t);                                                              \
+    template void launch_rbgs<T>(const Dims&, T*, const T*, const Coef<T>&, T, int, int, hipStream_t);                \
+    template void launch_resid_restrict<T>(const Dims&, const T*, const T*, const Coef<T>&, T, T*, hipStream_t);      \
     template void launch_prolong<T>(const Dims&, T*, const T*, hipStream_t);                                          \
     template void launch_bottom<T>(const Dims&, const T*, T*, const T*, const T*, const T*, double, double, int, int, \
                                    double*, hipStream_t);

@@ -160,7 +160,8 @@ void launch_copy(const double* src, double* dst, long long n, hipStream_t s)
 __global__ __launch_bounds__(kBlock) void k_fill(Dims d, int lz, double h, int geometry,
                                                  const double* __restrict__ tab, int n1d, double dr, double cx0,
                                                  double cy0, double cz0, const double* __restrict__ rho,
-                                                 double* __restrict__ beta0, double* __restrict__ ccell, double* part)
+                                                 double* __restrict__ beta0, double* __restrict__ ccell,
+                                                 float* __restrict__ ccell32, double* part)
 {
     __shared__ double sh[kBlock / kWave];
     MP_ZCOL
@@ -188,20 +189,21 @@ __global__ __launch_bounds__(kBlock) void k_fill(Dims d, int lz, double h, int g
         const double c = b / rq;
         beta0[q] = b;
         ccell[q] = c;
+        if (ccell32) ccell32[q] = (float)c;
         if (!(rq > 0.0) || !isfinite(rq) || !isfinite(c) || !(b > 0.0)) bad += 1.0;
     }
     zpart_store(part, block_sum(bad, sh));
 }
 
 void launch_fill(const Dims& d, double h, int geometry, const double* tab, int n1d, double dr, double cx0, double cy0,
-                 double cz0, const double* rho, double* beta0, double* ccell, double* partials, hipStream_t s)
+                 double cz0, const double* rho, double* beta0, double* ccell, float* ccell32, double* partials,
+                 hipStream_t s)
 {
     const ShapeZ sh = zmarch(d.nx, d.ny, d.nz, kZBlocks);
     hipLaunchKernelGGL(k_fill, sh.grid, sh.block, 0, s, d, sh.lz, h, geometry, tab, n1d, dr, cx0, cy0, cz0, rho,
-                       beta0, ccell, partials);
+                       beta0, ccell, ccell32, partials);
 }
 
-__device__ __forceinline__ double harmonic(double a, double b) { return 2.0 * a * b / (a + b); }
 
 // External face indices of the low faces of cell (i,j,k) and of the Neumann
 // high walls.
@@ -231,12 +233,14 @@ __global__ __launch_bounds__(kBlock) void k_faces_from_cells(Dims d, const doubl
     const long long q = ((long long)k * d.ny + j) * d.nx + i;
     const Nbr b = neighbours(d, q, i, j, k);
     const double c0 = cc[q];
-    const double fx = (i > 0 || d.px) ? harmonic(cc[b.xm], c0) : 0.0;
-    const double fy = (j > 0 || d.py) ? harmonic(cc[b.ym], c0) : 0.0;
-    const double fz = (k > 0 || d.pz) ? harmonic(cc[b.zm], c0) : 0.0;
-    c64x[q] = fx;
-    c64y[q] = fy;
-    c64z[q] = fz;
+    const double fx = (i > 0 || d.px) ? harm(cc[b.xm], c0) : 0.0;
+    const double fy = (j > 0 || d.py) ? harm(cc[b.ym], c0) : 0.0;
+    const double fz = (k > 0 || d.pz) ? harm(cc[b.zm], c0) : 0.0;
+    if (c64x) {
+        c64x[q] = fx;
+        c64y[q] = fy;
+        c64z[q] = fz;
+    }
     if (c32x) {
         c32x[q] = (float)fx;
         c32y[q] = (float)fy;
@@ -333,6 +337,52 @@ void launch_coef_restrict(const Dims& fine, const Tin* fx, const Tin* fy, const 
     hipLaunchKernelGGL((k_coef_restrict<Tin, Tout>), sh.grid, sh.block, 0, s, fine, fx, fy, fz, cx, cy, cz);
 }
 
+// Coarse low faces from fine cell values: the fine faces are harmonic means
+// (FP64, as in face mode) summed in the same order as k_coef_restrict.
+template <typename Tout>
+__global__ __launch_bounds__(kBlock) void k_coef_restrict_cells(Dims f, const double* __restrict__ cc,
+                                                                Tout* __restrict__ cx, Tout* __restrict__ cy,
+                                                                Tout* __restrict__ cz)
+{
+    const int nxc = f.nx / 2, nyc = f.ny / 2, nzc = f.nz / 2;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (I >= nxc || J >= nyc || K >= nzc) return;
+    const long long q = ((long long)K * nyc + J) * nxc + I;
+    const long long sy = f.nx, sz = (long long)f.nx * f.ny;
+    const long long base = (long long)(2 * K) * sz + (long long)(2 * J) * sy + 2 * I;
+    // low faces of the fine cells at i = 2I (x), j = 2J (y), k = 2K (z)
+    auto fx = [&](long long qq) {
+        const long long qm = I > 0 ? qq - 1 : (f.px ? qq + f.nx - 1 : -1);
+        return qm >= 0 ? harm(cc[qm], cc[qq]) : 0.0;
+    };
+    auto fy = [&](long long qq) {
+        const long long qm = J > 0 ? qq - sy : (f.py ? qq + (long long)(f.ny - 1) * sy : -1);
+        return qm >= 0 ? harm(cc[qm], cc[qq]) : 0.0;
+    };
+    auto fz = [&](long long qq) {
+        const long long qm = K > 0 ? qq - sz : (f.pz ? qq + (long long)(f.nz - 1) * sz : -1);
+        return qm >= 0 ? harm(cc[qm], cc[qq]) : 0.0;
+    };
+    const double ax = fx(base) + fx(base + sy) + fx(base + sz) + fx(base + sy + sz);
+    const double ay = fy(base) + fy(base + 1) + fy(base + sz) + fy(base + 1 + sz);
+    const double az = fz(base) + fz(base + 1) + fz(base + sy) + fz(base + 1 + sy);
+    cx[q] = (Tout)(0.25 * ax);
+    cy[q] = (Tout)(0.25 * ay);
+    cz[q] = (Tout)(0.25 * az);
+}
+
+template <typename Tout>
+void launch_coef_restrict_cells(const Dims& fine, const double* cc, Tout* cx, Tout* cy, Tout* cz, hipStream_t s)
+{
+    const Shape3 sh = cells3(fine.nx / 2, fine.ny / 2, fine.nz / 2);
+    hipLaunchKernelGGL((k_coef_restrict_cells<Tout>), sh.grid, sh.block, 0, s, fine, cc, cx, cy, cz);
+}
+
+template void launch_coef_restrict_cells<double>(const Dims&, const double*, double*, double*, double*, hipStream_t);
+template void launch_coef_restrict_cells<float>(const Dims&, const double*, float*, float*, float*, hipStream_t);
+
 template void launch_coef_restrict<double, double>(const Dims&, const double*, const double*, const double*, double*,
                                                    double*, double*, hipStream_t);
 template void launch_coef_restrict<double, float>(const Dims&, const double*, const double*, const double*, float*,
@@ -411,9 +461,8 @@ __device__ __forceinline__ double corrected(double u, double c, double bl, doubl
 
 // Each thread owns the low faces of its cell: it alone reads and writes them,
 // so the update is race-free in place.  Neumann walls are left unchanged.
-__global__ __launch_bounds__(kBlock) void k_vel_correct(Dims d, double inv_h, const double* __restrict__ c64x,
-                                                        const double* __restrict__ c64y,
-                                                        const double* __restrict__ c64z,
+template <bool CELL>
+__global__ __launch_bounds__(kBlock) void k_vel_correct(Dims d, double inv_h, Coef<double> C,
                                                         const double* __restrict__ beta0,
                                                         const double* __restrict__ phi, double* __restrict__ ux,
                                                         double* __restrict__ uy, double* __restrict__ uz)
@@ -424,16 +473,21 @@ __global__ __launch_bounds__(kBlock) void k_vel_correct(Dims d, double inv_h, co
     const Nbr nb = neighbours(d, q, i, j, k);
     const ExtIdx e = ext_low(d, i, j, k);
     const double b0 = beta0[q], p0 = phi[q];
-    if (i > 0 || d.px) ux[e.xl] = corrected(ux[e.xl], c64x[q], beta0[nb.xm], b0, phi[nb.xm], p0, inv_h);
-    if (j > 0 || d.py) uy[e.yl] = corrected(uy[e.yl], c64y[q], beta0[nb.ym], b0, phi[nb.ym], p0, inv_h);
-    if (k > 0 || d.pz) uz[e.zl] = corrected(uz[e.zl], c64z[q], beta0[nb.zm], b0, phi[nb.zm], p0, inv_h);
+    double c0, c1, c2, c3, c4, c5;
+    coef6<double, CELL>(C, d, q, nb, i, j, k, c0, c1, c2, c3, c4, c5);
+    if (i > 0 || d.px) ux[e.xl] = corrected(ux[e.xl], c0, beta0[nb.xm], b0, phi[nb.xm], p0, inv_h);
+    if (j > 0 || d.py) uy[e.yl] = corrected(uy[e.yl], c2, beta0[nb.ym], b0, phi[nb.ym], p0, inv_h);
+    if (k > 0 || d.pz) uz[e.zl] = corrected(uz[e.zl], c4, beta0[nb.zm], b0, phi[nb.zm], p0, inv_h);
 }
 
-void launch_vel_correct(const Dims& d, double inv_h, const double* c64x, const double* c64y, const double* c64z,
-                        const double* beta0, const double* phi, double* ux, double* uy, double* uz, hipStream_t s)
+void launch_vel_correct(const Dims& d, double inv_h, const Coef<double>& c64, const double* beta0, const double* phi,
+                        double* ux, double* uy, double* uz, hipStream_t s)
 {
     const Shape3 sh = cells3(d.nx, d.ny, d.nz);
-    hipLaunchKernelGGL(k_vel_correct, sh.grid, sh.block, 0, s, d, inv_h, c64x, c64y, c64z, beta0, phi, ux, uy, uz);
+    if (c64.cell)
+        hipLaunchKernelGGL(k_vel_correct<true>, sh.grid, sh.block, 0, s, d, inv_h, c64, beta0, phi, ux, uy, uz);
+    else
+        hipLaunchKernelGGL(k_vel_correct<false>, sh.grid, sh.block, 0, s, d, inv_h, c64, beta0, phi, ux, uy, uz);
 }
 
 // Coefficient gradient on the low faces of each cell; Neumann high walls 0.

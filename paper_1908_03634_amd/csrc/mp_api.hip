@@ -41,7 +41,7 @@ struct Level {
     bool fused = false;  // both colours in one launch on this level
 };
 
-constexpr long long kCoarseCells = 32768;  // levels at or below run in one workgroup
+constexpr long long kCoarseCells = 4096;  // levels at or below run in one workgroup
 constexpr long long kWaveBottomCells = 256;
 constexpr long long kFusedMinCells = 1LL << 22;  // fused sweeps on levels at least this large
 
@@ -69,6 +69,8 @@ struct mp_ctx {
     std::vector<double> kev_bytes;
     int kev_used = 0;
     int nbz = 1;            // partials written by the z-marching reductions
+    bool cell_mode = false;  // finest level reads cell values beta0/rho (faces formed on the fly)
+    float* ccell32 = nullptr;  // FP32 copy of the cell values (mixed precision)
     int coarse_start = -1;  // first level of the single-workgroup coarse cycle, -1 = off
     bool have_coefs = false, have_base = false;
     std::string err;
@@ -144,6 +146,7 @@ void free_all(mp_ctx* c)
     double* bufs[] = {c->c64x, c->c64y, c->c64z, c->beta0, c->ccell, c->b64, c->partials, c->dscal, c->bottom_work};
     for (double* p : bufs)
         if (p) (void)hipFree(p);
+    if (c->ccell32) (void)hipFree(c->ccell32);
     if (c->hscal) (void)hipHostFree(c->hscal);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -152,6 +155,25 @@ void free_all(mp_ctx* c)
 }
 
 bool mixed(const mp_ctx* c) { return c->cfg.precision == MP_MIXED; }
+
+// FP64 finest-level coefficients (refinement residual, operator, correction).
+mp::Coef<double> coef64(const mp_ctx* c)
+{
+    if (c->cell_mode) return mp::Coef<double>{nullptr, nullptr, nullptr, c->ccell};
+    return mp::Coef<double>{c->c64x, c->c64y, c->c64z, nullptr};
+}
+
+// Coefficients of level l in the precision of the V-cycle.
+template <typename T>
+mp::Coef<T> level_coef(const mp_ctx* c, int l)
+{
+    const Level& L = c->lv[l];
+    if (l == 0 && c->cell_mode) {
+        if constexpr (sizeof(T) == 4) return mp::Coef<T>{nullptr, nullptr, nullptr, (const T*)c->ccell32};
+        else return mp::Coef<T>{nullptr, nullptr, nullptr, (const T*)c->ccell};
+    }
+    return mp::Coef<T>{(const T*)L.cx, (const T*)L.cy, (const T*)L.cz, nullptr};
+}
 
 int sync_read(mp_ctx* c, int first, int count)
 {
@@ -170,7 +192,14 @@ void build_pyramid(mp_ctx* c)
     for (size_t l = 1; l < c->lv.size(); l++) {
         Level& F = c->lv[l - 1];
         Level& C = c->lv[l];
-        if (mixed(c)) {
+        if (l == 1 && c->cell_mode) {
+            if (mixed(c))
+                mp::launch_coef_restrict_cells<float>(F.d, c->ccell, (float*)C.cx, (float*)C.cy, (float*)C.cz,
+                                                      c->stream);
+            else
+                mp::launch_coef_restrict_cells<double>(F.d, c->ccell, (double*)C.cx, (double*)C.cy, (double*)C.cz,
+                                                       c->stream);
+        } else if (mixed(c)) {
             if (l == 1)
                 mp::launch_coef_restrict<double, float>(F.d, c->c64x, c->c64y, c->c64z, (float*)C.cx, (float*)C.cy,
                                                         (float*)C.cz, c->stream);
@@ -207,7 +236,8 @@ void smooth(mp_ctx* c, int l, bool zero_init, const T* ec)
     const T h2 = (T)(L.h * L.h);
     const bool tm = c->cfg.kernel_timing && l == 0;
     const double cells = (double)L.d.n();
-    if (L.fused) {
+    const mp::Coef<T> C = level_coef<T>(c, l);
+    if (L.fused && !C.cell) {
         // words per cell: x_old (unless zero), b, 3 coefficients, x_new, 1/8 coarse e
         const double words = (zero_init ? 0.0 : 1.0) + 1.0 + 3.0 + 1.0 + (ec ? 0.125 : 0.0);
         timed_begin(c, tm);
@@ -219,11 +249,13 @@ void smooth(mp_ctx* c, int l, bool zero_init, const T* ec)
     }
     if (ec) mp::launch_prolong<T>(L.d, (T*)L.x, ec, c->stream);
     for (int colour = 0; colour < 2; colour++) {
-        // per colour: x (both colours share every line), 3 coefficients, b and x of one colour
+        // per colour: x (both colours share every line; not read when zero),
+        // coefficients (3 face words, or 1 cell word), b and x of one colour
+        const bool zi = zero_init && colour == 0;
+        const double words = (zi ? 0.0 : 1.0) + (C.cell ? 1.0 : 3.0) + 0.5 + (zi ? 1.0 : 0.5);
         timed_begin(c, tm);
-        mp::launch_rbgs<T>(L.d, (T*)L.x, (const T*)L.b, (const T*)L.cx, (const T*)L.cy, (const T*)L.cz, h2, colour,
-                           (zero_init && colour == 0) ? 1 : 0, c->stream);
-        timed_end(c, tm, 5.0 * sizeof(T) * cells);
+        mp::launch_rbgs<T>(L.d, (T*)L.x, (const T*)L.b, C, h2, colour, zi ? 1 : 0, c->stream);
+        timed_end(c, tm, words * sizeof(T) * cells);
     }
 }
 
@@ -278,8 +310,8 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
     if (zero_init && c->cfg.nu1 == 0) (void)hipMemsetAsync(L.x, 0, sizeof(T) * L.d.n(), c->stream);
     for (int s = 0; s < c->cfg.nu1; s++) smooth<T>(c, l, zero_init && s == 0, (const T*)nullptr);
     Level& C = c->lv[l + 1];
-    mp::launch_resid_restrict<T>(L.d, (const T*)L.x, (const T*)L.b, (const T*)L.cx, (const T*)L.cy, (const T*)L.cz,
-                                 (T)(1.0 / (L.h * L.h)), (T*)C.b, c->stream);
+    mp::launch_resid_restrict<T>(L.d, (const T*)L.x, (const T*)L.b, level_coef<T>(c, l), (T)(1.0 / (L.h * L.h)),
+                                 (T*)C.b, c->stream);
     vcycle<T>(c, l + 1, true);
     if (c->cfg.nu2 == 0) {
         mp::launch_prolong<T>(L.d, (T*)L.x, (const T*)C.x, c->stream);
@@ -314,8 +346,8 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
         double* sp = c->dscal + S_PAIR0 + 2 * p;
         double* sq = c->dscal + S_PAIR0 + 2 * (1 - p);
         int nbr = 0;
-        mp::launch_resid64(c->d0, phi, c->b64, c->c64x, c->c64y, c->c64z, inv_h2, mx ? (float*)c->lv[0].b : nullptr,
-                           sp + 1, c->partials, &nbr, c->stream);
+        mp::launch_resid64(c->d0, phi, c->b64, coef64(c), inv_h2, mx ? (float*)c->lv[0].b : nullptr, sp + 1,
+                           c->partials, &nbr, c->stream);
         mp::launch_final_sum(c->partials, nbr, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
         int st = sync_read(c, S_RR, 1);
         if (st) return st;
@@ -471,6 +503,7 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
     c->beta0 = dalloc<double>(c->n0, e), good &= ok(c->beta0);
     c->ccell = dalloc<double>(c->n0, e), good &= ok(c->ccell);
     c->b64 = dalloc<double>(c->n0, e), good &= ok(c->b64);
+    if (mx) c->ccell32 = dalloc<float>(c->n0, e), good &= ok(c->ccell32);
     c->nbz = mp::zred_blocks(c->d0);
     c->partials = dalloc<double>(c->nbz > mp::kMaxRedBlocks ? c->nbz : mp::kMaxRedBlocks, e), good &= ok(c->partials);
     c->dscal = dalloc<double>(kScal, e), good &= ok(c->dscal);
@@ -606,13 +639,20 @@ int mp_map_base_state(mp_ctx* c, int geometry, const double* beta0_1d, int n1d, 
     (void)hipSetDevice(c->cfg.device);
 
     HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-    mp::launch_fill(c->d0, c->cfg.h, geometry, beta0_1d, n1d, dr, c0, c1, c2, rho, c->beta0, c->ccell, c->partials,
-                    c->stream);
-    mp::launch_final_sum(c->partials, c->nbz, c->dscal + S_BAD, 1.0, nullptr, 0.0, c->stream);
+    // cell mode whenever the finest level is not also the coarsest
+    c->cell_mode = c->lv.size() >= 2;
     Level& L0 = c->lv[0];
     const bool mx = mixed(c);
-    mp::launch_faces_from_cells(c->d0, c->ccell, c->c64x, c->c64y, c->c64z, mx ? (float*)L0.cx : nullptr,
-                                mx ? (float*)L0.cy : nullptr, mx ? (float*)L0.cz : nullptr, cx, cy, cz, c->stream);
+    mp::launch_fill(c->d0, c->cfg.h, geometry, beta0_1d, n1d, dr, c0, c1, c2, rho, c->beta0, c->ccell,
+                    (mx && c->cell_mode) ? c->ccell32 : nullptr, c->partials, c->stream);
+    mp::launch_final_sum(c->partials, c->nbz, c->dscal + S_BAD, 1.0, nullptr, 0.0, c->stream);
+    if (!c->cell_mode)
+        mp::launch_faces_from_cells(c->d0, c->ccell, c->c64x, c->c64y, c->c64z, mx ? (float*)L0.cx : nullptr,
+                                    mx ? (float*)L0.cy : nullptr, mx ? (float*)L0.cz : nullptr, cx, cy, cz,
+                                    c->stream);
+    else if (cx)
+        mp::launch_faces_from_cells(c->d0, c->ccell, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, cx, cy, cz,
+                                    c->stream);
     build_pyramid(c);
     int st = sync_read(c, S_BAD, 1);
     if (st) return st;
@@ -633,6 +673,7 @@ int mp_set_coefs(mp_ctx* c, const double* cx, const double* cy, const double* cz
 
     Level& L0 = c->lv[0];
     const bool mx = mixed(c);
+    c->cell_mode = false;
     mp::launch_import_faces(c->d0, cx, cy, cz, c->c64x, c->c64y, c->c64z, mx ? (float*)L0.cx : nullptr,
                             mx ? (float*)L0.cy : nullptr, mx ? (float*)L0.cz : nullptr, c->partials, c->stream);
     mp::launch_final_sum(c->partials, c->nbz, c->dscal + S_BAD, 1.0, nullptr, 0.0, c->stream);
@@ -692,7 +733,7 @@ int mp_mac_project(mp_ctx* c, double* ux, double* uy, double* uz, const double* 
     int solve_st = run_solve(c, phi, use_initial_guess, info);
     if (solve_st != MP_OK && solve_st != MP_ERR_NOT_CONVERGED) return solve_st;
     HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
-    mp::launch_vel_correct(c->d0, inv_h, c->c64x, c->c64y, c->c64z, c->beta0, phi, ux, uy, uz, c->stream);
+    mp::launch_vel_correct(c->d0, inv_h, coef64(c), c->beta0, phi, ux, uy, uz, c->stream);
     mp::launch_rhs_defect(c->d0, inv_h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, c->partials, c->stream);
     mp::launch_final_sum(c->partials, c->nbz, c->dscal + S_DEF, 1.0, nullptr, 0.0, c->stream);
     HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
@@ -738,7 +779,7 @@ int mp_apply(mp_ctx* c, const double* x, double* y)
     if (!x || !y) return fail(c, MP_ERR_ARG, "x and y are required");
     if (!c->have_coefs) return fail(c, MP_ERR_STATE, "no face coefficients");
     (void)hipSetDevice(c->cfg.device);
-    mp::launch_apply64(c->d0, x, c->c64x, c->c64y, c->c64z, 1.0 / (c->cfg.h * c->cfg.h), y, c->stream);
+    mp::launch_apply64(c->d0, x, coef64(c), 1.0 / (c->cfg.h * c->cfg.h), y, c->stream);
     HIPCHK(c, hipGetLastError());
     return MP_OK;
 }

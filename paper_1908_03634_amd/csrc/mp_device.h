@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mp_kernels.h"
+
 #pragma clang fp contract(off)
 
 namespace mp {
@@ -131,6 +133,37 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
 // the single-workgroup coarse cycle, the fused sweep) evaluates a cell with
 // exactly this arithmetic, so the variants agree bit for bit.
 
+// Harmonic mean 2ab/(a+b).  FP64 uses the same expression as the stored face
+// coefficients (so both modes agree bit for bit); FP32, used only inside the
+// refinement's V-cycles, multiplies by the hardware reciprocal.
+__device__ __forceinline__ double harm(double a, double b) { return 2.0 * a * b / (a + b); }
+__device__ __forceinline__ float harm(float a, float b) { return 2.0f * a * b * __builtin_amdgcn_rcpf(a + b); }
+
+// The six face coefficients of cell q in stencil order (x low, x high,
+// y low, y high, z low, z high); walls give 0.
+template <typename T, bool CELL>
+__device__ __forceinline__ void coef6(const Coef<T>& C, const Dims& d, long long q, const Nbr& nb, int i, int j, int k,
+                                      T& c0, T& c1, T& c2, T& c3, T& c4, T& c5)
+{
+    if constexpr (CELL) {
+        const T* cc = C.cell;
+        const T cq = cc[q];
+        c0 = (i > 0 || d.px) ? harm(cc[nb.xm], cq) : T(0);
+        c1 = nb.cxp >= 0 ? harm(cq, cc[nb.xp]) : T(0);
+        c2 = (j > 0 || d.py) ? harm(cc[nb.ym], cq) : T(0);
+        c3 = nb.cyp >= 0 ? harm(cq, cc[nb.yp]) : T(0);
+        c4 = (k > 0 || d.pz) ? harm(cc[nb.zm], cq) : T(0);
+        c5 = nb.czp >= 0 ? harm(cq, cc[nb.zp]) : T(0);
+    } else {
+        c0 = C.x[q];
+        c1 = ld_or0(C.x, nb.cxp);
+        c2 = C.y[q];
+        c3 = ld_or0(C.y, nb.cyp);
+        c4 = C.z[q];
+        c5 = ld_or0(C.z, nb.czp);
+    }
+}
+
 // Gauss-Seidel value of cell q from its neighbours in x:
 //   (h^2 b_q + sum_f c_f x_nb(f)) / sum_f c_f,
 // or the old value when the cell has no coupling.
@@ -148,15 +181,28 @@ __device__ __forceinline__ T gs_value(T c0, T c1, T c2, T c3, T c4, T c5, T xm, 
     return csum > T(0) ? fma(h2, bq, s) / csum : old;
 }
 
+// Residual b - A x of one cell from its coefficients and neighbour values.
+template <typename T>
+__device__ __forceinline__ T resid_value(T c0, T c1, T c2, T c3, T c4, T c5, T xm, T xp, T ym, T yp, T zm, T zp, T x0,
+                                         T bq, T inv_h2)
+{
+    const T csum = ((((c0 + c1) + c2) + c3) + c4) + c5;
+    T s = c0 * xm;
+    s = fma(c1, xp, s);
+    s = fma(c2, ym, s);
+    s = fma(c3, yp, s);
+    s = fma(c4, zm, s);
+    s = fma(c5, zp, s);
+    return bq - (csum * x0 - s) * inv_h2;
+}
+
 // One cell of one colour of red-black Gauss-Seidel on A x = b, in place.
 // (p, j, k): pair index along x, row, plane; the cell updated is the one of
 // the pair with (i + j + k) % 2 == colour.  zero_init: x is zero on entry;
 // neighbours are not read and the other cell of the pair is cleared.
-template <typename T>
-__device__ __forceinline__ void rbgs_cell(const Dims& d, T* __restrict__ x, const T* __restrict__ b,
-                                          const T* __restrict__ cx, const T* __restrict__ cy,
-                                          const T* __restrict__ cz, T h2, int colour, int zero_init, int p, int j,
-                                          int k)
+template <typename T, bool CELL>
+__device__ __forceinline__ void rbgs_cell(const Dims& d, T* __restrict__ x, const T* __restrict__ b, const Coef<T>& C,
+                                          T h2, int colour, int zero_init, int p, int j, int k)
 {
     const int par = (j + k + colour) & 1;
     const int i = 2 * p + par;
@@ -168,8 +214,8 @@ __device__ __forceinline__ void rbgs_cell(const Dims& d, T* __restrict__ x, cons
     if (i >= d.nx) return;
     const long long q = rbase + i;
     const Nbr nb = neighbours(d, q, i, j, k);
-    const T c0 = cx[q], c1 = ld_or0(cx, nb.cxp), c2 = cy[q], c3 = ld_or0(cy, nb.cyp), c4 = cz[q],
-            c5 = ld_or0(cz, nb.czp);
+    T c0, c1, c2, c3, c4, c5;
+    coef6<T, CELL>(C, d, q, nb, i, j, k, c0, c1, c2, c3, c4, c5);
     if (zero_init)
         x[q] = gs_value<T>(c0, c1, c2, c3, c4, c5, T(0), T(0), T(0), T(0), T(0), T(0), b[q], h2, T(0));
     else
@@ -178,23 +224,22 @@ __device__ __forceinline__ void rbgs_cell(const Dims& d, T* __restrict__ x, cons
 }
 
 // Residual r = b - A x at one cell.
-template <typename T>
+template <typename T, bool CELL>
 __device__ __forceinline__ T resid_cell(const Dims& d, const T* __restrict__ x, const T* __restrict__ b,
-                                        const T* __restrict__ cx, const T* __restrict__ cy, const T* __restrict__ cz,
-                                        T inv_h2, int i, int j, int k)
+                                        const Coef<T>& C, T inv_h2, int i, int j, int k)
 {
     const long long q = ((long long)k * d.ny + j) * d.nx + i;
     const Nbr nb = neighbours(d, q, i, j, k);
-    T csum, cv;
-    stencil_sums<T>(cx, cy, cz, x, q, nb, csum, cv);
-    return b[q] - (csum * x[q] - cv) * inv_h2;
+    T c0, c1, c2, c3, c4, c5;
+    coef6<T, CELL>(C, d, q, nb, i, j, k, c0, c1, c2, c3, c4, c5);
+    return resid_value<T>(c0, c1, c2, c3, c4, c5, x[nb.xm], x[nb.xp], x[nb.ym], x[nb.yp], x[nb.zm], x[nb.zp], x[q],
+                          b[q], inv_h2);
 }
 
 // Coarse right-hand side of coarse cell (I,J,K): mean of the 8 fine residuals.
-template <typename T>
+template <typename T, bool CELL>
 __device__ __forceinline__ T restrict_cell(const Dims& d, const T* __restrict__ x, const T* __restrict__ b,
-                                           const T* __restrict__ cx, const T* __restrict__ cy,
-                                           const T* __restrict__ cz, T inv_h2, int I, int J, int K)
+                                           const Coef<T>& C, T inv_h2, int I, int J, int K)
 {
     T acc = T(0);
 #pragma unroll
@@ -202,7 +247,8 @@ __device__ __forceinline__ T restrict_cell(const Dims& d, const T* __restrict__ 
 #pragma unroll
         for (int bb = 0; bb < 2; bb++)
 #pragma unroll
-            for (int a = 0; a < 2; a++) acc += resid_cell<T>(d, x, b, cx, cy, cz, inv_h2, 2 * I + a, 2 * J + bb, 2 * K + c);
+            for (int a = 0; a < 2; a++)
+                acc += resid_cell<T, CELL>(d, x, b, C, inv_h2, 2 * I + a, 2 * J + bb, 2 * K + c);
     return T(0.125) * acc;
 }
 

@@ -7,6 +7,19 @@ namespace mp {
 
 struct Dims;
 
+// Coefficients of one level.  Face mode: three low-face arrays (x, y, z).
+// Cell mode (cell != nullptr): one array of cell values beta0/rho; the face
+// value between cells L and R is their harmonic mean, formed when needed.
+// The mapping defines the faces exactly that way, so on the finest level cell
+// mode reads one word per cell instead of three.
+template <typename T>
+struct Coef {
+    const T* x;
+    const T* y;
+    const T* z;
+    const T* cell;
+};
+
 constexpr int kBlock = 256;
 // Reductions write one partial per block; z-marching launches are shaped to
 // stay near this many blocks (see mp_launch.h).
@@ -34,11 +47,14 @@ void launch_neg_copy_sum(const double* rhs, double* b, long long n, double* part
 
 // ---- mapping and coefficients ---------------------------------------------
 // beta0 on cells (planar injection or spherical linear interpolation) and
-// ccell = beta0 / rho; partials (zred_blocks) = per-block count of invalid cells.
+// ccell = beta0 / rho (and its FP32 copy when ccell32 != nullptr); partials
+// (zred_blocks) = per-block count of invalid cells.
 void launch_fill(const Dims& d, double h, int geometry, const double* tab, int n1d, double dr, double cx0, double cy0,
-                 double cz0, const double* rho, double* beta0, double* ccell, double* partials, hipStream_t s);
-// Internal low-face coefficients from cell values (harmonic mean), FP64 and
-// optionally FP32; optional external FP64 face arrays (nullptr to skip).
+                 double cz0, const double* rho, double* beta0, double* ccell, float* ccell32, double* partials,
+                 hipStream_t s);
+// Face coefficients from cell values (harmonic mean): internal low-face FP64
+// (c64*, may be nullptr) and FP32 (c32*, may be nullptr) arrays and external
+// FP64 face arrays (e*, may be nullptr).
 void launch_faces_from_cells(const Dims& d, const double* ccell, double* c64x, double* c64y, double* c64z,
                              float* c32x, float* c32y, float* c32z, double* ex, double* ey, double* ez,
                              hipStream_t s);
@@ -51,6 +67,9 @@ void launch_import_faces(const Dims& d, const double* ex, const double* ey, cons
 template <typename Tin, typename Tout>
 void launch_coef_restrict(const Dims& fine, const Tin* fx, const Tin* fy, const Tin* fz, Tout* cx, Tout* cy,
                           Tout* cz, hipStream_t s);
+// The same from fine cell values (fine faces = harmonic means, in FP64).
+template <typename Tout>
+void launch_coef_restrict_cells(const Dims& fine, const double* cc, Tout* cx, Tout* cy, Tout* cz, hipStream_t s);
 
 // ---- projection ------------------------------------------------------------
 // b = beta0 S - D(beta0 U) (= minus the MAC right-hand side); partials
@@ -62,8 +81,8 @@ void launch_mac_rhs(const Dims& d, double inv_h, const double* beta0, const doub
 void launch_rhs_defect(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
                        const double* uz, const double* S, const double* shift, double* partials, hipStream_t s);
 // U <- U - (c/beta0_f) G phi on every non-wall face (in place).
-void launch_vel_correct(const Dims& d, double inv_h, const double* c64x, const double* c64y, const double* c64z,
-                        const double* beta0, const double* phi, double* ux, double* uy, double* uz, hipStream_t s);
+void launch_vel_correct(const Dims& d, double inv_h, const Coef<double>& c64, const double* beta0, const double* phi,
+                        double* ux, double* uy, double* uz, hipStream_t s);
 // g = (G lam)(G phi) on every non-wall face, external layout; walls 0.
 void launch_coef_grad(const Dims& d, double inv_h2, const double* lam, const double* phi, double* gx, double* gy,
                       double* gz, hipStream_t s);
@@ -71,8 +90,8 @@ void launch_coef_grad(const Dims& d, double inv_h2, const double* lam, const dou
 // ---- multigrid -----------------------------------------------------------
 // One colour of red-black Gauss-Seidel, in place (reference / fallback).
 template <typename T>
-void launch_rbgs(const Dims& d, T* phi, const T* rhs, const T* cx, const T* cy, const T* cz, T h2, int colour,
-                 int zero_init, hipStream_t s);
+void launch_rbgs(const Dims& d, T* phi, const T* rhs, const Coef<T>& c, T h2, int colour, int zero_init,
+                 hipStream_t s);
 // Both colours in one launch, out of place (xo -> xn).  zero_init: xo is
 // taken as zero.  ec: coarse correction added to xo while reading
 // (prolongation fused into the sweep), or nullptr.
@@ -81,8 +100,8 @@ void launch_sweep(const Dims& d, const T* xo, T* xn, const T* b, const T* cx, co
                   int zero_init, const T* ec, hipStream_t s);
 bool sweep_supported(const Dims& d);
 template <typename T>
-void launch_resid_restrict(const Dims& fine, const T* phi, const T* rhs, const T* cx, const T* cy, const T* cz,
-                           T inv_h2, T* coarse_rhs, hipStream_t s);
+void launch_resid_restrict(const Dims& fine, const T* phi, const T* rhs, const Coef<T>& c, T inv_h2, T* coarse_rhs,
+                           hipStream_t s);
 template <typename T>
 void launch_prolong(const Dims& fine, T* phi, const T* coarse_phi, hipStream_t s);
 // BiCGStab in FP64 on the coarsest grid (one workgroup); work = 7 * n doubles.
@@ -120,13 +139,11 @@ void launch_coarse_cycle(const CoarseArgs<T>& a, hipStream_t s);
 
 // ---- FP64 level-0 operations --------------------------------------------
 // y = M x = -(A x).
-void launch_apply64(const Dims& d, const double* x, const double* cx, const double* cy, const double* cz,
-                    double inv_h2, double* y, hipStream_t s);
+void launch_apply64(const Dims& d, const double* x, const Coef<double>& c, double inv_h2, double* y, hipStream_t s);
 // r = b - A phi; partials (*nb_out of them) = per-block sum r^2; when
 // r32 != nullptr, r32 = float(r * inv_s[0]).
-void launch_resid64(const Dims& d, const double* phi, const double* b, const double* cx, const double* cy,
-                    const double* cz, double inv_h2, float* r32, const double* inv_s, double* partials, int* nb_out,
-                    hipStream_t s);
+void launch_resid64(const Dims& d, const double* phi, const double* b, const Coef<double>& c, double inv_h2,
+                    float* r32, const double* inv_s, double* partials, int* nb_out, hipStream_t s);
 // phi += s[0] * e.
 void launch_ir_update(long long n, double* phi, const float* e, const double* s, hipStream_t st);
 

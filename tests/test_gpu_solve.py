@@ -204,3 +204,48 @@ def test_coarse_cycle_kernel_matches_per_level_launches(precision):
     assert outs[0][1]["rel_resid"] <= 1e-12 and outs[1][1]["rel_resid"] <= 1e-12
     assert rel(outs[0][0], outs[1][0]) < 1e-9
     assert abs(outs[0][1]["outer_iters"] - outs[1][1]["outer_iters"]) <= 1
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("shape,bc", [((64, 64, 64), (0, 0, 1)), ((128, 32, 48), (1, 1, 1)), ((40, 24, 16), (0, 1, 0))])
+def test_fused_sweep_bitwise_with_face_coefficients(precision, shape, bc):
+    """Caller face coefficients (face mode on every level): the fused sweep on
+    every level against one launch per colour."""
+    nx, ny, nz = shape
+    say("fused vs per-colour, face mode", shape, bc, precision)
+    cx, cy, cz = W.random_coefs(nx, ny, nz, bc, 909)
+    rhs = W.random_cells(nx, ny, nz, 910)
+    outs = []
+    for sm in ("fused", "per_colour"):
+        ctx = mproj.Context(nx, ny, nz, h=1.0 / nz, bc=bc, precision=precision, rtol=1e-10, smoother=sm)
+        ctx.set_coefs(T(cx), T(cy), T(cz))
+        x, info = ctx.solve(T(rhs))
+        outs.append((N(x), info["resid_hist"]))
+        ctx.close()
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cell_and_face_coefficient_modes_agree(precision):
+    """Mapped coefficients are read as one value per cell on the finest level
+    (faces formed on the fly); the same faces passed explicitly give the same
+    FP64 operator, so the FP64 path is bitwise equal and the mixed path equal
+    to the tolerance."""
+    p = W.planar_problem(64, contrast=1e4, seed=808)
+    rhs = W.random_cells(64, 64, 64, 811)
+    a = context_for(p, precision, rtol=1e-12)
+    cx, cy, cz = a.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center)
+    xa, ia = a.solve(T(rhs))
+    ya = N(a.apply(T(rhs)))
+    b = context_for(p, precision, rtol=1e-12)
+    b.set_coefs(cx, cy, cz)
+    xb, ib = b.solve(T(rhs))
+    yb = N(b.apply(T(rhs)))
+    assert np.array_equal(ya, yb)
+    if precision == "fp64":
+        assert np.array_equal(N(xa), N(xb))
+    else:
+        assert rel(N(xa), N(xb)) < 1e-9
+    a.close()
+    b.close()
