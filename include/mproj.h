@@ -90,6 +90,12 @@ typedef struct mp_config {
     int coarse_cycle;        /* 1: run levels of <= 4096 cells in one workgroup
                                 (bottom <= 256 cells by one wavefront); 0: one
                                 launch per operation on every level */
+    int blocked;             /* 1: on the finest level, register-blocked
+                                kernels (two x cells and four rows per lane,
+                                marching along z) when its coefficients are
+                                cell values (after mp_map_base_state) and
+                                nx % 128 == 0, ny % 4 == 0, nz even >= 4;
+                                0: one cell per thread.  Same bits in FP64. */
     void *stream;            /* hipStream_t for every launch; NULL = null stream */
     int device;              /* HIP device ordinal */
 } mp_config;
@@ -117,7 +123,7 @@ typedef struct mp_ctx mp_ctx;
 /* Fill *cfg with defaults for an nx x ny x nz grid: h = 1/nz, periodic x/y,
  * Neumann z, MIXED, rtol 1e-10, max_outer 100, V(2,2), 1 cycle per step,
  * bottom 1e-8 / 400 iterations, demean 1, automatic smoother, coarse cycle on,
- * null stream, device 0. */
+ * blocked kernels on, null stream, device 0. */
 void mp_config_default(mp_config *cfg, int nx, int ny, int nz);
 
 /* Create a context: validates cfg, selects the device, allocates the

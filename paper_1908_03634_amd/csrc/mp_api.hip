@@ -39,6 +39,7 @@ struct Level {
     void* cz = nullptr;
     bool own_x = false, own_b = false, own_c = false, own_x2 = false;
     bool fused = false;  // both colours in one launch on this level
+    bool blk = false;    // register-blocked kernels (finest level, cell mode)
 };
 
 constexpr long long kCoarseCells = 4096;  // levels at or below run in one workgroup
@@ -72,6 +73,8 @@ struct mp_ctx {
     bool cell_mode = false;  // finest level reads cell values beta0/rho (faces formed on the fly)
     float* ccell32 = nullptr;  // FP32 copy of the cell values (mixed precision)
     int coarse_start = -1;  // first level of the single-workgroup coarse cycle, -1 = off
+    double* ir_phi = nullptr;     // refinement update fused into the V-cycle's last pass
+    const double* ir_s = nullptr;  // (phi += ir_s[0] * e), or nullptr
     bool have_coefs = false, have_base = false;
     std::string err;
 };
@@ -127,6 +130,7 @@ int check_config(const mp_config* c, mp_ctx* ctx)
     if (c->smoother != MP_SMOOTH_AUTO && c->smoother != MP_SMOOTH_PER_COLOUR && c->smoother != MP_SMOOTH_FUSED)
         return fail(ctx, MP_ERR_ARG, "bad smoother");
     if (c->coarse_cycle != 0 && c->coarse_cycle != 1) return fail(ctx, MP_ERR_ARG, "coarse_cycle must be 0 or 1");
+    if (c->blocked != 0 && c->blocked != 1) return fail(ctx, MP_ERR_ARG, "blocked must be 0 or 1");
     return MP_OK;
 }
 
@@ -186,6 +190,9 @@ int sync_read(mp_ctx* c, int first, int count)
 
 int nblk(const mp_ctx* c) { return mp::red_blocks(c->n0); }
 
+// Register-blocked kernels on level l (finest level with cell values only).
+bool use_blk(const mp_ctx* c, int l) { return l == 0 && c->cell_mode && c->lv[0].blk; }
+
 // Coefficients of levels 1.. from level 0.
 void build_pyramid(mp_ctx* c)
 {
@@ -228,9 +235,9 @@ void timed_end(mp_ctx* c, bool on, double bytes)
 }
 
 // One smoothing sweep on level l.  ec: coarse correction to add first
-// (prolongation), or nullptr.
+// (prolongation), or nullptr.  last: the final sweep of the V-cycle.
 template <typename T>
-void smooth(mp_ctx* c, int l, bool zero_init, const T* ec)
+void smooth(mp_ctx* c, int l, bool zero_init, const T* ec, bool last = false)
 {
     Level& L = c->lv[l];
     const T h2 = (T)(L.h * L.h);
@@ -245,6 +252,22 @@ void smooth(mp_ctx* c, int l, bool zero_init, const T* ec)
                             (const T*)L.cz, h2, zero_init ? 1 : 0, ec, c->stream);
         timed_end(c, tm, words * sizeof(T) * cells);
         std::swap(L.x, L.x2);
+        return;
+    }
+    if (use_blk(c, l)) {
+        // per colour: x read (not when zero) and written, b and c read, all
+        // as whole rows; 1/8 word of coarse correction after prolongation
+        for (int colour = 0; colour < 2; colour++) {
+            const bool zi = zero_init && colour == 0;
+            const int mode = zi ? mp::GS_ZERO : !ec ? mp::GS_PLAIN : colour == 0 ? mp::GS_E_ALL : mp::GS_E_OWN;
+            const bool iru = last && colour == 1 && c->ir_phi != nullptr;
+            const double words = (zi ? 3.0 : 4.0) + (ec ? 0.125 : 0.0);
+            timed_begin(c, tm);
+            mp::launch_gs_blk<T>(L.d, (T*)L.x, (const T*)L.b, C.cell, h2, colour, mode, ec,
+                                 iru ? c->ir_phi : nullptr, iru ? c->ir_s : nullptr, c->stream);
+            // the fused refinement update adds 16 bytes per cell (phi in and out)
+            timed_end(c, tm, words * sizeof(T) * cells + (iru ? 16.0 * cells : 0.0));
+        }
         return;
     }
     if (ec) mp::launch_prolong<T>(L.d, (T*)L.x, ec, c->stream);
@@ -310,14 +333,19 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
     if (zero_init && c->cfg.nu1 == 0) (void)hipMemsetAsync(L.x, 0, sizeof(T) * L.d.n(), c->stream);
     for (int s = 0; s < c->cfg.nu1; s++) smooth<T>(c, l, zero_init && s == 0, (const T*)nullptr);
     Level& C = c->lv[l + 1];
-    mp::launch_resid_restrict<T>(L.d, (const T*)L.x, (const T*)L.b, level_coef<T>(c, l), (T)(1.0 / (L.h * L.h)),
-                                 (T*)C.b, c->stream);
+    if (use_blk(c, l))
+        mp::launch_rr_blk<T>(L.d, (const T*)L.x, (const T*)L.b, level_coef<T>(c, l).cell, (T)(1.0 / (L.h * L.h)),
+                             (T*)C.b, c->stream);
+    else
+        mp::launch_resid_restrict<T>(L.d, (const T*)L.x, (const T*)L.b, level_coef<T>(c, l), (T)(1.0 / (L.h * L.h)),
+                                     (T*)C.b, c->stream);
     vcycle<T>(c, l + 1, true);
     if (c->cfg.nu2 == 0) {
         mp::launch_prolong<T>(L.d, (T*)L.x, (const T*)C.x, c->stream);
         return;
     }
-    for (int s = 0; s < c->cfg.nu2; s++) smooth<T>(c, l, false, s == 0 ? (const T*)C.x : (const T*)nullptr);
+    for (int s = 0; s < c->cfg.nu2; s++)
+        smooth<T>(c, l, false, s == 0 ? (const T*)C.x : (const T*)nullptr, s == c->cfg.nu2 - 1);
 }
 
 // Solve A phi = b64 (b64 mean-zero, ||b64||^2 = nb2 in hscal[S_NB2]).
@@ -346,8 +374,12 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
         double* sp = c->dscal + S_PAIR0 + 2 * p;
         double* sq = c->dscal + S_PAIR0 + 2 * (1 - p);
         int nbr = 0;
-        mp::launch_resid64(c->d0, phi, c->b64, coef64(c), inv_h2, mx ? (float*)c->lv[0].b : nullptr, sp + 1,
-                           c->partials, &nbr, c->stream);
+        if (use_blk(c, 0))
+            mp::launch_resid64_blk(c->d0, phi, c->b64, c->ccell, inv_h2, mx ? (float*)c->lv[0].b : nullptr, sp + 1,
+                                   c->partials, &nbr, c->stream);
+        else
+            mp::launch_resid64(c->d0, phi, c->b64, coef64(c), inv_h2, mx ? (float*)c->lv[0].b : nullptr, sp + 1,
+                               c->partials, &nbr, c->stream);
         mp::launch_final_sum(c->partials, nbr, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
         int st = sync_read(c, S_RR, 1);
         if (st) return st;
@@ -376,11 +408,18 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
             break;
         }
         if (mx) {
+            // the last V-cycle of the step applies phi += s e in its final
+            // smoother pass when the finest level runs blocked kernels
+            const bool fuse_ir = use_blk(c, 0) && c->cfg.nu2 >= 1;
             for (int k = 0; k < c->cfg.cycles_per_outer; k++) {
+                const bool lastc = k == c->cfg.cycles_per_outer - 1;
+                c->ir_phi = fuse_ir && lastc ? phi : nullptr;
+                c->ir_s = sp;
                 vcycle<float>(c, 0, k == 0);
+                c->ir_phi = nullptr;
                 vc++;
             }
-            mp::launch_ir_update(n, phi, (const float*)c->lv[0].x, sp, c->stream);
+            if (!fuse_ir) mp::launch_ir_update(n, phi, (const float*)c->lv[0].x, sp, c->stream);
         } else {
             vcycle<double>(c, 0, it == 0 && !use_guess);
             vc++;
@@ -460,6 +499,7 @@ void mp_config_default(mp_config* cfg, int nx, int ny, int nz)
     cfg->kernel_timing = 0;
     cfg->smoother = MP_SMOOTH_AUTO;
     cfg->coarse_cycle = 1;
+    cfg->blocked = 1;
     cfg->stream = nullptr;
     cfg->device = 0;
 }
@@ -505,7 +545,11 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
     c->b64 = dalloc<double>(c->n0, e), good &= ok(c->b64);
     if (mx) c->ccell32 = dalloc<float>(c->n0, e), good &= ok(c->ccell32);
     c->nbz = mp::zred_blocks(c->d0);
-    c->partials = dalloc<double>(c->nbz > mp::kMaxRedBlocks ? c->nbz : mp::kMaxRedBlocks, e), good &= ok(c->partials);
+    {
+        int np = c->nbz > mp::kMaxRedBlocks ? c->nbz : mp::kMaxRedBlocks;
+        if (mp::blk_supported(c->d0) && mp::blk_reduce_blocks(c->d0) > np) np = mp::blk_reduce_blocks(c->d0);
+        c->partials = dalloc<double>(np, e), good &= ok(c->partials);
+    }
     c->dscal = dalloc<double>(kScal, e), good &= ok(c->dscal);
     // levels
     Dims d = c->d0;
@@ -560,6 +604,7 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
             if (lc == 0) lc = 1;  // the finest level keeps its own launches (its iterate may be the caller's)
             c->coarse_start = lc;
         }
+        c->lv[0].blk = cfg->blocked && nlev >= 2 && mp::blk_supported(c->d0);
         for (int l = 0; l < nlev - 1; l++) {
             Level& L = c->lv[l];
             if (c->coarse_start >= 0 && l >= c->coarse_start) break;

@@ -137,6 +137,34 @@ struct CoarseArgs {
 template <typename T>
 void launch_coarse_cycle(const CoarseArgs<T>& a, hipStream_t s);
 
+// ---- register-blocked finest-level kernels (cell-value coefficients) -----
+// Each lane owns two x-adjacent cells in 4 rows and marches along z; valid
+// when blk_supported(d).  Results equal the one-cell kernels' bit for bit.
+bool blk_supported(const Dims& d);
+// Partials written by launch_resid64_blk on these dims (<= kMaxRedBlocks
+// unless nx * ny alone needs more blocks).
+int blk_reduce_blocks(const Dims& d);
+// Smoother pass modes.
+//   GS_PLAIN:  x as stored.
+//   GS_ZERO:   x is zero on entry (not read; the other colour is written 0).
+//   GS_E_ALL:  first colour after prolongation: every x value read is taken
+//              as x + e of its parent coarse cell (ec = coarse correction).
+//   GS_E_OWN:  second colour after prolongation: the updated cell's own value
+//              is x + e.  GS_E_ALL then GS_E_OWN equals launch_prolong
+//              followed by two GS_PLAIN passes.
+enum { GS_PLAIN = 0, GS_ZERO = 1, GS_E_ALL = 2, GS_E_OWN = 3 };
+// phi != nullptr (FP32 only): also phi += irs[0] * x on every cell (the
+// refinement update fused into the last pass of a V-cycle).
+template <typename T>
+void launch_gs_blk(const Dims& d, T* x, const T* b, const T* cc, T h2, int colour, int mode, const T* ec,
+                   double* phi, const double* irs, hipStream_t s);
+// Coarse rhs = mean of the 8 fine residuals b - A x (as launch_resid_restrict).
+template <typename T>
+void launch_rr_blk(const Dims& d, const T* x, const T* b, const T* cc, T inv_h2, T* bc, hipStream_t s);
+// As launch_resid64 with cell-value coefficients cc.
+void launch_resid64_blk(const Dims& d, const double* x, const double* b, const double* cc, double inv_h2, float* r32,
+                        const double* inv_s, double* partials, int* nb_out, hipStream_t s);
+
 // ---- FP64 level-0 operations --------------------------------------------
 // y = M x = -(A x).
 void launch_apply64(const Dims& d, const double* x, const Coef<double>& c, double inv_h2, double* y, hipStream_t s);

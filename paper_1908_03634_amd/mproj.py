@@ -55,6 +55,7 @@ class Config(ctypes.Structure):
         ("kernel_timing", ctypes.c_int),
         ("smoother", ctypes.c_int),
         ("coarse_cycle", ctypes.c_int),
+        ("blocked", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("device", ctypes.c_int),
     ]
@@ -144,7 +145,7 @@ class Context:
 
     def __init__(self, nx, ny, nz, h=None, bc=(PERIODIC, PERIODIC, NEUMANN), precision="mixed", rtol=1e-10,
                  max_outer=100, nu1=2, nu2=2, cycles_per_outer=1, bottom_rtol=1e-8, bottom_max_iter=400,
-                 demean=True, kernel_timing=False, smoother="auto", coarse_cycle=True, device=None, stream=None):
+                 demean=True, kernel_timing=False, smoother="auto", coarse_cycle=True, blocked=True, device=None, stream=None):
         self.lib = load_library()
         if not torch.cuda.is_available():
             raise MprojError(2, "no GPU visible to torch")
@@ -165,6 +166,7 @@ class Context:
         cfg.kernel_timing = 1 if kernel_timing else 0
         cfg.smoother = {"auto": 0, "per_colour": 1, "fused": 2}[smoother]
         cfg.coarse_cycle = 1 if coarse_cycle else 0
+        cfg.blocked = 1 if blocked else 0
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = st
         cfg.stream = ctypes.c_void_p(st.cuda_stream)

@@ -1,0 +1,120 @@
+"""Register-blocked finest-level kernels (two x cells and four rows per lane,
+z-marching) against the one-cell-per-thread kernels and the oracle.
+
+The blocked smoother and restriction evaluate every cell with the same
+arithmetic as the one-cell kernels, so FP64 solves are bitwise equal.  The
+blocked FP64 residual sums r^2 in another order, which only moves the last
+bits of the norms: FP64 iterates are unaffected (the norms only decide when
+to stop), mixed-precision iterates agree bitwise through the first
+refinement step (its scale comes from the right-hand side) and to the
+tolerance after it."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1908_03634_amd import workloads as W
+from tests.gpu_util import N, T, context_for, rel, say
+
+pytestmark = pytest.mark.gpu
+
+BCS = [(0, 0, 1), (1, 1, 1), (0, 0, 0), (1, 0, 1), (0, 1, 0)]
+# (nx, ny, nz): one wavefront of columns with a single live row group; ragged
+# row groups (ny not a multiple of 16) and plane chunks; several x tiles.
+SHAPES = [(128, 4, 4), (128, 12, 6), (256, 20, 10), (128, 36, 32), (256, 48, 64)]
+
+
+def _problem(shape, bc, seed):
+    nx, ny, nz = shape
+    return W.planar_problem(nx=nx, ny=ny, nz=nz, contrast=1e3, bc=bc, seed=seed, rho_noise=0.15)
+
+
+def _solve(p, precision, blocked, rhs, **kw):
+    ctx = context_for(p, precision, blocked=blocked, **kw)
+    ctx.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center, want_coefs=False)
+    x, info = ctx.solve(T(rhs), allow_not_converged=kw.get("max_outer", 100) < 100)
+    out = N(x)
+    ctx.close()
+    return out, info
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_blocked_fp64_solve_is_bitwise_equal(shape, bc):
+    say("blocked fp64", shape, bc)
+    p = _problem(shape, bc, 4100 + sum(shape))
+    rhs = W.random_cells(*shape, 4200 + sum(shape))
+    xa, ia = _solve(p, "fp64", True, rhs, rtol=1e-11)
+    xb, ib = _solve(p, "fp64", False, rhs, rtol=1e-11)
+    assert np.array_equal(xa, xb)
+    assert ia["vcycles"] == ib["vcycles"]
+    assert ia["rel_resid"] == pytest.approx(ib["rel_resid"], rel=1e-6)
+    assert ia["rel_resid"] <= 1e-11
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_blocked_mixed_first_step_is_bitwise_equal(shape, bc):
+    """One refinement step (restriction, both smoother colours, the zero
+    start and the prolongation folded into the post-smoother, all in FP32)."""
+    say("blocked mixed step", shape, bc)
+    p = _problem(shape, bc, 4300 + sum(shape))
+    rhs = W.random_cells(*shape, 4400 + sum(shape))
+    xa, _ = _solve(p, "mixed", True, rhs, max_outer=1)
+    xb, _ = _solve(p, "mixed", False, rhs, max_outer=1)
+    assert np.array_equal(xa, xb)
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 1), (1, 1, 1)])
+@pytest.mark.parametrize("shape", [(128, 36, 32), (256, 48, 64)])
+def test_blocked_mixed_solve_matches_oracle(shape, bc):
+    say("blocked mixed solve", shape, bc)
+    p = _problem(shape, bc, 4500 + sum(shape))
+    rhs = W.random_cells(*shape, 4600 + sum(shape))
+    xa, ia = _solve(p, "mixed", True, rhs, rtol=1e-11)
+    xb, _ = _solve(p, "mixed", False, rhs, rtol=1e-11)
+    assert ia["rel_resid"] <= 1e-11
+    assert rel(xa, xb) < 1e-9
+    g = oracle.Grid(p.nx, p.ny, p.nz, p.h, p.bc)
+    beta0 = oracle.fill_beta0(g, p.geometry, p.beta0_1d, p.dr, p.center)
+    cx, cy, cz = oracle.face_coefs(g, beta0, p.rho)
+    ref, _ = oracle.solve(g, cx, cy, cz, rhs, tol=1e-13)
+    assert rel(xa, ref) < 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_blocked_spherical_projection(precision):
+    """128^3 spherical star, Neumann walls on every axis, 1e5 contrast: the
+    blocked path against the one-cell path and the oracle's projection."""
+    say("blocked spherical", precision)
+    p = W.spherical_problem(128, contrast=1e5, seed=4700)
+    ref = oracle.mac_project(p, tol=1e-12)
+    out = {}
+    for blocked in (True, False):
+        ctx = context_for(p, precision, blocked=blocked, rtol=1e-11)
+        ctx.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center, want_coefs=False)
+        ux, uy, uz, S = T(p.ux), T(p.uy), T(p.uz), T(p.S)
+        phi, info = ctx.mac_project(ux, uy, uz, S)
+        out[blocked] = (N(phi), N(ux), info)
+        ctx.close()
+    (pa, ua, ia), (pb, ub, ib) = out[True], out[False]
+    if precision == "fp64":
+        assert np.array_equal(pa, pb)
+        assert np.array_equal(ua, ub)
+    assert ia["rel_resid"] <= 1e-11
+    assert ia["div_defect"] <= 2e-11
+    assert rel(pa, ref["phi"]) < 1e-8
+
+
+@pytest.mark.parametrize("nu1,nu2,cycles", [(1, 1, 1), (2, 2, 2), (2, 0, 1), (0, 2, 1), (3, 1, 2)])
+def test_blocked_mixed_first_step_smoothing_variants(nu1, nu2, cycles):
+    """The refinement update rides on the last smoother pass (plain, or right
+    after prolongation when nu2 = 1, or on the second of two V-cycles); with no
+    post-smoothing it stays a separate pass."""
+    shape, bc = (256, 20, 10), (0, 0, 1)
+    say("blocked mixed variants", nu1, nu2, cycles)
+    p = _problem(shape, bc, 4800)
+    rhs = W.random_cells(*shape, 4801)
+    kw = dict(max_outer=1, nu1=nu1, nu2=nu2, cycles_per_outer=cycles)
+    xa, _ = _solve(p, "mixed", True, rhs, **kw)
+    xb, _ = _solve(p, "mixed", False, rhs, **kw)
+    assert np.array_equal(xa, xb)
