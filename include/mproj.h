@@ -87,15 +87,17 @@ typedef struct mp_config {
                                 every level; MP_SMOOTH_FUSED: both colours in one
                                 launch wherever the grid allows.  All three give
                                 the same bits. */
-    int coarse_cycle;        /* 1: run levels of <= 4096 cells in one workgroup
+    int coarse_cycle;        /* 1: run levels of <= 512 cells in one workgroup
                                 (bottom <= 256 cells by one wavefront); 0: one
                                 launch per operation on every level */
     int blocked;             /* 1: on the finest level, register-blocked
-                                kernels (two x cells and four rows per lane,
-                                marching along z) when its coefficients are
-                                cell values (after mp_map_base_state) and
-                                nx % 128 == 0, ny % 4 == 0, nz even >= 4;
-                                0: one cell per thread.  Same bits in FP64. */
+                                kernels (a strip of 2-8 x cells in 2-4 rows
+                                per lane, marching along z) when its
+                                coefficients are cell values (after
+                                mp_map_base_state), nx % 128 == 0,
+                                ny % 4 == 0, nz is even and >= 4, and the
+                                solution array is 16-byte aligned; 0: one
+                                cell per thread.  Same bits in FP64. */
     void *stream;            /* hipStream_t for every launch; NULL = null stream */
     int device;              /* HIP device ordinal */
 } mp_config;

@@ -42,7 +42,7 @@ struct Level {
     bool blk = false;    // register-blocked kernels (finest level, cell mode)
 };
 
-constexpr long long kCoarseCells = 4096;  // levels at or below run in one workgroup
+constexpr long long kCoarseCells = 512;  // levels at or below run in one workgroup
 constexpr long long kWaveBottomCells = 256;
 constexpr long long kFusedMinCells = 1LL << 22;  // fused sweeps on levels at least this large
 
@@ -73,6 +73,7 @@ struct mp_ctx {
     bool cell_mode = false;  // finest level reads cell values beta0/rho (faces formed on the fly)
     float* ccell32 = nullptr;  // FP32 copy of the cell values (mixed precision)
     int coarse_start = -1;  // first level of the single-workgroup coarse cycle, -1 = off
+    bool phi_aligned = true;      // the caller's iterate allows 16-byte accesses
     double* ir_phi = nullptr;     // refinement update fused into the V-cycle's last pass
     const double* ir_s = nullptr;  // (phi += ir_s[0] * e), or nullptr
     bool have_coefs = false, have_base = false;
@@ -191,7 +192,7 @@ int sync_read(mp_ctx* c, int first, int count)
 int nblk(const mp_ctx* c) { return mp::red_blocks(c->n0); }
 
 // Register-blocked kernels on level l (finest level with cell values only).
-bool use_blk(const mp_ctx* c, int l) { return l == 0 && c->cell_mode && c->lv[0].blk; }
+bool use_blk(const mp_ctx* c, int l) { return l == 0 && c->cell_mode && c->lv[0].blk && c->phi_aligned; }
 
 // Coefficients of levels 1.. from level 0.
 void build_pyramid(mp_ctx* c)
@@ -363,6 +364,7 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
         return MP_OK;
     }
     if (!use_guess) HIPCHK(c, hipMemsetAsync(phi, 0, sizeof(double) * n, c->stream));
+    c->phi_aligned = ((uintptr_t)phi & 15) == 0;
     const bool mx = mixed(c);
     if (!mx) c->lv[0].x = phi;  // x2 stays the internal second buffer
     int status = MP_ERR_NOT_CONVERGED;

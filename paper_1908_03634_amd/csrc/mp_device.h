@@ -164,6 +164,11 @@ __device__ __forceinline__ void coef6(const Coef<T>& C, const Dims& d, long long
     }
 }
 
+// Quotient of the Gauss-Seidel update: correctly rounded in FP64; in FP32
+// (the refinement's V-cycles only) a multiply by the hardware reciprocal.
+__device__ __forceinline__ double gs_div(double n, double d) { return n / d; }
+__device__ __forceinline__ float gs_div(float n, float d) { return n * __builtin_amdgcn_rcpf(d); }
+
 // Gauss-Seidel value of cell q from its neighbours in x:
 //   (h^2 b_q + sum_f c_f x_nb(f)) / sum_f c_f,
 // or the old value when the cell has no coupling.
@@ -178,7 +183,7 @@ __device__ __forceinline__ T gs_value(T c0, T c1, T c2, T c3, T c4, T c5, T xm, 
     s = fma(c3, yp, s);
     s = fma(c4, zm, s);
     s = fma(c5, zp, s);
-    return csum > T(0) ? fma(h2, bq, s) / csum : old;
+    return csum > T(0) ? gs_div(fma(h2, bq, s), csum) : old;
 }
 
 // Residual b - A x of one cell from its coefficients and neighbour values.

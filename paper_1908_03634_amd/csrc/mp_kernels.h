@@ -138,8 +138,9 @@ template <typename T>
 void launch_coarse_cycle(const CoarseArgs<T>& a, hipStream_t s);
 
 // ---- register-blocked finest-level kernels (cell-value coefficients) -----
-// Each lane owns two x-adjacent cells in 4 rows and marches along z; valid
-// when blk_supported(d).  Results equal the one-cell kernels' bit for bit.
+// Each lane owns a strip of 2-8 x-adjacent cells in 2-4 rows and marches
+// along z; valid when blk_supported(d) and every array is 16-byte aligned.
+// Results equal the one-cell kernels' bit for bit.
 bool blk_supported(const Dims& d);
 // Partials written by launch_resid64_blk on these dims (<= kMaxRedBlocks
 // unless nx * ny alone needs more blocks).

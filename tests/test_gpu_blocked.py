@@ -20,7 +20,11 @@ pytestmark = pytest.mark.gpu
 BCS = [(0, 0, 1), (1, 1, 1), (0, 0, 0), (1, 0, 1), (0, 1, 0)]
 # (nx, ny, nz): one wavefront of columns with a single live row group; ragged
 # row groups (ny not a multiple of 16) and plane chunks; several x tiles.
-SHAPES = [(128, 4, 4), (128, 12, 6), (256, 20, 10), (128, 36, 32), (256, 48, 64)]
+# Strips of 2M cells per lane: M = nx / 128 when the wavefront spans the row
+# (1 to 4, x neighbours and a periodic wrap by lane rotation), else tiles
+# with halo columns (640: five tiles of pairs; 1024: two tiles of 8 cells).
+SHAPES = [(128, 4, 4), (128, 12, 6), (256, 20, 10), (128, 36, 32), (256, 48, 64), (384, 8, 6), (512, 4, 4),
+          (640, 8, 4), (1024, 4, 4)]
 
 
 def _problem(shape, bc, seed):
@@ -118,3 +122,23 @@ def test_blocked_mixed_first_step_smoothing_variants(nu1, nu2, cycles):
     xa, _ = _solve(p, "mixed", True, rhs, **kw)
     xb, _ = _solve(p, "mixed", False, rhs, **kw)
     assert np.array_equal(xa, xb)
+
+
+def test_unaligned_solution_array_uses_one_cell_kernels():
+    """A solution array that is only 8-byte aligned cannot take the blocked
+    kernels' 16-byte accesses: the one-cell kernels run and the FP64 result
+    is bitwise the same."""
+    import torch
+    shape, bc = (256, 20, 10), (0, 0, 1)
+    p = _problem(shape, bc, 4900)
+    rhs = W.random_cells(*shape, 4901)
+    n = int(np.prod(shape))
+    ctx = context_for(p, "fp64", rtol=1e-11)
+    ctx.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center, want_coefs=False)
+    xa, _ = ctx.solve(T(rhs))
+    buf = torch.zeros(n + 1, dtype=torch.float64, device=xa.device)
+    xu = buf[1:].view(shape[::-1])
+    assert xu.data_ptr() % 16 == 8
+    xb, _ = ctx.solve(T(rhs), x=xu)
+    assert np.array_equal(N(xa), N(xb))
+    ctx.close()
