@@ -73,9 +73,13 @@ typedef struct mp_config {
     int precision;           /* MP_FP64: FP64 V-cycles; MP_MIXED: FP32 V-cycles
                                 inside FP64 iterative refinement */
     double rtol;             /* stop when ||rhs - M phi||_2 <= rtol ||rhs||_2 (FP64) */
-    int max_outer;           /* max V-cycles (FP64) or refinement steps (MIXED) */
+    int max_outer;           /* max residual checks: refinement steps (MIXED)
+                                or groups of V-cycles (FP64) */
     int nu1, nu2;            /* red-black Gauss-Seidel sweeps before / after */
-    int cycles_per_outer;    /* FP32 V-cycles per refinement step (MIXED) */
+    int cycles_per_outer;    /* V-cycles between residual checks (FP32
+                                V-cycles per refinement step in MIXED);
+                                0: predicted from the last step's
+                                contraction (1 to 4) */
     double bottom_rtol;      /* BiCGStab tolerance on the coarsest grid */
     int bottom_max_iter;     /* BiCGStab iteration cap */
     int demean;              /* 1: remove the mean of the rhs; 0: require mean ~ 0 */
@@ -104,7 +108,8 @@ typedef struct mp_config {
 
 /* Per-call report, filled by mp_mac_project and mp_solve. */
 typedef struct mp_info {
-    int outer_iters;         /* refinement steps (MIXED) or V-cycles (FP64) */
+    int outer_iters;         /* residual checks after the first (refinement
+                                steps in MIXED) */
     int vcycles;             /* V-cycles run */
     int bottom_iters_total;  /* reserved (BiCGStab counts stay on the device) */
     int levels;              /* multigrid levels, finest included */
@@ -112,7 +117,7 @@ typedef struct mp_info {
     double div_defect;       /* ||D(beta0 U_new) - beta0 S - m||_2 / ||rhs||_2 */
     double rhs_norm;         /* ||rhs||_2 after the mean is removed */
     double rhs_mean;         /* mean removed from div(beta0 U) - beta0 S */
-    double resid_hist[64];   /* relative residual before each step */
+    double resid_hist[64];   /* relative residual at each check */
     double ms_rhs, ms_solve, ms_correct;   /* phase times (HIP events) */
     double smooth_ms_total;  /* summed finest-level smoother time (kernel_timing) */
     int smooth_launches;     /* number of launches summed above */
@@ -123,7 +128,8 @@ typedef struct mp_info {
 typedef struct mp_ctx mp_ctx;
 
 /* Fill *cfg with defaults for an nx x ny x nz grid: h = 1/nz, periodic x/y,
- * Neumann z, MIXED, rtol 1e-10, max_outer 100, V(2,2), 1 cycle per step,
+ * Neumann z, MIXED, rtol 1e-10, max_outer 100, V(2,2), predicted cycles per
+ * step,
  * bottom 1e-8 / 400 iterations, demean 1, automatic smoother, coarse cycle on,
  * blocked kernels on, null stream, device 0. */
 void mp_config_default(mp_config *cfg, int nx, int ny, int nz);
@@ -165,6 +171,11 @@ int mp_mac_project(mp_ctx *ctx, double *ux, double *uy, double *uz, const double
 /* Solve M x = rhs (rhs mean removed when demean = 1); x mean-zero.  This is
  * also the adjoint solve, M being symmetric. */
 int mp_solve(mp_ctx *ctx, const double *rhs, double *x, int use_initial_guess, mp_info *info);
+
+/* Switch the per-launch timing of the finest-level smoother (mp_config
+ * kernel_timing) on or off for the following calls; it records a start and
+ * end timestamp with each of those launches.  Errors: MP_ERR_ARG, MP_ERR_DEVICE. */
+int mp_set_kernel_timing(mp_ctx *ctx, int on);
 
 /* y = M x with the context's FP64 level-0 coefficients. */
 int mp_apply(mp_ctx *ctx, const double *x, double *y);

@@ -24,6 +24,8 @@
 #include "mp_device.h"
 #include "mp_kernels.h"
 
+#include <hip/hip_ext.h>
+
 namespace mp {
 
 constexpr int BK_W = 4;  // wavefronts per block
@@ -671,63 +673,74 @@ int blk_reduce_blocks(const Dims& d)
     return (int)(g.x * g.y * g.z);
 }
 
+// Launch timing: when ev0 != nullptr the launch records its start and end
+// in (ev0, ev1) (timestamps of the dispatch itself, no extra stream markers).
+struct LaunchEv {
+    hipEvent_t ev0, ev1;
+};
+
 template <typename T, int MODE, int M, bool IRU>
 static void gs_launch(const Dims& d, T* x, const T* b, const T* cc, T h2, int colour, const T* ec, double* phi,
-                      const double* irs, hipStream_t s)
+                      const double* irs, LaunchEv ev, hipStream_t s)
 {
     constexpr int R = rows_for<T>(M);
     int lz;
     const dim3 grid = blk_grid(d, M, R, kBlkMinBlocks, 1LL << 30, lz);
-    hipLaunchKernelGGL((k_gs_blk<T, MODE, M, R, IRU>), grid, dim3(256), 0, s, d, lz, x, b, cc, h2, colour, ec, phi,
-                       irs);
+    if (ev.ev0)
+        hipExtLaunchKernelGGL((k_gs_blk<T, MODE, M, R, IRU>), grid, dim3(256), 0, s, ev.ev0, ev.ev1, 0, d, lz, x, b,
+                              cc, h2, colour, ec, phi, irs);
+    else
+        hipLaunchKernelGGL((k_gs_blk<T, MODE, M, R, IRU>), grid, dim3(256), 0, s, d, lz, x, b, cc, h2, colour, ec,
+                           phi, irs);
 }
 
 template <typename T, int M, bool IRU>
 static void gs_mode(int mode, const Dims& d, T* x, const T* b, const T* cc, T h2, int colour, const T* ec,
-                    double* phi, const double* irs, hipStream_t s)
+                    double* phi, const double* irs, LaunchEv ev, hipStream_t s)
 {
     if constexpr (IRU) {
         // the refinement update rides on the last pass of a V-cycle: colour 1
         // of a plain sweep, or of the first sweep after prolongation
-        if (mode == GS_E_OWN) gs_launch<T, GS_E_OWN, M, true>(d, x, b, cc, h2, colour, ec, phi, irs, s);
-        else gs_launch<T, GS_PLAIN, M, true>(d, x, b, cc, h2, colour, ec, phi, irs, s);
+        if (mode == GS_E_OWN) gs_launch<T, GS_E_OWN, M, true>(d, x, b, cc, h2, colour, ec, phi, irs, ev, s);
+        else gs_launch<T, GS_PLAIN, M, true>(d, x, b, cc, h2, colour, ec, phi, irs, ev, s);
         return;
     }
     switch (mode) {
-    case GS_ZERO: gs_launch<T, GS_ZERO, M, false>(d, x, b, cc, h2, colour, ec, phi, irs, s); break;
-    case GS_E_ALL: gs_launch<T, GS_E_ALL, M, false>(d, x, b, cc, h2, colour, ec, phi, irs, s); break;
-    case GS_E_OWN: gs_launch<T, GS_E_OWN, M, false>(d, x, b, cc, h2, colour, ec, phi, irs, s); break;
-    default: gs_launch<T, GS_PLAIN, M, false>(d, x, b, cc, h2, colour, ec, phi, irs, s); break;
+    case GS_ZERO: gs_launch<T, GS_ZERO, M, false>(d, x, b, cc, h2, colour, ec, phi, irs, ev, s); break;
+    case GS_E_ALL: gs_launch<T, GS_E_ALL, M, false>(d, x, b, cc, h2, colour, ec, phi, irs, ev, s); break;
+    case GS_E_OWN: gs_launch<T, GS_E_OWN, M, false>(d, x, b, cc, h2, colour, ec, phi, irs, ev, s); break;
+    default: gs_launch<T, GS_PLAIN, M, false>(d, x, b, cc, h2, colour, ec, phi, irs, ev, s); break;
     }
 }
 
 template <typename T, bool IRU>
 static void gs_width(int mode, const Dims& d, T* x, const T* b, const T* cc, T h2, int colour, const T* ec,
-                     double* phi, const double* irs, hipStream_t s)
+                     double* phi, const double* irs, LaunchEv ev, hipStream_t s)
 {
     if constexpr (sizeof(T) == 8) {
-        gs_mode<T, 1, IRU>(mode, d, x, b, cc, h2, colour, ec, phi, irs, s);  // FP64: pairs
+        gs_mode<T, 1, IRU>(mode, d, x, b, cc, h2, colour, ec, phi, irs, ev, s);  // FP64: pairs
     } else {
         switch (strip_pairs(d)) {
-        case 4: gs_mode<T, 4, IRU>(mode, d, x, b, cc, h2, colour, ec, phi, irs, s); break;
-        case 3: gs_mode<T, 3, IRU>(mode, d, x, b, cc, h2, colour, ec, phi, irs, s); break;
-        case 2: gs_mode<T, 2, IRU>(mode, d, x, b, cc, h2, colour, ec, phi, irs, s); break;
-        default: gs_mode<T, 1, IRU>(mode, d, x, b, cc, h2, colour, ec, phi, irs, s); break;
+        case 4: gs_mode<T, 4, IRU>(mode, d, x, b, cc, h2, colour, ec, phi, irs, ev, s); break;
+        case 3: gs_mode<T, 3, IRU>(mode, d, x, b, cc, h2, colour, ec, phi, irs, ev, s); break;
+        case 2: gs_mode<T, 2, IRU>(mode, d, x, b, cc, h2, colour, ec, phi, irs, ev, s); break;
+        default: gs_mode<T, 1, IRU>(mode, d, x, b, cc, h2, colour, ec, phi, irs, ev, s); break;
         }
     }
 }
 
 template <typename T>
 void launch_gs_blk(const Dims& d, T* x, const T* b, const T* cc, T h2, int colour, int mode, const T* ec,
-                   double* phi, const double* irs, hipStream_t s)
+                   double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
 {
+    const LaunchEv ev{ev0, ev1};
     if constexpr (sizeof(T) == 4) {
         if (phi) {
-            gs_width<T, true>(mode, d, x, b, cc, h2, colour, ec, phi, irs, s);
+            gs_width<T, true>(mode, d, x, b, cc, h2, colour, ec, phi, irs, ev, s);
             return;
         }
     }
-    gs_width<T, false>(mode, d, x, b, cc, h2, colour, ec, nullptr, nullptr, s);
+    gs_width<T, false>(mode, d, x, b, cc, h2, colour, ec, nullptr, nullptr, ev, s);
 }
 
 template <typename T, int M>
@@ -766,9 +779,9 @@ void launch_resid64_blk(const Dims& d, const double* x, const double* b, const d
 }
 
 template void launch_gs_blk<float>(const Dims&, float*, const float*, const float*, float, int, int, const float*,
-                                   double*, const double*, hipStream_t);
+                                   double*, const double*, hipEvent_t, hipEvent_t, hipStream_t);
 template void launch_gs_blk<double>(const Dims&, double*, const double*, const double*, double, int, int,
-                                    const double*, double*, const double*, hipStream_t);
+                                    const double*, double*, const double*, hipEvent_t, hipEvent_t, hipStream_t);
 template void launch_rr_blk<float>(const Dims&, const float*, const float*, const float*, float, float*, hipStream_t);
 template void launch_rr_blk<double>(const Dims&, const double*, const double*, const double*, double, double*,
                                     hipStream_t);

@@ -125,7 +125,7 @@ int check_config(const mp_config* c, mp_ctx* ctx)
     if (c->max_outer < 0 || c->max_outer > 10000) return fail(ctx, MP_ERR_ARG, "bad max_outer");
     if (c->nu1 < 0 || c->nu2 < 0 || c->nu1 + c->nu2 < 1 || c->nu1 > 16 || c->nu2 > 16)
         return fail(ctx, MP_ERR_ARG, "nu1/nu2 out of range");
-    if (c->cycles_per_outer < 1 || c->cycles_per_outer > 16) return fail(ctx, MP_ERR_ARG, "bad cycles_per_outer");
+    if (c->cycles_per_outer < 0 || c->cycles_per_outer > 16) return fail(ctx, MP_ERR_ARG, "bad cycles_per_outer");
     if (!(c->bottom_rtol > 0.0) || c->bottom_max_iter < 1) return fail(ctx, MP_ERR_ARG, "bad bottom settings");
     if (c->demean != 0 && c->demean != 1) return fail(ctx, MP_ERR_ARG, "demean must be 0 or 1");
     if (c->smoother != MP_SMOOTH_AUTO && c->smoother != MP_SMOOTH_PER_COLOUR && c->smoother != MP_SMOOTH_FUSED)
@@ -155,7 +155,8 @@ void free_all(mp_ctx* c)
     if (c->hscal) (void)hipHostFree(c->hscal);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
-    for (auto& e : c->kev) (void)hipEventDestroy(e);
+    for (auto& e : c->kev)
+        if (e) (void)hipEventDestroy(e);
     c->kev.clear();
 }
 
@@ -221,6 +222,17 @@ void build_pyramid(mp_ctx* c)
     }
 }
 
+// Event pool for per-launch timing of the finest-level smoother.
+int make_timing_events(mp_ctx* c)
+{
+    if (!c->kev.empty()) return MP_OK;
+    c->kev.assign(2048, nullptr);
+    c->kev_bytes.assign(1024, 0.0);
+    for (auto& ev : c->kev)
+        if (hipEventCreate(&ev) != hipSuccess) return fail(c, MP_ERR_DEVICE, "hipEventCreate failed");
+    return MP_OK;
+}
+
 void timed_begin(mp_ctx* c, bool on)
 {
     if (on && c->kev_used + 1 < (int)c->kev.size()) (void)hipEventRecord(c->kev[c->kev_used], c->stream);
@@ -263,11 +275,17 @@ void smooth(mp_ctx* c, int l, bool zero_init, const T* ec, bool last = false)
             const int mode = zi ? mp::GS_ZERO : !ec ? mp::GS_PLAIN : colour == 0 ? mp::GS_E_ALL : mp::GS_E_OWN;
             const bool iru = last && colour == 1 && c->ir_phi != nullptr;
             const double words = (zi ? 3.0 : 4.0) + (ec ? 0.125 : 0.0);
-            timed_begin(c, tm);
-            mp::launch_gs_blk<T>(L.d, (T*)L.x, (const T*)L.b, C.cell, h2, colour, mode, ec,
-                                 iru ? c->ir_phi : nullptr, iru ? c->ir_s : nullptr, c->stream);
             // the fused refinement update adds 16 bytes per cell (phi in and out)
-            timed_end(c, tm, words * sizeof(T) * cells + (iru ? 16.0 * cells : 0.0));
+            const double bytes = words * sizeof(T) * cells + (iru ? 16.0 * cells : 0.0);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (tm && c->kev_used + 1 < (int)c->kev.size()) {
+                e0 = c->kev[c->kev_used];
+                e1 = c->kev[c->kev_used + 1];
+                c->kev_bytes[c->kev_used / 2] = bytes;
+                c->kev_used += 2;
+            }
+            mp::launch_gs_blk<T>(L.d, (T*)L.x, (const T*)L.b, C.cell, h2, colour, mode, ec,
+                                 iru ? c->ir_phi : nullptr, iru ? c->ir_s : nullptr, e0, e1, c->stream);
         }
         return;
     }
@@ -349,6 +367,21 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
         smooth<T>(c, l, false, s == 0 ? (const T*)C.x : (const T*)nullptr, s == c->cfg.nu2 - 1);
 }
 
+// V-cycles before the next residual check.  cycles_per_outer > 0 fixes the
+// count; 0 predicts it from the contraction of the last step,
+// rho = (rel / rel_prev)^(1 / m_prev): about log(rtol / rel) / log(rho)
+// cycles, at least 1 and at most 4 (FP32 corrections gain nothing beyond).
+int cycles_this_step(const mp_ctx* c, int it, double rel, double rel_prev, int m_prev)
+{
+    if (c->cfg.cycles_per_outer > 0) return c->cfg.cycles_per_outer;
+    if (it == 0 || !(rel_prev > 0.0) || !(rel > 0.0)) return 1;
+    const double rho = pow(rel / rel_prev, 1.0 / m_prev);
+    if (!(rho > 0.0) || rho >= 0.5) return 1;
+    const double need = log(c->cfg.rtol / rel) / log(rho);
+    const int m = (int)ceil(need - 0.25);
+    return m < 1 ? 1 : m > 4 ? 4 : m;
+}
+
 // Solve A phi = b64 (b64 mean-zero, ||b64||^2 = nb2 in hscal[S_NB2]).
 int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
 {
@@ -368,9 +401,9 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
     const bool mx = mixed(c);
     if (!mx) c->lv[0].x = phi;  // x2 stays the internal second buffer
     int status = MP_ERR_NOT_CONVERGED;
-    double rel = 1.0;
+    double rel = 1.0, rel_prev = 1.0;
     double hist[64];
-    int vc = 0, it = 0;
+    int vc = 0, it = 0, m_prev = 1;
     for (it = 0;; it++) {
         const int p = it & 1;
         double* sp = c->dscal + S_PAIR0 + 2 * p;
@@ -409,12 +442,15 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
             fail(c, MP_ERR_NOT_CONVERGED, "stagnated at step %d (rel. residual %.3e)", it, rel);
             break;
         }
+        const int m = cycles_this_step(c, it, rel, rel_prev, m_prev);
+        rel_prev = rel;
+        m_prev = m;
         if (mx) {
             // the last V-cycle of the step applies phi += s e in its final
             // smoother pass when the finest level runs blocked kernels
             const bool fuse_ir = use_blk(c, 0) && c->cfg.nu2 >= 1;
-            for (int k = 0; k < c->cfg.cycles_per_outer; k++) {
-                const bool lastc = k == c->cfg.cycles_per_outer - 1;
+            for (int k = 0; k < m; k++) {
+                const bool lastc = k == m - 1;
                 c->ir_phi = fuse_ir && lastc ? phi : nullptr;
                 c->ir_s = sp;
                 vcycle<float>(c, 0, k == 0);
@@ -423,12 +459,15 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
             }
             if (!fuse_ir) mp::launch_ir_update(n, phi, (const float*)c->lv[0].x, sp, c->stream);
         } else {
-            vcycle<double>(c, 0, it == 0 && !use_guess);
-            vc++;
-            // out-of-place sweeps may leave the iterate in the second buffer
-            if (c->lv[0].x != (void*)phi) {
-                HIPCHK(c, hipMemcpyAsync(phi, c->lv[0].x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-                std::swap(c->lv[0].x, c->lv[0].x2);
+            for (int k = 0; k < m; k++) {
+                vcycle<double>(c, 0, it == 0 && k == 0 && !use_guess);
+                vc++;
+                // out-of-place sweeps may leave the iterate in the second buffer
+                if (c->lv[0].x != (void*)phi) {
+                    HIPCHK(c,
+                           hipMemcpyAsync(phi, c->lv[0].x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+                    std::swap(c->lv[0].x, c->lv[0].x2);
+                }
             }
         }
     }
@@ -494,7 +533,7 @@ void mp_config_default(mp_config* cfg, int nx, int ny, int nz)
     cfg->max_outer = 100;
     cfg->nu1 = 2;
     cfg->nu2 = 2;
-    cfg->cycles_per_outer = 1;
+    cfg->cycles_per_outer = 0;
     cfg->bottom_rtol = 1e-8;
     cfg->bottom_max_iter = 400;
     cfg->demean = 1;
@@ -626,12 +665,7 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
         good = false;
     for (auto& ev : c->ev)
         if (good && hipEventCreate(&ev) != hipSuccess) good = false;
-    if (good && cfg->kernel_timing) {
-        c->kev.resize(2048);
-        c->kev_bytes.assign(1024, 0.0);
-        for (auto& ev : c->kev)
-            if (good && hipEventCreate(&ev) != hipSuccess) good = false;
-    }
+    if (good && cfg->kernel_timing && make_timing_events(c) != MP_OK) good = false;
     if (!good) {
         free_all(c);
         delete c;
@@ -818,6 +852,19 @@ int mp_solve(mp_ctx* c, const double* rhs, double* x, int use_initial_guess, mp_
     HIPCHK(c, hipStreamSynchronize(c->stream));
     finish_timing(c, info);
     return solve_st;
+}
+
+int mp_set_kernel_timing(mp_ctx* c, int on)
+{
+    if (!c) return MP_ERR_ARG;
+    if (on != 0 && on != 1) return fail(c, MP_ERR_ARG, "on must be 0 or 1");
+    (void)hipSetDevice(c->cfg.device);
+    if (on) {
+        int st = make_timing_events(c);
+        if (st) return st;
+    }
+    c->cfg.kernel_timing = on;
+    return MP_OK;
 }
 
 int mp_apply(mp_ctx* c, const double* x, double* y)

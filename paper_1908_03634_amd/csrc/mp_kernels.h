@@ -155,10 +155,11 @@ int blk_reduce_blocks(const Dims& d);
 //              followed by two GS_PLAIN passes.
 enum { GS_PLAIN = 0, GS_ZERO = 1, GS_E_ALL = 2, GS_E_OWN = 3 };
 // phi != nullptr (FP32 only): also phi += irs[0] * x on every cell (the
-// refinement update fused into the last pass of a V-cycle).
+// refinement update fused into the last pass of a V-cycle).  ev0 != nullptr:
+// the launch records its own start and end in ev0 / ev1.
 template <typename T>
 void launch_gs_blk(const Dims& d, T* x, const T* b, const T* cc, T h2, int colour, int mode, const T* ec,
-                   double* phi, const double* irs, hipStream_t s);
+                   double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
 // Coarse rhs = mean of the 8 fine residuals b - A x (as launch_resid_restrict).
 template <typename T>
 void launch_rr_blk(const Dims& d, const T* x, const T* b, const T* cc, T inv_h2, T* bc, hipStream_t s);

@@ -90,7 +90,7 @@ class Info(ctypes.Structure):
 
 # Every exported symbol of include/mproj.h.
 EXPORTS = ["mp_config_default", "mp_init", "mp_map_base_state", "mp_set_coefs", "mp_mac_project", "mp_solve",
-           "mp_apply", "mp_coef_grad", "mp_free", "mp_last_error", "mp_version"]
+           "mp_set_kernel_timing", "mp_apply", "mp_coef_grad", "mp_free", "mp_last_error", "mp_version"]
 
 _lib = None
 
@@ -119,6 +119,8 @@ def load_library(path=None):
     lib.mp_mac_project.restype = I
     lib.mp_solve.argtypes = [P, P, P, I, ctypes.POINTER(Info)]
     lib.mp_solve.restype = I
+    lib.mp_set_kernel_timing.argtypes = [P, I]
+    lib.mp_set_kernel_timing.restype = I
     lib.mp_apply.argtypes = [P, P, P]
     lib.mp_apply.restype = I
     lib.mp_coef_grad.argtypes = [P, P, P, P, P, P]
@@ -144,7 +146,7 @@ class Context:
     hierarchy on one device and stream."""
 
     def __init__(self, nx, ny, nz, h=None, bc=(PERIODIC, PERIODIC, NEUMANN), precision="mixed", rtol=1e-10,
-                 max_outer=100, nu1=2, nu2=2, cycles_per_outer=1, bottom_rtol=1e-8, bottom_max_iter=400,
+                 max_outer=100, nu1=2, nu2=2, cycles_per_outer=0, bottom_rtol=1e-8, bottom_max_iter=400,
                  demean=True, kernel_timing=False, smoother="auto", coarse_cycle=True, blocked=True, device=None, stream=None):
         self.lib = load_library()
         if not torch.cuda.is_available():
@@ -261,6 +263,10 @@ class Context:
             self._check(code, "mp_solve", d)
         d["status"] = code
         return x, d
+
+    def set_kernel_timing(self, on):
+        """Time the finest-level smoother launches of the following calls."""
+        self._check(self.lib.mp_set_kernel_timing(self._h, 1 if on else 0), "mp_set_kernel_timing")
 
     def apply(self, x, out=None):
         """M x = div(c grad x) with the FP64 finest-level coefficients."""

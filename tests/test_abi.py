@@ -52,8 +52,9 @@ def test_defaults():
 
 
 @pytest.mark.parametrize("field,value", [("nx", 0), ("h", 0.0), ("rtol", 0.0), ("rtol", 1.5), ("precision", 7),
-                                         ("nu1", -1), ("cycles_per_outer", 0), ("demean", 3),
-                                         ("bottom_max_iter", 0)])
+                                         ("nu1", -1), ("cycles_per_outer", -1), ("demean", 3),
+                                         ("bottom_max_iter", 0), ("smoother", 9), ("coarse_cycle", 2),
+                                         ("blocked", 2)])
 def test_bad_config_is_rejected_before_any_device_call(field, value):
     lib, c = _cfg()
     setattr(c, field, value)
@@ -77,6 +78,10 @@ def test_null_arguments():
     assert lib.mp_map_base_state(None, 0, None, 0, 0.0, None, None, None, None, None) == 1
     assert lib.mp_mac_project(None, None, None, None, None, None, 0, None) == 1
     assert lib.mp_solve(None, None, None, 0, None) == 1
+    assert lib.mp_set_coefs(None, None, None, None) == 1
+    assert lib.mp_set_kernel_timing(None, 1) == 1
+    assert lib.mp_apply(None, None, None) == 1
+    assert lib.mp_coef_grad(None, None, None, None, None, None) == 1
     assert lib.mp_version().startswith(b"mproj")
 
 
