@@ -40,7 +40,7 @@ def _parse():
     ap.add_argument("--cpu-samples", type=int, default=1, help="oracle projections timed on the host")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one precision only")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 256 MiB device copy (reference for the HBM traffic counters)")
+                    help="also run a 256 MiB streaming copy (reference for the HBM traffic counters)")
     return ap.parse_args()
 
 
@@ -66,6 +66,15 @@ def _traffic_record(kernel):
     if digest != rec.get("sha256"):
         return None
     return rec
+
+
+def _describe(p):
+    bcs = "".join("PN"[b] for b in p.bc)
+    if p.geometry == 0:
+        shape = f"plane-parallel exponential atmosphere, {p.meta.get('contrast'):.0e} density contrast"
+    else:
+        shape = f"spherical star (linear radial fill at dr = h/5), {p.meta.get('contrast'):.0e} contrast to the box face"
+    return f"{p.nx}x{p.ny}x{p.nz} {shape}, boundaries (x,y,z) {bcs}"
 
 
 def main():
@@ -122,13 +131,17 @@ def main():
         return dt, infos
 
     if args.copy_calibration:
+        # a streaming kernel of known traffic (reads and writes 256 MiB each;
+        # an elementwise product, so its name differs from every copy the
+        # benchmark makes) to scale the HBM counters of the other kernels
         nbytes = 256 << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
-        print(f"[bench] copy calibration: 3 copies of {nbytes} bytes", file=sys.stderr, flush=True)
+        print(f"[bench] copy calibration: 3 elementwise copies reading and writing {nbytes} bytes each",
+              file=sys.stderr, flush=True)
         del src, dst
 
     res = {}
@@ -158,12 +171,16 @@ def main():
     bytes_per_launch = tot_bytes / cnt if cnt else float("nan")
     achieved = bytes_per_launch / avg_s / 1e9
     kname = "k_gs_blk<float>" if main_prec == "mixed" else "k_gs_blk<double>"
-    rec = _traffic_record(kname)
+    rec = _traffic_record(f"{args.workload}:{kname}")
     traffic = None
     if rec:
+        # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counters,
+        # averaged over the same launches as `achieved` and scaled by the
+        # counters' reading of the calibration copy
         traffic = {"fetch_bytes": rec["fetch_bytes"], "write_bytes": rec["write_bytes"],
                    "total_bytes": rec["fetch_bytes"] + rec["write_bytes"],
-                   "algorithmic_bytes": rec.get("algorithmic_bytes"), "calibration": rec.get("calibration")}
+                   "algorithmic_bytes": rec.get("algorithmic_bytes"), "calibration": rec.get("calibration"),
+                   "summary": rec.get("summary")}
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": traffic["total_bytes"] if traffic else None, "traffic_detail": traffic,
@@ -199,8 +216,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if main_prec == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {p.nx}^3 plane-parallel, periodic x/y, Neumann z, "
-                               f"{p.meta.get('contrast'):.0e} density contrast; map + rhs + solve to 1e-10 + "
+        "config": {"workload": f"{args.workload}: {_describe(p)}; map + rhs + solve to 1e-10 + "
                                f"velocity correction per step",
                    "precision": main_prec, "smoother": "red-black Gauss-Seidel V(2,2)",
                    "outer_steps": last["outer_iters"], "vcycles": last["vcycles"], "rel_resid": last["rel_resid"],

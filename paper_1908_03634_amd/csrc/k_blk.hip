@@ -29,6 +29,7 @@
 namespace mp {
 
 constexpr int BK_W = 4;  // wavefronts per block
+constexpr int BK_T = 64 * BK_W;  // threads per block
 
 template <typename T>
 struct V2;
@@ -131,18 +132,34 @@ struct BlkGeo {
     bool ylast;   // row j0 + R - 1 has a face above
 };
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup p runs on XCD p % 8),
+// and each XCD has its own L2.  Renumbering so that every XCD receives one
+// contiguous run of (x tile, row block, plane chunk) keeps the halo rows and
+// planes shared by neighbouring blocks inside one L2.
+__device__ __forceinline__ void blk_tile(unsigned& bx, unsigned& by, unsigned& bz)
+{
+    const unsigned gx = gridDim.x, gy = gridDim.y, n = gridDim.x * gridDim.y * gridDim.z;
+    unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    if (n % 8 == 0) p = (p % 8) * (n / 8) + p / 8;
+    bx = p % gx;
+    by = (p / gx) % gy;
+    bz = p / (gx * gy);
+}
+
 template <int M, int R>
 __device__ __forceinline__ BlkGeo blk_geo(const Dims& d, int lz)
 {
     constexpr int W = 128 * M;  // columns per wavefront
+    unsigned bx, by, bz;
+    blk_tile(bx, by, bz);
     BlkGeo g;
     g.lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    const int x0 = blockIdx.x * W;
+    const int x0 = (int)bx * W;
     g.xi = x0 + 2 * M * g.lane;
-    g.j0 = (blockIdx.y * BK_W + w) * R;
+    g.j0 = ((int)by * BK_W + w) * R;
     g.live = g.j0 < d.ny;
-    g.z0 = blockIdx.z * lz;
+    g.z0 = (int)bz * lz;
     g.z1 = min(g.z0 + lz, d.nz);
     const bool whole = W == d.nx;
     g.hal = !whole && (g.lane == 0 || g.lane == kWave - 1);
@@ -265,7 +282,7 @@ __device__ __forceinline__ Strip<T, M> add_e(const Strip<T, M>& x, const EStrip<
 // IRU (FP32 only, last pass of a V-cycle): also phi += s[0] * x on every
 // cell (the refinement update, otherwise a separate pass).
 template <typename T, int MODE, int M, int R, bool IRU>
-__global__ __launch_bounds__(256) void k_gs_blk(Dims d, int lz, T* __restrict__ x, const T* __restrict__ b,
+__global__ __launch_bounds__(BK_T) void k_gs_blk(Dims d, int lz, T* __restrict__ x, const T* __restrict__ b,
                                                 const T* __restrict__ cc, T h2, int colour, const T* __restrict__ ec,
                                                 double* __restrict__ phi, const double* __restrict__ irs)
 {
@@ -532,7 +549,7 @@ __device__ __forceinline__ void ring_shift(Strip<T, M> (&xm)[R], Strip<T, M> (&x
 // holds the x children of M coarse cells; planes are taken in pairs (chunks
 // start on even planes), rows in pairs (j0 is even).
 template <typename T, int M, int R>
-__global__ __launch_bounds__(256) void k_rr_blk(Dims d, int lz, const T* __restrict__ x, const T* __restrict__ b,
+__global__ __launch_bounds__(BK_T) void k_rr_blk(Dims d, int lz, const T* __restrict__ x, const T* __restrict__ b,
                                                 const T* __restrict__ cc, T inv_h2, T* __restrict__ bc)
 {
     using S = Strip<T, M>;
@@ -585,7 +602,7 @@ __global__ __launch_bounds__(256) void k_rr_blk(Dims d, int lz, const T* __restr
 // FP64 refinement residual r = b - A x, its scaled FP32 copy
 // r32 = float(r * inv_s[0]) (when r32 != nullptr) and per-block sums of r^2.
 template <int M, int R>
-__global__ __launch_bounds__(256) void k_resid64_blk(Dims d, int lz, const double* __restrict__ x,
+__global__ __launch_bounds__(BK_T) void k_resid64_blk(Dims d, int lz, const double* __restrict__ x,
                                                      const double* __restrict__ b, const double* __restrict__ cc,
                                                      double inv_h2, float* __restrict__ r32,
                                                      const double* __restrict__ inv_s, double* partials)
@@ -687,10 +704,10 @@ static void gs_launch(const Dims& d, T* x, const T* b, const T* cc, T h2, int co
     int lz;
     const dim3 grid = blk_grid(d, M, R, kBlkMinBlocks, 1LL << 30, lz);
     if (ev.ev0)
-        hipExtLaunchKernelGGL((k_gs_blk<T, MODE, M, R, IRU>), grid, dim3(256), 0, s, ev.ev0, ev.ev1, 0, d, lz, x, b,
+        hipExtLaunchKernelGGL((k_gs_blk<T, MODE, M, R, IRU>), grid, dim3(BK_T), 0, s, ev.ev0, ev.ev1, 0, d, lz, x, b,
                               cc, h2, colour, ec, phi, irs);
     else
-        hipLaunchKernelGGL((k_gs_blk<T, MODE, M, R, IRU>), grid, dim3(256), 0, s, d, lz, x, b, cc, h2, colour, ec,
+        hipLaunchKernelGGL((k_gs_blk<T, MODE, M, R, IRU>), grid, dim3(BK_T), 0, s, d, lz, x, b, cc, h2, colour, ec,
                            phi, irs);
 }
 
@@ -749,7 +766,7 @@ static void rr_launch(const Dims& d, const T* x, const T* b, const T* cc, T inv_
     constexpr int R = rows_for<T>(M);
     int lz;
     const dim3 grid = blk_grid(d, M, R, kBlkMinBlocks, 1LL << 30, lz);
-    hipLaunchKernelGGL((k_rr_blk<T, M, R>), grid, dim3(256), 0, s, d, lz, x, b, cc, inv_h2, bc);
+    hipLaunchKernelGGL((k_rr_blk<T, M, R>), grid, dim3(BK_T), 0, s, d, lz, x, b, cc, inv_h2, bc);
 }
 
 template <typename T>
@@ -774,7 +791,7 @@ void launch_resid64_blk(const Dims& d, const double* x, const double* b, const d
     int lz;
     const dim3 grid = blk_grid(d, kResidPairs, R, kBlkMinBlocks, kMaxRedBlocks, lz);
     *nb_out = (int)(grid.x * grid.y * grid.z);
-    hipLaunchKernelGGL((k_resid64_blk<kResidPairs, R>), grid, dim3(256), 0, s, d, lz, x, b, cc, inv_h2, r32, inv_s,
+    hipLaunchKernelGGL((k_resid64_blk<kResidPairs, R>), grid, dim3(BK_T), 0, s, d, lz, x, b, cc, inv_h2, r32, inv_s,
                        partials);
 }
 
