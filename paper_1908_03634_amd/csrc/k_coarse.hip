@@ -1,7 +1,8 @@
 // k_coarse.hip -- the coarse end of a V-cycle in one workgroup.
 //
-// Below about 16^3 cells a level's kernels finish in well under the cost of a
-// launch, so a V-cycle spends most of its coarse-grid time in launch gaps.
+// On the smallest levels (a few hundred cells) a kernel finishes in well under
+// the cost of a launch, so a V-cycle would spend its coarse-grid time in launch
+// gaps.
 // This kernel runs every level of the coarse set (pre-smoothing, residual
 // restriction, bottom solve, prolongation, post-smoothing) in a single
 // 1024-thread workgroup, separated by workgroup barriers.  The per-cell
