@@ -40,6 +40,7 @@ struct Level {
     bool own_x = false, own_b = false, own_c = false, own_x2 = false;
     bool fused = false;  // both colours in one launch on this level
     bool blk = false;    // register-blocked kernels (finest level, cell mode)
+    bool fsw = false;    // ... with both colours of a sweep in one pass
 };
 
 constexpr long long kCoarseCells = 512;  // levels at or below run in one workgroup
@@ -264,6 +265,28 @@ void smooth(mp_ctx* c, int l, bool zero_init, const T* ec, bool last = false)
         mp::launch_sweep<T>(L.d, (const T*)L.x, (T*)L.x2, (const T*)L.b, (const T*)L.cx, (const T*)L.cy,
                             (const T*)L.cz, h2, zero_init ? 1 : 0, ec, c->stream);
         timed_end(c, tm, words * sizeof(T) * cells);
+        std::swap(L.x, L.x2);
+        return;
+    }
+    if (use_blk(c, l) && L.fsw && sizeof(T) == 4) {
+        // one pass for both colours, out of place: x read (not when zero) and
+        // written, b and c read, one word each per cell; 1/8 word of coarse
+        // correction after prolongation; 16 bytes per cell (phi in and out)
+        // when the refinement update rides on the sweep
+        const bool iru = last && c->ir_phi != nullptr;
+        const int mode = zero_init ? mp::FS_ZERO : ec ? mp::FS_PROLONG : mp::FS_PLAIN;
+        const double bytes =
+            ((zero_init ? 3.0 : 4.0) + (ec ? 0.125 : 0.0)) * sizeof(T) * cells + (iru ? 16.0 * cells : 0.0);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (tm && c->kev_used + 1 < (int)c->kev.size()) {
+            e0 = c->kev[c->kev_used];
+            e1 = c->kev[c->kev_used + 1];
+            c->kev_bytes[c->kev_used / 2] = bytes;
+            c->kev_used += 2;
+        }
+        if constexpr (sizeof(T) == 4)
+            mp::launch_fsw_blk<T>(L.d, (const T*)L.x, (T*)L.x2, (const T*)L.b, C.cell, h2, mode, ec,
+                                  iru ? c->ir_phi : nullptr, iru ? c->ir_s : nullptr, e0, e1, c->stream);
         std::swap(L.x, L.x2);
         return;
     }
@@ -646,6 +669,17 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
             c->coarse_start = lc;
         }
         c->lv[0].blk = cfg->blocked && nlev >= 2 && mp::blk_supported(c->d0);
+        // the one-pass sweep recomputes halo rows and keeps four planes in
+        // registers; on gfx950 two colour passes are faster, so it runs on
+        // request only
+        c->lv[0].fsw = c->lv[0].blk && mx && mp::fsw_supported(c->d0) && cfg->smoother == MP_SMOOTH_FUSED;
+        if (c->lv[0].fsw) {
+            void* p = nullptr;
+            e = hipMalloc(&p, tsz * c->n0);
+            good &= e == hipSuccess;
+            c->lv[0].x2 = p;
+            c->lv[0].own_x2 = true;
+        }
         for (int l = 0; l < nlev - 1; l++) {
             Level& L = c->lv[l];
             if (c->coarse_start >= 0 && l >= c->coarse_start) break;

@@ -160,6 +160,19 @@ enum { GS_PLAIN = 0, GS_ZERO = 1, GS_E_ALL = 2, GS_E_OWN = 3 };
 template <typename T>
 void launch_gs_blk(const Dims& d, T* x, const T* b, const T* cc, T h2, int colour, int mode, const T* ec,
                    double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
+// Both colours of one red-black sweep in one pass, out of place (xo -> xn),
+// in FP32 when fsw_supported(d) (blocked layout, nx = 128 or 256).  Modes:
+//   FS_PLAIN:   xo as stored;
+//   FS_ZERO:    xo is zero (not read);
+//   FS_PROLONG: xo + e of each cell's parent coarse cell (ec), i.e. the
+//               prolongation applied on the fly.
+// phi != nullptr (FP32): also phi += irs[0] * xn.  Equal bit for bit to two
+// launch_gs_blk colour passes.
+enum { FS_PLAIN = 0, FS_ZERO = 1, FS_PROLONG = 2 };
+bool fsw_supported(const Dims& d);
+template <typename T>
+void launch_fsw_blk(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, T h2, int mode, const T* ec,
+                    double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
 // Coarse rhs = mean of the 8 fine residuals b - A x (as launch_resid_restrict).
 template <typename T>
 void launch_rr_blk(const Dims& d, const T* x, const T* b, const T* cc, T inv_h2, T* bc, hipStream_t s);

@@ -142,3 +142,20 @@ def test_unaligned_solution_array_uses_one_cell_kernels():
     xb, _ = ctx.solve(T(rhs), x=xu)
     assert np.array_equal(N(xa), N(xb))
     ctx.close()
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(128, 12, 6), (128, 36, 32), (256, 20, 10), (256, 48, 64)])
+def test_fused_blocked_sweep_equals_colour_passes(shape, bc):
+    """Both colours of a sweep in one out-of-place pass (rows wider than the
+    owned ones recomputed, plane chunks started two planes early) equal the two
+    in-place colour passes bit for bit, through a refinement step and over a
+    full solve."""
+    say("fused blocked sweep", shape, bc)
+    p = _problem(shape, bc, 5000 + sum(shape))
+    rhs = W.random_cells(*shape, 5100 + sum(shape))
+    for kw in (dict(max_outer=1), dict(rtol=1e-11)):
+        xa, ia = _solve(p, "mixed", True, rhs, smoother="fused", **kw)
+        xb, ib = _solve(p, "mixed", True, rhs, smoother="per_colour", **kw)
+        assert np.array_equal(xa, xb)
+        assert ia["vcycles"] == ib["vcycles"]
