@@ -58,6 +58,12 @@ def _declare(lib):
     lib.or_dot.argtypes = [_I, _I, _I, _D, _D]
     lib.or_dot.restype = _F
     lib.or_num_threads.restype = _I
+    lib.or_radius_count.argtypes = [_I, _I, _I]
+    lib.or_radius_count.restype = ctypes.c_long
+    lib.or_radius_index.argtypes = [_I, _I, _I, ctypes.POINTER(ctypes.c_long)]
+    lib.or_radius_index.restype = _I
+    lib.or_average_irregular.argtypes = [_I, _I, _I, _D, ctypes.c_long, _D, _D]
+    lib.or_average_irregular.restype = _I
     return lib
 
 
@@ -154,8 +160,10 @@ def cell_radius(g, center):
 
 
 def fill_beta0(g, geometry, beta0_1d, dr, center):
-    """Fill module of Sec. 3.1: direct injection (planar, table per z cell) or
-    interpolation in r (spherical, table on (j+1/2) dr, linear)."""
+    """Fill module of Sec. 3.1: direct injection (planar, table per z cell),
+    interpolation in r on (j+1/2) dr (spherical: 1 linear, 3 quadratic), or
+    lookup by the radius index m (2, irregular base state; centre at the
+    middle node of the box)."""
     out = g.cells()
     b = np.ascontiguousarray(beta0_1d, dtype=np.float64)
     c = np.ascontiguousarray(center, dtype=np.float64)
@@ -163,6 +171,34 @@ def fill_beta0(g, geometry, beta0_1d, dr, center):
     if st:
         raise ValueError("bad base-state table for this geometry")
     return out
+
+
+def radius_count(nx, ny, nz):
+    """Number of radii h sqrt(0.75 + 2m) of the irregular base state (0 when an
+    extent is odd)."""
+    return int(_load().or_radius_count(nx, ny, nz))
+
+
+def radius_index(nx, ny, nz):
+    """Radius index m of every cell (cell layout, int64)."""
+    out = np.zeros((nz, ny, nx), dtype=np.int64)
+    st = _load().or_radius_index(nx, ny, nz, out.ctypes.data_as(ctypes.POINTER(ctypes.c_long)))
+    if st:
+        raise ValueError("the irregular base state needs even extents")
+    return out
+
+
+def average_irregular(phi):
+    """Lateral average over the irregular radii (Sec. 3.1): (avg, count) per m."""
+    nz, ny, nx = phi.shape
+    nm = radius_count(nx, ny, nz)
+    a = np.ascontiguousarray(phi, dtype=np.float64)
+    avg = np.zeros(nm)
+    cnt = np.zeros(nm)
+    st = _load().or_average_irregular(nx, ny, nz, _p(a), nm, _p(avg), _p(cnt))
+    if st:
+        raise ValueError("the irregular base state needs even extents")
+    return avg, cnt
 
 
 def face_coefs(g, beta0_cc, rho):

@@ -11,8 +11,11 @@
  *
  *  - fill (Sec. 3.1): the 1D base state beta0 mapped onto the Cartesian cells,
  *    by direct injection in planar geometry and by interpolation in the radius
- *    r = |x - centre| in spherical geometry (linear here, on the uniform radial
- *    grid r_j = (j + 1/2) dr);
+ *    r = |x - centre| in spherical geometry (linear or quadratic, on the
+ *    uniform radial grid r_j = (j + 1/2) dr), or, for the irregular base state,
+ *    by the index m of the radius h sqrt(0.75 + 2m) of each cell centre;
+ *  - the lateral Average (Sec. 3.1 and the Average module of Sec. 3.2) over
+ *    those irregular radii;
  *  - the MAC projection of Sec. 3.2 Steps 3 and 7 (the constraints div1/div2,
  *    i.e. the velocity constraint of Sec. 2 with the dp0/dt term folded into
  *    S) and Appendix A: find phi with
@@ -107,6 +110,75 @@ static double radial_lookup(const double *tab, int n1d, double dr, double r)
     return (1.0 - w) * tab[j] + w * tab[j + 1];
 }
 
+/* Quadratic interpolation of the same table: the Lagrange parabola through
+ * the three table points around the nearest one (the stencil kept inside the
+ * table), end values held beyond the first and last table points. */
+static double radial_quadratic(const double *tab, int n1d, double dr, double r)
+{
+    double t = r / dr - 0.5;
+    if (t <= 0.0) return tab[0];
+    if (t >= (double)(n1d - 1)) return tab[n1d - 1];
+    int j = (int)floor(t + 0.5);
+    if (j < 1) j = 1;
+    if (j > n1d - 2) j = n1d - 2;
+    double s = t - j;
+    return tab[j - 1] * (0.5 * s * (s - 1.0)) + tab[j] * (1.0 - s * s) + tab[j + 1] * (0.5 * s * (s + 1.0));
+}
+
+/* Irregular radial base state (Sec. 3.1): with the star centre on the grid
+ * node in the middle of the box (all extents even), the centre of cell
+ * (i,j,k) lies at distance h sqrt(0.75 + 2m) for the integer
+ *     m = ((2i+1-nx)^2 + (2j+1-ny)^2 + (2k+1-nz)^2 - 3) / 8,
+ * since the three offsets from the centre are odd multiples of h/2.  Returns
+ * -1 when an extent is odd. */
+static long radius_index(const grid_t *g, int i, int j, int k)
+{
+    long a = 2L * i + 1 - g->nx, b = 2L * j + 1 - g->ny, c = 2L * k + 1 - g->nz;
+    return (a * a + b * b + c * c - 3) / 8;
+}
+
+/* Number of radii of the irregular base state (m = 0 .. m_max), or 0 when an
+ * extent is odd (no grid node at the centre of the box). */
+long or_radius_count(int nx, int ny, int nz)
+{
+    if (nx % 2 || ny % 2 || nz % 2) return 0;
+    grid_t g = mkgrid(nx, ny, nz, 1.0, 0, 0, 0);
+    return radius_index(&g, 0, 0, 0) + 1;
+}
+
+/* m of every cell (layout of a cell array). */
+int or_radius_index(int nx, int ny, int nz, long *m)
+{
+    if (nx % 2 || ny % 2 || nz % 2) return 1;
+    grid_t g = mkgrid(nx, ny, nz, 1.0, 0, 0, 0);
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) m[cell(&g, i, j, k)] = radius_index(&g, i, j, k);
+    return 0;
+}
+
+/* Lateral average over the irregular radii (Sec. 3.1, the Average module of
+ * Sec. 3.2): the sum of phi over all cells whose centres lie at radius r_m,
+ * divided by the number of those cells.  Radii no cell centre reaches get
+ * count 0 and average 0.  Cells are summed in memory order. */
+int or_average_irregular(int nx, int ny, int nz, const double *phi, long nm, double *avg, double *count)
+{
+    if (nx % 2 || ny % 2 || nz % 2 || nm != or_radius_count(nx, ny, nz)) return 1;
+    grid_t g = mkgrid(nx, ny, nz, 1.0, 0, 0, 0);
+    double *sum = (double *)calloc((size_t)nm, sizeof(double));
+    for (long m = 0; m < nm; m++) count[m] = 0.0;
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                long m = radius_index(&g, i, j, k);
+                sum[m] += phi[cell(&g, i, j, k)];
+                count[m] += 1.0;
+            }
+    for (long m = 0; m < nm; m++) avg[m] = count[m] > 0.0 ? sum[m] / count[m] : 0.0;
+    free(sum);
+    return 0;
+}
+
 void or_cell_radius(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *center, double *r)
 {
     grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
@@ -116,13 +188,20 @@ void or_cell_radius(int nx, int ny, int nz, double h, int bx, int by, int bz, co
 }
 
 /* geometry 0: planar, table indexed by the z cell (n1d == nz, direct injection).
- * geometry 1: spherical, table on r_j = (j + 1/2) dr about `center`. */
+ * geometry 1: spherical, table on r_j = (j + 1/2) dr about `center`, linear.
+ * geometry 2: spherical irregular base state, table indexed by the radius
+ *             index m of each cell (n1d == number of radii; the centre is the
+ *             node in the middle of the box; no interpolation).
+ * geometry 3: as 1 with quadratic interpolation (uniform dr). */
 int or_fill_beta0(int nx, int ny, int nz, double h, int bx, int by, int bz, int geometry, const double *b1d, int n1d,
                   double dr, const double *center, double *beta0_cc)
 {
     grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
     if (geometry == 0 && n1d != nz) return 1;
     if (geometry == 1 && (n1d < 2 || !(dr > 0.0))) return 1;
+    if (geometry == 3 && (n1d < 3 || !(dr > 0.0))) return 1;
+    if (geometry == 2 && (long)n1d != or_radius_count(nx, ny, nz)) return 1;
+    if (geometry < 0 || geometry > 3) return 1;
 #pragma omp parallel for
     for (int k = 0; k < nz; k++)
         for (int j = 0; j < ny; j++)
@@ -130,8 +209,12 @@ int or_fill_beta0(int nx, int ny, int nz, double h, int bx, int by, int bz, int 
                 double v;
                 if (geometry == 0)
                     v = b1d[k];
-                else
+                else if (geometry == 1)
                     v = radial_lookup(b1d, n1d, dr, cell_radius(&g, center, i, j, k));
+                else if (geometry == 2)
+                    v = b1d[radius_index(&g, i, j, k)];
+                else
+                    v = radial_quadratic(b1d, n1d, dr, cell_radius(&g, center, i, j, k));
                 beta0_cc[cell(&g, i, j, k)] = v;
             }
     return 0;

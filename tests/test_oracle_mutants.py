@@ -104,6 +104,32 @@ def pin_coef_grad_fd():
     return abs(fd - dd) <= 1e-6 * abs(dd)
 
 
+def pin_radius_index():
+    from tests.test_oracle_irregular import radii_over_h
+
+    m = oracle.radius_index(12, 10, 6)
+    return bool(np.abs(radii_over_h(12, 10, 6) ** 2 - (0.75 + 2 * m)).max() < 1e-9)
+
+
+def pin_radial_average():
+    from tests.test_oracle_irregular import radii_over_h
+
+    r = radii_over_h(8, 8, 8)
+    avg, cnt = oracle.average_irregular(1.0 + r**2)
+    rm2 = 0.75 + 2 * np.arange(len(avg))
+    return bool(np.allclose(avg[cnt > 0], 1.0 + rm2[cnt > 0], rtol=1e-13, atol=0))
+
+
+def pin_quadratic_fill():
+    n, h = 8, 1.0 / 8
+    dr = h / 5
+    rj = (np.arange(W.spherical_n1d(n)) + 0.5) * dr
+    b = oracle.fill_beta0(oracle.Grid(n, n, n, h, (1, 1, 1)), 3, 1.0 + rj + 4.0 * rj**2, dr, (0.5, 0.5, 0.5))
+    x = (np.arange(n) + 0.5) * h - 0.5
+    r = np.sqrt(x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2)
+    return bool(np.allclose(b, 1.0 + r + 4.0 * r**2, rtol=1e-12, atol=0))
+
+
 MUTANTS = [
     ("harmonic mean replaced by arithmetic mean", "v = 2.0 * a * b / (a + b);", "v = 0.5 * (a + b);",
      pin_series_conductance),
@@ -127,6 +153,12 @@ MUTANTS = [
     ("convergence test on a mis-scaled norm", "rel = norm2(&lv[0].g, lv[0].res) / nb;",
      "rel = norm2(&lv[0].g, lv[0].res) / (1e6 * nb);", pin_sparse_lu),
     ("z factor dropped from the coefficient gradient", "    face_product(mz, gz, pz, gz);\n", "\n", pin_coef_grad_fd),
+    ("radius index measured from a cell centre", "long a = 2L * i + 1 - g->nx,", "long a = 2L * i - g->nx,",
+     pin_radius_index),
+    ("average divided by the number of cells", "avg[m] = count[m] > 0.0 ? sum[m] / count[m] : 0.0;",
+     "avg[m] = count[m] > 0.0 ? sum[m] / (double)ncell(&g) : 0.0;", pin_radial_average),
+    ("quadratic weights of the outer points swapped", "tab[j - 1] * (0.5 * s * (s - 1.0))",
+     "tab[j - 1] * (0.5 * s * (s + 1.0))", pin_quadratic_fill),
 ]
 
 
