@@ -61,7 +61,7 @@ typedef enum {
 } mp_status;
 
 enum { MP_BC_PERIODIC = 0, MP_BC_NEUMANN = 1 };
-enum { MP_PLANAR = 0, MP_SPHERICAL = 1 };
+enum { MP_PLANAR = 0, MP_SPHERICAL = 1, MP_SPHERICAL_IRREGULAR = 2, MP_SPHERICAL_QUADRATIC = 3 };
 enum { MP_FP64 = 0, MP_MIXED = 1 };
 enum { MP_SMOOTH_AUTO = 0, MP_SMOOTH_PER_COLOUR = 1, MP_SMOOTH_FUSED = 2 };
 
@@ -151,6 +151,14 @@ int mp_init(const mp_config *cfg, mp_ctx **out);
  *   point center[3] (host array, physical units); each cell takes the linear
  *   interpolation at the distance of its centre, holding the end values beyond
  *   the table.
+ * geometry MP_SPHERICAL_QUADRATIC: the same table, quadratic interpolation
+ *   (the parabola through the three table points around the nearest one,
+ *   kept inside the table); n1d >= 3.
+ * geometry MP_SPHERICAL_IRREGULAR: the irregular base state of Sec. 3.1: the
+ *   star centre is the grid node in the middle of the box (all extents even),
+ *   every cell centre lies at h sqrt(0.75 + 2m) for an integer m, and
+ *   beta0_1d[m] is beta0 at that radius (n1d == mp_radius_count); no
+ *   interpolation; dr and center are ignored.
  * rho: cell density (> 0).  cx, cy, cz: output face coefficients beta0/rho
  * (harmonic mean, walls 0), FP64, face layouts above; all three or none may be
  * NULL (the solver keeps its own copy either way).
@@ -174,6 +182,21 @@ int mp_mac_project(mp_ctx *ctx, double *ux, double *uy, double *uz, const double
 /* Solve M x = rhs (rhs mean removed when demean = 1); x mean-zero.  This is
  * also the adjoint solve, M being symmetric. */
 int mp_solve(mp_ctx *ctx, const double *rhs, double *x, int use_initial_guess, mp_info *info);
+
+/* Number of radii h sqrt(0.75 + 2m), m = 0 .. *nm - 1, of the irregular base
+ * state (Sec. 3.1) on this grid: ((nx-1)^2 + (ny-1)^2 + (nz-1)^2 - 3)/8 + 1,
+ * or 0 when an extent is odd (no grid node in the middle of the box). */
+int mp_radius_count(const mp_ctx *ctx, long long *nm);
+
+/* Lateral Average over the irregular radii (Sec. 3.1; the Average module of
+ * Sec. 3.2): avg[m] = (sum of phi over the cells whose centres lie at radius
+ * m) / (number of those cells); count[m] = that number.  Radii that no cell
+ * centre reaches get 0 and 0.  phi: cells; avg, count: device arrays of
+ * mp_radius_count doubles (count may be NULL).  The summation order is fixed,
+ * so results are reproducible.  The first call builds the list of cells per
+ * radius (host counting sort, 4 bytes per cell of device memory).
+ * Errors: MP_ERR_ARG (odd extents, NULL, >= 2^32 cells), MP_ERR_NOMEM. */
+int mp_average(mp_ctx *ctx, const double *phi, double *avg, double *count);
 
 /* Switch the per-launch timing of the finest-level smoother (mp_config
  * kernel_timing) on or off for the following calls; it records a start and

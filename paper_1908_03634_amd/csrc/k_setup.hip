@@ -155,8 +155,33 @@ void launch_copy(const double* src, double* dst, long long n, hipStream_t s)
 
 // ------------------------------------------------------------------- fill
 
-// Fill (Sec. 3.1): planar direct injection of the z table; spherical linear
-// interpolation in r on r_j = (j + 1/2) dr, end values held beyond the table.
+// Fill (Sec. 3.1) of one cell from the 1D table:
+//   0 planar: direct injection of the z table;
+//   1 spherical: linear interpolation in r on r_j = (j + 1/2) dr;
+//   3 spherical: quadratic (Lagrange through the three table points around
+//     the nearest one, the stencil kept inside the table) on the same grid;
+//   2 spherical irregular base state: the table is indexed by the integer m
+//     with |x - centre| = h sqrt(0.75 + 2m) (centre on the middle node);
+// interpolated fills hold the end values beyond the table.
+__device__ __forceinline__ double fill_value(int geometry, const double* __restrict__ tab, int n1d, double dr,
+                                             double x, double y, double z, long long m)
+{
+    if (geometry == 2) return tab[m];
+    const double r = sqrt(x * x + y * y + z * z);
+    const double t = r / dr - 0.5;
+    if (t <= 0.0) return tab[0];
+    if (t >= (double)(n1d - 1)) return tab[n1d - 1];
+    if (geometry == 3) {
+        int jj = (int)floor(t + 0.5);
+        jj = jj < 1 ? 1 : (jj > n1d - 2 ? n1d - 2 : jj);
+        const double s = t - jj;
+        return tab[jj - 1] * (0.5 * s * (s - 1.0)) + tab[jj] * (1.0 - s * s) + tab[jj + 1] * (0.5 * s * (s + 1.0));
+    }
+    const int jj = (int)floor(t);
+    const double w = t - jj;
+    return (1.0 - w) * tab[jj] + w * tab[jj + 1];
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill(Dims d, int lz, double h, int geometry,
                                                  const double* __restrict__ tab, int n1d, double dr, double cx0,
                                                  double cy0, double cz0, const double* __restrict__ rho,
@@ -172,18 +197,9 @@ __global__ __launch_bounds__(kBlock) void k_fill(Dims d, int lz, double h, int g
         if (geometry == 0) {
             b = tab[k];
         } else {
-            const double x = (i + 0.5) * h - cx0, y = (j + 0.5) * h - cy0, z = (k + 0.5) * h - cz0;
-            const double r = sqrt(x * x + y * y + z * z);
-            const double t = r / dr - 0.5;
-            if (t <= 0.0) {
-                b = tab[0];
-            } else if (t >= (double)(n1d - 1)) {
-                b = tab[n1d - 1];
-            } else {
-                const int jj = (int)floor(t);
-                const double w = t - jj;
-                b = (1.0 - w) * tab[jj] + w * tab[jj + 1];
-            }
+            const long long a2 = 2LL * i + 1 - d.nx, b2 = 2LL * j + 1 - d.ny, c2 = 2LL * k + 1 - d.nz;
+            const long long m = (a2 * a2 + b2 * b2 + c2 * c2 - 3) / 8;
+            b = fill_value(geometry, tab, n1d, dr, (i + 0.5) * h - cx0, (j + 0.5) * h - cy0, (k + 0.5) * h - cz0, m);
         }
         const double rq = rho[q];
         const double c = b / rq;

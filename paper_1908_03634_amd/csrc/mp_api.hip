@@ -75,6 +75,9 @@ struct mp_ctx {
     float* ccell32 = nullptr;  // FP32 copy of the cell values (mixed precision)
     int coarse_start = -1;  // first level of the single-workgroup coarse cycle, -1 = off
     bool phi_aligned = true;      // the caller's iterate allows 16-byte accesses
+    long long nm = 0;                   // radii of the irregular base state (0: odd extents)
+    long long* rad_offs = nullptr;      // cells of radius m: rad_cells[rad_offs[m] .. rad_offs[m+1])
+    unsigned* rad_cells = nullptr;      // built on the first mp_average
     double* ir_phi = nullptr;     // refinement update fused into the V-cycle's last pass
     const double* ir_s = nullptr;  // (phi += ir_s[0] * e), or nullptr
     bool have_coefs = false, have_base = false;
@@ -153,6 +156,8 @@ void free_all(mp_ctx* c)
     for (double* p : bufs)
         if (p) (void)hipFree(p);
     if (c->ccell32) (void)hipFree(c->ccell32);
+    if (c->rad_offs) (void)hipFree(c->rad_offs);
+    if (c->rad_cells) (void)hipFree(c->rad_cells);
     if (c->hscal) (void)hipHostFree(c->hscal);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -192,6 +197,60 @@ int sync_read(mp_ctx* c, int first, int count)
 }
 
 int nblk(const mp_ctx* c) { return mp::red_blocks(c->n0); }
+
+// Irregular radial base state (Sec. 3.1): with the star centre on the node
+// in the middle of the box, the centre of cell (i,j,k) lies at
+// h sqrt(0.75 + 2m), m = ((2i+1-nx)^2 + (2j+1-ny)^2 + (2k+1-nz)^2 - 3) / 8.
+long long radius_count(const Dims& d)
+{
+    if (d.nx % 2 || d.ny % 2 || d.nz % 2) return 0;
+    const long long a = d.nx - 1, b = d.ny - 1, e = d.nz - 1;
+    return (a * a + b * b + e * e - 3) / 8 + 1;
+}
+
+// Cells grouped by radius, each group in memory order (counting sort on the
+// host, once per context), uploaded to the device.
+int build_radius_list(mp_ctx* c)
+{
+    if (c->rad_cells) return MP_OK;
+    const Dims& d = c->d0;
+    if (c->nm == 0) return fail(c, MP_ERR_ARG, "the irregular base state needs even extents");
+    if (c->n0 >= (1LL << 32)) return fail(c, MP_ERR_ARG, "too many cells for the radius list");
+    std::vector<long long> offs((size_t)c->nm + 1, 0);
+    for (int k = 0; k < d.nz; k++)
+        for (int j = 0; j < d.ny; j++) {
+            const long long bj = 2LL * j + 1 - d.ny, bk = 2LL * k + 1 - d.nz, base = bj * bj + bk * bk - 3;
+            for (int i = 0; i < d.nx; i++) {
+                const long long a = 2LL * i + 1 - d.nx;
+                offs[(size_t)((a * a + base) / 8) + 1]++;
+            }
+        }
+    for (size_t m = 0; m < (size_t)c->nm; m++) offs[m + 1] += offs[m];
+    std::vector<long long> pos(offs.begin(), offs.end() - 1);
+    std::vector<unsigned> cells((size_t)c->n0);
+    unsigned q = 0;
+    for (int k = 0; k < d.nz; k++)
+        for (int j = 0; j < d.ny; j++) {
+            const long long bj = 2LL * j + 1 - d.ny, bk = 2LL * k + 1 - d.nz, base = bj * bj + bk * bk - 3;
+            for (int i = 0; i < d.nx; i++, q++) {
+                const long long a = 2LL * i + 1 - d.nx;
+                cells[(size_t)pos[(size_t)((a * a + base) / 8)]++] = q;
+            }
+        }
+    hipError_t e1 = hipMalloc((void**)&c->rad_offs, sizeof(long long) * offs.size());
+    hipError_t e2 = hipMalloc((void**)&c->rad_cells, sizeof(unsigned) * cells.size());
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (c->rad_offs) (void)hipFree(c->rad_offs);
+        if (c->rad_cells) (void)hipFree(c->rad_cells);
+        c->rad_offs = nullptr;
+        c->rad_cells = nullptr;
+        (void)hipGetLastError();
+        return fail(c, MP_ERR_NOMEM, "no device memory for the radius list");
+    }
+    HIPCHK(c, hipMemcpy(c->rad_offs, offs.data(), sizeof(long long) * offs.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->rad_cells, cells.data(), sizeof(unsigned) * cells.size(), hipMemcpyHostToDevice));
+    return MP_OK;
+}
 
 // Register-blocked kernels on level l (finest level with cell values only).
 bool use_blk(const mp_ctx* c, int l) { return l == 0 && c->cell_mode && c->lv[0].blk && c->phi_aligned; }
@@ -596,6 +655,7 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
     c->d0 = Dims{cfg->nx, cfg->ny, cfg->nz, cfg->bc[0] == MP_BC_PERIODIC, cfg->bc[1] == MP_BC_PERIODIC,
                  cfg->bc[2] == MP_BC_PERIODIC};
     c->n0 = c->d0.n();
+    c->nm = radius_count(c->d0);
     const bool mx = mixed(c);
     const size_t tsz = mx ? sizeof(float) : sizeof(double);
     hipError_t e = hipSuccess;
@@ -735,15 +795,22 @@ int mp_map_base_state(mp_ctx* c, int geometry, const double* beta0_1d, int n1d, 
                       const double* rho, double* cx, double* cy, double* cz)
 {
     if (!c) return MP_ERR_ARG;
-    if (geometry != MP_PLANAR && geometry != MP_SPHERICAL) return fail(c, MP_ERR_ARG, "bad geometry");
+    if (geometry != MP_PLANAR && geometry != MP_SPHERICAL && geometry != MP_SPHERICAL_IRREGULAR &&
+        geometry != MP_SPHERICAL_QUADRATIC)
+        return fail(c, MP_ERR_ARG, "bad geometry");
     if (!beta0_1d || !rho) return fail(c, MP_ERR_ARG, "beta0_1d and rho are required");
     if ((cx == nullptr) != (cy == nullptr) || (cx == nullptr) != (cz == nullptr))
         return fail(c, MP_ERR_ARG, "cx, cy, cz must be all given or all NULL");
     double c0 = 0, c1 = 0, c2 = 0;
     if (geometry == MP_PLANAR) {
         if (n1d != c->cfg.nz) return fail(c, MP_ERR_ARG, "planar table needs n1d == nz (%d != %d)", n1d, c->cfg.nz);
+    } else if (geometry == MP_SPHERICAL_IRREGULAR) {
+        if (c->nm == 0) return fail(c, MP_ERR_ARG, "the irregular base state needs even extents");
+        if ((long long)n1d != c->nm)
+            return fail(c, MP_ERR_ARG, "irregular table needs one entry per radius (%d != %lld)", n1d, c->nm);
     } else {
-        if (n1d < 2) return fail(c, MP_ERR_ARG, "spherical table needs n1d >= 2");
+        if (n1d < (geometry == MP_SPHERICAL_QUADRATIC ? 3 : 2))
+            return fail(c, MP_ERR_ARG, "spherical table too short (%d entries)", n1d);
         if (!(dr > 0.0) || !isfinite(dr)) return fail(c, MP_ERR_ARG, "dr must be positive");
         if (!center) return fail(c, MP_ERR_ARG, "center is required for spherical geometry");
         c0 = center[0];
@@ -886,6 +953,26 @@ int mp_solve(mp_ctx* c, const double* rhs, double* x, int use_initial_guess, mp_
     HIPCHK(c, hipStreamSynchronize(c->stream));
     finish_timing(c, info);
     return solve_st;
+}
+
+int mp_radius_count(const mp_ctx* c, long long* nm)
+{
+    if (!c || !nm) return MP_ERR_ARG;
+    *nm = c->nm;
+    return MP_OK;
+}
+
+int mp_average(mp_ctx* c, const double* phi, double* avg, double* count)
+{
+    if (!c) return MP_ERR_ARG;
+    if (!phi || !avg) return fail(c, MP_ERR_ARG, "phi and avg are required");
+    if (c->nm == 0) return fail(c, MP_ERR_ARG, "the irregular base state needs even extents");
+    (void)hipSetDevice(c->cfg.device);
+    int st = build_radius_list(c);
+    if (st) return st;
+    mp::launch_average(c->nm, c->rad_offs, c->rad_cells, phi, avg, count, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MP_OK;
 }
 
 int mp_set_kernel_timing(mp_ctx* c, int on)

@@ -190,6 +190,13 @@ void launch_resid64(const Dims& d, const double* phi, const double* b, const Coe
 // phi += s[0] * e.
 void launch_ir_update(long long n, double* phi, const float* e, const double* s, hipStream_t st);
 
+// ---- irregular radial base state ------------------------------------------
+// Lateral average over radii m = 0 .. nm-1: cells[offs[m] .. offs[m+1]) lists
+// the cells at radius m (memory order); avg[m] = their mean (0 if none),
+// count[m] = their number (count may be nullptr).
+void launch_average(long long nm, const long long* offs, const unsigned* cells, const double* phi, double* avg,
+                    double* count, hipStream_t s);
+
 // Plain device copy (bandwidth calibration of the traffic counters).
 void launch_copy(const double* src, double* dst, long long n, hipStream_t s);
 

@@ -27,7 +27,7 @@ STATUS = {
 }
 MP_ERR_NOT_CONVERGED = 4
 PERIODIC, NEUMANN = 0, 1
-PLANAR, SPHERICAL = 0, 1
+PLANAR, SPHERICAL, SPHERICAL_IRREGULAR, SPHERICAL_QUADRATIC = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 
 
@@ -90,7 +90,8 @@ class Info(ctypes.Structure):
 
 # Every exported symbol of include/mproj.h.
 EXPORTS = ["mp_config_default", "mp_init", "mp_map_base_state", "mp_set_coefs", "mp_mac_project", "mp_solve",
-           "mp_set_kernel_timing", "mp_apply", "mp_coef_grad", "mp_free", "mp_last_error", "mp_version"]
+           "mp_radius_count", "mp_average", "mp_set_kernel_timing", "mp_apply", "mp_coef_grad", "mp_free",
+           "mp_last_error", "mp_version"]
 
 _lib = None
 
@@ -119,6 +120,10 @@ def load_library(path=None):
     lib.mp_mac_project.restype = I
     lib.mp_solve.argtypes = [P, P, P, I, ctypes.POINTER(Info)]
     lib.mp_solve.restype = I
+    lib.mp_radius_count.argtypes = [P, ctypes.POINTER(ctypes.c_longlong)]
+    lib.mp_radius_count.restype = I
+    lib.mp_average.argtypes = [P, P, P, P]
+    lib.mp_average.restype = I
     lib.mp_set_kernel_timing.argtypes = [P, I]
     lib.mp_set_kernel_timing.restype = I
     lib.mp_apply.argtypes = [P, P, P]
@@ -212,7 +217,8 @@ class Context:
 
     # -- API -------------------------------------------------------------
     def map_base_state(self, geometry, beta0_1d, rho, dr=0.0, center=None, out=None, want_coefs=True):
-        """Fill beta0 (planar injection / spherical linear interpolation) and
+        """Fill beta0 (planar injection; spherical linear or quadratic
+        interpolation; irregular spherical base state indexed by radius) and
         build the face coefficients; returns (cx, cy, cz) or None."""
         n1d = int(beta0_1d.shape[0])
         tab = self._ptr(beta0_1d, (n1d,), "beta0_1d")
@@ -263,6 +269,24 @@ class Context:
             self._check(code, "mp_solve", d)
         d["status"] = code
         return x, d
+
+    def radius_count(self):
+        """Number of radii h sqrt(0.75 + 2m) of the irregular base state."""
+        nm = ctypes.c_longlong()
+        self._check(self.lib.mp_radius_count(self._h, ctypes.byref(nm)), "mp_radius_count")
+        return int(nm.value)
+
+    def average(self, phi, out=None, count=True):
+        """Lateral average of a cell field over the irregular radii:
+        returns (avg, count) (count None when not asked for)."""
+        nm = self.radius_count()
+        pp = self._ptr(phi, self.shape, "phi")
+        avg = out if out is not None else torch.empty(nm, dtype=torch.float64, device=self.device)
+        cnt = torch.empty(nm, dtype=torch.float64, device=self.device) if count else None
+        pa = self._ptr(avg, (nm,), "avg")
+        pc = self._ptr(cnt, (nm,), "count") if count else None
+        self._check(self.lib.mp_average(self._h, pp, pa, pc), "mp_average")
+        return avg, cnt
 
     def set_kernel_timing(self, on):
         """Time the finest-level smoother launches of the following calls."""

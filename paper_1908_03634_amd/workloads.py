@@ -35,6 +35,8 @@ PERIODIC = 0
 NEUMANN = 1
 PLANAR = 0
 SPHERICAL = 1
+SPHERICAL_IRREGULAR = 2
+SPHERICAL_QUADRATIC = 3
 GAMMA = 5.0 / 3.0
 
 # Seeds: 20190805 + configuration number; the 16^3 finite-difference copy of
@@ -145,20 +147,30 @@ def spherical_n1d(n):
 
 
 def spherical_problem(n, *, contrast=1e5, bc=(NEUMANN, NEUMANN, NEUMANN), seed=SEED_BASE,
-                      rho_noise=1e-3, s_sigma=1e-2, with_w=False, name="spherical", radial_refine=5):
+                      rho_noise=1e-3, s_sigma=1e-2, with_w=False, name="spherical", radial_refine=5,
+                      base="linear"):
     """Full-star box: rho0(r) = (1 + (r/R)^2)^(-5/2) about the box centre.
 
-    The 1D beta0 table lives on r_j = (j + 1/2) dr with dr = h/radial_refine
-    (the paper's default uniform spacing is dx/5, Sec. 3.1).  The cell density is
-    the analytic profile at the cell centre times (1 + rho_noise * N(0,1)).
+    base "linear" / "quadratic": the 1D beta0 table lives on r_j = (j + 1/2) dr
+    with dr = h/radial_refine (the paper's default uniform spacing is dx/5,
+    Sec. 3.1), interpolated linearly or quadratically.  base "irregular": the
+    table holds beta0 at the radii h sqrt(0.75 + 2m) of the irregular base
+    state (n even; one entry per m).  The cell density is the analytic profile
+    at the cell centre times (1 + rho_noise * N(0,1)).
     """
     nx = ny = nz = n
     h = 1.0 / n
     rng = np.random.default_rng(seed)
     R = star_radius_for_contrast(contrast)
     dr = h / radial_refine
-    n1d = spherical_n1d(n) if radial_refine == 5 else int(math.ceil(radial_refine * math.sqrt(3.0) * n / 2.0)) + 2
-    rj = (np.arange(n1d) + 0.5) * dr
+    if base == "irregular":
+        nm = ((n - 1) ** 2 * 3 - 3) // 8 + 1
+        rj = h * np.sqrt(0.75 + 2.0 * np.arange(nm))
+        geometry = SPHERICAL_IRREGULAR
+    else:
+        n1d = spherical_n1d(n) if radial_refine == 5 else int(math.ceil(radial_refine * math.sqrt(3.0) * n / 2.0)) + 2
+        rj = (np.arange(n1d) + 0.5) * dr
+        geometry = SPHERICAL if base == "linear" else SPHERICAL_QUADRATIC
     beta0_1d = ((1.0 + (rj / R) ** 2) ** -2.5) ** (1.0 / GAMMA)
     center = (0.5, 0.5, 0.5)
     c1 = (np.arange(n) + 0.5) * h - 0.5
@@ -171,10 +183,10 @@ def spherical_problem(n, *, contrast=1e5, bc=(NEUMANN, NEUMANN, NEUMANN), seed=S
     ux, uy, uz = _draw_faces(rng, nx, ny, nz, bc)
     S = s_sigma * rng.standard_normal((nz, ny, nx))
     w = rng.standard_normal((nz, ny, nx)) if with_w else None
-    return Problem(name=name, nx=nx, ny=ny, nz=nz, h=h, bc=tuple(bc), geometry=SPHERICAL,
+    return Problem(name=name, nx=nx, ny=ny, nz=nz, h=h, bc=tuple(bc), geometry=geometry,
                    beta0_1d=np.ascontiguousarray(beta0_1d), dr=dr, center=center,
                    rho=rho, ux=ux, uy=uy, uz=uz, S=S, w=w,
-                   meta=dict(contrast=contrast, R=R, seed=seed, rho_noise=rho_noise))
+                   meta=dict(contrast=contrast, R=R, seed=seed, rho_noise=rho_noise, base=base))
 
 
 # The five workloads: sizes, boundaries and contrasts.

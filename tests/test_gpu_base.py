@@ -1,0 +1,109 @@
+"""Irregular radial base state on the GPU (Sec. 3.1): fill by radius index,
+quadratic fill, and the lateral Average, against the oracle; projections on
+stars mapped each way."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1908_03634_amd import mproj, workloads as W
+from tests.gpu_util import N, T, context_for, gpu_project, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def radii_over_h(nx, ny, nz):
+    x = np.arange(nx) + 0.5 - nx / 2
+    y = np.arange(ny) + 0.5 - ny / 2
+    z = np.arange(nz) + 0.5 - nz / 2
+    return np.sqrt(z[:, None, None] ** 2 + y[None, :, None] ** 2 + x[None, None, :] ** 2)
+
+
+@pytest.mark.parametrize("base", ["irregular", "quadratic", "linear"])
+@pytest.mark.parametrize("n", [16, 32])
+def test_fill_modes_give_the_oracles_face_coefficients(base, n):
+    say("fill", base, n)
+    p = W.spherical_problem(n, contrast=1e5, seed=6100 + n, base=base)
+    g = oracle.Grid.of(p)
+    b0 = oracle.fill_beta0(g, p.geometry, p.beta0_1d, p.dr, p.center)
+    ref = oracle.face_coefs(g, b0, p.rho)
+    ctx = context_for(p, "fp64")
+    got = ctx.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center)
+    for a, b in zip(got, ref):
+        if base == "irregular":
+            assert np.array_equal(N(a), b)  # a lookup: the same bits
+        else:
+            assert np.abs(N(a) - b).max() <= 1e-14 * np.abs(b).max()
+    ctx.close()
+
+
+def test_irregular_table_of_the_wrong_length_is_rejected():
+    p = W.spherical_problem(16, base="irregular", seed=6200)
+    ctx = context_for(p, "fp64")
+    assert ctx.radius_count() == len(p.beta0_1d) == oracle.radius_count(16, 16, 16)
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.map_base_state(p.geometry, T(p.beta0_1d[:-1]), T(p.rho), p.dr, p.center)
+    assert e.value.code == 1
+    ctx.close()
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (12, 10, 6), (64, 64, 64), (96, 64, 32), (256, 256, 256)])
+def test_average_matches_the_oracle(shape):
+    nx, ny, nz = shape
+    say("average", shape)
+    phi = W.random_cells(nx, ny, nz, 6300 + nx)
+    avg_ref, cnt_ref = oracle.average_irregular(phi)
+    ctx = mproj.Context(nx, ny, nz, bc=(1, 1, 1), precision="fp64")
+    assert ctx.radius_count() == len(avg_ref)
+    avg, cnt = ctx.average(T(phi))
+    avg, cnt = N(avg), N(cnt)
+    assert np.array_equal(cnt, cnt_ref)
+    assert np.abs(avg - avg_ref).max() <= 1e-13 * np.abs(avg_ref).max()
+    # reproducible to the bit
+    avg2, _ = ctx.average(T(phi), count=False)
+    assert np.array_equal(N(avg2), avg)
+    ctx.close()
+
+
+def test_average_of_a_radial_function_and_the_paper_count():
+    """256^3: 24,384 + 1 radii (Sec. 4.1); the average of f(r) is f(r_m)."""
+    n = 256
+    r = radii_over_h(n, n, n)
+    f = np.exp(-r / 40.0)
+    ctx = mproj.Context(n, n, n, bc=(1, 1, 1), precision="mixed")
+    assert ctx.radius_count() - 1 == 24384
+    avg, cnt = ctx.average(T(f))
+    avg, cnt = N(avg), N(cnt)
+    rm = np.sqrt(0.75 + 2 * np.arange(len(avg)))
+    on = cnt > 0
+    assert cnt.sum() == n**3
+    assert np.allclose(avg[on], np.exp(-rm[on] / 40.0), rtol=1e-13, atol=0)
+    assert np.all(avg[~on] == 0)
+    ctx.close()
+
+
+def test_average_needs_even_extents():
+    lib = mproj.load_library()
+    ctx = mproj.Context(9, 8, 8, bc=(1, 1, 1), precision="fp64")
+    assert ctx.radius_count() == 0
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.average(torch.zeros((8, 8, 9), dtype=torch.float64, device="cuda:0"))
+    assert e.value.code == 1
+    assert lib.mp_average(ctx._h, None, None, None) == 1
+    ctx.close()
+
+
+@pytest.mark.parametrize("base", ["irregular", "quadratic"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_star_projection_with_each_base_state(base, precision):
+    say("star projection", base, precision)
+    p = W.spherical_problem(64, contrast=1e5, seed=6400, base=base)
+    ref = oracle.mac_project(p, tol=1e-12)
+    r = gpu_project(p, precision, rtol=1e-12)
+    assert rel(N(r["phi"]), ref["phi"]) < 1e-9
+    assert r["info"]["div_defect"] <= 2e-12
+    g = ref["grid"]
+    assert oracle.residual_norm(g, ref["cx"], ref["cy"], ref["cz"], ref["rhs"], N(r["phi"])) <= 1.01e-12
+    r["ctx"].close()
