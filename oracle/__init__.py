@@ -58,6 +58,9 @@ def _declare(lib):
     lib.or_dot.argtypes = [_I, _I, _I, _D, _D]
     lib.or_dot.restype = _F
     lib.or_num_threads.restype = _I
+    lib.or_plane_average.argtypes = [_I, _I, _I, _D, _D]
+    lib.or_split_source.argtypes = [_I, _I, _I, _I, _D, _D, _D]
+    lib.or_split_source.restype = _I
     lib.or_radius_count.argtypes = [_I, _I, _I]
     lib.or_radius_count.restype = ctypes.c_long
     lib.or_radius_index.argtypes = [_I, _I, _I, ctypes.POINTER(ctypes.c_long)]
@@ -201,6 +204,28 @@ def average_irregular(phi):
     return avg, cnt
 
 
+def plane_average(phi):
+    """Lateral average of a planar atmosphere: mean of each horizontal plane."""
+    nz, ny, nx = phi.shape
+    a = np.ascontiguousarray(phi, dtype=np.float64)
+    out = np.zeros(nz)
+    _load().or_plane_average(nx, ny, nz, _p(a), _p(out))
+    return out
+
+
+def split_source(geometry, S):
+    """(S - Sbar on the cells, Sbar): the source of the velocity-split
+    constraint div(beta0 U~) = beta0 (S - Sbar) of Appendix A, Sbar the
+    lateral average (planes for geometry 0, irregular radii for geometry 2)."""
+    nz, ny, nx = S.shape
+    a = np.ascontiguousarray(S, dtype=np.float64)
+    out = np.zeros_like(a)
+    sbar = np.zeros(nz if geometry == 0 else max(radius_count(nx, ny, nz), 1))
+    if _load().or_split_source(nx, ny, nz, int(geometry), _p(a), _p(out), _p(sbar)):
+        raise ValueError("the split source needs a planar or irregular spherical base state")
+    return out, sbar
+
+
 def face_coefs(g, beta0_cc, rho):
     """beta0/rho at faces: harmonic mean of the two cells; walls 0 (momentum
     equation of Sec. 2 carries beta0/rho in front of the pressure gradient)."""
@@ -284,13 +309,18 @@ def residual_norm(g, cx, cy, cz, rhs, phi):
     return float(np.sqrt(lib.or_dot(g.nx, g.ny, g.nz, _p(r), _p(r)) / lib.or_dot(g.nx, g.ny, g.nz, _p(rhs), _p(rhs))))
 
 
-def mac_project(prob, tol=1e-12, maxcycles=200):
+def mac_project(prob, tol=1e-12, maxcycles=200, split=False):
     """Whole projection on a workloads.Problem: map, rhs, solve, correct.
-    Returns a dict of every intermediate."""
+    split: project onto div(beta0 U~) = beta0 (S - Sbar) (Appendix A) instead
+    of div(beta0 U) = beta0 S.  Returns a dict of every intermediate."""
     g = Grid.of(prob)
     beta0_cc, (cx, cy, cz) = map_base_state(g, prob.geometry, prob.beta0_1d, prob.dr, prob.center, prob.rho)
-    rhs, m = mac_rhs(g, beta0_cc, prob.ux, prob.uy, prob.uz, prob.S)
+    S = prob.S
+    sbar = None
+    if split:
+        S, sbar = split_source(prob.geometry, prob.S)
+    rhs, m = mac_rhs(g, beta0_cc, prob.ux, prob.uy, prob.uz, S)
     phi, info = solve(g, cx, cy, cz, rhs, tol=tol, maxcycles=maxcycles)
     ux, uy, uz = velocity_correct(g, cx, cy, cz, beta0_cc, phi, prob.ux, prob.uy, prob.uz)
     return dict(grid=g, beta0_cc=beta0_cc, cx=cx, cy=cy, cz=cz, rhs=rhs, mean=m, phi=phi, info=info,
-                ux=ux, uy=uy, uz=uz)
+                ux=ux, uy=uy, uz=uz, S_eff=S, sbar=sbar)

@@ -15,7 +15,8 @@
  *    uniform radial grid r_j = (j + 1/2) dr), or, for the irregular base state,
  *    by the index m of the radius h sqrt(0.75 + 2m) of each cell centre;
  *  - the lateral Average (Sec. 3.1 and the Average module of Sec. 3.2) over
- *    those irregular radii;
+ *    those irregular radii, or over the planes of a planar atmosphere, and the
+ *    source S - Sbar of the velocity-split constraint of Appendix A;
  *  - the MAC projection of Sec. 3.2 Steps 3 and 7 (the constraints div1/div2,
  *    i.e. the velocity constraint of Sec. 2 with the dp0/dt term folded into
  *    S) and Appendix A: find phi with
@@ -177,6 +178,49 @@ int or_average_irregular(int nx, int ny, int nz, const double *phi, long nm, dou
     for (long m = 0; m < nm; m++) avg[m] = count[m] > 0.0 ? sum[m] / count[m] : 0.0;
     free(sum);
     return 0;
+}
+
+/* Lateral average in planar geometry (Sec. 3.1): the arithmetic mean of the
+ * cells of each horizontal plane k (base-state cells align with the planes). */
+void or_plane_average(int nx, int ny, int nz, const double *phi, double *avg)
+{
+    grid_t g = mkgrid(nx, ny, nz, 1.0, 0, 0, 0);
+    for (int k = 0; k < nz; k++) {
+        double s = 0.0;
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) s += phi[cell(&g, i, j, k)];
+        avg[k] = s / ((double)nx * ny);
+    }
+}
+
+/* Source of the velocity-split constraint (Appendix A): the perturbational
+ * velocity satisfies div(beta0 U~) = beta0 (S - Sbar), with Sbar the lateral
+ * average of S filled back onto the cells.  geometry 0: plane averages
+ * (sbar has nz entries); 2: averages over the irregular radii (sbar has one
+ * entry per radius).  Writes S - Sbar to s_out.  Returns 1 on a bad geometry. */
+int or_split_source(int nx, int ny, int nz, int geometry, const double *S, double *s_out, double *sbar)
+{
+    grid_t g = mkgrid(nx, ny, nz, 1.0, 0, 0, 0);
+    if (geometry == 0) {
+        or_plane_average(nx, ny, nz, S, sbar);
+        for (int k = 0; k < nz; k++)
+            for (int j = 0; j < ny; j++)
+                for (int i = 0; i < nx; i++) s_out[cell(&g, i, j, k)] = S[cell(&g, i, j, k)] - sbar[k];
+        return 0;
+    }
+    if (geometry == 2) {
+        long nm = or_radius_count(nx, ny, nz);
+        if (nm == 0) return 1;
+        double *cnt = (double *)malloc(sizeof(double) * (size_t)nm);
+        or_average_irregular(nx, ny, nz, S, nm, sbar, cnt);
+        free(cnt);
+        for (int k = 0; k < nz; k++)
+            for (int j = 0; j < ny; j++)
+                for (int i = 0; i < nx; i++)
+                    s_out[cell(&g, i, j, k)] = S[cell(&g, i, j, k)] - sbar[radius_index(&g, i, j, k)];
+        return 0;
+    }
+    return 1;
 }
 
 void or_cell_radius(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *center, double *r)

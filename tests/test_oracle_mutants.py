@@ -130,6 +130,20 @@ def pin_quadratic_fill():
     return bool(np.allclose(b, 1.0 + r + 4.0 * r**2, rtol=1e-12, atol=0))
 
 
+def pin_plane_average():
+    rng = np.random.default_rng(4)
+    f = rng.normal(size=6)
+    a = rng.normal(size=(6, 5, 7))
+    phi = f[:, None, None] + (a - a.mean(axis=(1, 2), keepdims=True))
+    return bool(np.allclose(oracle.plane_average(phi), f, rtol=0, atol=1e-14))
+
+
+def pin_split_zero_sums():
+    S = W.random_cells(10, 6, 8, 91)
+    s_eff, _ = oracle.split_source(0, S)
+    return bool(np.abs(s_eff.sum(axis=(1, 2))).max() <= 1e-13 * np.abs(S).sum())
+
+
 MUTANTS = [
     ("harmonic mean replaced by arithmetic mean", "v = 2.0 * a * b / (a + b);", "v = 0.5 * (a + b);",
      pin_series_conductance),
@@ -159,6 +173,10 @@ MUTANTS = [
      "avg[m] = count[m] > 0.0 ? sum[m] / (double)ncell(&g) : 0.0;", pin_radial_average),
     ("quadratic weights of the outer points swapped", "tab[j - 1] * (0.5 * s * (s - 1.0))",
      "tab[j - 1] * (0.5 * s * (s + 1.0))", pin_quadratic_fill),
+    ("plane average divided by the row length", "avg[k] = s / ((double)nx * ny);", "avg[k] = s / (double)nx;",
+     pin_plane_average),
+    ("split source takes the next plane's average", "S[cell(&g, i, j, k)] - sbar[k];",
+     "S[cell(&g, i, j, k)] - sbar[(k + 1) % nz];", pin_split_zero_sums),
 ]
 
 
