@@ -179,6 +179,17 @@ int mp_set_coefs(mp_ctx *ctx, const double *cx, const double *cy, const double *
 int mp_mac_project(mp_ctx *ctx, double *ux, double *uy, double *uz, const double *S, double *phi,
                    int use_initial_guess, mp_info *info);
 
+/* Velocity-split MAC projection (Appendix A): as mp_mac_project with the
+ * source S replaced by S - Sbar, Sbar being the lateral average of S
+ * (Sec. 3.1): the plane averages after an MP_PLANAR mapping, the averages
+ * over the irregular radii after an MP_SPHERICAL_IRREGULAR mapping.  The
+ * projected velocity U~ then satisfies div(beta0 U~) = beta0 (S - Sbar) up to
+ * the solve residual; the base-state velocity w0 of the split is not computed
+ * here.  sbar: device array receiving Sbar (nz, or mp_radius_count entries),
+ * or NULL.  Errors as mp_mac_project; MP_ERR_STATE after any other mapping. */
+int mp_mac_project_split(mp_ctx *ctx, double *ux, double *uy, double *uz, const double *S, double *phi,
+                         int use_initial_guess, double *sbar, mp_info *info);
+
 /* Solve M x = rhs (rhs mean removed when demean = 1); x mean-zero.  This is
  * also the adjoint solve, M being symmetric. */
 int mp_solve(mp_ctx *ctx, const double *rhs, double *x, int use_initial_guess, mp_info *info);

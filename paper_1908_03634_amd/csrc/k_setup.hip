@@ -410,9 +410,25 @@ template void launch_coef_restrict<float, float>(const Dims&, const float*, cons
 
 // beta0 on a face: arithmetic mean of the two cells.
 // b = beta0 S - D(beta0 U): minus the MAC right-hand side of Sec. 3.2 Steps 3/7.
+// Source of a cell: S, or S - Sbar for the velocity-split constraint
+// (Appendix A) with Sbar the lateral average per plane (smode 1) or per
+// irregular radius (smode 2).
+__device__ __forceinline__ double cell_source(const Dims& d, const double* __restrict__ S,
+                                              const double* __restrict__ sbar, int smode, long long q, int i, int j,
+                                              int k)
+{
+    if (smode == 1) return S[q] - sbar[k];
+    if (smode == 2) {
+        const long long a = 2LL * i + 1 - d.nx, b = 2LL * j + 1 - d.ny, c = 2LL * k + 1 - d.nz;
+        return S[q] - sbar[(a * a + b * b + c * c - 3) / 8];
+    }
+    return S[q];
+}
+
 __global__ __launch_bounds__(kBlock) void k_mac_rhs(Dims d, int lz, double inv_h, const double* __restrict__ beta0,
                                                     const double* __restrict__ ux, const double* __restrict__ uy,
                                                     const double* __restrict__ uz, const double* __restrict__ S,
+                                                    const double* __restrict__ sbar, int smode,
                                                     double* __restrict__ b, double* part,
                                                     const double* __restrict__ shift)
 {
@@ -440,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_mac_rhs(Dims d, int lz, double inv_h
         if (k < d.nz - 1) fzh = 0.5 * (b0 + beta0[nb.zp]) * uz[e.zl + (long long)d.nx * d.ny];
         else if (d.pz) fzh = 0.5 * (b0 + beta0[nb.zp]) * uz[e.zl - (long long)(d.nz - 1) * d.nx * d.ny];
         const double div = ((fxh - fxl) + (fyh - fyl) + (fzh - fzl)) * inv_h;
-        const double v = b0 * S[q] - div;
+        const double v = b0 * cell_source(d, S, sbar, smode, q, i, j, k) - div;
         if (shift) {
             const double e2 = v - sh0;
             acc = fma(e2, e2, acc);
@@ -453,19 +469,40 @@ __global__ __launch_bounds__(kBlock) void k_mac_rhs(Dims d, int lz, double inv_h
 }
 
 void launch_mac_rhs(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
-                    const double* uz, const double* S, double* b, double* partials, hipStream_t s)
+                    const double* uz, const double* S, const double* sbar, int smode, double* b, double* partials,
+                    hipStream_t s)
 {
     const ShapeZ sh = zmarch(d.nx, d.ny, d.nz, kZBlocks);
-    hipLaunchKernelGGL(k_mac_rhs, sh.grid, sh.block, 0, s, d, sh.lz, inv_h, beta0, ux, uy, uz, S, b, partials,
-                       (const double*)nullptr);
+    hipLaunchKernelGGL(k_mac_rhs, sh.grid, sh.block, 0, s, d, sh.lz, inv_h, beta0, ux, uy, uz, S, sbar, smode, b,
+                       partials, (const double*)nullptr);
 }
 
 void launch_rhs_defect(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
-                       const double* uz, const double* S, const double* shift, double* partials, hipStream_t s)
+                       const double* uz, const double* S, const double* sbar, int smode, const double* shift,
+                       double* partials, hipStream_t s)
 {
     const ShapeZ sh = zmarch(d.nx, d.ny, d.nz, kZBlocks);
-    hipLaunchKernelGGL(k_mac_rhs, sh.grid, sh.block, 0, s, d, sh.lz, inv_h, beta0, ux, uy, uz, S, (double*)nullptr,
-                       partials, shift);
+    hipLaunchKernelGGL(k_mac_rhs, sh.grid, sh.block, 0, s, d, sh.lz, inv_h, beta0, ux, uy, uz, S, sbar, smode,
+                       (double*)nullptr, partials, shift);
+}
+
+// Lateral average of a planar atmosphere (Sec. 3.1): one block per plane,
+// fixed-order sum of its cells, divided by their number.
+__global__ __launch_bounds__(kBlock) void k_plane_average(Dims d, const double* __restrict__ phi,
+                                                          double* __restrict__ avg)
+{
+    __shared__ double sh[kBlock / kWave];
+    const long long np = (long long)d.nx * d.ny;
+    const double* p = phi + (long long)blockIdx.x * np;
+    double s = 0.0;
+    for (long long q = threadIdx.x; q < np; q += kBlock) s += p[q];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) avg[blockIdx.x] = s / (double)np;
+}
+
+void launch_plane_average(const Dims& d, const double* phi, double* avg, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_plane_average, dim3((unsigned)d.nz), dim3(kBlock), 0, s, d, phi, avg);
 }
 
 // Velocity correction of one face: U - (c / beta0_f) (phi_R - phi_L) / h.

@@ -75,6 +75,9 @@ struct mp_ctx {
     float* ccell32 = nullptr;  // FP32 copy of the cell values (mixed precision)
     int coarse_start = -1;  // first level of the single-workgroup coarse cycle, -1 = off
     bool phi_aligned = true;      // the caller's iterate allows 16-byte accesses
+    int geometry = -1;                  // geometry of the last successful mapping
+    double* sbar = nullptr;             // lateral average of S (velocity-split source)
+    long long sbar_n = 0;
     long long nm = 0;                   // radii of the irregular base state (0: odd extents)
     long long* rad_offs = nullptr;      // cells of radius m: rad_cells[rad_offs[m] .. rad_offs[m+1])
     unsigned* rad_cells = nullptr;      // built on the first mp_average
@@ -156,6 +159,7 @@ void free_all(mp_ctx* c)
     for (double* p : bufs)
         if (p) (void)hipFree(p);
     if (c->ccell32) (void)hipFree(c->ccell32);
+    if (c->sbar) (void)hipFree(c->sbar);
     if (c->rad_offs) (void)hipFree(c->rad_offs);
     if (c->rad_cells) (void)hipFree(c->rad_cells);
     if (c->hscal) (void)hipHostFree(c->hscal);
@@ -240,7 +244,8 @@ int build_radius_list(mp_ctx* c)
     hipError_t e1 = hipMalloc((void**)&c->rad_offs, sizeof(long long) * offs.size());
     hipError_t e2 = hipMalloc((void**)&c->rad_cells, sizeof(unsigned) * cells.size());
     if (e1 != hipSuccess || e2 != hipSuccess) {
-        if (c->rad_offs) (void)hipFree(c->rad_offs);
+        if (c->sbar) (void)hipFree(c->sbar);
+    if (c->rad_offs) (void)hipFree(c->rad_offs);
         if (c->rad_cells) (void)hipFree(c->rad_cells);
         c->rad_offs = nullptr;
         c->rad_cells = nullptr;
@@ -844,6 +849,7 @@ int mp_map_base_state(mp_ctx* c, int geometry, const double* beta0_1d, int n1d, 
                     c->hscal[S_BAD]);
     }
     c->have_base = c->have_coefs = true;
+    c->geometry = geometry;
     return MP_OK;
 }
 
@@ -891,20 +897,15 @@ static int finish_rhs(mp_ctx* c, int nb_sum, int nb)
     return MP_OK;
 }
 
-int mp_mac_project(mp_ctx* c, double* ux, double* uy, double* uz, const double* S, double* phi,
-                   int use_initial_guess, mp_info* info)
+// The projection of mp_mac_project / mp_mac_project_split: source S, or
+// S - Sbar (sbar per plane for smode 1, per irregular radius for smode 2).
+static int project(mp_ctx* c, double* ux, double* uy, double* uz, const double* S, const double* sbar, int smode,
+                   double* phi, int use_initial_guess, mp_info* info)
 {
-    if (!c) return MP_ERR_ARG;
-    reset_info(info);
-    if (!ux || !uy || !uz || !S || !phi) return fail(c, MP_ERR_ARG, "ux, uy, uz, S and phi are required");
-    if (!c->have_base) return fail(c, MP_ERR_STATE, "mp_map_base_state has not succeeded on this context");
-    if (!c->have_coefs) return fail(c, MP_ERR_STATE, "face coefficients missing");
-    (void)hipSetDevice(c->cfg.device);
     c->kev_used = 0;
     const int nb = nblk(c);
     const double inv_h = 1.0 / c->cfg.h;
-    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-    mp::launch_mac_rhs(c->d0, inv_h, c->beta0, ux, uy, uz, S, c->b64, c->partials, c->stream);
+    mp::launch_mac_rhs(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->b64, c->partials, c->stream);
     int st = finish_rhs(c, c->nbz, nb);
     if (st) return st;
     if (info) {
@@ -916,7 +917,8 @@ int mp_mac_project(mp_ctx* c, double* ux, double* uy, double* uz, const double* 
     if (solve_st != MP_OK && solve_st != MP_ERR_NOT_CONVERGED) return solve_st;
     HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
     mp::launch_vel_correct(c->d0, inv_h, coef64(c), c->beta0, phi, ux, uy, uz, c->stream);
-    mp::launch_rhs_defect(c->d0, inv_h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, c->partials, c->stream);
+    mp::launch_rhs_defect(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->dscal + S_MEAN, c->partials,
+                          c->stream);
     mp::launch_final_sum(c->partials, c->nbz, c->dscal + S_DEF, 1.0, nullptr, 0.0, c->stream);
     HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
     st = sync_read(c, S_DEF, 1);
@@ -927,6 +929,60 @@ int mp_mac_project(mp_ctx* c, double* ux, double* uy, double* uz, const double* 
         finish_timing(c, info);
     }
     return solve_st;
+}
+
+static int project_checks(mp_ctx* c, double* ux, double* uy, double* uz, const double* S, double* phi)
+{
+    if (!ux || !uy || !uz || !S || !phi) return fail(c, MP_ERR_ARG, "ux, uy, uz, S and phi are required");
+    if (!c->have_base) return fail(c, MP_ERR_STATE, "mp_map_base_state has not succeeded on this context");
+    if (!c->have_coefs) return fail(c, MP_ERR_STATE, "face coefficients missing");
+    return MP_OK;
+}
+
+int mp_mac_project(mp_ctx* c, double* ux, double* uy, double* uz, const double* S, double* phi,
+                   int use_initial_guess, mp_info* info)
+{
+    if (!c) return MP_ERR_ARG;
+    reset_info(info);
+    int st = project_checks(c, ux, uy, uz, S, phi);
+    if (st) return st;
+    (void)hipSetDevice(c->cfg.device);
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    return project(c, ux, uy, uz, S, nullptr, 0, phi, use_initial_guess, info);
+}
+
+int mp_mac_project_split(mp_ctx* c, double* ux, double* uy, double* uz, const double* S, double* phi,
+                         int use_initial_guess, double* sbar, mp_info* info)
+{
+    if (!c) return MP_ERR_ARG;
+    reset_info(info);
+    int st = project_checks(c, ux, uy, uz, S, phi);
+    if (st) return st;
+    if (c->geometry != MP_PLANAR && c->geometry != MP_SPHERICAL_IRREGULAR)
+        return fail(c, MP_ERR_STATE, "the split source needs a planar or irregular spherical base state");
+    (void)hipSetDevice(c->cfg.device);
+    const long long ns = c->geometry == MP_PLANAR ? c->d0.nz : c->nm;
+    if (!sbar) {
+        if (!c->sbar) {
+            if (hipMalloc((void**)&c->sbar, sizeof(double) * (size_t)ns) != hipSuccess) {
+                c->sbar = nullptr;
+                (void)hipGetLastError();
+                return fail(c, MP_ERR_NOMEM, "no device memory for the lateral average");
+            }
+            c->sbar_n = ns;
+        }
+        if (c->sbar_n < ns) return fail(c, MP_ERR_STATE, "lateral average buffer too small");
+        sbar = c->sbar;
+    }
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    if (c->geometry == MP_PLANAR) {
+        mp::launch_plane_average(c->d0, S, sbar, c->stream);
+    } else {
+        st = build_radius_list(c);
+        if (st) return st;
+        mp::launch_average(c->nm, c->rad_offs, c->rad_cells, S, sbar, nullptr, c->stream);
+    }
+    return project(c, ux, uy, uz, S, sbar, c->geometry == MP_PLANAR ? 1 : 2, phi, use_initial_guess, info);
 }
 
 int mp_solve(mp_ctx* c, const double* rhs, double* x, int use_initial_guess, mp_info* info)

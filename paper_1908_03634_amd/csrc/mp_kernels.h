@@ -72,14 +72,19 @@ template <typename Tout>
 void launch_coef_restrict_cells(const Dims& fine, const double* cc, Tout* cx, Tout* cy, Tout* cz, hipStream_t s);
 
 // ---- projection ------------------------------------------------------------
-// b = beta0 S - D(beta0 U) (= minus the MAC right-hand side); partials
-// (zred_blocks) = sum b.
+// b = beta0 S' - D(beta0 U) (= minus the MAC right-hand side); partials
+// (zred_blocks) = sum b.  S' = S (smode 0), or S - Sbar with Sbar per plane
+// (smode 1) or per irregular radius (smode 2): the velocity-split source.
 void launch_mac_rhs(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
-                    const double* uz, const double* S, double* b, double* partials, hipStream_t s);
-// partials (zred_blocks) = per-block sum of (beta0 S - D(beta0 U) - shift[0])^2
+                    const double* uz, const double* S, const double* sbar, int smode, double* b, double* partials,
+                    hipStream_t s);
+// partials (zred_blocks) = per-block sum of (beta0 S' - D(beta0 U) - shift[0])^2
 // (no write): the divergence defect of a projected velocity.
 void launch_rhs_defect(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
-                       const double* uz, const double* S, const double* shift, double* partials, hipStream_t s);
+                       const double* uz, const double* S, const double* sbar, int smode, const double* shift,
+                       double* partials, hipStream_t s);
+// avg[k] = mean of plane k (lateral average of a planar atmosphere).
+void launch_plane_average(const Dims& d, const double* phi, double* avg, hipStream_t s);
 // U <- U - (c/beta0_f) G phi on every non-wall face (in place).
 void launch_vel_correct(const Dims& d, double inv_h, const Coef<double>& c64, const double* beta0, const double* phi,
                         double* ux, double* uy, double* uz, hipStream_t s);

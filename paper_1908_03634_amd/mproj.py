@@ -90,7 +90,7 @@ class Info(ctypes.Structure):
 
 # Every exported symbol of include/mproj.h.
 EXPORTS = ["mp_config_default", "mp_init", "mp_map_base_state", "mp_set_coefs", "mp_mac_project", "mp_solve",
-           "mp_radius_count", "mp_average", "mp_set_kernel_timing", "mp_apply", "mp_coef_grad", "mp_free",
+           "mp_mac_project_split", "mp_radius_count", "mp_average", "mp_set_kernel_timing", "mp_apply", "mp_coef_grad", "mp_free",
            "mp_last_error", "mp_version"]
 
 _lib = None
@@ -120,6 +120,8 @@ def load_library(path=None):
     lib.mp_mac_project.restype = I
     lib.mp_solve.argtypes = [P, P, P, I, ctypes.POINTER(Info)]
     lib.mp_solve.restype = I
+    lib.mp_mac_project_split.argtypes = [P, P, P, P, P, P, I, P, ctypes.POINTER(Info)]
+    lib.mp_mac_project_split.restype = I
     lib.mp_radius_count.argtypes = [P, ctypes.POINTER(ctypes.c_longlong)]
     lib.mp_radius_count.restype = I
     lib.mp_average.argtypes = [P, P, P, P]
@@ -238,8 +240,11 @@ class Context:
         ps = [self._ptr(f, s, n) for f, s, n in zip((cx, cy, cz), self.face_shapes(), ("cx", "cy", "cz"))]
         self._check(self.lib.mp_set_coefs(self._h, *ps), "mp_set_coefs")
 
-    def mac_project(self, ux, uy, uz, S, phi=None, use_initial_guess=False, allow_not_converged=False):
-        """Project (ux, uy, uz) in place; returns (phi, info dict)."""
+    def mac_project(self, ux, uy, uz, S, phi=None, use_initial_guess=False, allow_not_converged=False,
+                    split=False, sbar=None):
+        """Project (ux, uy, uz) in place; returns (phi, info dict).  split:
+        velocity-split constraint div(beta0 U~) = beta0 (S - Sbar), Sbar (the
+        lateral average of S) written to `sbar` when given."""
         sx, sy, sz = self.face_shapes()
         pu = [self._ptr(ux, sx, "ux"), self._ptr(uy, sy, "uy"), self._ptr(uz, sz, "uz")]
         ps = self._ptr(S, self.shape, "S")
@@ -248,10 +253,15 @@ class Context:
             use_initial_guess = False
         pp = self._ptr(phi, self.shape, "phi")
         info = Info()
-        code = self.lib.mp_mac_project(self._h, *pu, ps, pp, int(bool(use_initial_guess)), ctypes.byref(info))
+        if split:
+            pb = self._ptr(sbar, None, "sbar") if sbar is not None else None
+            code = self.lib.mp_mac_project_split(self._h, *pu, ps, pp, int(bool(use_initial_guess)), pb,
+                                                 ctypes.byref(info))
+        else:
+            code = self.lib.mp_mac_project(self._h, *pu, ps, pp, int(bool(use_initial_guess)), ctypes.byref(info))
         d = info.as_dict()
         if not (allow_not_converged and code == MP_ERR_NOT_CONVERGED):
-            self._check(code, "mp_mac_project", d)
+            self._check(code, "mp_mac_project_split" if split else "mp_mac_project", d)
         d["status"] = code
         return phi, d
 

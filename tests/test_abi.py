@@ -81,6 +81,7 @@ def test_null_arguments():
     assert lib.mp_set_coefs(None, None, None, None) == 1
     assert lib.mp_set_kernel_timing(None, 1) == 1
     assert lib.mp_radius_count(None, None) == 1
+    assert lib.mp_mac_project_split(None, None, None, None, None, None, 0, None, None) == 1
     assert lib.mp_average(None, None, None, None) == 1
     assert lib.mp_apply(None, None, None) == 1
     assert lib.mp_coef_grad(None, None, None, None, None, None) == 1

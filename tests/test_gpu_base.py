@@ -107,3 +107,52 @@ def test_star_projection_with_each_base_state(base, precision):
     g = ref["grid"]
     assert oracle.residual_norm(g, ref["cx"], ref["cy"], ref["cz"], ref["rhs"], N(r["phi"])) <= 1.01e-12
     r["ctx"].close()
+
+
+def _split_case(p, precision):
+    ref = oracle.mac_project(p, tol=1e-12, split=True)
+    ctx = context_for(p, precision, rtol=1e-12)
+    ctx.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center, want_coefs=False)
+    ux, uy, uz, S = T(p.ux), T(p.uy), T(p.uz), T(p.S)
+    sbar = torch.zeros(len(ref["sbar"]), dtype=torch.float64, device="cuda:0")
+    phi, info = ctx.mac_project(ux, uy, uz, S, split=True, sbar=sbar)
+    phi = N(phi)
+    g = ref["grid"]
+    assert np.abs(N(sbar) - ref["sbar"]).max() <= 1e-13 * np.abs(ref["sbar"]).max()
+    assert rel(phi, ref["phi"]) < 1e-9
+    assert oracle.residual_norm(g, ref["cx"], ref["cy"], ref["cz"], ref["rhs"], phi) <= 1.01e-12
+    # the split source has a zero sum on every plane / radius: nothing to de-mean
+    assert abs(info["rhs_mean"]) <= 1e-13 * info["rhs_norm"] / np.sqrt(p.ncell)
+    assert info["div_defect"] <= 2e-12
+    vx, vy, vz = oracle.velocity_correct(g, ref["cx"], ref["cy"], ref["cz"], ref["beta0_cc"], phi, p.ux, p.uy, p.uz)
+    for a, b in ((ux, vx), (uy, vy), (uz, vz)):
+        assert np.abs(N(a) - b).max() <= 1e-12 * np.abs(b).max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 1), (1, 1, 1), (0, 0, 0)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_split_projection_planar_matches_oracle(bc, precision):
+    say("split planar", bc, precision)
+    _split_case(W.planar_problem(nx=48, ny=32, nz=40, contrast=1e4, bc=bc, seed=6500), precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_split_projection_irregular_star_matches_oracle(precision):
+    say("split star", precision)
+    _split_case(W.spherical_problem(64, contrast=1e5, seed=6600, base="irregular"), precision)
+
+
+def test_split_projection_full_size_planar():
+    say("split c2 256^3")
+    _split_case(W.config_problem("c2", seed_offset=300), "mixed")
+
+
+def test_split_needs_a_planar_or_irregular_mapping():
+    p = W.spherical_problem(16, seed=6700)
+    ctx = context_for(p, "fp64")
+    ctx.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center, want_coefs=False)
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.mac_project(T(p.ux), T(p.uy), T(p.uz), T(p.S), split=True)
+    assert e.value.code == 7
+    ctx.close()
