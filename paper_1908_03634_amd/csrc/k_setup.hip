@@ -30,16 +30,33 @@ static inline unsigned grid1(long long n)
 int zred_blocks(const Dims& d) { return (int)zmarch(d.nx, d.ny, d.nz, kZBlocks).blocks(); }
 
 // Index helpers of the 3D launches.
+// Workgroup p runs on XCD p % 8, each with its own L2: renumber so that each
+// XCD takes one contiguous run of (column tile, plane chunk), keeping the
+// rows and planes shared by neighbouring tiles inside one L2.
+__device__ __forceinline__ void zcol_tile(int& bx, int& by, int& bz)
+{
+    const unsigned gx = gridDim.x, gy = gridDim.y, n = gridDim.x * gridDim.y * gridDim.z;
+    unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    if (n % 8 == 0) p = (p % 8) * (n / 8) + p / 8;
+    bx = (int)(p % gx);
+    by = (int)((p / gx) % gy);
+    bz = (int)(p / (gx * gy));
+}
+
 #define MP_IJK3                                                                                                       \
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;                                                             \
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;                                                             \
-    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    int bx3_, by3_, bz3_;                                                                                             \
+    zcol_tile(bx3_, by3_, bz3_);                                                                                      \
+    const int i = bx3_ * blockDim.x + threadIdx.x;                                                                    \
+    const int j = by3_ * blockDim.y + threadIdx.y;                                                                    \
+    const int k = bz3_ * blockDim.z + threadIdx.z;
 
 // Column (i, j) and z range [z0, z1) of a z-marching launch.
 #define MP_ZCOL                                                                                                       \
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;                                                             \
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;                                                             \
-    const int z0 = blockIdx.z * lz;                                                                                   \
+    int bx_, by_, bz_;                                                                                                \
+    zcol_tile(bx_, by_, bz_);                                                                                         \
+    const int i = bx_ * blockDim.x + threadIdx.x;                                                                     \
+    const int j = by_ * blockDim.y + threadIdx.y;                                                                     \
+    const int z0 = bz_ * lz;                                                                                          \
     const int z1 = min(z0 + lz, d.nz);                                                                                \
     const bool col = i < d.nx && j < d.ny;
 
@@ -438,23 +455,33 @@ __global__ __launch_bounds__(kBlock) void k_mac_rhs(Dims d, int lz, double inv_h
     __shared__ double sh[kBlock / kWave];
     MP_ZCOL
     double acc = 0.0;
+    // the z flux through the low face of plane k; the high face's flux of
+    // plane k is carried to plane k+1 (same operands, same value)
+    double fzl = 0.0, b0 = 0.0;
+    if (col) {
+        const long long q = ((long long)z0 * d.ny + j) * d.nx + i;
+        b0 = beta0[q];
+        if (z0 > 0 || d.pz) {
+            const long long qm = z0 > 0 ? q - (long long)d.nx * d.ny : q + (long long)(d.nz - 1) * d.nx * d.ny;
+            fzl = 0.5 * (beta0[qm] + b0) * uz[ext_low(d, i, j, z0).zl];
+        }
+    }
     for (int k = z0; col && k < z1; k++) {
         const long long q = ((long long)k * d.ny + j) * d.nx + i;
         const Nbr nb = neighbours(d, q, i, j, k);
         const ExtIdx e = ext_low(d, i, j, k);
-        const double b0 = beta0[q];
         // low faces
         const double fxl = (i > 0 || d.px) ? 0.5 * (beta0[nb.xm] + b0) * ux[e.xl] : 0.0;
         const double fyl = (j > 0 || d.py) ? 0.5 * (beta0[nb.ym] + b0) * uy[e.yl] : 0.0;
-        const double fzl = (k > 0 || d.pz) ? 0.5 * (beta0[nb.zm] + b0) * uz[e.zl] : 0.0;
         // high faces
         double fxh = 0.0, fyh = 0.0, fzh = 0.0;
         if (i < d.nx - 1) fxh = 0.5 * (b0 + beta0[nb.xp]) * ux[e.xl + 1];
         else if (d.px) fxh = 0.5 * (b0 + beta0[nb.xp]) * ux[e.xl - (d.nx - 1)];
         if (j < d.ny - 1) fyh = 0.5 * (b0 + beta0[nb.yp]) * uy[e.yl + d.nx];
         else if (d.py) fyh = 0.5 * (b0 + beta0[nb.yp]) * uy[e.yl - (long long)(d.ny - 1) * d.nx];
-        if (k < d.nz - 1) fzh = 0.5 * (b0 + beta0[nb.zp]) * uz[e.zl + (long long)d.nx * d.ny];
-        else if (d.pz) fzh = 0.5 * (b0 + beta0[nb.zp]) * uz[e.zl - (long long)(d.nz - 1) * d.nx * d.ny];
+        const double bzp = beta0[nb.zp];
+        if (k < d.nz - 1) fzh = 0.5 * (b0 + bzp) * uz[e.zl + (long long)d.nx * d.ny];
+        else if (d.pz) fzh = 0.5 * (b0 + bzp) * uz[e.zl - (long long)(d.nz - 1) * d.nx * d.ny];
         const double div = ((fxh - fxl) + (fyh - fyl) + (fzh - fzl)) * inv_h;
         const double v = b0 * cell_source(d, S, sbar, smode, q, i, j, k) - div;
         if (shift) {
@@ -464,6 +491,8 @@ __global__ __launch_bounds__(kBlock) void k_mac_rhs(Dims d, int lz, double inv_h
             b[q] = v;
             acc += v;
         }
+        fzl = fzh;
+        b0 = bzp;
     }
     zpart_store(part, block_sum(acc, sh));
 }
