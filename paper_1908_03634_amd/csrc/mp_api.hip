@@ -41,6 +41,7 @@ struct Level {
     bool fused = false;  // both colours in one launch on this level
     bool blk = false;    // register-blocked kernels (finest level, cell mode)
     bool fsw = false;    // ... with both colours of a sweep in one pass
+    bool blkf = false;   // register-blocked kernels with stored face coefficients
 };
 
 constexpr long long kCoarseCells = 512;  // levels at or below run in one workgroup
@@ -260,6 +261,12 @@ int build_radius_list(mp_ctx* c)
 // Register-blocked kernels on level l (finest level with cell values only).
 bool use_blk(const mp_ctx* c, int l) { return l == 0 && c->cell_mode && c->lv[0].blk && c->phi_aligned; }
 
+// Register-blocked kernels on a level with stored face coefficients.
+bool use_blkf(const mp_ctx* c, int l)
+{
+    return c->lv[l].blkf && !(l == 0 && (c->cell_mode || !c->phi_aligned));
+}
+
 // Coefficients of levels 1.. from level 0.
 void build_pyramid(mp_ctx* c)
 {
@@ -322,6 +329,18 @@ void smooth(mp_ctx* c, int l, bool zero_init, const T* ec, bool last = false)
     const bool tm = c->cfg.kernel_timing && l == 0;
     const double cells = (double)L.d.n();
     const mp::Coef<T> C = level_coef<T>(c, l);
+    if (use_blkf(c, l)) {
+        for (int colour = 0; colour < 2; colour++) {
+            const bool zi = zero_init && colour == 0;
+            const int mode = zi ? mp::GS_ZERO : !ec ? mp::GS_PLAIN : colour == 0 ? mp::GS_E_ALL : mp::GS_E_OWN;
+            // per colour: x in and out, b, three face words; 1/8 word of e
+            const double words = (zi ? 5.0 : 6.0) + (ec ? 0.125 : 0.0);
+            timed_begin(c, tm);
+            mp::launch_gs_blkf<T>(L.d, (T*)L.x, (const T*)L.b, C, h2, colour, mode, ec, c->stream);
+            timed_end(c, tm, words * sizeof(T) * cells);
+        }
+        return;
+    }
     if (L.fused && !C.cell) {
         // words per cell: x_old (unless zero), b, 3 coefficients, x_new, 1/8 coarse e
         const double words = (zero_init ? 0.0 : 1.0) + 1.0 + 3.0 + 1.0 + (ec ? 0.125 : 0.0);
@@ -442,6 +461,9 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
     if (use_blk(c, l))
         mp::launch_rr_blk<T>(L.d, (const T*)L.x, (const T*)L.b, level_coef<T>(c, l).cell, (T)(1.0 / (L.h * L.h)),
                              (T*)C.b, c->stream);
+    else if (use_blkf(c, l))
+        mp::launch_rr_blkf<T>(L.d, (const T*)L.x, (const T*)L.b, level_coef<T>(c, l), (T)(1.0 / (L.h * L.h)),
+                              (T*)C.b, c->stream);
     else
         mp::launch_resid_restrict<T>(L.d, (const T*)L.x, (const T*)L.b, level_coef<T>(c, l), (T)(1.0 / (L.h * L.h)),
                                      (T*)C.b, c->stream);
@@ -748,7 +770,9 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
         for (int l = 0; l < nlev - 1; l++) {
             Level& L = c->lv[l];
             if (c->coarse_start >= 0 && l >= c->coarse_start) break;
-            L.fused = mp::sweep_supported(L.d) &&
+            // FP32 levels only: the FP64 variants need too many registers
+            L.blkf = cfg->blocked && mx && mp::blk_supported(L.d);
+            L.fused = !L.blkf && mp::sweep_supported(L.d) &&
                       (cfg->smoother == MP_SMOOTH_FUSED ||
                        (cfg->smoother == MP_SMOOTH_AUTO && L.d.n() >= kFusedMinCells));
             if (L.fused) {

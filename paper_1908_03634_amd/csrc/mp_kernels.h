@@ -178,6 +178,12 @@ bool fsw_supported(const Dims& d);
 template <typename T>
 void launch_fsw_blk(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, T h2, int mode, const T* ec,
                     double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
+// The same two kernels on a level with stored low-face coefficients c.
+template <typename T>
+void launch_gs_blkf(const Dims& d, T* x, const T* b, const Coef<T>& c, T h2, int colour, int mode, const T* ec,
+                    hipStream_t s);
+template <typename T>
+void launch_rr_blkf(const Dims& d, const T* x, const T* b, const Coef<T>& c, T inv_h2, T* bc, hipStream_t s);
 // Coarse rhs = mean of the 8 fine residuals b - A x (as launch_resid_restrict).
 template <typename T>
 void launch_rr_blk(const Dims& d, const T* x, const T* b, const T* cc, T inv_h2, T* bc, hipStream_t s);

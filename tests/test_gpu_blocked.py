@@ -159,3 +159,22 @@ def test_fused_blocked_sweep_equals_colour_passes(shape, bc):
         xb, ib = _solve(p, "mixed", True, rhs, smoother="per_colour", **kw)
         assert np.array_equal(xa, xb)
         assert ia["vcycles"] == ib["vcycles"]
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(256, 64, 32), (512, 16, 16), (1024, 8, 8)])
+def test_blocked_face_coefficient_levels(shape, bc):
+    """Coarse levels with stored face coefficients also run blocked kernels
+    (whole-row strips of 2 and 4 cells, and tiles with halo columns): one
+    refinement step equals the one-cell kernels bit for bit, and a full solve
+    reaches the tolerance in the same number of cycles."""
+    say("blocked face levels", shape, bc)
+    p = _problem(shape, bc, 5200 + sum(shape))
+    rhs = W.random_cells(*shape, 5300 + sum(shape))
+    xa, _ = _solve(p, "mixed", True, rhs, max_outer=1)
+    xb, _ = _solve(p, "mixed", False, rhs, max_outer=1)
+    assert np.array_equal(xa, xb)
+    xa, ia = _solve(p, "mixed", True, rhs, rtol=1e-11)
+    xb, ib = _solve(p, "mixed", False, rhs, rtol=1e-11)
+    assert ia["vcycles"] == ib["vcycles"] and ia["rel_resid"] <= 1e-11
+    assert rel(xa, xb) < 1e-9
