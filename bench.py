@@ -58,12 +58,15 @@ def _traffic_record(kernel):
     # the counters belong to the kernel source they were taken on
     import hashlib
 
-    src = os.path.join(ROOT, rec.get("source", ""))
-    if not os.path.exists(src):
-        return None
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
-    if digest != rec.get("sha256"):
+    # (the .hip file and the headers it includes, hashed in the listed order)
+    h = hashlib.sha256()
+    for rel in rec.get("sources", []):
+        src = os.path.join(ROOT, rel)
+        if not os.path.exists(src):
+            return None
+        with open(src, "rb") as f:
+            h.update(f.read())
+    if not rec.get("sources") or h.hexdigest() != rec.get("sha256"):
         return None
     return rec
 
