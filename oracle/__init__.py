@@ -5,6 +5,7 @@ baseline leg of the benchmark may import this package; the product path (the
 HIP library and its Python binding) never does, and shares no code with it.
 
 The arithmetic lives in `mproj_oracle.c` (plain C, FP64, OpenMP over z planes);
+the nodal projection of Sec. 3.2 Step 11 is in `nodal_oracle.c` / `nodal.py`;
 this module builds it with gcc and wraps it for numpy arrays.  Each wrapper
 names the passage of the paper it follows; see the C file's header for the
 discretisation.
@@ -24,11 +25,14 @@ _lib = None
 
 
 def build(force=True):
-    """Compile the oracle with gcc (FP64, -O2, OpenMP)."""
+    """Compile the oracle (and the nodal-projection oracle) with gcc (FP64, -O2, OpenMP)."""
     cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", _LIB + ".tmp", _SRC, "-lm"]
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
+    from . import nodal
+
+    nodal.build(force=force)
     return _LIB
 
 

@@ -109,12 +109,21 @@ def _draw_faces(rng, nx, ny, nz, bc):
     return ux, uy, uz
 
 
+def _draw_velocity(rng, nx, ny, nz, bc, velocity):
+    """Face velocity (MAC projection) or cell-centred velocity (nodal projection)."""
+    if velocity == "cells":
+        return tuple(rng.standard_normal((nz, ny, nx)) for _ in range(3))
+    return _draw_faces(rng, nx, ny, nz, bc)
+
+
 def planar_problem(n=None, *, nx=None, ny=None, nz=None, contrast=1e4, bc=(PERIODIC, PERIODIC, NEUMANN),
-                   seed=SEED_BASE, rho_noise=1e-3, s_sigma=1e-2, u_sigma=1.0, with_w=False, name="planar"):
+                   seed=SEED_BASE, rho_noise=1e-3, s_sigma=1e-2, u_sigma=1.0, with_w=False, name="planar",
+                   velocity="faces"):
     """Plane-parallel atmosphere on the unit-spacing grid h = 1/nz.
 
     Draw order from numpy's PCG64 `default_rng(seed)`: density noise (cells),
-    Ux, Uy, Uz (face shapes), S (cells), then w (cells) when requested.
+    Ux, Uy, Uz (face shapes, or cell shapes with velocity="cells"), S (cells),
+    then w (cells) when requested.
     """
     nx = nx or n
     ny = ny or n
@@ -128,7 +137,7 @@ def planar_problem(n=None, *, nx=None, ny=None, nz=None, contrast=1e4, bc=(PERIO
     xi = rng.standard_normal((nz, ny, nx))
     rho = rho0[:, None, None] * (1.0 + rho_noise * xi)
     del xi
-    ux, uy, uz = _draw_faces(rng, nx, ny, nz, bc)
+    ux, uy, uz = _draw_velocity(rng, nx, ny, nz, bc, velocity)
     if u_sigma != 1.0:
         ux *= u_sigma
         uy *= u_sigma
@@ -138,7 +147,7 @@ def planar_problem(n=None, *, nx=None, ny=None, nz=None, contrast=1e4, bc=(PERIO
     return Problem(name=name, nx=nx, ny=ny, nz=nz, h=h, bc=tuple(bc), geometry=PLANAR,
                    beta0_1d=np.ascontiguousarray(beta0_1d), dr=h, center=(0.0, 0.0, 0.0),
                    rho=rho, ux=ux, uy=uy, uz=uz, S=S, w=w,
-                   meta=dict(contrast=contrast, H=H, seed=seed, rho_noise=rho_noise))
+                   meta=dict(contrast=contrast, H=H, seed=seed, rho_noise=rho_noise, velocity=velocity))
 
 
 def spherical_n1d(n):
@@ -148,7 +157,7 @@ def spherical_n1d(n):
 
 def spherical_problem(n, *, contrast=1e5, bc=(NEUMANN, NEUMANN, NEUMANN), seed=SEED_BASE,
                       rho_noise=1e-3, s_sigma=1e-2, with_w=False, name="spherical", radial_refine=5,
-                      base="linear"):
+                      base="linear", velocity="faces"):
     """Full-star box: rho0(r) = (1 + (r/R)^2)^(-5/2) about the box centre.
 
     base "linear" / "quadratic": the 1D beta0 table lives on r_j = (j + 1/2) dr
@@ -156,7 +165,8 @@ def spherical_problem(n, *, contrast=1e5, bc=(NEUMANN, NEUMANN, NEUMANN), seed=S
     Sec. 3.1), interpolated linearly or quadratically.  base "irregular": the
     table holds beta0 at the radii h sqrt(0.75 + 2m) of the irregular base
     state (n even; one entry per m).  The cell density is the analytic profile
-    at the cell centre times (1 + rho_noise * N(0,1)).
+    at the cell centre times (1 + rho_noise * N(0,1)).  velocity="cells" draws
+    a cell-centred velocity (nodal projection) instead of face velocities.
     """
     nx = ny = nz = n
     h = 1.0 / n
@@ -180,13 +190,13 @@ def spherical_problem(n, *, contrast=1e5, bc=(NEUMANN, NEUMANN, NEUMANN), seed=S
     xi = rng.standard_normal((nz, ny, nx))
     rho = rho0_cells * (1.0 + rho_noise * xi)
     del xi, rho0_cells
-    ux, uy, uz = _draw_faces(rng, nx, ny, nz, bc)
+    ux, uy, uz = _draw_velocity(rng, nx, ny, nz, bc, velocity)
     S = s_sigma * rng.standard_normal((nz, ny, nx))
     w = rng.standard_normal((nz, ny, nx)) if with_w else None
     return Problem(name=name, nx=nx, ny=ny, nz=nz, h=h, bc=tuple(bc), geometry=geometry,
                    beta0_1d=np.ascontiguousarray(beta0_1d), dr=dr, center=center,
                    rho=rho, ux=ux, uy=uy, uz=uz, S=S, w=w,
-                   meta=dict(contrast=contrast, R=R, seed=seed, rho_noise=rho_noise, base=base))
+                   meta=dict(contrast=contrast, R=R, seed=seed, rho_noise=rho_noise, base=base, velocity=velocity))
 
 
 # The five workloads: sizes, boundaries and contrasts.
@@ -199,17 +209,20 @@ CONFIGS = {
 }
 
 
-def config_problem(name, n=None, seed_offset=0):
-    """Problem for workload `name` ('c1'..'c5'); `n` overrides the grid size."""
+def config_problem(name, n=None, seed_offset=0, velocity="faces"):
+    """Problem for workload `name` ('c1'..'c5'); `n` overrides the grid size.
+    velocity="cells": the same base state and density with a cell-centred
+    velocity, the input of the nodal projection (Sec. 3.2 Step 11)."""
     cfg = CONFIGS[name]
     idx = int(name[1:])
     seed = SEED_BASE + idx + seed_offset
     size = n or cfg["n"]
+    tag = "" if velocity == "faces" else "-nodal"
     if cfg["kind"] == "planar":
         return planar_problem(size, contrast=cfg["contrast"], seed=seed, with_w=cfg.get("with_w", False),
-                              name=f"{name}-{size}^3")
+                              name=f"{name}{tag}-{size}^3", velocity=velocity)
     return spherical_problem(size, contrast=cfg["contrast"], seed=seed, with_w=cfg.get("with_w", False),
-                             name=f"{name}-{size}^3")
+                             name=f"{name}{tag}-{size}^3", velocity=velocity)
 
 
 def fd_copy_problem():
