@@ -190,6 +190,44 @@ int mp_mac_project(mp_ctx *ctx, double *ux, double *uy, double *uz, const double
 int mp_mac_project_split(mp_ctx *ctx, double *ux, double *uy, double *uz, const double *S, double *phi,
                          int use_initial_guess, double *sbar, mp_info *info);
 
+/* ---- nodal projection (Sec. 3.2 Step 11, Appendix A) --------------------
+ * The velocity update of Step 11 projects a CELL-CENTRED velocity with a
+ * scalar phi on the grid NODES.  The paper defers the discretisation to an
+ * earlier paper; here it is trilinear finite elements on the cells:
+ *   phi_h = sum_n phi_n N_n (N_n the trilinear hat function of node n),
+ *   sigma = beta0/rho constant per cell (from the last mp_map_base_state),
+ *   (M phi)_n = -h^-3 sum_e sigma_e int_e grad phi_h . grad N_n,
+ *   (D V)_n   = -h^-3 sum_e V_e . int_e grad N_n      (nodal divergence),
+ *   (G phi)_e =  h^-3 int_e grad phi_h                 (cell-average gradient),
+ *   (L f)_n   =  h^-3 sum_e f_e int_e N_n              (load: 1/8 per corner).
+ * Node counts per axis: n (periodic; node n is node 0) or n + 1 (Neumann
+ * walls, whose nodes are unknowns taking only the cells inside).  Node arrays
+ * are C order [nz+bz][ny+by][nx+bx], x fastest (b = 1 for Neumann axes).  */
+
+/* Node counts (x, y, z) of this context's grid. */
+int mp_nodal_shape(const mp_ctx *ctx, int *mx, int *my, int *mz);
+
+/* Nodal projection.  Solves M phi = D(beta0 U) - L(beta0 S - m), m the cell
+ * mean of beta0 S, to the configured relative residual (FP64, or FP32
+ * V-cycles inside FP64 refinement in MP_MIXED; 4-colour Gauss-Seidel V(nu1,
+ * nu2), full-weighting restriction, trilinear prolongation, cell sigma
+ * coarsened as the mean of its 8 children, FP64 conjugate gradients on the
+ * coarsest grid of at most 16384 nodes), returns phi with zero node mean,
+ * then U_e <- U_e - (sigma_e / beta0_e)(G phi)_e on every cell.  D sigma G
+ * differs from M, so U meets the constraint only approximately (an
+ * approximate projection); info->div_defect reports
+ * ||D(beta0 U_new) - L(beta0 S - m)|| / ||right-hand side||.
+ * ux, uy, uz: cells, device, in/out; S: cells; phi: nodes (initial guess when
+ * use_initial_guess).  info->rhs_mean = m.  Needs a prior mp_map_base_state
+ * (MP_ERR_STATE).  The first call allocates the node hierarchy (MP_ERR_NOMEM).
+ * MP_ERR_ARG: NULL arrays, or a coarsest grid above 16384 nodes.
+ * MP_ERR_NOT_CONVERGED / MP_ERR_NONFINITE as mp_mac_project. */
+int mp_nodal_project(mp_ctx *ctx, double *ux, double *uy, double *uz, const double *S, double *phi,
+                     int use_initial_guess, mp_info *info);
+
+/* y = M x on the nodes, FP64, with sigma from the last mapping. */
+int mp_nodal_apply(mp_ctx *ctx, const double *x, double *y);
+
 /* Solve M x = rhs (rhs mean removed when demean = 1); x mean-zero.  This is
  * also the adjoint solve, M being symmetric. */
 int mp_solve(mp_ctx *ctx, const double *rhs, double *x, int use_initial_guess, mp_info *info);

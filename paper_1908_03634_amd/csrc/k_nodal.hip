@@ -1,0 +1,563 @@
+// k_nodal.hip -- nodal projection kernels (Sec. 3.2 Step 11, Appendix A).
+//
+// phi lives on the grid nodes, the velocity U and sigma = beta0/rho at cell
+// centres.  The discretisation is trilinear finite elements on the cells (the
+// paper defers it to an earlier paper): with the hat function N_n of node n,
+//   (A phi)_n = h^-3 sum_e sigma_e int_e grad phi_h . grad N_n   (A = -M, SPD)
+// For a cube cell the element matrix couples a node to the three corners
+// across a face of the cell (two axes differ) and the far corner (three
+// differ) with weight -h/12 each, to itself with h/3, and not at all to the
+// three corners along an edge.  So, with S_e the sum of phi over those four
+// corners of cell e,
+//   (A phi)_n = (1/(12 h^2)) sum_e sigma_e (4 phi_n - S_e),
+// a 21-point stencil in which nodes of equal (i mod 2, j mod 2) never couple:
+// Gauss-Seidel runs in four colours.
+//   divergence of a cell field V:  (D V)_n = -(1/(4h)) sum_e sum_d s_d V_e,d
+//   cell-average gradient:         (G phi)_e,d = (1/(4h)) sum_B s_d(B) phi_B
+//   load of a cell field f:        (L f)_n = (1/8) sum_e f_e
+// where s_d = +1 when the node (corner B) is on the high side of the cell
+// along d and -1 otherwise.
+//
+// Nodes: n per periodic axis (node n is node 0), n + 1 per axis with Neumann
+// walls; wall nodes are unknowns whose equations take only the cells inside.
+// Layout [mz][my][mx], x fastest; cells [nz][ny][nx].
+#include "mp_device.h"
+#include "mp_kernels.h"
+#include "mp_launch.h"
+
+namespace mp {
+
+namespace {
+
+// Node neighbours along one axis (offsets -1, 0, +1) and the cells below and
+// above the node (offsets -1, 0).  Missing ones (beyond a wall) are flagged
+// and point at the node itself / cell 0 so every load stays in bounds.
+struct Axis {
+    int nd[3];
+    bool nok[3];
+    int ce[2];
+    bool cok[2];
+};
+
+__device__ __forceinline__ Axis axis_of(int i, int n, int per)
+{
+    Axis a;
+#pragma unroll
+    for (int o = 0; o < 3; o++) {
+        int t = i + o - 1;
+        if (per) {
+            t = t < 0 ? t + n : (t >= n ? t - n : t);
+            a.nd[o] = t;
+            a.nok[o] = true;
+        } else {
+            a.nok[o] = t >= 0 && t <= n;
+            a.nd[o] = a.nok[o] ? t : i;
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < 2; o++) {
+        int t = i + o - 1;
+        if (per) {
+            t = t < 0 ? t + n : t;
+            a.ce[o] = t;
+            a.cok[o] = true;
+        } else {
+            a.cok[o] = t >= 0 && t < n;
+            a.ce[o] = a.cok[o] ? t : 0;
+        }
+    }
+    return a;
+}
+
+// Sums of the stencil at node (i,j,k) in precision T (fixed order: cells by
+// z, y, x offset; in each cell the three face-diagonal corners, then the far
+// corner).
+template <typename T>
+__device__ __forceinline__ void node_sums(const NDims& d, const T* __restrict__ x, const T* __restrict__ sg, int i,
+                                          int j, int k, T& ssig, T& ss)
+{
+    const Axis ax = axis_of(i, d.nx, d.px), ay = axis_of(j, d.ny, d.py), az = axis_of(k, d.nz, d.pz);
+    const long long sy = d.mx, sz = (long long)d.mx * d.my;
+    T v[3][3][3];
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                const int dist = (a != 1) + (b != 1) + (c != 1);
+                if (dist >= 2) {
+                    const bool ok = ax.nok[a] && ay.nok[b] && az.nok[c];
+                    v[c][b][a] = ok ? x[az.nd[c] * sz + ay.nd[b] * sy + ax.nd[a]] : T(0);
+                } else {
+                    v[c][b][a] = T(0);
+                }
+            }
+    const long long cy = d.nx, cz = (long long)d.nx * d.ny;
+    T s1 = T(0), s2 = T(0);
+#pragma unroll
+    for (int oz = 0; oz < 2; oz++)
+#pragma unroll
+        for (int oy = 0; oy < 2; oy++)
+#pragma unroll
+            for (int ox = 0; ox < 2; ox++) {
+                const bool ok = ax.cok[ox] && ay.cok[oy] && az.cok[oz];
+                const T se = ok ? sg[az.ce[oz] * cz + ay.ce[oy] * cy + ax.ce[ox]] : T(0);
+                // the cell lies on side ox (0 = below, 1 = above) of the node;
+                // its other corners are at node offsets 2*ox (i.e. -1 or +1)
+                const int a = ox * 2, b = oy * 2, c = oz * 2;
+                const T sum = ((v[1][b][a] + v[c][1][a]) + v[c][b][1]) + v[c][b][a];
+                s1 += se;
+                s2 = fma(se, sum, s2);
+            }
+    ssig = s1;
+    ss = s2;
+}
+
+__device__ __forceinline__ long long node_index(const NDims& d, int i, int j, int k)
+{
+    return ((long long)k * d.my + j) * d.mx + i;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- smoother
+
+// One colour of the four-colour Gauss-Seidel sweep on A x = b:
+//   x_n = (sum_e sigma_e S_e + 12 h^2 b_n) / (4 sum_e sigma_e)
+// for the nodes with (i mod 2, j mod 2) = (colour & 1, colour >> 1).
+template <typename T>
+__global__ __launch_bounds__(256) void k_nd_gs(NDims d, T* __restrict__ x, const T* __restrict__ b,
+                                               const T* __restrict__ sg, T h12, int colour)
+{
+    const int i = 2 * (blockIdx.x * blockDim.x + threadIdx.x) + (colour & 1);
+    const int j = 2 * (blockIdx.y * blockDim.y + threadIdx.y) + (colour >> 1);
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= d.mx || j >= d.my || k >= d.mz) return;
+    T ssig, ss;
+    node_sums<T>(d, x, sg, i, j, k, ssig, ss);
+    const long long q = node_index(d, i, j, k);
+    x[q] = (ss + h12 * b[q]) / (T(4) * ssig);
+}
+
+template <typename T>
+void launch_nd_gs(const NDims& d, T* x, const T* b, const T* sg, T h12, int colour, hipStream_t s)
+{
+    const int ni = (d.mx - (colour & 1) + 1) / 2, nj = (d.my - (colour >> 1) + 1) / 2;
+    const Shape3 sh = cells3(ni, nj, d.mz);
+    hipLaunchKernelGGL((k_nd_gs<T>), sh.grid, sh.block, 0, s, d, x, b, sg, h12, colour);
+}
+
+// r = b - A x on every node.
+template <typename T>
+__global__ __launch_bounds__(256) void k_nd_resid(NDims d, const T* __restrict__ x, const T* __restrict__ b,
+                                                  const T* __restrict__ sg, T inv_h12, T* __restrict__ r)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= d.mx || j >= d.my || k >= d.mz) return;
+    T ssig, ss;
+    node_sums<T>(d, x, sg, i, j, k, ssig, ss);
+    const long long q = node_index(d, i, j, k);
+    r[q] = b[q] - (T(4) * ssig * x[q] - ss) * inv_h12;
+}
+
+template <typename T>
+void launch_nd_resid(const NDims& d, const T* x, const T* b, const T* sg, T inv_h12, T* r, hipStream_t s)
+{
+    const Shape3 sh = cells3(d.mx, d.my, d.mz);
+    hipLaunchKernelGGL((k_nd_resid<T>), sh.grid, sh.block, 0, s, d, x, b, sg, inv_h12, r);
+}
+
+// ------------------------------------------------------------- transfers
+
+// Coarse right-hand side = (1/8) P^T r: the fine nodes 2I-1, 2I, 2I+1 per
+// axis with weights 1/2, 1, 1/2 (wrapped when periodic, dropped beyond a wall).
+template <typename T>
+__global__ __launch_bounds__(256) void k_nd_restrict(NDims f, NDims c, const T* __restrict__ rf, T* __restrict__ bc)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (I >= c.mx || J >= c.my || K >= c.mz) return;
+    const Axis ax = axis_of(2 * I, f.nx, f.px), ay = axis_of(2 * J, f.ny, f.py), az = axis_of(2 * K, f.nz, f.pz);
+    const long long sy = f.mx, sz = (long long)f.mx * f.my;
+    T acc = T(0);
+#pragma unroll
+    for (int cc = 0; cc < 3; cc++) {
+        T row = T(0);
+#pragma unroll
+        for (int bb = 0; bb < 3; bb++) {
+            T line = T(0);
+#pragma unroll
+            for (int aa = 0; aa < 3; aa++) {
+                const bool ok = ax.nok[aa] && ay.nok[bb] && az.nok[cc];
+                const T v = ok ? rf[az.nd[cc] * sz + ay.nd[bb] * sy + ax.nd[aa]] : T(0);
+                line += aa == 1 ? v : T(0.5) * v;
+            }
+            row += bb == 1 ? line : T(0.5) * line;
+        }
+        acc += cc == 1 ? row : T(0.5) * row;
+    }
+    bc[((long long)K * c.my + J) * c.mx + I] = T(0.125) * acc;
+}
+
+template <typename T>
+void launch_nd_restrict(const NDims& f, const NDims& c, const T* rf, T* bc, hipStream_t s)
+{
+    const Shape3 sh = cells3(c.mx, c.my, c.mz);
+    hipLaunchKernelGGL((k_nd_restrict<T>), sh.grid, sh.block, 0, s, f, c, rf, bc);
+}
+
+// x_f += P e_c, trilinear: an even fine index takes coarse node i/2, an odd
+// one the mean of coarse nodes (i-1)/2 and (i+1)/2 (wrapped when periodic).
+template <typename T>
+__global__ __launch_bounds__(256) void k_nd_prolong(NDims f, NDims c, T* __restrict__ xf, const T* __restrict__ ec)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= f.mx || j >= f.my || k >= f.mz) return;
+    int I[2], J[2], K[2];
+    I[0] = i >> 1;
+    I[1] = (i & 1) ? ((i + 1) >> 1 == c.mx ? 0 : (i + 1) >> 1) : I[0];
+    J[0] = j >> 1;
+    J[1] = (j & 1) ? ((j + 1) >> 1 == c.my ? 0 : (j + 1) >> 1) : J[0];
+    K[0] = k >> 1;
+    K[1] = (k & 1) ? ((k + 1) >> 1 == c.mz ? 0 : (k + 1) >> 1) : K[0];
+    const long long sy = c.mx, sz = (long long)c.mx * c.my;
+    T acc = T(0);
+#pragma unroll
+    for (int cc = 0; cc < 2; cc++) {
+        T row = T(0);
+#pragma unroll
+        for (int bb = 0; bb < 2; bb++) {
+            const T l = ec[K[cc] * sz + J[bb] * sy + I[0]] + ec[K[cc] * sz + J[bb] * sy + I[1]];
+            row += l;
+        }
+        acc += row;
+    }
+    xf[((long long)k * f.my + j) * f.mx + i] += T(0.125) * acc;
+}
+
+template <typename T>
+void launch_nd_prolong(const NDims& f, const NDims& c, T* xf, const T* ec, hipStream_t s)
+{
+    const Shape3 sh = cells3(f.mx, f.my, f.mz);
+    hipLaunchKernelGGL((k_nd_prolong<T>), sh.grid, sh.block, 0, s, f, c, xf, ec);
+}
+
+// Coarse cell sigma = mean of its 8 children; with fine == coarse shape
+// (same dims) it is a plain precision conversion.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_nd_sigma(int nx, int ny, int nz, const Tin* __restrict__ sf,
+                                                  Tout* __restrict__ sc, int coarsen)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    const int NX = coarsen ? nx / 2 : nx, NY = coarsen ? ny / 2 : ny, NZ = coarsen ? nz / 2 : nz;
+    if (I >= NX || J >= NY || K >= NZ) return;
+    const long long qc = ((long long)K * NY + J) * NX + I;
+    if (!coarsen) {
+        sc[qc] = (Tout)sf[qc];
+        return;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int a = 0; a < 2; a++) s += (double)sf[((long long)(2 * K + c) * ny + 2 * J + b) * nx + 2 * I + a];
+    sc[qc] = (Tout)(0.125 * s);
+}
+
+template <typename Tin, typename Tout>
+void launch_nd_sigma(int nx, int ny, int nz, const Tin* sf, Tout* sc, int coarsen, hipStream_t s)
+{
+    const Shape3 sh = coarsen ? cells3(nx / 2, ny / 2, nz / 2) : cells3(nx, ny, nz);
+    hipLaunchKernelGGL((k_nd_sigma<Tin, Tout>), sh.grid, sh.block, 0, s, nx, ny, nz, sf, sc, coarsen);
+}
+
+// ------------------------------------------------------------- FP64 level 0
+
+__device__ __forceinline__ void node_ijk(const NDims& d, long long q, int& i, int& j, int& k)
+{
+    const long long t = q / d.mx;
+    i = (int)(q - t * d.mx);
+    k = (int)(t / d.my);
+    j = (int)(t - (long long)k * d.my);
+}
+
+// partials[block] = sum over the cells of beta0 * S (grid-stride).
+__global__ __launch_bounds__(kBlock) void k_nd_src_sum(long long n, const double* __restrict__ beta0,
+                                                       const double* __restrict__ S, double* part)
+{
+    __shared__ double sh[kBlock / kWave];
+    double v = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        v = fma(beta0[q], S[q], v);
+    const double s = block_sum(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_nd_src_sum(long long n, const double* beta0, const double* S, double* partials, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nd_src_sum, dim3(nb), dim3(kBlock), 0, s, n, beta0, S, partials);
+}
+
+// b_n = L(beta0 S - m)_n - D(beta0 U)_n  (= minus the nodal right-hand side),
+//     = sum_e [ (beta0_e S_e - m) / 8 + (1/(4h)) sum_d s_d beta0_e U_e,d ].
+// out != nullptr: written; partials[block] = sum of b_n^2 (squares) or of b_n
+// (grid-stride).
+__global__ __launch_bounds__(kBlock) void k_nd_rhs(NDims d, double inv4h, const double* __restrict__ beta0,
+                                                   const double* __restrict__ ux, const double* __restrict__ uy,
+                                                   const double* __restrict__ uz, const double* __restrict__ S,
+                                                   const double* __restrict__ mean, double* __restrict__ out,
+                                                   int squares, double* part)
+{
+    __shared__ double sh[kBlock / kWave];
+    const long long nn = (long long)d.mx * d.my * d.mz;
+    const double m = mean[0];
+    const long long cy = d.nx, cz = (long long)d.nx * d.ny;
+    double acc = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nn;
+         q += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        node_ijk(d, q, i, j, k);
+        const Axis ax = axis_of(i, d.nx, d.px), ay = axis_of(j, d.ny, d.py), az = axis_of(k, d.nz, d.pz);
+        double src = 0.0, div = 0.0;
+        for (int oz = 0; oz < 2; oz++)
+            for (int oy = 0; oy < 2; oy++)
+                for (int ox = 0; ox < 2; ox++) {
+                    if (!(ax.cok[ox] && ay.cok[oy] && az.cok[oz])) continue;
+                    const long long e = az.ce[oz] * cz + ay.ce[oy] * cy + ax.ce[ox];
+                    const double b0 = beta0[e];
+                    src += fma(b0, S[e], -m);
+                    // the node is the high corner of the cell below it (o = 0)
+                    const double vx = b0 * ux[e], vy = b0 * uy[e], vz = b0 * uz[e];
+                    div += (ox ? -vx : vx) + (oy ? -vy : vy) + (oz ? -vz : vz);
+                }
+        const double bn = 0.125 * src + inv4h * div;
+        if (out) out[q] = bn;
+        acc = squares ? fma(bn, bn, acc) : acc + bn;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_nd_rhs(const NDims& d, double inv4h, const double* beta0, const double* ux, const double* uy,
+                   const double* uz, const double* S, const double* mean, double* out, int squares,
+                   double* partials, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nd_rhs, dim3(nb), dim3(kBlock), 0, s, d, inv4h, beta0, ux, uy, uz, S, mean, out, squares,
+                       partials);
+}
+
+// r = b - A x in FP64; r32 = float(r * inv_s[0]) when r32 != nullptr;
+// partials[block] = sum r^2 (grid-stride).
+__global__ __launch_bounds__(kBlock) void k_nd_resid64(NDims d, const double* __restrict__ x,
+                                                       const double* __restrict__ b, const double* __restrict__ sg,
+                                                       double inv_h12, float* __restrict__ r32,
+                                                       const double* __restrict__ inv_s, double* part)
+{
+    __shared__ double sh[kBlock / kWave];
+    const long long nn = (long long)d.mx * d.my * d.mz;
+    const double is = r32 ? inv_s[0] : 0.0;
+    double acc = 0.0;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nn;
+         q += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        node_ijk(d, q, i, j, k);
+        double ssig, ss;
+        node_sums<double>(d, x, sg, i, j, k, ssig, ss);
+        const double r = b[q] - (4.0 * ssig * x[q] - ss) * inv_h12;
+        if (r32) r32[q] = (float)(r * is);
+        acc = fma(r, r, acc);
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+void launch_nd_resid64(const NDims& d, const double* x, const double* b, const double* sg, double inv_h12,
+                       float* r32, const double* inv_s, double* partials, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nd_resid64, dim3(nb), dim3(kBlock), 0, s, d, x, b, sg, inv_h12, r32, inv_s, partials);
+}
+
+// y = M x = -(A x) on every node, FP64.
+__global__ __launch_bounds__(256) void k_nd_apply64(NDims d, const double* __restrict__ x,
+                                                    const double* __restrict__ sg, double inv_h12,
+                                                    double* __restrict__ y)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= d.mx || j >= d.my || k >= d.mz) return;
+    double ssig, ss;
+    node_sums<double>(d, x, sg, i, j, k, ssig, ss);
+    const long long q = node_index(d, i, j, k);
+    y[q] = (ss - 4.0 * ssig * x[q]) * inv_h12;
+}
+
+void launch_nd_apply64(const NDims& d, const double* x, const double* sg, double inv_h12, double* y, hipStream_t s)
+{
+    const Shape3 sh = cells3(d.mx, d.my, d.mz);
+    hipLaunchKernelGGL(k_nd_apply64, sh.grid, sh.block, 0, s, d, x, sg, inv_h12, y);
+}
+
+// U_e -= (sigma_e / beta0_e) (G phi)_e with (G phi)_e,d = (1/(4h)) sum_B s_d(B) phi_B.
+__global__ __launch_bounds__(256) void k_nd_correct(NDims d, double inv4h, const double* __restrict__ sg,
+                                                    const double* __restrict__ beta0, const double* __restrict__ phi,
+                                                    double* __restrict__ ux, double* __restrict__ uy,
+                                                    double* __restrict__ uz)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= d.nx || j >= d.ny || k >= d.nz) return;
+    const int i1 = i + 1 == d.mx ? 0 : i + 1;  // periodic: node nx is node 0
+    const int j1 = j + 1 == d.my ? 0 : j + 1;
+    const int k1 = k + 1 == d.mz ? 0 : k + 1;
+    const long long sy = d.mx, sz = (long long)d.mx * d.my;
+    const double p000 = phi[k * sz + j * sy + i], p001 = phi[k * sz + j * sy + i1];
+    const double p010 = phi[k * sz + j1 * sy + i], p011 = phi[k * sz + j1 * sy + i1];
+    const double p100 = phi[k1 * sz + j * sy + i], p101 = phi[k1 * sz + j * sy + i1];
+    const double p110 = phi[k1 * sz + j1 * sy + i], p111 = phi[k1 * sz + j1 * sy + i1];
+    const double gx = ((p001 - p000) + (p011 - p010) + (p101 - p100) + (p111 - p110)) * inv4h;
+    const double gy = ((p010 - p000) + (p011 - p001) + (p110 - p100) + (p111 - p101)) * inv4h;
+    const double gz = ((p100 - p000) + (p101 - p001) + (p110 - p010) + (p111 - p011)) * inv4h;
+    const long long e = ((long long)k * d.ny + j) * d.nx + i;
+    const double w = sg[e] / beta0[e];
+    ux[e] -= w * gx;
+    uy[e] -= w * gy;
+    uz[e] -= w * gz;
+}
+
+void launch_nd_correct(const NDims& d, double inv4h, const double* sg, const double* beta0, const double* phi,
+                       double* ux, double* uy, double* uz, hipStream_t s)
+{
+    const Shape3 sh = cells3(d.nx, d.ny, d.nz);
+    hipLaunchKernelGGL(k_nd_correct, sh.grid, sh.block, 0, s, d, inv4h, sg, beta0, phi, ux, uy, uz);
+}
+
+// ------------------------------------------------------------- bottom solve
+
+// Conjugate gradients in FP64 on the coarsest node grid, one workgroup:
+// b is made mean-zero (constants are the null space) and the residual is kept
+// mean-zero; x starts at zero, or at the x passed in when use_x0 (the
+// tolerance is then relative to the initial residual), and is returned
+// mean-zero.  Stops at ||r|| <= rtol ||r0|| or maxit.  work holds 4 n doubles.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_nd_bottom(NDims d, const T* __restrict__ bin, T* __restrict__ xout,
+                                                    const T* __restrict__ sg, double inv_h12, double rtol, int maxit,
+                                                    int use_x0, double* __restrict__ work)
+{
+    __shared__ double sh[16];
+    const int n = d.mx * d.my * d.mz;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double* x = work;
+    double* r = work + n;
+    double* p = work + 2 * n;
+    double* ap = work + 3 * n;
+    const long long sy = d.mx, sz = (long long)d.mx * d.my, cy = d.nx, cz = (long long)d.nx * d.ny;
+    // out = A y (sigma in T, y in FP64); returns sum of y . out
+    auto apply = [&](const double* y, double* out) {
+        __syncthreads();
+        double acc = 0.0;
+        for (int q = tid; q < n; q += nt) {
+            int i, j, k;
+            node_ijk(d, q, i, j, k);
+            const Axis ax = axis_of(i, d.nx, d.px), ay = axis_of(j, d.ny, d.py), az = axis_of(k, d.nz, d.pz);
+            double ssig = 0.0, ss = 0.0;
+            for (int oz = 0; oz < 2; oz++)
+                for (int oy = 0; oy < 2; oy++)
+                    for (int ox = 0; ox < 2; ox++) {
+                        if (!(ax.cok[ox] && ay.cok[oy] && az.cok[oz])) continue;
+                        const double se = (double)sg[az.ce[oz] * cz + ay.ce[oy] * cy + ax.ce[ox]];
+                        const int a = ox * 2, b = oy * 2, c = oz * 2;
+                        const double sum = y[az.nd[1] * sz + ay.nd[b] * sy + ax.nd[a]] +
+                                           y[az.nd[c] * sz + ay.nd[1] * sy + ax.nd[a]] +
+                                           y[az.nd[c] * sz + ay.nd[b] * sy + ax.nd[1]] +
+                                           y[az.nd[c] * sz + ay.nd[b] * sy + ax.nd[a]];
+                        ssig += se;
+                        ss = fma(se, sum, ss);
+                    }
+            const double v = (4.0 * ssig * y[q] - ss) * inv_h12;
+            out[q] = v;
+            acc = fma(y[q], v, acc);
+        }
+        return block_sum(acc, sh);
+    };
+    double part = 0.0;
+    for (int q = tid; q < n; q += nt) part += (double)bin[q];
+    const double mb = block_sum(part, sh) / n;
+    for (int q = tid; q < n; q += nt) x[q] = use_x0 ? (double)xout[q] : 0.0;
+    if (use_x0) (void)apply(x, ap);
+    part = 0.0;
+    for (int q = tid; q < n; q += nt) part += ((double)bin[q] - mb) - (use_x0 ? ap[q] : 0.0);
+    const double m0 = block_sum(part, sh) / n;
+    part = 0.0;
+    for (int q = tid; q < n; q += nt) {
+        const double rq = ((double)bin[q] - mb) - (use_x0 ? ap[q] : 0.0) - m0;
+        r[q] = rq;
+        p[q] = rq;
+        part = fma(rq, rq, part);
+    }
+    double rr = block_sum(part, sh);
+    const double tol2 = rtol * rtol * rr;
+    for (int it = 0; it < maxit && rr > tol2 && rr > 0.0; it++) {
+        const double pap = apply(p, ap);
+        if (!(pap > 0.0)) break;
+        const double alpha = rr / pap;
+        part = 0.0;
+        for (int q = tid; q < n; q += nt) {
+            x[q] = fma(alpha, p[q], x[q]);
+            r[q] = fma(-alpha, ap[q], r[q]);
+            part += r[q];
+        }
+        const double mr = block_sum(part, sh) / n;
+        part = 0.0;
+        for (int q = tid; q < n; q += nt) {
+            const double rq = r[q] - mr;
+            r[q] = rq;
+            part = fma(rq, rq, part);
+        }
+        const double rr1 = block_sum(part, sh);
+        const double beta = rr1 / rr;
+        rr = rr1;
+        for (int q = tid; q < n; q += nt) p[q] = fma(beta, p[q], r[q]);
+    }
+    __syncthreads();
+    part = 0.0;
+    for (int q = tid; q < n; q += nt) part += x[q];
+    const double mx = block_sum(part, sh) / n;
+    for (int q = tid; q < n; q += nt) xout[q] = (T)(x[q] - mx);
+}
+
+template <typename T>
+void launch_nd_bottom(const NDims& d, const T* b, T* x, const T* sg, double inv_h12, double rtol, int maxit,
+                      int use_x0, double* work, hipStream_t s)
+{
+    const int n = d.mx * d.my * d.mz;
+    int nt = ((n + 63) / 64) * 64;
+    if (nt > 1024) nt = 1024;
+    hipLaunchKernelGGL((k_nd_bottom<T>), dim3(1), dim3(nt), 0, s, d, b, x, sg, inv_h12, rtol, maxit, use_x0, work);
+}
+
+#define ND_INST(T)                                                                                        \
+    template void launch_nd_gs<T>(const NDims&, T*, const T*, const T*, T, int, hipStream_t);             \
+    template void launch_nd_resid<T>(const NDims&, const T*, const T*, const T*, T, T*, hipStream_t);     \
+    template void launch_nd_restrict<T>(const NDims&, const NDims&, const T*, T*, hipStream_t);           \
+    template void launch_nd_prolong<T>(const NDims&, const NDims&, T*, const T*, hipStream_t);            \
+    template void launch_nd_bottom<T>(const NDims&, const T*, T*, const T*, double, double, int, int,     \
+                                      double*, hipStream_t);
+ND_INST(float)
+ND_INST(double)
+template void launch_nd_sigma<double, float>(int, int, int, const double*, float*, int, hipStream_t);
+template void launch_nd_sigma<double, double>(int, int, int, const double*, double*, int, hipStream_t);
+template void launch_nd_sigma<float, float>(int, int, int, const float*, float*, int, hipStream_t);
+
+}  // namespace mp

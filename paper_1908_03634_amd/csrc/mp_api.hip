@@ -26,7 +26,7 @@ using mp::Dims;
 constexpr int kMaxBottomCells = 16384;
 constexpr int kScal = 64;  // device scalar slots
 // scalar slots
-enum { S_MEAN = 0, S_NB2 = 1, S_RR = 2, S_DEF = 3, S_BAD = 4, S_GAUGE = 5, S_ZERO = 6, S_PAIR0 = 8 };
+enum { S_MEAN = 0, S_NB2 = 1, S_RR = 2, S_DEF = 3, S_BAD = 4, S_GAUGE = 5, S_ZERO = 6, S_NMEAN = 7, S_PAIR0 = 8 };
 
 struct Level {
     Dims d;
@@ -53,6 +53,35 @@ constexpr long long kFusedMinCells = 1LL << 22;  // fused sweeps on levels at le
 inline bool can_coarsen(int nx, int ny, int nz)
 {
     return nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0 && nx >= 4 && ny >= 4 && nz >= 4;
+}
+
+// Nodal projection (Sec. 3.2 Step 11): its own node hierarchy, allocated on
+// the first mp_nodal_project / mp_nodal_apply call.
+struct NLevel {
+    mp::NDims d;
+    double h = 0.0;
+    long long nn = 0;  // nodes
+    void* x = nullptr;
+    void* b = nullptr;
+    void* r = nullptr;
+    void* sig = nullptr;  // cell sigma in the V-cycle's precision
+    bool own_x = false, own_b = false, own_sig = false;
+};
+
+struct NodalState {
+    std::vector<NLevel> lv;
+    double* b64 = nullptr;          // FP64 right-hand side on the finest nodes
+    double* bottom_work = nullptr;  // 4 * coarsest nodes
+    long long sig_serial = -1;      // mapping the sigma pyramid was built from
+    int nb = 1;                     // reduction blocks over the finest nodes
+};
+
+constexpr long long kNodalBottomMax = 16384;  // nodes of the coarsest nodal grid
+
+inline mp::NDims node_dims(const Dims& d)
+{
+    return mp::NDims{d.nx, d.ny, d.nz, d.px, d.py, d.pz, d.nx + (d.px ? 0 : 1), d.ny + (d.py ? 0 : 1),
+                     d.nz + (d.pz ? 0 : 1)};
 }
 
 }  // namespace
@@ -85,6 +114,8 @@ struct mp_ctx {
     double* ir_phi = nullptr;     // refinement update fused into the V-cycle's last pass
     const double* ir_s = nullptr;  // (phi += ir_s[0] * e), or nullptr
     bool have_coefs = false, have_base = false;
+    long long map_serial = 0;  // successful mappings so far
+    NodalState* nd = nullptr;
     std::string err;
 };
 
@@ -169,6 +200,18 @@ void free_all(mp_ctx* c)
     for (auto& e : c->kev)
         if (e) (void)hipEventDestroy(e);
     c->kev.clear();
+    if (c->nd) {
+        for (auto& L : c->nd->lv) {
+            if (L.own_x) (void)hipFree(L.x);
+            if (L.own_b) (void)hipFree(L.b);
+            (void)hipFree(L.r);
+            if (L.own_sig) (void)hipFree(L.sig);
+        }
+        if (c->nd->b64) (void)hipFree(c->nd->b64);
+        if (c->nd->bottom_work) (void)hipFree(c->nd->bottom_work);
+        delete c->nd;
+        c->nd = nullptr;
+    }
 }
 
 bool mixed(const mp_ctx* c) { return c->cfg.precision == MP_MIXED; }
@@ -592,6 +635,204 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
     return status;
 }
 
+// ---------------------------------------------------------------- nodal
+
+// Node hierarchy: the cell grids of the MAC levels (halving while every
+// extent is even and >= 4), with their nodes.  Level 0 of the FP64 path
+// iterates on the caller's phi and reads the context's FP64 cell values.
+int nd_setup(mp_ctx* c)
+{
+    if (c->nd) return MP_OK;
+    NodalState* N = new NodalState();
+    c->nd = N;
+    const bool mx = mixed(c);
+    const size_t tsz = mx ? sizeof(float) : sizeof(double);
+    bool good = true;
+    auto alloc = [&](size_t bytes) {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes > 0 ? bytes : 1) != hipSuccess) {
+            good = false;
+            return (void*)nullptr;
+        }
+        return p;
+    };
+    Dims d = c->d0;
+    double h = c->cfg.h;
+    for (int l = 0;; l++) {
+        NLevel L;
+        L.d = node_dims(d);
+        L.h = h;
+        L.nn = (long long)L.d.mx * L.d.my * L.d.mz;
+        if (mx || l > 0) {
+            L.x = alloc(tsz * L.nn);
+            L.b = alloc(tsz * L.nn);
+            L.own_x = L.own_b = true;
+        }
+        L.r = alloc(tsz * L.nn);
+        if (mx || l > 0) {
+            L.sig = alloc(tsz * d.n());
+            L.own_sig = true;
+        }
+        N->lv.push_back(L);
+        if (!can_coarsen(d.nx, d.ny, d.nz)) break;
+        d = Dims{d.nx / 2, d.ny / 2, d.nz / 2, d.px, d.py, d.pz};
+        h *= 2.0;
+    }
+    N->b64 = (double*)alloc(sizeof(double) * N->lv[0].nn);
+    if (!mx) N->lv[0].b = N->b64;
+    N->bottom_work = (double*)alloc(sizeof(double) * 4 * N->lv.back().nn);
+    N->nb = mp::red_blocks(N->lv[0].nn);
+    if (!good) {
+        (void)hipGetLastError();
+        return fail(c, MP_ERR_NOMEM, "no device memory for the nodal hierarchy");
+    }
+    return MP_OK;
+}
+
+// Cell sigma of every nodal level from the mapped beta0/rho (FP64 cells).
+void nd_build_sigma(mp_ctx* c)
+{
+    NodalState& N = *c->nd;
+    if (N.sig_serial == c->map_serial) return;
+    const bool mx = mixed(c);
+    for (size_t l = 0; l < N.lv.size(); l++) {
+        NLevel& L = N.lv[l];
+        if (l == 0) {
+            if (mx) mp::launch_nd_sigma<double, float>(L.d.nx, L.d.ny, L.d.nz, c->ccell, (float*)L.sig, 0, c->stream);
+            else L.sig = c->ccell;
+            continue;
+        }
+        const NLevel& F = N.lv[l - 1];
+        if (l == 1)
+            mx ? mp::launch_nd_sigma<double, float>(F.d.nx, F.d.ny, F.d.nz, c->ccell, (float*)L.sig, 1, c->stream)
+               : mp::launch_nd_sigma<double, double>(F.d.nx, F.d.ny, F.d.nz, c->ccell, (double*)L.sig, 1, c->stream);
+        else if (mx)
+            mp::launch_nd_sigma<float, float>(F.d.nx, F.d.ny, F.d.nz, (const float*)F.sig, (float*)L.sig, 1,
+                                              c->stream);
+        else
+            mp::launch_nd_sigma<double, double>(F.d.nx, F.d.ny, F.d.nz, (const double*)F.sig, (double*)L.sig, 1,
+                                                c->stream);
+    }
+    N.sig_serial = c->map_serial;
+}
+
+// One V-cycle on nodal level l for A x = b (x as it stands on level l; the
+// coarser levels start from zero).
+template <typename T>
+void nd_vcycle(mp_ctx* c, int l)
+{
+    NodalState& N = *c->nd;
+    NLevel& L = N.lv[l];
+    const int nlev = (int)N.lv.size();
+    const double h2 = L.h * L.h;
+    if (l == nlev - 1) {
+        // on a one-level grid the finest iterate carries the previous steps
+        mp::launch_nd_bottom<T>(L.d, (const T*)L.b, (T*)L.x, (const T*)L.sig, 1.0 / (12.0 * h2),
+                                c->cfg.bottom_rtol, c->cfg.bottom_max_iter, l == 0 ? 1 : 0, N.bottom_work,
+                                c->stream);
+        return;
+    }
+    const T h12 = (T)(12.0 * h2), inv_h12 = (T)(1.0 / (12.0 * h2));
+    for (int s = 0; s < c->cfg.nu1; s++)
+        for (int colour = 0; colour < 4; colour++)
+            mp::launch_nd_gs<T>(L.d, (T*)L.x, (const T*)L.b, (const T*)L.sig, h12, colour, c->stream);
+    NLevel& C = N.lv[l + 1];
+    mp::launch_nd_resid<T>(L.d, (const T*)L.x, (const T*)L.b, (const T*)L.sig, inv_h12, (T*)L.r, c->stream);
+    mp::launch_nd_restrict<T>(L.d, C.d, (const T*)L.r, (T*)C.b, c->stream);
+    if (l + 1 < nlev - 1) (void)hipMemsetAsync(C.x, 0, sizeof(T) * C.nn, c->stream);
+    nd_vcycle<T>(c, l + 1);
+    mp::launch_nd_prolong<T>(L.d, C.d, (T*)L.x, (const T*)C.x, c->stream);
+    for (int s = 0; s < c->cfg.nu2; s++)
+        for (int colour = 3; colour >= 0; colour--)
+            mp::launch_nd_gs<T>(L.d, (T*)L.x, (const T*)L.b, (const T*)L.sig, h12, colour, c->stream);
+}
+
+// Solve A phi = N.b64 on the nodes (||b||^2 in hscal[S_NB2], its rms pair in
+// the first scale pair): FP64 V-cycles on phi, or FP32 V-cycles inside FP64
+// refinement.  phi is returned with zero node mean.
+int nd_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
+{
+    NodalState& N = *c->nd;
+    NLevel& L0 = N.lv[0];
+    const long long n = L0.nn;
+    const double nb2 = c->hscal[S_NB2];
+    const double inv_h12 = 1.0 / (12.0 * c->cfg.h * c->cfg.h);
+    if (info) info->levels = (int)N.lv.size();
+    if (!isfinite(nb2)) return fail(c, MP_ERR_NONFINITE, "right-hand side is not finite");
+    if (nb2 == 0.0) {
+        HIPCHK(c, hipMemsetAsync(phi, 0, sizeof(double) * n, c->stream));
+        if (info) info->rel_resid = 0.0;
+        return MP_OK;
+    }
+    if (!use_guess) HIPCHK(c, hipMemsetAsync(phi, 0, sizeof(double) * n, c->stream));
+    const bool mx = mixed(c);
+    if (!mx) L0.x = phi;
+    const double* sig64 = c->ccell;
+    int status = MP_ERR_NOT_CONVERGED;
+    double rel = 1.0, rel_prev = 1.0;
+    double hist[64];
+    int vc = 0, it = 0, m_prev = 1;
+    for (it = 0;; it++) {
+        const int p = it & 1;
+        double* sp = c->dscal + S_PAIR0 + 2 * p;
+        double* sq = c->dscal + S_PAIR0 + 2 * (1 - p);
+        mp::launch_nd_resid64(L0.d, phi, N.b64, sig64, inv_h12, mx ? (float*)L0.b : nullptr, sp + 1, c->partials,
+                              N.nb, c->stream);
+        mp::launch_final_sum(c->partials, N.nb, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
+        int st = sync_read(c, S_RR, 1);
+        if (st) return st;
+        rel = sqrt(c->hscal[S_RR] / nb2);
+        if (it < 64) {
+            hist[it] = rel;
+            if (info) info->resid_hist[it] = rel;
+        }
+        if (log_on()) fprintf(stderr, "[mproj] nodal step %d rel_resid %.3e\n", it, rel);
+        if (!isfinite(rel)) {
+            status = MP_ERR_NONFINITE;
+            fail(c, status, "nodal residual became non-finite at step %d", it);
+            break;
+        }
+        if (rel <= c->cfg.rtol) {
+            status = MP_OK;
+            break;
+        }
+        if (it >= c->cfg.max_outer) {
+            fail(c, MP_ERR_NOT_CONVERGED, "nodal solve not converged after %d steps (rel. residual %.3e)", it, rel);
+            break;
+        }
+        if (it >= 6 && it < 64 && rel > 0.9 * hist[it - 6]) {
+            if (info) info->flags |= 1;
+            fail(c, MP_ERR_NOT_CONVERGED, "nodal solve stagnated at step %d (rel. residual %.3e)", it, rel);
+            break;
+        }
+        const int m = cycles_this_step(c, it, rel, rel_prev, m_prev);
+        rel_prev = rel;
+        m_prev = m;
+        if (mx) {
+            HIPCHK(c, hipMemsetAsync(L0.x, 0, sizeof(float) * n, c->stream));
+            for (int k = 0; k < m; k++) {
+                nd_vcycle<float>(c, 0);
+                vc++;
+            }
+            mp::launch_ir_update(n, phi, (const float*)L0.x, sp, c->stream);
+        } else {
+            for (int k = 0; k < m; k++) {
+                nd_vcycle<double>(c, 0);
+                vc++;
+            }
+        }
+    }
+    mp::launch_sum(phi, n, c->partials, N.nb, c->stream);
+    mp::launch_final_sum(c->partials, N.nb, c->dscal + S_GAUGE, 1.0 / (double)n, nullptr, 0.0, c->stream);
+    mp::launch_sub_mean(phi, n, c->dscal + S_GAUGE, c->stream);
+    if (info) {
+        info->outer_iters = it;
+        info->vcycles = vc;
+        info->rel_resid = rel;
+    }
+    return status;
+}
+
 void finish_timing(mp_ctx* c, mp_info* info)
 {
     if (!info) return;
@@ -874,6 +1115,7 @@ int mp_map_base_state(mp_ctx* c, int geometry, const double* beta0_1d, int n1d, 
     }
     c->have_base = c->have_coefs = true;
     c->geometry = geometry;
+    c->map_serial++;
     return MP_OK;
 }
 
@@ -1033,6 +1275,92 @@ int mp_solve(mp_ctx* c, const double* rhs, double* x, int use_initial_guess, mp_
     HIPCHK(c, hipStreamSynchronize(c->stream));
     finish_timing(c, info);
     return solve_st;
+}
+
+int mp_nodal_shape(const mp_ctx* c, int* mx, int* my, int* mz)
+{
+    if (!c || !mx || !my || !mz) return MP_ERR_ARG;
+    const mp::NDims d = node_dims(c->d0);
+    *mx = d.mx;
+    *my = d.my;
+    *mz = d.mz;
+    return MP_OK;
+}
+
+static int nodal_ready(mp_ctx* c)
+{
+    if (!c->have_base) return fail(c, MP_ERR_STATE, "mp_map_base_state has not succeeded on this context");
+    int st = nd_setup(c);
+    if (st) return st;
+    if (c->nd->lv.back().nn > kNodalBottomMax)
+        return fail(c, MP_ERR_ARG, "coarsest nodal grid has %lld nodes (at most %lld)", c->nd->lv.back().nn,
+                    kNodalBottomMax);
+    nd_build_sigma(c);
+    return MP_OK;
+}
+
+int mp_nodal_project(mp_ctx* c, double* ux, double* uy, double* uz, const double* S, double* phi,
+                     int use_initial_guess, mp_info* info)
+{
+    if (!c) return MP_ERR_ARG;
+    reset_info(info);
+    if (!ux || !uy || !uz || !S || !phi) return fail(c, MP_ERR_ARG, "ux, uy, uz, S and phi are required");
+    (void)hipSetDevice(c->cfg.device);
+    int st = nodal_ready(c);
+    if (st) return st;
+    NodalState& N = *c->nd;
+    const mp::NDims& d = N.lv[0].d;
+    const long long nn = N.lv[0].nn;
+    const double inv4h = 1.0 / (4.0 * c->cfg.h);
+    const int nbc = nblk(c);
+    c->kev_used = 0;
+    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    // mean of beta0 S over the cells, then b = L(beta0 S - m) - D(beta0 U)
+    mp::launch_nd_src_sum(c->n0, c->beta0, S, c->partials, nbc, c->stream);
+    mp::launch_final_sum(c->partials, nbc, c->dscal + S_MEAN, 1.0 / (double)c->n0, nullptr, 0.0, c->stream);
+    mp::launch_nd_rhs(d, inv4h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, N.b64, 0, c->partials, N.nb, c->stream);
+    // remove the node mean (rounding only, in exact arithmetic the sum is 0):
+    // b then lies in the range of A, which is orthogonal to the constants
+    mp::launch_final_sum(c->partials, N.nb, c->dscal + S_NMEAN, 1.0 / (double)nn, nullptr, 0.0, c->stream);
+    mp::launch_sub_mean_sumsq(N.b64, nn, c->dscal + S_NMEAN, c->partials, N.nb, c->stream);
+    mp::launch_final_sum(c->partials, N.nb, c->dscal + S_NB2, 1.0, c->dscal + S_PAIR0, (double)nn, c->stream);
+    st = sync_read(c, S_MEAN, 2);
+    if (st) return st;
+    if (!isfinite(c->hscal[S_MEAN]) || !isfinite(c->hscal[S_NB2]))
+        return fail(c, MP_ERR_NONFINITE, "non-finite nodal right-hand side");
+    if (info) {
+        info->rhs_norm = sqrt(c->hscal[S_NB2]);
+        info->rhs_mean = c->hscal[S_MEAN];
+    }
+    HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+    int solve_st = nd_solve(c, phi, use_initial_guess, info);
+    if (solve_st != MP_OK && solve_st != MP_ERR_NOT_CONVERGED) return solve_st;
+    HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+    mp::launch_nd_correct(d, inv4h, c->ccell, c->beta0, phi, ux, uy, uz, c->stream);
+    mp::launch_nd_rhs(d, inv4h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, nullptr, 1, c->partials, N.nb,
+                      c->stream);
+    mp::launch_final_sum(c->partials, N.nb, c->dscal + S_DEF, 1.0, nullptr, 0.0, c->stream);
+    HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
+    st = sync_read(c, S_DEF, 1);
+    if (st) return st;
+    if (info) {
+        const double nb2 = c->hscal[S_NB2];
+        info->div_defect = nb2 > 0.0 ? sqrt(c->hscal[S_DEF] / nb2) : sqrt(c->hscal[S_DEF]);
+        finish_timing(c, info);
+    }
+    return solve_st;
+}
+
+int mp_nodal_apply(mp_ctx* c, const double* x, double* y)
+{
+    if (!c) return MP_ERR_ARG;
+    if (!x || !y) return fail(c, MP_ERR_ARG, "x and y are required");
+    (void)hipSetDevice(c->cfg.device);
+    if (!c->have_base) return fail(c, MP_ERR_STATE, "mp_map_base_state has not succeeded on this context");
+    const mp::NDims d = node_dims(c->d0);
+    mp::launch_nd_apply64(d, x, c->ccell, 1.0 / (12.0 * c->cfg.h * c->cfg.h), y, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MP_OK;
 }
 
 int mp_radius_count(const mp_ctx* c, long long* nm)

@@ -208,6 +208,55 @@ void launch_ir_update(long long n, double* phi, const float* e, const double* s,
 void launch_average(long long nm, const long long* offs, const unsigned* cells, const double* phi, double* avg,
                     double* count, hipStream_t s);
 
+// ---- nodal projection (node-based phi, cell-centred U and sigma) --------
+// Cells nx x ny x nz with per-axis periodicity; nodes mx = nx + (1 - px) etc.
+// Node arrays [mz][my][mx], cell arrays [nz][ny][nx].  A is the trilinear
+// finite-element operator h^-3 sum_e sigma_e int grad . grad (symmetric
+// positive semi-definite); the solver works on A x = b with b = -R.
+struct NDims {
+    int nx, ny, nz;
+    int px, py, pz;
+    int mx, my, mz;
+};
+// One colour (0..3, by i and j parity) of Gauss-Seidel on A x = b; h12 = 12 h^2.
+template <typename T>
+void launch_nd_gs(const NDims& d, T* x, const T* b, const T* sg, T h12, int colour, hipStream_t s);
+// r = b - A x; inv_h12 = 1 / (12 h^2).
+template <typename T>
+void launch_nd_resid(const NDims& d, const T* x, const T* b, const T* sg, T inv_h12, T* r, hipStream_t s);
+// bc = (1/8) P^T rf (P trilinear interpolation from the grid coarsened by 2).
+template <typename T>
+void launch_nd_restrict(const NDims& f, const NDims& c, const T* rf, T* bc, hipStream_t s);
+// xf += P ec.
+template <typename T>
+void launch_nd_prolong(const NDims& f, const NDims& c, T* xf, const T* ec, hipStream_t s);
+// Cell sigma of the grid coarsened by 2 (mean of 8 children), or, with
+// coarsen = 0, a precision conversion of the same grid.
+template <typename Tin, typename Tout>
+void launch_nd_sigma(int nx, int ny, int nz, const Tin* sf, Tout* sc, int coarsen, hipStream_t s);
+// FP64 conjugate gradients on the coarsest nodes (one workgroup); x from 0
+// (or from x when use_x0), returned mean-zero; work = 4 * nodes doubles.
+template <typename T>
+void launch_nd_bottom(const NDims& d, const T* b, T* x, const T* sg, double inv_h12, double rtol, int maxit,
+                      int use_x0, double* work, hipStream_t s);
+// partials (nb blocks) = per-block sum of beta0 * S over the cells.
+void launch_nd_src_sum(long long n, const double* beta0, const double* S, double* partials, int nb, hipStream_t s);
+// b = L(beta0 S - mean[0]) - D(beta0 U) on the nodes (out may be nullptr);
+// partials (nb blocks) = per-block sum of b^2 (squares) or of b.
+// inv4h = 1 / (4h).
+void launch_nd_rhs(const NDims& d, double inv4h, const double* beta0, const double* ux, const double* uy,
+                   const double* uz, const double* S, const double* mean, double* out, int squares,
+                   double* partials, int nb, hipStream_t s);
+// r = b - A x in FP64 (sigma FP64); r32 = float(r * inv_s[0]) when r32 !=
+// nullptr; partials (nb blocks) = per-block sum of r^2.
+void launch_nd_resid64(const NDims& d, const double* x, const double* b, const double* sg, double inv_h12,
+                       float* r32, const double* inv_s, double* partials, int nb, hipStream_t s);
+// y = -(A x) in FP64.
+void launch_nd_apply64(const NDims& d, const double* x, const double* sg, double inv_h12, double* y, hipStream_t s);
+// U -= (sigma / beta0) G phi on every cell (cell-average gradient of phi_h).
+void launch_nd_correct(const NDims& d, double inv4h, const double* sg, const double* beta0, const double* phi,
+                       double* ux, double* uy, double* uz, hipStream_t s);
+
 // Plain device copy (bandwidth calibration of the traffic counters).
 void launch_copy(const double* src, double* dst, long long n, hipStream_t s);
 

@@ -90,8 +90,8 @@ class Info(ctypes.Structure):
 
 # Every exported symbol of include/mproj.h.
 EXPORTS = ["mp_config_default", "mp_init", "mp_map_base_state", "mp_set_coefs", "mp_mac_project", "mp_solve",
-           "mp_mac_project_split", "mp_radius_count", "mp_average", "mp_set_kernel_timing", "mp_apply", "mp_coef_grad", "mp_free",
-           "mp_last_error", "mp_version"]
+           "mp_mac_project_split", "mp_radius_count", "mp_average", "mp_set_kernel_timing", "mp_apply", "mp_coef_grad",
+           "mp_nodal_shape", "mp_nodal_project", "mp_nodal_apply", "mp_free", "mp_last_error", "mp_version"]
 
 _lib = None
 
@@ -132,6 +132,12 @@ def load_library(path=None):
     lib.mp_apply.restype = I
     lib.mp_coef_grad.argtypes = [P, P, P, P, P, P]
     lib.mp_coef_grad.restype = I
+    lib.mp_nodal_shape.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]
+    lib.mp_nodal_shape.restype = I
+    lib.mp_nodal_project.argtypes = [P, P, P, P, P, P, I, ctypes.POINTER(Info)]
+    lib.mp_nodal_project.restype = I
+    lib.mp_nodal_apply.argtypes = [P, P, P]
+    lib.mp_nodal_apply.restype = I
     lib.mp_free.argtypes = [P]
     lib.mp_free.restype = I
     lib.mp_last_error.argtypes = [P]
@@ -316,6 +322,42 @@ class Context:
         self._check(self.lib.mp_coef_grad(self._h, self._ptr(lam, self.shape, "lam"),
                                           self._ptr(phi, self.shape, "phi"), *ps), "mp_coef_grad")
         return g
+
+    # -- nodal projection (Sec. 3.2 Step 11) -------------------------------
+    @property
+    def node_shape(self):
+        """Node array shape (z, y, x): n per periodic axis, n + 1 per Neumann axis."""
+        mx, my, mz = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.mp_nodal_shape(self._h, ctypes.byref(mx), ctypes.byref(my), ctypes.byref(mz)),
+                    "mp_nodal_shape")
+        return (mz.value, my.value, mx.value)
+
+    def empty_nodes(self):
+        return torch.empty(self.node_shape, dtype=torch.float64, device=self.device)
+
+    def nodal_project(self, ux, uy, uz, S, phi=None, use_initial_guess=False, allow_not_converged=False):
+        """Nodal projection of the cell-centred velocity (ux, uy, uz), in
+        place, with phi on the nodes; returns (phi, info dict)."""
+        pu = [self._ptr(u, self.shape, n) for u, n in ((ux, "ux"), (uy, "uy"), (uz, "uz"))]
+        ps = self._ptr(S, self.shape, "S")
+        if phi is None:
+            phi = self.empty_nodes()
+            use_initial_guess = False
+        pp = self._ptr(phi, self.node_shape, "phi")
+        info = Info()
+        code = self.lib.mp_nodal_project(self._h, *pu, ps, pp, int(bool(use_initial_guess)), ctypes.byref(info))
+        d = info.as_dict()
+        if not (allow_not_converged and code == MP_ERR_NOT_CONVERGED):
+            self._check(code, "mp_nodal_project", d)
+        d["status"] = code
+        return phi, d
+
+    def nodal_apply(self, x, out=None):
+        """M x on the nodes (finite-element div(sigma grad x)), FP64."""
+        y = out if out is not None else self.empty_nodes()
+        ns = self.node_shape
+        self._check(self.lib.mp_nodal_apply(self._h, self._ptr(x, ns, "x"), self._ptr(y, ns, "y")), "mp_nodal_apply")
+        return y
 
     def close(self):
         if getattr(self, "_h", None):

@@ -78,6 +78,9 @@ def test_null_arguments():
     assert lib.mp_map_base_state(None, 0, None, 0, 0.0, None, None, None, None, None) == 1
     assert lib.mp_mac_project(None, None, None, None, None, None, 0, None) == 1
     assert lib.mp_solve(None, None, None, 0, None) == 1
+    assert lib.mp_nodal_project(None, None, None, None, None, None, 0, None) == 1
+    assert lib.mp_nodal_apply(None, None, None) == 1
+    assert lib.mp_nodal_shape(None, None, None, None) == 1
     assert lib.mp_set_coefs(None, None, None, None) == 1
     assert lib.mp_set_kernel_timing(None, 1) == 1
     assert lib.mp_radius_count(None, None) == 1

@@ -1,0 +1,170 @@
+"""Nodal projection (Sec. 3.2 Step 11) on the GPU against the nodal oracle:
+the node operator, the projection in both precisions over shapes and
+boundaries, the full-size workload by properties the oracle checks at any
+size, and the error paths."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import nodal as nd
+from paper_1908_03634_amd import mproj, workloads as W
+from tests.gpu_util import N, T, context_for, rel, say
+
+pytestmark = pytest.mark.gpu
+
+BCS = [(0, 0, 1), (1, 1, 1), (0, 0, 0), (1, 0, 1)]
+SHAPES = [(16, 16, 16), (32, 24, 20), (48, 32, 40), (12, 10, 14), (8, 8, 6), (7, 9, 5)]
+
+
+def _mapped(p, precision, **kw):
+    ctx = context_for(p, precision, **kw)
+    ctx.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center, want_coefs=False)
+    return ctx
+
+
+def _sigma(p):
+    g = oracle.Grid.of(p)
+    b0 = oracle.fill_beta0(g, p.geometry, p.beta0_1d, p.dr, p.center)
+    return g, b0, b0 / p.rho
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_node_operator_matches_the_oracle(shape, bc):
+    nx, ny, nz = shape
+    say("nodal apply", shape, bc)
+    p = W.planar_problem(nx=nx, ny=ny, nz=nz, contrast=1e3, bc=bc, seed=7000 + nx, velocity="cells")
+    g, _, sigma = _sigma(p)
+    ctx = _mapped(p, "fp64")
+    assert ctx.node_shape == nd.node_shape(g)
+    x = np.random.default_rng(nx * ny).standard_normal(nd.node_shape(g))
+    y = N(ctx.nodal_apply(T(x)))
+    ref = nd.apply(g, sigma, x)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    ctx.close()
+
+
+def _project_case(p, precision, rtol=1e-12):
+    g, b0, sigma = _sigma(p)
+    ref = nd.project(p, tol=1e-12)
+    ctx = _mapped(p, precision, rtol=rtol)
+    ux, uy, uz, S = T(p.ux), T(p.uy), T(p.uz), T(p.S)
+    phi, info = ctx.nodal_project(ux, uy, uz, S)
+    phi = N(phi)
+    assert rel(phi, ref["phi"]) < 1e-9
+    assert nd.residual_norm(g, sigma, ref["R"], phi) <= 1.01 * rtol
+    assert abs(phi.mean()) <= 1e-12 * np.abs(phi).max()
+    for a, b in ((ux, ref["ux"]), (uy, ref["uy"]), (uz, ref["uz"])):
+        assert np.abs(N(a) - b).max() <= 1e-9 * np.abs(b).max()
+    assert info["rhs_mean"] == pytest.approx(ref["mean"], rel=1e-12, abs=1e-18)
+    Rn, _ = nd.rhs(g, b0, *(N(u) for u in (ux, uy, uz)), p.S)
+    defect = np.sqrt(nd.node_dot(g, Rn, Rn) / nd.node_dot(g, ref["R"], ref["R"]))
+    assert info["div_defect"] == pytest.approx(defect, rel=1e-8)
+    ctx.close()
+    return info
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(16, 16, 16), (48, 32, 40), (12, 10, 14), (7, 9, 5)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_nodal_projection_matches_the_oracle(shape, bc, precision):
+    nx, ny, nz = shape
+    say("nodal project", shape, bc, precision)
+    p = W.planar_problem(nx=nx, ny=ny, nz=nz, contrast=1e4, bc=bc, seed=7100 + nz, velocity="cells")
+    _project_case(p, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_nodal_projection_of_a_64_cube(precision):
+    say("nodal project 64^3", precision)
+    _project_case(W.planar_problem(64, contrast=1e4, seed=7200, velocity="cells"), precision)
+
+
+@pytest.mark.parametrize("base", ["irregular", "linear"])
+def test_nodal_projection_on_a_star(base):
+    say("nodal star", base)
+    _project_case(W.spherical_problem(32, contrast=1e5, seed=7300, base=base, velocity="cells"), "mixed")
+
+
+def test_nodal_projection_full_size():
+    """256^3 plane-parallel atmosphere, mixed precision, rtol 1e-10: the
+    oracle's FP64 operator confirms the residual of the GPU's phi and its
+    gradient confirms the velocity update."""
+    say("nodal c2 256^3")
+    p = W.config_problem("c2", velocity="cells")
+    g, b0, sigma = _sigma(p)
+    ctx = _mapped(p, "mixed", rtol=1e-10)
+    ux, uy, uz, S = T(p.ux), T(p.uy), T(p.uz), T(p.S)
+    phi, info = ctx.nodal_project(ux, uy, uz, S)
+    phi = N(phi)
+    R, m = nd.rhs(g, b0, p.ux, p.uy, p.uz, p.S)
+    assert info["rel_resid"] <= 1e-10
+    assert nd.residual_norm(g, sigma, R, phi) <= 1.05e-10
+    assert info["rhs_mean"] == pytest.approx(m, rel=1e-12)
+    gx, gy, gz = nd.gradient(g, phi)
+    w = sigma / b0
+    for new, old, gr in ((ux, p.ux, gx), (uy, p.uy, gy), (uz, p.uz, gz)):
+        assert np.abs((old - N(new)) - w * gr).max() <= 1e-12 * np.abs(old).max()
+    say("nodal c2", info["vcycles"], info["outer_iters"], info["ms_solve"])
+    ctx.close()
+
+
+def test_nodal_projection_is_reproducible_and_warm_starts():
+    p = W.planar_problem(32, contrast=1e4, seed=7400, velocity="cells")
+    ctx = _mapped(p, "mixed", rtol=1e-11)
+    outs = []
+    for _ in range(2):
+        ux, uy, uz, S = T(p.ux), T(p.uy), T(p.uz), T(p.S)
+        phi, info = ctx.nodal_project(ux, uy, uz, S)
+        outs.append((N(phi), N(ux)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    ux, uy, uz, S = T(p.ux), T(p.uy), T(p.uz), T(p.S)
+    phi0 = T(outs[0][0])
+    _, info = ctx.nodal_project(ux, uy, uz, S, phi=phi0, use_initial_guess=True)
+    assert info["outer_iters"] == 0 and info["vcycles"] == 0
+    ctx.close()
+
+
+def test_nodal_sigma_follows_a_new_mapping():
+    a = W.planar_problem(16, contrast=1e2, seed=7500, velocity="cells")
+    b = W.planar_problem(16, contrast=1e5, seed=7501, velocity="cells")
+    ctx = _mapped(a, "mixed")
+    ctx.nodal_project(T(a.ux), T(a.uy), T(a.uz), T(a.S))
+    ctx.map_base_state(b.geometry, T(b.beta0_1d), T(b.rho), b.dr, b.center, want_coefs=False)
+    phi, _ = ctx.nodal_project(T(b.ux), T(b.uy), T(b.uz), T(b.S))
+    ref = nd.project(b, tol=1e-12)
+    assert rel(N(phi), ref["phi"]) < 1e-6
+    ctx.close()
+
+
+def test_zero_and_rounding_level_right_hand_sides():
+    p = W.planar_problem(16, contrast=1e3, seed=7600, velocity="cells")
+    ctx = _mapped(p, "mixed")
+    z = torch.zeros(p.shape, dtype=torch.float64, device="cuda:0")
+    phi, info = ctx.nodal_project(z.clone(), z.clone(), z.clone(), z.clone())
+    assert info["rhs_norm"] == 0.0 and np.abs(N(phi)).max() == 0.0
+    # beta0 S constant: all of it is the removed mean, R is rounding noise
+    _, b0, _ = _sigma(p)
+    phi, info = ctx.nodal_project(z.clone(), z.clone(), z.clone(), T(0.25 / b0))
+    assert info["rhs_mean"] == pytest.approx(0.25, rel=1e-14)
+    assert info["rhs_norm"] <= 1e-13 * np.sqrt(p.ncell)
+    assert np.abs(N(phi)).max() <= 1e-12
+    ctx.close()
+
+
+def test_nodal_errors():
+    p = W.planar_problem(16, contrast=1e3, seed=7700, velocity="cells")
+    ctx = context_for(p, "mixed")
+    u = T(p.ux)
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.nodal_project(u, u.clone(), u.clone(), T(p.S))
+    assert e.value.code == 7  # no mapping yet
+    ctx.close()
+    # 25^3 cells cannot coarsen: 26^3 nodes on the coarsest grid is too many
+    q = W.planar_problem(25, contrast=1e3, bc=(1, 1, 1), seed=7701, velocity="cells")
+    ctx = _mapped(q, "fp64")
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.nodal_project(T(q.ux), T(q.uy), T(q.uz), T(q.S))
+    assert e.value.code == 1
+    ctx.close()
