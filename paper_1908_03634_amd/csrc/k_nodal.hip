@@ -170,6 +170,200 @@ void launch_nd_resid(const NDims& d, const T* x, const T* b, const T* sg, T inv_
     hipLaunchKernelGGL((k_nd_resid<T>), sh.grid, sh.block, 0, s, d, x, b, sg, inv_h12, r);
 }
 
+// ------------------------------------------------------------- z-marching
+
+// The same stencil evaluated by threads that each walk one node column (i, j)
+// through lz planes: the 3 x 3 neighbour columns of planes k-1, k, k+1 and the
+// 2 x 2 cell columns below and above stay in registers, so each node costs
+// one new plane of 8 neighbour values and 4 sigma values instead of 20 + 8
+// loads.  Same arithmetic in the same order as node_sums (bitwise equal).
+//   ND_GS:      one Gauss-Seidel colour (columns of that i, j parity);
+//   ND_RESID:   r = b - A x on every node;
+//   ND_RESID64: the same in FP64, r32 = float(r * inv_s) and per-block
+//               partial sums of r^2.
+enum { ND_GS = 0, ND_RESID = 1, ND_RESID64 = 2 };
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_nd_col(NDims d, int lz, T* __restrict__ x, const T* __restrict__ b,
+                                                const T* __restrict__ sg, T h12, T inv_h12, int colour,
+                                                T* __restrict__ r, float* __restrict__ r32,
+                                                const double* __restrict__ inv_s, double* part)
+{
+    const int ti = blockIdx.x * blockDim.x + threadIdx.x;
+    const int tj = blockIdx.y * blockDim.y + threadIdx.y;
+    const int i = MODE == ND_GS ? 2 * ti + (colour & 1) : ti;
+    const int j = MODE == ND_GS ? 2 * tj + (colour >> 1) : tj;
+    const int k0 = blockIdx.z * lz;
+    const int k1 = min(k0 + lz, d.mz);
+    double acc = 0.0;
+    if (i < d.mx && j < d.my) {
+        const Axis ax = axis_of(i, d.nx, d.px), ay = axis_of(j, d.ny, d.py);
+        const long long sy = d.mx, sz = (long long)d.mx * d.my;
+        const long long cy = d.nx, cz = (long long)d.nx * d.ny;
+        long long col[3][3];
+        bool cok[3][3];
+#pragma unroll
+        for (int bb = 0; bb < 3; bb++)
+#pragma unroll
+            for (int aa = 0; aa < 3; aa++) {
+                col[bb][aa] = ay.nd[bb] * sy + ax.nd[aa];
+                cok[bb][aa] = ax.nok[aa] && ay.nok[bb];
+            }
+        long long ccol[2][2];
+        bool ccok[2][2];
+#pragma unroll
+        for (int oy = 0; oy < 2; oy++)
+#pragma unroll
+            for (int ox = 0; ox < 2; ox++) {
+                ccol[oy][ox] = ay.ce[oy] * cy + ax.ce[ox];
+                ccok[oy][ox] = ax.cok[ox] && ay.cok[oy];
+            }
+        // node plane kk (may be -1 or mz: wrapped when periodic, absent at a wall)
+        auto ld_plane = [&](int kk, T (&v)[3][3]) {
+            bool okz = true;
+            if (d.pz) kk = kk < 0 ? kk + d.nz : (kk >= d.nz ? kk - d.nz : kk);
+            else okz = kk >= 0 && kk <= d.nz;
+#pragma unroll
+            for (int bb = 0; bb < 3; bb++)
+#pragma unroll
+                for (int aa = 0; aa < 3; aa++) {
+                    const bool need = MODE == ND_GS ? !(aa == 1 && bb == 1) : true;
+                    v[bb][aa] = (need && okz && cok[bb][aa]) ? x[(long long)kk * sz + col[bb][aa]] : T(0);
+                }
+        };
+        // cell plane kc (below node k: k-1; above: k)
+        auto ld_cells = [&](int kc, T (&s)[2][2]) {
+            bool okz = true;
+            if (d.pz) kc = kc < 0 ? kc + d.nz : kc;
+            else okz = kc >= 0 && kc < d.nz;
+#pragma unroll
+            for (int oy = 0; oy < 2; oy++)
+#pragma unroll
+                for (int ox = 0; ox < 2; ox++)
+                    s[oy][ox] = (okz && ccok[oy][ox]) ? sg[(long long)(okz ? kc : 0) * cz + ccol[oy][ox]] : T(0);
+        };
+        T v0[3][3], v1[3][3], v2[3][3], s0[2][2], s1[2][2];
+        ld_plane(k0 - 1, v0);
+        ld_plane(k0, v1);
+        ld_cells(k0 - 1, s0);
+        const double is = MODE == ND_RESID64 ? inv_s[0] : 0.0;
+        for (int k = k0; k < k1; k++) {
+            ld_plane(k + 1, v2);
+            ld_cells(k, s1);
+            const long long q = (long long)k * sz + (long long)j * sy + i;
+            T a1 = T(0), a2 = T(0);
+#pragma unroll
+            for (int oz = 0; oz < 2; oz++)
+#pragma unroll
+                for (int oy = 0; oy < 2; oy++)
+#pragma unroll
+                    for (int ox = 0; ox < 2; ox++) {
+                        const T se = oz ? s1[oy][ox] : s0[oy][ox];
+                        const int aa = ox * 2, bb = oy * 2;
+                        const T(&vc)[3][3] = oz ? v2 : v0;
+                        const T sum = ((v1[bb][aa] + vc[1][aa]) + vc[bb][1]) + vc[bb][aa];
+                        a1 += se;
+                        a2 = fma(se, sum, a2);
+                    }
+            if constexpr (MODE == ND_GS) {
+                x[q] = (a2 + h12 * b[q]) / (T(4) * a1);
+            } else {
+                const T rv = b[q] - (T(4) * a1 * v1[1][1] - a2) * inv_h12;
+                if constexpr (MODE == ND_RESID) {
+                    r[q] = rv;
+                } else {
+                    if (r32) r32[q] = (float)((double)rv * is);
+                    acc = fma((double)rv, (double)rv, acc);
+                }
+            }
+#pragma unroll
+            for (int bb = 0; bb < 3; bb++)
+#pragma unroll
+                for (int aa = 0; aa < 3; aa++) {
+                    v0[bb][aa] = v1[bb][aa];
+                    v1[bb][aa] = v2[bb][aa];
+                }
+#pragma unroll
+            for (int oy = 0; oy < 2; oy++)
+#pragma unroll
+                for (int ox = 0; ox < 2; ox++) s0[oy][ox] = s1[oy][ox];
+        }
+    }
+    if constexpr (MODE == ND_RESID64) {
+        __shared__ double sh[kBlock / kWave];
+        const double sblk = block_sum(acc, sh);
+        if (threadIdx.x == 0 && threadIdx.y == 0)
+            part[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = sblk;
+    }
+}
+
+namespace {
+
+// Columns (ni x nj) in 64 x 4 blocks, planes in chunks of lz: the largest lz
+// (<= 16) that still gives at least min_blocks blocks, then doubled while
+// the count exceeds max_blocks.
+struct ColShape {
+    dim3 grid, block;
+    int lz;
+};
+
+ColShape col_shape(int ni, int nj, int mz, long long min_blocks, long long max_blocks)
+{
+    ColShape c;
+    c.block = dim3(64, 4, 1);
+    const long long bxy = (long long)((ni + 63) / 64) * ((nj + 3) / 4);
+    int lz = 16;
+    while (lz > 2 && bxy * ((mz + lz - 1) / lz) < min_blocks) lz /= 2;
+    while (bxy * ((mz + lz - 1) / lz) > max_blocks && lz < mz) lz *= 2;
+    c.lz = lz;
+    c.grid = dim3((ni + 63) / 64, (nj + 3) / 4, (mz + lz - 1) / lz);
+    return c;
+}
+
+}  // namespace
+
+bool nd_col_supported(const NDims& d) { return d.mz >= 2; }
+
+int nd_col_reduce_blocks(const NDims& d)
+{
+    const ColShape c = col_shape(d.mx, d.my, d.mz, 1024, kMaxRedBlocks);
+    return (int)(c.grid.x * c.grid.y * c.grid.z);
+}
+
+template <typename T>
+void launch_nd_gs_col(const NDims& d, T* x, const T* b, const T* sg, T h12, int colour, hipStream_t s)
+{
+    const int ni = (d.mx - (colour & 1) + 1) / 2, nj = (d.my - (colour >> 1) + 1) / 2;
+    const ColShape c = col_shape(ni, nj, d.mz, 2048, 1LL << 30);
+    hipLaunchKernelGGL((k_nd_col<T, ND_GS>), c.grid, c.block, 0, s, d, c.lz, x, b, sg, h12, T(0), colour,
+                       (T*)nullptr, (float*)nullptr, (const double*)nullptr, (double*)nullptr);
+}
+
+template <typename T>
+void launch_nd_resid_col(const NDims& d, const T* x, const T* b, const T* sg, T inv_h12, T* r, hipStream_t s)
+{
+    const ColShape c = col_shape(d.mx, d.my, d.mz, 2048, 1LL << 30);
+    hipLaunchKernelGGL((k_nd_col<T, ND_RESID>), c.grid, c.block, 0, s, d, c.lz, const_cast<T*>(x), b, sg, T(0),
+                       inv_h12, 0, r, (float*)nullptr, (const double*)nullptr, (double*)nullptr);
+}
+
+void launch_nd_resid64_col(const NDims& d, const double* x, const double* b, const double* sg, double inv_h12,
+                           float* r32, const double* inv_s, double* partials, int* nb_out, hipStream_t s)
+{
+    const ColShape c = col_shape(d.mx, d.my, d.mz, 1024, kMaxRedBlocks);
+    *nb_out = (int)(c.grid.x * c.grid.y * c.grid.z);
+    hipLaunchKernelGGL((k_nd_col<double, ND_RESID64>), c.grid, c.block, 0, s, d, c.lz, const_cast<double*>(x), b,
+                       sg, 0.0, inv_h12, 0, (double*)nullptr, r32, inv_s, partials);
+}
+
+template void launch_nd_gs_col<float>(const NDims&, float*, const float*, const float*, float, int, hipStream_t);
+template void launch_nd_gs_col<double>(const NDims&, double*, const double*, const double*, double, int,
+                                       hipStream_t);
+template void launch_nd_resid_col<float>(const NDims&, const float*, const float*, const float*, float, float*,
+                                         hipStream_t);
+template void launch_nd_resid_col<double>(const NDims&, const double*, const double*, const double*, double,
+                                          double*, hipStream_t);
+
 // ------------------------------------------------------------- transfers
 
 // Coarse right-hand side = (1/8) P^T r: the fine nodes 2I-1, 2I, 2I+1 per

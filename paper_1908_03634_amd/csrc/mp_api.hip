@@ -66,14 +66,16 @@ struct NLevel {
     void* r = nullptr;
     void* sig = nullptr;  // cell sigma in the V-cycle's precision
     bool own_x = false, own_b = false, own_sig = false;
+    bool col = false;  // z-marching column kernels
 };
 
 struct NodalState {
     std::vector<NLevel> lv;
     double* b64 = nullptr;          // FP64 right-hand side on the finest nodes
     double* bottom_work = nullptr;  // 4 * coarsest nodes
+    double* partials = nullptr;     // per-block partial sums of the nodal reductions
     long long sig_serial = -1;      // mapping the sigma pyramid was built from
-    int nb = 1;                     // reduction blocks over the finest nodes
+    int nb = 1;                     // blocks of the grid-stride reductions over the finest nodes
 };
 
 constexpr long long kNodalBottomMax = 16384;  // nodes of the coarsest nodal grid
@@ -209,6 +211,7 @@ void free_all(mp_ctx* c)
         }
         if (c->nd->b64) (void)hipFree(c->nd->b64);
         if (c->nd->bottom_work) (void)hipFree(c->nd->bottom_work);
+        if (c->nd->partials) (void)hipFree(c->nd->partials);
         delete c->nd;
         c->nd = nullptr;
     }
@@ -673,10 +676,15 @@ int nd_setup(mp_ctx* c)
             L.sig = alloc(tsz * d.n());
             L.own_sig = true;
         }
+        L.col = c->cfg.blocked && mp::nd_col_supported(L.d);
         N->lv.push_back(L);
         if (!can_coarsen(d.nx, d.ny, d.nz)) break;
         d = Dims{d.nx / 2, d.ny / 2, d.nz / 2, d.px, d.py, d.pz};
         h *= 2.0;
+    }
+    {
+        const int np1 = mp::red_blocks(N->lv[0].nn), np2 = mp::nd_col_reduce_blocks(N->lv[0].d);
+        N->partials = (double*)alloc(sizeof(double) * (np1 > np2 ? np1 : np2));
     }
     N->b64 = (double*)alloc(sizeof(double) * N->lv[0].nn);
     if (!mx) N->lv[0].b = N->b64;
@@ -733,18 +741,23 @@ void nd_vcycle(mp_ctx* c, int l)
         return;
     }
     const T h12 = (T)(12.0 * h2), inv_h12 = (T)(1.0 / (12.0 * h2));
+    auto gs = [&](int colour) {
+        if (L.col) mp::launch_nd_gs_col<T>(L.d, (T*)L.x, (const T*)L.b, (const T*)L.sig, h12, colour, c->stream);
+        else mp::launch_nd_gs<T>(L.d, (T*)L.x, (const T*)L.b, (const T*)L.sig, h12, colour, c->stream);
+    };
     for (int s = 0; s < c->cfg.nu1; s++)
-        for (int colour = 0; colour < 4; colour++)
-            mp::launch_nd_gs<T>(L.d, (T*)L.x, (const T*)L.b, (const T*)L.sig, h12, colour, c->stream);
+        for (int colour = 0; colour < 4; colour++) gs(colour);
     NLevel& C = N.lv[l + 1];
-    mp::launch_nd_resid<T>(L.d, (const T*)L.x, (const T*)L.b, (const T*)L.sig, inv_h12, (T*)L.r, c->stream);
+    if (L.col)
+        mp::launch_nd_resid_col<T>(L.d, (const T*)L.x, (const T*)L.b, (const T*)L.sig, inv_h12, (T*)L.r, c->stream);
+    else
+        mp::launch_nd_resid<T>(L.d, (const T*)L.x, (const T*)L.b, (const T*)L.sig, inv_h12, (T*)L.r, c->stream);
     mp::launch_nd_restrict<T>(L.d, C.d, (const T*)L.r, (T*)C.b, c->stream);
     if (l + 1 < nlev - 1) (void)hipMemsetAsync(C.x, 0, sizeof(T) * C.nn, c->stream);
     nd_vcycle<T>(c, l + 1);
     mp::launch_nd_prolong<T>(L.d, C.d, (T*)L.x, (const T*)C.x, c->stream);
     for (int s = 0; s < c->cfg.nu2; s++)
-        for (int colour = 3; colour >= 0; colour--)
-            mp::launch_nd_gs<T>(L.d, (T*)L.x, (const T*)L.b, (const T*)L.sig, h12, colour, c->stream);
+        for (int colour = 3; colour >= 0; colour--) gs(colour);
 }
 
 // Solve A phi = N.b64 on the nodes (||b||^2 in hscal[S_NB2], its rms pair in
@@ -776,9 +789,14 @@ int nd_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
         const int p = it & 1;
         double* sp = c->dscal + S_PAIR0 + 2 * p;
         double* sq = c->dscal + S_PAIR0 + 2 * (1 - p);
-        mp::launch_nd_resid64(L0.d, phi, N.b64, sig64, inv_h12, mx ? (float*)L0.b : nullptr, sp + 1, c->partials,
-                              N.nb, c->stream);
-        mp::launch_final_sum(c->partials, N.nb, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
+        int nbr = N.nb;
+        if (L0.col)
+            mp::launch_nd_resid64_col(L0.d, phi, N.b64, sig64, inv_h12, mx ? (float*)L0.b : nullptr, sp + 1,
+                                      N.partials, &nbr, c->stream);
+        else
+            mp::launch_nd_resid64(L0.d, phi, N.b64, sig64, inv_h12, mx ? (float*)L0.b : nullptr, sp + 1, N.partials,
+                                  N.nb, c->stream);
+        mp::launch_final_sum(N.partials, nbr, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
         int st = sync_read(c, S_RR, 1);
         if (st) return st;
         rel = sqrt(c->hscal[S_RR] / nb2);
@@ -822,8 +840,8 @@ int nd_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
             }
         }
     }
-    mp::launch_sum(phi, n, c->partials, N.nb, c->stream);
-    mp::launch_final_sum(c->partials, N.nb, c->dscal + S_GAUGE, 1.0 / (double)n, nullptr, 0.0, c->stream);
+    mp::launch_sum(phi, n, N.partials, N.nb, c->stream);
+    mp::launch_final_sum(N.partials, N.nb, c->dscal + S_GAUGE, 1.0 / (double)n, nullptr, 0.0, c->stream);
     mp::launch_sub_mean(phi, n, c->dscal + S_GAUGE, c->stream);
     if (info) {
         info->outer_iters = it;
@@ -1318,12 +1336,12 @@ int mp_nodal_project(mp_ctx* c, double* ux, double* uy, double* uz, const double
     // mean of beta0 S over the cells, then b = L(beta0 S - m) - D(beta0 U)
     mp::launch_nd_src_sum(c->n0, c->beta0, S, c->partials, nbc, c->stream);
     mp::launch_final_sum(c->partials, nbc, c->dscal + S_MEAN, 1.0 / (double)c->n0, nullptr, 0.0, c->stream);
-    mp::launch_nd_rhs(d, inv4h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, N.b64, 0, c->partials, N.nb, c->stream);
+    mp::launch_nd_rhs(d, inv4h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, N.b64, 0, N.partials, N.nb, c->stream);
     // remove the node mean (rounding only, in exact arithmetic the sum is 0):
     // b then lies in the range of A, which is orthogonal to the constants
-    mp::launch_final_sum(c->partials, N.nb, c->dscal + S_NMEAN, 1.0 / (double)nn, nullptr, 0.0, c->stream);
-    mp::launch_sub_mean_sumsq(N.b64, nn, c->dscal + S_NMEAN, c->partials, N.nb, c->stream);
-    mp::launch_final_sum(c->partials, N.nb, c->dscal + S_NB2, 1.0, c->dscal + S_PAIR0, (double)nn, c->stream);
+    mp::launch_final_sum(N.partials, N.nb, c->dscal + S_NMEAN, 1.0 / (double)nn, nullptr, 0.0, c->stream);
+    mp::launch_sub_mean_sumsq(N.b64, nn, c->dscal + S_NMEAN, N.partials, N.nb, c->stream);
+    mp::launch_final_sum(N.partials, N.nb, c->dscal + S_NB2, 1.0, c->dscal + S_PAIR0, (double)nn, c->stream);
     st = sync_read(c, S_MEAN, 2);
     if (st) return st;
     if (!isfinite(c->hscal[S_MEAN]) || !isfinite(c->hscal[S_NB2]))
@@ -1337,9 +1355,9 @@ int mp_nodal_project(mp_ctx* c, double* ux, double* uy, double* uz, const double
     if (solve_st != MP_OK && solve_st != MP_ERR_NOT_CONVERGED) return solve_st;
     HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
     mp::launch_nd_correct(d, inv4h, c->ccell, c->beta0, phi, ux, uy, uz, c->stream);
-    mp::launch_nd_rhs(d, inv4h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, nullptr, 1, c->partials, N.nb,
+    mp::launch_nd_rhs(d, inv4h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, nullptr, 1, N.partials, N.nb,
                       c->stream);
-    mp::launch_final_sum(c->partials, N.nb, c->dscal + S_DEF, 1.0, nullptr, 0.0, c->stream);
+    mp::launch_final_sum(N.partials, N.nb, c->dscal + S_DEF, 1.0, nullptr, 0.0, c->stream);
     HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
     st = sync_read(c, S_DEF, 1);
     if (st) return st;

@@ -230,6 +230,19 @@ void launch_nd_restrict(const NDims& f, const NDims& c, const T* rf, T* bc, hipS
 // xf += P ec.
 template <typename T>
 void launch_nd_prolong(const NDims& f, const NDims& c, T* xf, const T* ec, hipStream_t s);
+// The smoother colour and the residuals above by threads that walk node
+// columns along z (registers carry the neighbour planes); bitwise equal to
+// the one-node kernels.  Valid when nd_col_supported(d).
+bool nd_col_supported(const NDims& d);
+// Partials written by launch_nd_resid64_col on these dims.
+int nd_col_reduce_blocks(const NDims& d);
+template <typename T>
+void launch_nd_gs_col(const NDims& d, T* x, const T* b, const T* sg, T h12, int colour, hipStream_t s);
+template <typename T>
+void launch_nd_resid_col(const NDims& d, const T* x, const T* b, const T* sg, T inv_h12, T* r, hipStream_t s);
+// As launch_nd_resid64; *nb_out partials (<= kMaxRedBlocks).
+void launch_nd_resid64_col(const NDims& d, const double* x, const double* b, const double* sg, double inv_h12,
+                           float* r32, const double* inv_s, double* partials, int* nb_out, hipStream_t s);
 // Cell sigma of the grid coarsened by 2 (mean of 8 children), or, with
 // coarsen = 0, a precision conversion of the same grid.
 template <typename Tin, typename Tout>

@@ -168,3 +168,29 @@ def test_nodal_errors():
         ctx.nodal_project(T(q.ux), T(q.uy), T(q.uz), T(q.S))
     assert e.value.code == 1
     ctx.close()
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", [(32, 24, 20), (12, 10, 14), (64, 64, 64), (8, 8, 6)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_column_kernels_equal_the_one_node_kernels(shape, bc, precision):
+    """The z-marching smoother and residuals give the same bits as the
+    one-node kernels (blocked=False) in FP64.  In mixed precision the FP64
+    residual's norm is summed over a different block tree, so the refinement
+    scale s (and with it every FP32 value) moves by rounding: there the
+    results agree to rounding and take the same number of V-cycles."""
+    nx, ny, nz = shape
+    say("nodal columns", shape, bc, precision)
+    p = W.planar_problem(nx=nx, ny=ny, nz=nz, contrast=1e4, bc=bc, seed=7800 + nx, velocity="cells")
+    outs = []
+    for blocked in (True, False):
+        ctx = _mapped(p, precision, rtol=1e-11, blocked=blocked)
+        ux, uy, uz = T(p.ux), T(p.uy), T(p.uz)
+        phi, info = ctx.nodal_project(ux, uy, uz, T(p.S))
+        outs.append((N(phi), N(ux), info["vcycles"]))
+        ctx.close()
+    assert outs[0][2] == outs[1][2]
+    if precision == "fp64":
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    else:
+        assert rel(outs[0][0], outs[1][0]) < 1e-8 and rel(outs[0][1], outs[1][1]) < 1e-8
