@@ -71,6 +71,14 @@ def _declare(lib):
     lib.or_radius_index.restype = _I
     lib.or_average_irregular.argtypes = [_I, _I, _I, _D, ctypes.c_long, _D, _D]
     lib.or_average_irregular.restype = _I
+    lib.or_irregular_radii.argtypes = [ctypes.c_long, _F, _D, _D]
+    lib.or_irregular_radii.restype = None
+    lib.or_enforce_hse.argtypes = [ctypes.c_long, _D, _D, _D, _F, _F, _D]
+    lib.or_enforce_hse.restype = ctypes.c_long
+    lib.or_beta0_from_p0.argtypes = [ctypes.c_long, _F, _D, _D, _D]
+    lib.or_beta0_from_p0.restype = None
+    lib.or_w0.argtypes = [_I, ctypes.c_long, _D, _D, _D, _D, _D, _D]
+    lib.or_w0.restype = _I
     return lib
 
 
@@ -228,6 +236,47 @@ def split_source(geometry, S):
     if _load().or_split_source(nx, ny, nz, int(geometry), _p(a), _p(out), _p(sbar)):
         raise ValueError("the split source needs a planar or irregular spherical base state")
     return out, sbar
+
+
+def irregular_radii(nm, h):
+    """(centres, edges) of the irregular base state: h sqrt(0.75 + 2m) and
+    h sqrt(2m - 0.25) (edge 0 at the centre of the star)."""
+    rc, re = np.zeros(nm), np.zeros(nm + 1)
+    _load().or_irregular_radii(int(nm), float(h), _p(rc), _p(re))
+    return rc, re
+
+
+def enforce_hse(rc, rho0, g_edge, p0_base, rho_cutoff=0.0):
+    """Enforce HSE (Sec. 3.2): p0 from rho0, trapezoidal across the centres
+    rc, held constant from the cutoff density outward.  Returns (p0, cutoff index)."""
+    rc, rho0, g_edge = (np.ascontiguousarray(a, dtype=np.float64) for a in (rc, rho0, g_edge))
+    n = len(rc)
+    assert len(rho0) == n and len(g_edge) == n + 1
+    p0 = np.zeros(n)
+    jc = _load().or_enforce_hse(n, _p(rc), _p(rho0), _p(g_edge), float(p0_base), float(rho_cutoff), _p(p0))
+    return p0, int(jc)
+
+
+def beta0_from_p0(rho0_centre, p0, gamma1):
+    """beta0 = rho0(0) exp(int dp0 / (Gamma1 p0)) (Sec. 2) on the base-state centres."""
+    p0, gamma1 = (np.ascontiguousarray(a, dtype=np.float64) for a in (p0, gamma1))
+    out = np.zeros(len(p0))
+    _load().or_beta0_from_p0(len(p0), float(rho0_centre), _p(p0), _p(gamma1), _p(out))
+    return out
+
+
+def w0(geometry, rc, re, beta0, sbar, psi=None):
+    """Base-state velocity w0 on the n + 1 edges re from div(beta0 w0 e_r) =
+    beta0 (Sbar - psi) (Appendix A), centres rc; geometry 0 planar, 1 spherical."""
+    rc, re, beta0, sbar = (np.ascontiguousarray(a, dtype=np.float64) for a in (rc, re, beta0, sbar))
+    n = len(beta0)
+    assert len(rc) == n and len(re) == n + 1 and len(sbar) == n
+    ps = None if psi is None else np.ascontiguousarray(psi, dtype=np.float64)
+    out = np.zeros(n + 1)
+    if _load().or_w0(int(geometry), n, _p(rc), _p(re), _p(beta0), _p(sbar), _p(ps) if ps is not None else None,
+                     _p(out)):
+        raise ValueError("w0 needs geometry 0 (planar) or 1 (spherical)")
+    return out
 
 
 def face_coefs(g, beta0_cc, rho):

@@ -17,6 +17,9 @@
  *  - the lateral Average (Sec. 3.1 and the Average module of Sec. 3.2) over
  *    those irregular radii, or over the planes of a planar atmosphere, and the
  *    source S - Sbar of the velocity-split constraint of Appendix A;
+ *  - the one-dimensional base state: centres and edges of the irregular radii,
+ *    Enforce HSE (p0 from rho0), beta0 from its definition in Sec. 2, and the
+ *    base-state velocity w0 of the velocity split (Appendix A);
  *  - the MAC projection of Sec. 3.2 Steps 3 and 7 (the constraints div1/div2,
  *    i.e. the velocity constraint of Sec. 2 with the dp0/dt term folded into
  *    S) and Appendix A: find phi with
@@ -221,6 +224,103 @@ int or_split_source(int nx, int ny, int nz, int geometry, const double *S, doubl
         return 0;
     }
     return 1;
+}
+
+/* ---------------------------------------------------------------------- */
+/* One-dimensional base state (Sec. 3.2 modules, Appendix A)               */
+/* ---------------------------------------------------------------------- */
+
+/* Centres and edges of the irregular base state (Sec. 3.1): centre m at
+ * h sqrt(0.75 + 2m); edge m (the inner edge of radius m) at the same map at
+ * m - 1/2, h sqrt(2m - 0.25), i.e. the r^2 midway between the neighbouring
+ * centres, with edge 0 at the centre of the star.  rc: nm, re: nm + 1. */
+void or_irregular_radii(long nm, double h, double *rc, double *re)
+{
+    for (long m = 0; m < nm; m++) rc[m] = h * sqrt(0.75 + 2.0 * (double)m);
+    re[0] = 0.0;
+    for (long m = 1; m <= nm; m++) re[m] = h * sqrt(2.0 * (double)m - 0.25);
+}
+
+/* Enforce HSE (Sec. 3.2): p0 from rho0 by integrating dp0/dr = -rho0 g (the
+ * hydrostatic condition of Sec. 2, g >= 0 the magnitude of the gravity that
+ * points to -e_r) outward from p0[0] = p0_base with the trapezoidal rule
+ * across each pair of centres, Delta r_{j+1/2} = rc[j+1] - rc[j] (not
+ * constant on the irregular base state):
+ *     p0[j+1] = p0[j] - (rc[j+1] - rc[j]) g_edge[j+1] (rho0[j] + rho0[j+1]) / 2,
+ * g_edge[j] the gravity at the edge between centres j-1 and j (n + 1
+ * entries, edges as in or_irregular_radii).  From the first centre whose
+ * density is at or below rho_cutoff outward, p0 stays at its value there.
+ * Returns that centre's index (n when no density is that low). */
+long or_enforce_hse(long n, const double *rc, const double *rho0, const double *g_edge, double p0_base,
+                    double rho_cutoff, double *p0)
+{
+    long jc = n;
+    for (long j = 0; j < n; j++)
+        if (rho0[j] <= rho_cutoff) {
+            jc = j;
+            break;
+        }
+    p0[0] = p0_base;
+    for (long j = 1; j < n; j++) {
+        if (j > jc) {
+            p0[j] = p0[j - 1];
+            continue;
+        }
+        p0[j] = p0[j - 1] - (rc[j] - rc[j - 1]) * g_edge[j] * 0.5 * (rho0[j - 1] + rho0[j]);
+    }
+    return jc;
+}
+
+/* beta0 by its definition (Sec. 2): beta0(r) = rho0(0) exp(int_0^r dp0/(Gamma1 p0)).
+ * Across each pair of centres the integral of dp0/(Gamma1 p0) is taken with
+ * Gamma1 at its mean over the pair, which makes it exact for a constant
+ * Gamma1: ln(p0[j+1]/p0[j]) / ((Gamma1[j] + Gamma1[j+1]) / 2). */
+void or_beta0_from_p0(long n, double rho0_centre, const double *p0, const double *gamma1, double *beta0)
+{
+    double acc = 0.0;
+    beta0[0] = rho0_centre;
+    for (long j = 1; j < n; j++) {
+        acc += log(p0[j] / p0[j - 1]) / (0.5 * (gamma1[j - 1] + gamma1[j]));
+        beta0[j] = rho0_centre * exp(acc);
+    }
+}
+
+/* Base-state velocity w0 of the velocity split (Appendix A):
+ *     div(beta0 w0 e_r) = beta0 (Sbar - psi),  psi = dp0/dt / (Gamma1 p0),
+ * integrated outward from w0 = 0 at the bottom wall (planar, geometry 0) or
+ * at the centre of the star (spherical, geometry 1) in flux form over the
+ * base-state cells [re[j], re[j+1]]:
+ *     F[j+1] = F[j] + beta0[j] (sbar[j] - psi[j]) V[j],
+ *     planar:    F = beta0_e w0,        V[j] = re[j+1] - re[j],
+ *     spherical: F = re^2 beta0_e w0,   V[j] = (re[j+1]^3 - re[j]^3) / 3,
+ * with beta0 on an edge interpolated linearly in r between the centres rc on
+ * either side, and extrapolated linearly from the last two centres on the
+ * outer edge (one centre: its value).  w0 has n + 1 edge values; psi may be
+ * NULL (0).  Returns 1 for a bad geometry. */
+static double edge_beta0(long n, const double *rc, const double *re, const double *beta0, long e)
+{
+    if (n == 1) return beta0[0];
+    long a = e < n ? e - 1 : n - 2, b = a + 1;
+    double t = (re[e] - rc[a]) / (rc[b] - rc[a]);
+    return beta0[a] + t * (beta0[b] - beta0[a]);
+}
+
+int or_w0(int geometry, long n, const double *rc, const double *re, const double *beta0, const double *sbar,
+          const double *psi, double *w0)
+{
+    if (geometry != 0 && geometry != 1) return 1;
+    double F = 0.0;
+    w0[0] = 0.0;
+    for (long j = 0; j < n; j++) {
+        double V = geometry == 0 ? re[j + 1] - re[j]
+                                 : (re[j + 1] * re[j + 1] * re[j + 1] - re[j] * re[j] * re[j]) / 3.0;
+        F += beta0[j] * (sbar[j] - (psi ? psi[j] : 0.0)) * V;
+        long e = j + 1;
+        double be = edge_beta0(n, rc, re, beta0, e);
+        double area = geometry == 0 ? 1.0 : re[e] * re[e];
+        w0[e] = F / (area * be);
+    }
+    return 0;
 }
 
 void or_cell_radius(int nx, int ny, int nz, double h, int bx, int by, int bz, const double *center, double *r)

@@ -144,6 +144,50 @@ def pin_split_zero_sums():
     return bool(np.abs(s_eff.sum(axis=(1, 2))).max() <= 1e-13 * np.abs(S).sum())
 
 
+def _passes(fn, *args):
+    try:
+        fn(*args)
+        return True
+    except AssertionError:
+        return False
+
+
+def pin_base1d_radii():
+    from tests import test_oracle_base1d as B
+
+    return _passes(B.test_irregular_centres_and_edges)
+
+
+def pin_hse_linear():
+    from tests import test_oracle_base1d as B
+
+    return _passes(B.test_hse_is_exact_for_a_linear_density_on_the_irregular_radii)
+
+
+def pin_hse_cutoff():
+    from tests import test_oracle_base1d as B
+
+    return _passes(B.test_hse_holds_pressure_from_the_cutoff_outward)
+
+
+def pin_beta0_gamma():
+    from tests import test_oracle_base1d as B
+
+    return _passes(B.test_beta0_with_a_varying_gamma1_converges_at_second_order)
+
+
+def pin_w0_exact():
+    from tests import test_oracle_base1d as B
+
+    return all(_passes(B.test_w0_of_a_constant_source_is_exact, g) for g in (0, 1))
+
+
+def pin_w0_rate():
+    from tests import test_oracle_base1d as B
+
+    return all(_passes(B.test_w0_with_a_stratified_beta0_converges_at_second_order, s) for s in ("uniform", "irregular"))
+
+
 MUTANTS = [
     ("harmonic mean replaced by arithmetic mean", "v = 2.0 * a * b / (a + b);", "v = 0.5 * (a + b);",
      pin_series_conductance),
@@ -177,6 +221,18 @@ MUTANTS = [
      pin_plane_average),
     ("split source takes the next plane's average", "S[cell(&g, i, j, k)] - sbar[k];",
      "S[cell(&g, i, j, k)] - sbar[(k + 1) % nz];", pin_split_zero_sums),
+    ("irregular edges placed at the centre formula", "re[m] = h * sqrt(2.0 * (double)m - 0.25);",
+     "re[m] = h * sqrt(0.75 + 2.0 * (double)m);", pin_base1d_radii),
+    ("HSE density taken at the inner centre only", "g_edge[j] * 0.5 * (rho0[j - 1] + rho0[j]);",
+     "g_edge[j] * rho0[j - 1];", pin_hse_linear),
+    ("HSE cutoff applied one centre late", "        if (j > jc) {\n            p0[j] = p0[j - 1];",
+     "        if (j > jc + 1) {\n            p0[j] = p0[j - 1];", pin_hse_cutoff),
+    ("beta0 integral with the outer Gamma1 only", "/ (0.5 * (gamma1[j - 1] + gamma1[j]));", "/ gamma1[j];",
+     pin_beta0_gamma),
+    ("spherical w0 shell volume as r^2 dr", "(re[j + 1] * re[j + 1] * re[j + 1] - re[j] * re[j] * re[j]) / 3.0;",
+     "re[j + 1] * re[j + 1] * (re[j + 1] - re[j]);", pin_w0_exact),
+    ("w0 edge beta0 taken from the inner centre", "    return beta0[a] + t * (beta0[b] - beta0[a]);",
+     "    return beta0[a];", pin_w0_rate),
 ]
 
 
