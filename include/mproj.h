@@ -247,6 +247,51 @@ int mp_radius_count(const mp_ctx *ctx, long long *nm);
  * Errors: MP_ERR_ARG (odd extents, NULL, >= 2^32 cells), MP_ERR_NOMEM. */
 int mp_average(mp_ctx *ctx, const double *phi, double *avg, double *count);
 
+/* ---- one-dimensional base state (Sec. 3.2 modules, Appendix A) ----------
+ * Arrays are device arrays of doubles owned by the caller; each call runs one
+ * workgroup on the context's stream and returns without waiting unless it
+ * reports a scalar.  Sums run in a fixed order (reproducible).  */
+
+/* Centres rc (mp_radius_count entries) and edges re (one more) of the
+ * irregular base state (Sec. 3.1): rc[m] = h sqrt(0.75 + 2m), re[m] =
+ * h sqrt(2m - 1/4) (the radius map at m - 1/2; re[0] = 0).
+ * MP_ERR_ARG: NULL, or odd extents. */
+int mp_base_radii(mp_ctx *ctx, double *rc, double *re);
+
+/* Enforce HSE (Sec. 3.2): p0 from rho0 on n base-state centres rc by the
+ * hydrostatic condition dp0/dr = -rho0 g of Sec. 2 (g >= 0, the magnitude of
+ * a gravity pointing to -e_r), trapezoidal across each pair of centres with
+ * the non-uniform Delta r_{j+1/2} = rc[j+1] - rc[j]:
+ *   p0[0] = p0_base,  p0[j] = p0[j-1] - (rc[j] - rc[j-1]) g_edge[j] (rho0[j-1] + rho0[j]) / 2,
+ * g_edge: n + 1 values on the edges (g_edge[j] between centres j-1 and j).
+ * From the first centre with rho0 <= rho_cutoff outward p0 keeps its value
+ * there.  cutoff_index (host, may be NULL): that centre, or n; when given the
+ * call waits for it.  MP_ERR_ARG: NULL arrays, n < 1, non-finite p0_base. */
+int mp_enforce_hse(mp_ctx *ctx, long long n, const double *rc, const double *rho0, const double *g_edge,
+                   double p0_base, double rho_cutoff, double *p0, long long *cutoff_index);
+
+/* beta0 from its definition (Sec. 2), beta0 = rho0(0) exp(int dp0 / (Gamma1 p0)),
+ * on n centres: beta0[0] = rho0_centre and across each pair of centres the
+ * integral is ln(p0[j] / p0[j-1]) / ((gamma1[j-1] + gamma1[j]) / 2) (exact
+ * for a constant Gamma1).  Waits for a validity check: MP_ERR_NONFINITE if
+ * any p0 or gamma1 is non-positive or non-finite; MP_ERR_ARG: NULL, n < 1,
+ * rho0_centre <= 0. */
+int mp_beta0_from_p0(mp_ctx *ctx, long long n, double rho0_centre, const double *p0, const double *gamma1,
+                     double *beta0);
+
+/* Base-state velocity w0 of the velocity split (Appendix A): integrates
+ * div(beta0 w0 e_r) = beta0 (sbar - psi) outward from w0 = 0 at the bottom
+ * wall (MP_PLANAR) or the centre of the star (the spherical geometries):
+ *   F[0] = 0, F[j+1] = F[j] + beta0[j] (sbar[j] - psi[j]) V[j],
+ *   V[j] = re[j+1] - re[j] (planar) or (re[j+1]^3 - re[j]^3) / 3 (spherical),
+ *   w0[e] = F[e] / (A[e] beta0_e[e]),  A = 1 (planar) or re[e]^2,
+ * beta0_e linear in r between the neighbouring centres rc (extrapolated from
+ * the last two at the outer edge).  psi = (dp0/dt) / (Gamma1 p0) per centre,
+ * or NULL for 0.  rc, beta0, sbar, psi: n; re, w0: n + 1.
+ * MP_ERR_ARG: bad geometry, NULL arrays, n < 1. */
+int mp_w0(mp_ctx *ctx, int geometry, long long n, const double *rc, const double *re, const double *beta0,
+          const double *sbar, const double *psi, double *w0);
+
 /* Switch the per-launch timing of the finest-level smoother (mp_config
  * kernel_timing) on or off for the following calls; it records a start and
  * end timestamp with each of those launches.  Errors: MP_ERR_ARG, MP_ERR_DEVICE. */

@@ -1381,6 +1381,64 @@ int mp_nodal_apply(mp_ctx* c, const double* x, double* y)
     return MP_OK;
 }
 
+int mp_base_radii(mp_ctx* c, double* rc, double* re)
+{
+    if (!c) return MP_ERR_ARG;
+    if (!rc || !re) return fail(c, MP_ERR_ARG, "rc and re are required");
+    if (c->nm == 0) return fail(c, MP_ERR_ARG, "the irregular base state needs even extents");
+    (void)hipSetDevice(c->cfg.device);
+    mp::launch_irregular_radii(c->nm, c->cfg.h, rc, re, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MP_OK;
+}
+
+int mp_enforce_hse(mp_ctx* c, long long n, const double* rc, const double* rho0, const double* g_edge,
+                   double p0_base, double rho_cutoff, double* p0, long long* cutoff_index)
+{
+    if (!c) return MP_ERR_ARG;
+    if (n < 1 || !rc || !rho0 || !g_edge || !p0) return fail(c, MP_ERR_ARG, "n >= 1, rc, rho0, g_edge, p0 required");
+    if (!isfinite(p0_base) || isnan(rho_cutoff)) return fail(c, MP_ERR_ARG, "p0_base must be finite");
+    (void)hipSetDevice(c->cfg.device);
+    mp::launch_enforce_hse(n, rc, rho0, g_edge, p0_base, rho_cutoff, p0, c->dscal + S_ZERO, c->stream);
+    HIPCHK(c, hipGetLastError());
+    if (cutoff_index) {
+        int st = sync_read(c, S_ZERO, 1);
+        if (st) return st;
+        *cutoff_index = (long long)c->hscal[S_ZERO];
+    }
+    return MP_OK;
+}
+
+int mp_beta0_from_p0(mp_ctx* c, long long n, double rho0_centre, const double* p0, const double* gamma1,
+                     double* beta0)
+{
+    if (!c) return MP_ERR_ARG;
+    if (n < 1 || !p0 || !gamma1 || !beta0) return fail(c, MP_ERR_ARG, "n >= 1, p0, gamma1, beta0 required");
+    if (!(rho0_centre > 0.0) || !isfinite(rho0_centre)) return fail(c, MP_ERR_ARG, "rho0_centre must be positive");
+    (void)hipSetDevice(c->cfg.device);
+    mp::launch_beta0_from_p0(n, rho0_centre, p0, gamma1, beta0, c->dscal + S_ZERO, c->stream);
+    int st = sync_read(c, S_ZERO, 1);
+    if (st) return st;
+    if (c->hscal[S_ZERO] != 0.0)
+        return fail(c, MP_ERR_NONFINITE, "%.0f non-positive or non-finite p0 / Gamma1 entries", c->hscal[S_ZERO]);
+    return MP_OK;
+}
+
+int mp_w0(mp_ctx* c, int geometry, long long n, const double* rc, const double* re, const double* beta0,
+          const double* sbar, const double* psi, double* w0)
+{
+    if (!c) return MP_ERR_ARG;
+    if (geometry != MP_PLANAR && geometry != MP_SPHERICAL && geometry != MP_SPHERICAL_IRREGULAR &&
+        geometry != MP_SPHERICAL_QUADRATIC)
+        return fail(c, MP_ERR_ARG, "bad geometry");
+    if (n < 1 || !rc || !re || !beta0 || !sbar || !w0)
+        return fail(c, MP_ERR_ARG, "n >= 1, rc, re, beta0, sbar, w0 required");
+    (void)hipSetDevice(c->cfg.device);
+    mp::launch_w0(geometry == MP_PLANAR ? 0 : 1, n, rc, re, beta0, sbar, psi, w0, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MP_OK;
+}
+
 int mp_radius_count(const mp_ctx* c, long long* nm)
 {
     if (!c || !nm) return MP_ERR_ARG;

@@ -270,6 +270,20 @@ void launch_nd_apply64(const NDims& d, const double* x, const double* sg, double
 void launch_nd_correct(const NDims& d, double inv4h, const double* sg, const double* beta0, const double* phi,
                        double* ux, double* uy, double* uz, hipStream_t s);
 
+// ---- one-dimensional base state (one workgroup each; deterministic scans) --
+// Centres rc (nm) and edges re (nm + 1) of the irregular base state.
+void launch_irregular_radii(long long nm, double h, double* rc, double* re, hipStream_t s);
+// Enforce HSE (trapezoidal across centres, cutoff density); jc_out[0] = the
+// first centre at or below rho_cutoff (n if none), as a double.
+void launch_enforce_hse(long long n, const double* rc, const double* rho0, const double* g_edge, double p0_base,
+                        double rho_cutoff, double* p0, double* jc_out, hipStream_t s);
+// beta0 from p0 and Gamma1 (definition of beta0); bad[0] counts invalid inputs.
+void launch_beta0_from_p0(long long n, double rho0_centre, const double* p0, const double* gamma1, double* beta0,
+                          double* bad, hipStream_t s);
+// w0 on the n + 1 edges from div(beta0 w0 e_r) = beta0 (sbar - psi) (psi may be nullptr).
+void launch_w0(int spherical, long long n, const double* rc, const double* re, const double* beta0, const double* sbar,
+               const double* psi, double* w0, hipStream_t s);
+
 // Plain device copy (bandwidth calibration of the traffic counters).
 void launch_copy(const double* src, double* dst, long long n, hipStream_t s);
 

@@ -91,7 +91,8 @@ class Info(ctypes.Structure):
 # Every exported symbol of include/mproj.h.
 EXPORTS = ["mp_config_default", "mp_init", "mp_map_base_state", "mp_set_coefs", "mp_mac_project", "mp_solve",
            "mp_mac_project_split", "mp_radius_count", "mp_average", "mp_set_kernel_timing", "mp_apply", "mp_coef_grad",
-           "mp_nodal_shape", "mp_nodal_project", "mp_nodal_apply", "mp_free", "mp_last_error", "mp_version"]
+           "mp_nodal_shape", "mp_nodal_project", "mp_nodal_apply", "mp_base_radii", "mp_enforce_hse",
+           "mp_beta0_from_p0", "mp_w0", "mp_free", "mp_last_error", "mp_version"]
 
 _lib = None
 
@@ -138,6 +139,15 @@ def load_library(path=None):
     lib.mp_nodal_project.restype = I
     lib.mp_nodal_apply.argtypes = [P, P, P]
     lib.mp_nodal_apply.restype = I
+    L = ctypes.c_longlong
+    lib.mp_base_radii.argtypes = [P, P, P]
+    lib.mp_base_radii.restype = I
+    lib.mp_enforce_hse.argtypes = [P, L, P, P, P, D, D, P, ctypes.POINTER(L)]
+    lib.mp_enforce_hse.restype = I
+    lib.mp_beta0_from_p0.argtypes = [P, L, D, P, P, P]
+    lib.mp_beta0_from_p0.restype = I
+    lib.mp_w0.argtypes = [P, I, L, P, P, P, P, P, P]
+    lib.mp_w0.restype = I
     lib.mp_free.argtypes = [P]
     lib.mp_free.restype = I
     lib.mp_last_error.argtypes = [P]
@@ -358,6 +368,48 @@ class Context:
         ns = self.node_shape
         self._check(self.lib.mp_nodal_apply(self._h, self._ptr(x, ns, "x"), self._ptr(y, ns, "y")), "mp_nodal_apply")
         return y
+
+    # -- one-dimensional base state ----------------------------------------
+    def _vec(self, n):
+        return torch.empty(n, dtype=torch.float64, device=self.device)
+
+    def base_radii(self):
+        """(centres, edges) of the irregular base state of this grid."""
+        nm = self.radius_count()
+        rc, re = self._vec(nm), self._vec(nm + 1)
+        self._check(self.lib.mp_base_radii(self._h, self._ptr(rc, (nm,), "rc"), self._ptr(re, (nm + 1,), "re")),
+                    "mp_base_radii")
+        return rc, re
+
+    def enforce_hse(self, rc, rho0, g_edge, p0_base, rho_cutoff=0.0, out=None):
+        """Enforce HSE: returns (p0, cutoff index)."""
+        n = int(rc.shape[0])
+        p0 = out if out is not None else self._vec(n)
+        jc = ctypes.c_longlong()
+        code = self.lib.mp_enforce_hse(self._h, n, self._ptr(rc, (n,), "rc"), self._ptr(rho0, (n,), "rho0"),
+                                       self._ptr(g_edge, (n + 1,), "g_edge"), float(p0_base), float(rho_cutoff),
+                                       self._ptr(p0, (n,), "p0"), ctypes.byref(jc))
+        self._check(code, "mp_enforce_hse")
+        return p0, int(jc.value)
+
+    def beta0_from_p0(self, rho0_centre, p0, gamma1, out=None):
+        """beta0 = rho0(0) exp(int dp0 / (Gamma1 p0)) on the base state."""
+        n = int(p0.shape[0])
+        b = out if out is not None else self._vec(n)
+        self._check(self.lib.mp_beta0_from_p0(self._h, n, float(rho0_centre), self._ptr(p0, (n,), "p0"),
+                                              self._ptr(gamma1, (n,), "gamma1"), self._ptr(b, (n,), "beta0")),
+                    "mp_beta0_from_p0")
+        return b
+
+    def w0(self, geometry, rc, re, beta0, sbar, psi=None, out=None):
+        """Base-state velocity on the n + 1 edges (Appendix A)."""
+        n = int(rc.shape[0])
+        w = out if out is not None else self._vec(n + 1)
+        pp = self._ptr(psi, (n,), "psi") if psi is not None else None
+        self._check(self.lib.mp_w0(self._h, int(geometry), n, self._ptr(rc, (n,), "rc"),
+                                   self._ptr(re, (n + 1,), "re"), self._ptr(beta0, (n,), "beta0"),
+                                   self._ptr(sbar, (n,), "sbar"), pp, self._ptr(w, (n + 1,), "w0")), "mp_w0")
+        return w
 
     def close(self):
         if getattr(self, "_h", None):

@@ -81,6 +81,10 @@ def test_null_arguments():
     assert lib.mp_nodal_project(None, None, None, None, None, None, 0, None) == 1
     assert lib.mp_nodal_apply(None, None, None) == 1
     assert lib.mp_nodal_shape(None, None, None, None) == 1
+    assert lib.mp_base_radii(None, None, None) == 1
+    assert lib.mp_enforce_hse(None, 0, None, None, None, 0.0, 0.0, None, None) == 1
+    assert lib.mp_beta0_from_p0(None, 0, 1.0, None, None, None) == 1
+    assert lib.mp_w0(None, 0, 0, None, None, None, None, None, None) == 1
     assert lib.mp_set_coefs(None, None, None, None) == 1
     assert lib.mp_set_kernel_timing(None, 1) == 1
     assert lib.mp_radius_count(None, None) == 1

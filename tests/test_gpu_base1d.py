@@ -1,0 +1,116 @@
+"""One-dimensional base state on the GPU (Enforce HSE, beta0 from its
+definition, w0 of the velocity split, irregular radii) against the oracle, on
+the irregular radii of the workloads and on long ragged arrays that cross
+many scan tiles."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1908_03634_amd import mproj
+from tests.gpu_util import N, T, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(n=16):
+    return mproj.Context(n, n, n, bc=(1, 1, 1), precision="fp64")
+
+
+@pytest.mark.parametrize("n", [16, 128, 256])
+def test_irregular_radii_equal_the_oracle(n):
+    ctx = _ctx(n)
+    rc, re = ctx.base_radii()
+    orc, ore = oracle.irregular_radii(ctx.radius_count(), 1.0 / n)
+    assert np.array_equal(N(rc), orc) and np.array_equal(N(re), ore)
+    ctx.close()
+
+
+def _star(n):
+    """Radii of the irregular base state of an n^3 box, a star-like density."""
+    nm = oracle.radius_count(n, n, n)
+    rc, re = oracle.irregular_radii(nm, 1.0 / n)
+    rho0 = (1.0 + (rc / 0.05) ** 2) ** -2.5
+    g = 1.0 / (0.01 + re**2)
+    return rc, re, rho0, g
+
+
+@pytest.mark.parametrize("n", [64, 256])
+@pytest.mark.parametrize("cut", [0.0, 1e-4])
+def test_enforce_hse_matches_the_oracle(n, cut):
+    say("hse", n, cut)
+    rc, re, rho0, g = _star(n)
+    ref, jc_ref = oracle.enforce_hse(rc, rho0, g, 2.0, cut)
+    ctx = _ctx()
+    p0, jc = ctx.enforce_hse(T(rc), T(rho0), T(g), 2.0, cut)
+    assert jc == jc_ref
+    assert np.abs(N(p0) - ref).max() <= 1e-13 * 2.0
+    if cut > 0:
+        assert jc < len(rc) and np.all(N(p0)[jc:] == N(p0)[jc])
+    ctx.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4095, 4096, 4097, 100003, 1000003])
+def test_scans_across_tiles(n):
+    say("scan", n)
+    rng = np.random.default_rng(n)
+    re = np.concatenate([[0.0], np.cumsum(rng.uniform(0.5, 1.5, n))]) / n
+    rc = 0.5 * (re[:-1] + re[1:])
+    rho0 = np.exp(-3.0 * rc) * (1 + 0.1 * rng.standard_normal(n))
+    g = rng.uniform(0.5, 2.0, n + 1)
+    ctx = _ctx()
+    p_ref, jc_ref = oracle.enforce_hse(rc, rho0, g, 3.0, 0.2)
+    p0, jc = ctx.enforce_hse(T(rc), T(rho0), T(g), 3.0, 0.2)
+    assert jc == jc_ref and np.abs(N(p0) - p_ref).max() <= 1e-12 * 3.0
+    p_pos = 1.0 + np.abs(p_ref)
+    gam = rng.uniform(1.2, 1.7, n)
+    b_ref = oracle.beta0_from_p0(0.7, p_pos, gam)
+    b = N(ctx.beta0_from_p0(0.7, T(p_pos), T(gam)))
+    assert np.allclose(b, b_ref, rtol=1e-12, atol=0)
+    sbar, psi = rng.standard_normal(n), rng.standard_normal(n)
+    for geometry in (0, 1):
+        w_ref = oracle.w0(geometry, rc, re, b_ref, sbar, psi)
+        w = N(ctx.w0(geometry, T(rc), T(re), T(b_ref), T(sbar), T(psi)))
+        assert np.abs(w - w_ref).max() <= 1e-12 * max(np.abs(w_ref).max(), 1e-300)
+    ctx.close()
+
+
+def test_chain_on_the_irregular_star():
+    """Radii -> HSE -> beta0 -> w0 on the 256^3 irregular base state, each
+    step fed with the GPU's previous output, against the oracle chain."""
+    n = 256
+    ctx = _ctx(n)
+    rc, re = ctx.base_radii()
+    orc, ore = oracle.irregular_radii(ctx.radius_count(), 1.0 / n)
+    rho0 = (1.0 + (orc / 0.05) ** 2) ** -2.5
+    g = 1.0 / (0.01 + ore**2)
+    p0, jc = ctx.enforce_hse(rc, T(rho0), T(g), 10.0, 1e-5)
+    p_ref, _ = oracle.enforce_hse(orc, rho0, g, 10.0, 1e-5)
+    assert np.all(p_ref > 0)
+    gam = np.full(len(orc), 5.0 / 3.0)
+    b = ctx.beta0_from_p0(rho0[0], p0, T(gam))
+    b_ref = oracle.beta0_from_p0(rho0[0], p_ref, gam)
+    assert np.allclose(N(b), b_ref, rtol=1e-11, atol=0)
+    sbar = np.sin(orc * 20.0)
+    w = ctx.w0(mproj.SPHERICAL_IRREGULAR, rc, re, b, T(sbar))
+    w_ref = oracle.w0(1, orc, ore, b_ref, sbar)
+    assert np.abs(N(w) - w_ref).max() <= 1e-11 * np.abs(w_ref).max()
+    ctx.close()
+
+
+def test_base1d_errors():
+    ctx = _ctx()
+    x = torch.ones(8, dtype=torch.float64, device="cuda:0")
+    bad = x.clone()
+    bad[3] = -1.0
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.beta0_from_p0(1.0, bad, x)
+    assert e.value.code == 5
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.w0(7, x, torch.ones(9, dtype=torch.float64, device="cuda:0"), x, x)
+    assert e.value.code == 1
+    ctx.close()
+    odd = mproj.Context(9, 8, 8, bc=(1, 1, 1), precision="fp64")
+    with pytest.raises(mproj.MprojError):
+        odd.base_radii()
+    odd.close()
