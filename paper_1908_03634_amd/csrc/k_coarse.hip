@@ -5,14 +5,15 @@
 // gaps.
 // This kernel runs every level of the coarse set (pre-smoothing, residual
 // restriction, bottom solve, prolongation, post-smoothing) in a single
-// 1024-thread workgroup, separated by workgroup barriers.  The per-cell
+// 1024-thread workgroup, separated by workgroup barriers, with every array of
+// the set held in LDS (up to kCoarseLdsBytes; 160 KB per CU on gfx950).  The per-cell
 // arithmetic is the shared code of the one-launch-per-operation kernels, so
 // the smoother and the transfers agree with them bit for bit.
 //
-// The bottom solve is BiCGStab in FP64 run by the first wavefront alone: each
-// lane holds up to NS cells in registers, neighbour values come from
-// cross-lane shuffles and dot products from wavefront reductions broadcast
-// from lane 0, so no barrier is needed inside the iteration.
+// The bottom solve is conjugate gradients in FP64 run by the first wavefront
+// alone: each lane holds up to NS cells in registers, neighbour values come
+// from cross-lane shuffles and dot products from wavefront reductions
+// broadcast from lane 0, so no barrier is needed inside the iteration.
 #include "mp_device.h"
 #include "mp_kernels.h"
 
@@ -34,7 +35,7 @@ __device__ __forceinline__ double wave_get(const double (&v)[NS], int nq)
 }
 
 template <typename T, int NS>
-__device__ void wave_bicgstab(const Dims& d, const T* __restrict__ bin, T* __restrict__ xout,
+__device__ void wave_cg(const Dims& d, const T* __restrict__ bin, T* __restrict__ xout,
                               const T* __restrict__ cx, const T* __restrict__ cy, const T* __restrict__ cz, double h2,
                               double rtol, int maxit)
 {
@@ -45,7 +46,7 @@ __device__ void wave_bicgstab(const Dims& d, const T* __restrict__ bin, T* __res
     double c[NS][6];
     int nbi[NS][6];
     bool live[NS];
-    double b[NS], x[NS], r[NS], rh[NS], p[NS], v[NS], s[NS], t[NS];
+    double b[NS], x[NS], r[NS], p[NS], v[NS];
 #pragma unroll
     for (int u = 0; u < NS; u++) {
         const int q = lane + kWave * u;
@@ -77,9 +78,7 @@ __device__ void wave_bicgstab(const Dims& d, const T* __restrict__ bin, T* __res
         b[u] = live[u] ? b[u] - mean : 0.0;
         x[u] = 0.0;
         r[u] = b[u];
-        rh[u] = b[u];
-        p[u] = 0.0;
-        v[u] = 0.0;
+        p[u] = b[u];
     }
     auto apply = [&](const double (&y)[NS], double (&out)[NS]) {
 #pragma unroll
@@ -100,46 +99,30 @@ __device__ void wave_bicgstab(const Dims& d, const T* __restrict__ bin, T* __res
         for (int u = 0; u < NS; u++) acc = fma(a[u], bb[u], acc);
         return wave_sum_bcast(acc);
     };
-    const double bnorm2 = dot(b, b);
-    const double tol2 = rtol * rtol * bnorm2;
-    double rho = 1.0, alpha = 1.0, omega = 1.0;
-    if (bnorm2 > 0.0) {
-        for (int it = 0; it < maxit; it++) {
-            const double rho1 = dot(rh, r);
-            if (rho1 == 0.0) break;
-            const double beta = (rho1 / rho) * (alpha / omega);
+    // conjugate gradients: A is symmetric and positive on mean-zero vectors;
+    // the residual is kept mean-zero against rounding
+    double rr = dot(r, r);
+    const double tol2 = rtol * rtol * rr;
+    for (int it = 0; it < maxit && rr > tol2 && rr > 0.0; it++) {
+        apply(p, v);
+        const double pv = dot(p, v);
+        if (!(pv > 0.0)) break;
+        const double alpha = rr / pv;
+        part = 0.0;
 #pragma unroll
-            for (int u = 0; u < NS; u++) p[u] = r[u] + beta * (p[u] - omega * v[u]);
-            apply(p, v);
-            const double rhv = dot(rh, v);
-            if (rhv == 0.0) break;
-            alpha = rho1 / rhv;
-#pragma unroll
-            for (int u = 0; u < NS; u++) s[u] = r[u] - alpha * v[u];
-            const double ss = dot(s, s);
-            if (ss <= tol2) {
-#pragma unroll
-                for (int u = 0; u < NS; u++) x[u] += alpha * p[u];
-                break;
-            }
-            apply(s, t);
-            const double ts = dot(t, s);
-            const double tt = dot(t, t);
-            if (tt == 0.0) {
-#pragma unroll
-                for (int u = 0; u < NS; u++) x[u] += alpha * p[u];
-                break;
-            }
-            omega = ts / tt;
-#pragma unroll
-            for (int u = 0; u < NS; u++) {
-                x[u] += alpha * p[u] + omega * s[u];
-                r[u] = s[u] - omega * t[u];
-            }
-            const double rr = dot(r, r);
-            rho = rho1;
-            if (rr <= tol2 || omega == 0.0) break;
+        for (int u = 0; u < NS; u++) {
+            x[u] = fma(alpha, p[u], x[u]);
+            r[u] = live[u] ? fma(-alpha, v[u], r[u]) : 0.0;
+            part += r[u];
         }
+        const double mr = wave_sum_bcast(part) / n;
+#pragma unroll
+        for (int u = 0; u < NS; u++) r[u] = live[u] ? r[u] - mr : 0.0;
+        const double rr1 = dot(r, r);
+        const double beta = rr1 / rr;
+        rr = rr1;
+#pragma unroll
+        for (int u = 0; u < NS; u++) p[u] = fma(beta, p[u], r[u]);
     }
     part = 0.0;
 #pragma unroll
@@ -165,15 +148,82 @@ __device__ void cg_smooth(const CoarseLevel<T>& L, const Dims& d, int zero_init)
     }
 }
 
+// The arrays of every coarse level (x, b and the three low-face
+// coefficients) staged in LDS for the whole cycle: level l starts at
+// 5 * (cells of the levels above it), in the order x, b, cx, cy, cz.
+template <typename T>
+__device__ __forceinline__ CoarseLevel<T> lds_level(const CoarseArgs<T>& a, int l, T* lds)
+{
+    long long off = 0;
+    for (int q = 0; q < l; q++) off += 5LL * a.lv[q].nx * a.lv[q].ny * a.lv[q].nz;
+    const long long n = (long long)a.lv[l].nx * a.lv[l].ny * a.lv[l].nz;
+    CoarseLevel<T> L = a.lv[l];
+    L.x = lds + off;
+    L.b = lds + off + n;
+    L.cx = lds + off + 2 * n;
+    L.cy = lds + off + 3 * n;
+    L.cz = lds + off + 4 * n;
+    return L;
+}
+
+// 16-byte vector of T.
+template <typename T>
+struct V16;
+template <>
+struct V16<float> {
+    using type = float4;
+    static constexpr int k = 4;
+};
+template <>
+struct V16<double> {
+    using type = double2;
+    static constexpr int k = 2;
+};
+
 template <typename T, int NS>
 __global__ __launch_bounds__(1024) void k_coarse_cycle(CoarseArgs<T> a)
 {
+    __shared__ T lds[kCoarseLdsBytes / sizeof(T)];
     const int nl = a.nlev;
     Dims dims[kMaxCoarse];
     for (int l = 0; l < nl; l++) dims[l] = Dims{a.lv[l].nx, a.lv[l].ny, a.lv[l].nz, a.px, a.py, a.pz};
+    // residual scratch for the restrictions, after the last level
+    T* rs = lds_level(a, nl - 1, lds).x + 5 * dims[nl - 1].n();
+    // stage the coefficients of every level and the right-hand side (and,
+    // unless it starts from zero, the iterate) of the top level, 16 bytes
+    // per access where the level allows it
+    for (int l = 0; l < nl; l++) {
+        const CoarseLevel<T> S = lds_level(a, l, lds);
+        const int n = (int)dims[l].n();
+        const bool top = l == 0, xin = l == 0 && !a.zero_init;
+        if (n % (int)V16<T>::k == 0) {
+            using V = typename V16<T>::type;
+            const int nv = n / (int)V16<T>::k;
+            for (int e = threadIdx.x; e < nv; e += blockDim.x) {
+                const V vx = ((const V*)a.lv[l].cx)[e], vy = ((const V*)a.lv[l].cy)[e], vz = ((const V*)a.lv[l].cz)[e];
+                V vb, vi;
+                if (top) vb = ((const V*)a.lv[0].b)[e];
+                if (xin) vi = ((const V*)a.lv[0].x)[e];
+                ((V*)S.cx)[e] = vx;
+                ((V*)S.cy)[e] = vy;
+                ((V*)S.cz)[e] = vz;
+                if (top) ((V*)S.b)[e] = vb;
+                if (xin) ((V*)S.x)[e] = vi;
+            }
+        } else {
+            for (int e = threadIdx.x; e < n; e += blockDim.x) {
+                const_cast<T*>(S.cx)[e] = a.lv[l].cx[e];
+                const_cast<T*>(S.cy)[e] = a.lv[l].cy[e];
+                const_cast<T*>(S.cz)[e] = a.lv[l].cz[e];
+                if (top) S.b[e] = a.lv[0].b[e];
+                if (xin) S.x[e] = a.lv[0].x[e];
+            }
+        }
+    }
+    __syncthreads();
     // down
     for (int l = 0; l < nl - 1; l++) {
-        const CoarseLevel<T>& L = a.lv[l];
+        const CoarseLevel<T> L = lds_level(a, l, lds);
         const int zi = (l > 0) || a.zero_init;
         if (zi && a.nu1 == 0) {
             const int cnt0 = dims[l].nx * dims[l].ny * dims[l].nz;
@@ -184,32 +234,56 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(CoarseArgs<T> a)
         const Dims& f = dims[l];
         const int nxc = f.nx / 2, nyc = f.ny / 2, nzc = f.nz / 2;
         const int cnt = nxc * nyc * nzc;
+        T* bc = lds_level(a, l + 1, lds).b;
+        // residual restriction in two parallel phases: every fine residual
+        // into the scratch, then the 8 children of each coarse cell summed in
+        // the order of restrict_cell (the same bits)
+        const int nf = (int)f.n();
+        const Coef<T> C{L.cx, L.cy, L.cz, nullptr};
+        for (int e = threadIdx.x; e < nf; e += blockDim.x) {
+            const int i = e % f.nx, t = e / f.nx, j = t % f.ny, k = t / f.ny;
+            rs[e] = resid_cell<T, false>(f, L.x, L.b, C, L.inv_h2, i, j, k);
+        }
+        __syncthreads();
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
             const int I = e % nxc, t = e / nxc, J = t % nyc, K = t / nyc;
-            a.lv[l + 1].b[e] = restrict_cell<T, false>(f, L.x, L.b, Coef<T>{L.cx, L.cy, L.cz, nullptr}, L.inv_h2, I, J,
-                                                       K);
+            T acc = T(0);
+#pragma unroll
+            for (int c = 0; c < 2; c++)
+#pragma unroll
+                for (int bb = 0; bb < 2; bb++)
+#pragma unroll
+                    for (int aa = 0; aa < 2; aa++)
+                        acc += rs[((2 * K + c) * f.ny + 2 * J + bb) * f.nx + 2 * I + aa];
+            bc[e] = T(0.125) * acc;
         }
         __syncthreads();
     }
     // bottom: first wavefront only; the others wait at the barrier below
     if (threadIdx.x < kWave) {
-        const CoarseLevel<T>& B = a.lv[nl - 1];
-        wave_bicgstab<T, NS>(dims[nl - 1], B.b, B.x, B.cx, B.cy, B.cz, B.h2d, a.bottom_rtol, a.bottom_maxit);
+        const CoarseLevel<T> B = lds_level(a, nl - 1, lds);
+        wave_cg<T, NS>(dims[nl - 1], B.b, B.x, B.cx, B.cy, B.cz, B.h2d, a.bottom_rtol, a.bottom_maxit);
     }
     __syncthreads();
     // up
     for (int l = nl - 2; l >= 0; l--) {
-        const CoarseLevel<T>& L = a.lv[l];
+        const CoarseLevel<T> L = lds_level(a, l, lds);
         const Dims& f = dims[l];
         const int nxc = f.nx / 2, nyc = f.ny / 2;
         const int cnt = f.nx * f.ny * f.nz;
-        const T* ec = a.lv[l + 1].x;
+        const T* ec = lds_level(a, l + 1, lds).x;
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
             const int i = e % f.nx, t = e / f.nx, j = t % f.ny, k = t / f.ny;
             L.x[e] += ec[((k >> 1) * nyc + (j >> 1)) * nxc + (i >> 1)];
         }
         __syncthreads();
         for (int s = 0; s < a.nu2; s++) cg_smooth<T>(L, f, 0);
+    }
+    // the top level's iterate goes back to the finer level's prolongation
+    {
+        const CoarseLevel<T> L = lds_level(a, 0, lds);
+        const int n = (int)dims[0].n();
+        for (int e = threadIdx.x; e < n; e += blockDim.x) a.lv[0].x[e] = L.x[e];
     }
 }
 

@@ -44,7 +44,7 @@ struct Level {
     bool blkf = false;   // register-blocked kernels with stored face coefficients
 };
 
-constexpr long long kCoarseCells = 512;  // levels at or below run in one workgroup
+constexpr long long kCoarseCells = 4096;  // levels at or below may run in one workgroup (LDS permitting)
 constexpr long long kWaveBottomCells = 256;
 constexpr long long kFusedMinCells = 1LL << 22;  // fused sweeps on levels at least this large
 
@@ -1009,8 +1009,16 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
         const int nlev = (int)c->lv.size();
         c->coarse_start = -1;
         if (cfg->coarse_cycle && nlev >= 2 && c->lv.back().d.n() <= kWaveBottomCells) {
+            // bytes of LDS the set of levels from..nlev-1 needs (5 arrays each)
+            auto lds_bytes = [&](int from) {
+                long long b = c->lv[from].d.n() * (long long)tsz;  // residual scratch
+                for (int q = from; q < nlev; q++) b += 5LL * c->lv[q].d.n() * (long long)tsz;
+                return b;
+            };
             int lc = nlev - 1;
-            while (lc > 0 && c->lv[lc - 1].d.n() <= kCoarseCells && nlev - (lc - 1) <= mp::kMaxCoarse) lc--;
+            while (lc > 0 && c->lv[lc - 1].d.n() <= kCoarseCells && nlev - (lc - 1) <= mp::kMaxCoarse &&
+                   lds_bytes(lc - 1) <= mp::kCoarseLdsBytes)
+                lc--;
             if (lc == 0) lc = 1;  // the finest level keeps its own launches (its iterate may be the caller's)
             c->coarse_start = lc;
         }

@@ -116,8 +116,12 @@ void launch_bottom(const Dims& d, const T* rhs, T* phi, const T* cx, const T* cy
                    int maxit, int use_x0, double* work, hipStream_t s);
 
 // The coarse end of a V-cycle in one workgroup (levels lv[0..nlev), the last
-// one solved by one-wavefront BiCGStab; it must hold <= 256 cells).
+// one solved by one-wavefront conjugate gradients; it must hold <= 256 cells).
+// The five arrays of every level and a residual scratch of the first level's
+// size ((5 * all cells + cells of lv[0]) * sizeof(T) bytes) must fit in
+// kCoarseLdsBytes of LDS.
 constexpr int kMaxCoarse = 8;
+constexpr int kCoarseLdsBytes = 128 * 1024;
 template <typename T>
 struct CoarseLevel {
     int nx, ny, nz;
