@@ -958,6 +958,8 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
     {
         int np = c->nbz > mp::kMaxRedBlocks ? c->nbz : mp::kMaxRedBlocks;
         if (mp::blk_supported(c->d0) && mp::blk_reduce_blocks(c->d0) > np) np = mp::blk_reduce_blocks(c->d0);
+        if (mp::proj_blk_supported(c->d0) && mp::proj_blk_reduce_blocks(c->d0) > np)
+            np = mp::proj_blk_reduce_blocks(c->d0);
         c->partials = dalloc<double>(np, e), good &= ok(c->partials);
     }
     c->dscal = dalloc<double>(kScal, e), good &= ok(c->dscal);
@@ -1191,14 +1193,25 @@ static int finish_rhs(mp_ctx* c, int nb_sum, int nb)
 
 // The projection of mp_mac_project / mp_mac_project_split: source S, or
 // S - Sbar (sbar per plane for smode 1, per irregular radius for smode 2).
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 static int project(mp_ctx* c, double* ux, double* uy, double* uz, const double* S, const double* sbar, int smode,
                    double* phi, int use_initial_guess, mp_info* info)
 {
     c->kev_used = 0;
     const int nb = nblk(c);
     const double inv_h = 1.0 / c->cfg.h;
-    mp::launch_mac_rhs(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->b64, c->partials, c->stream);
-    int st = finish_rhs(c, c->nbz, nb);
+    // register-blocked right-hand side, correction and defect (cell-value
+    // coefficients, periodic x and y, 16-byte aligned caller arrays)
+    const bool pblk = c->cfg.blocked && c->cell_mode && mp::proj_blk_supported(c->d0) && aligned16(ux) &&
+                      aligned16(uy) && aligned16(uz) && aligned16(S) && aligned16(phi);
+    int nbs = c->nbz;
+    if (pblk)
+        mp::launch_rhs_blk(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->b64, nullptr, c->partials, &nbs,
+                           c->stream);
+    else
+        mp::launch_mac_rhs(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->b64, c->partials, c->stream);
+    int st = finish_rhs(c, nbs, nb);
     if (st) return st;
     if (info) {
         info->rhs_norm = sqrt(c->hscal[S_NB2]);
@@ -1208,10 +1221,17 @@ static int project(mp_ctx* c, double* ux, double* uy, double* uz, const double* 
     int solve_st = run_solve(c, phi, use_initial_guess, info);
     if (solve_st != MP_OK && solve_st != MP_ERR_NOT_CONVERGED) return solve_st;
     HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
-    mp::launch_vel_correct(c->d0, inv_h, coef64(c), c->beta0, phi, ux, uy, uz, c->stream);
-    mp::launch_rhs_defect(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->dscal + S_MEAN, c->partials,
-                          c->stream);
-    mp::launch_final_sum(c->partials, c->nbz, c->dscal + S_DEF, 1.0, nullptr, 0.0, c->stream);
+    int nbd = c->nbz;
+    if (pblk) {
+        mp::launch_vc_blk(c->d0, inv_h, c->ccell, c->beta0, phi, ux, uy, uz, c->stream);
+        mp::launch_rhs_blk(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, nullptr, c->dscal + S_MEAN, c->partials,
+                           &nbd, c->stream);
+    } else {
+        mp::launch_vel_correct(c->d0, inv_h, coef64(c), c->beta0, phi, ux, uy, uz, c->stream);
+        mp::launch_rhs_defect(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->dscal + S_MEAN, c->partials,
+                              c->stream);
+    }
+    mp::launch_final_sum(c->partials, nbd, c->dscal + S_DEF, 1.0, nullptr, 0.0, c->stream);
     HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
     st = sync_read(c, S_DEF, 1);
     if (st) return st;

@@ -195,6 +195,20 @@ void launch_rr_blk(const Dims& d, const T* x, const T* b, const T* cc, T inv_h2,
 void launch_resid64_blk(const Dims& d, const double* x, const double* b, const double* cc, double inv_h2, float* r32,
                         const double* inv_s, double* partials, int* nb_out, hipStream_t s);
 
+// ---- register-blocked projection kernels (finest level, periodic x and y) --
+// Same results, bit for bit, as launch_mac_rhs / launch_rhs_defect /
+// launch_vel_correct (cell-value coefficients) when proj_blk_supported(d)
+// and every array is 16-byte aligned.
+bool proj_blk_supported(const Dims& d);
+// shift == nullptr: b written, partials = per-block sums of b; otherwise no
+// write and partials = per-block sums of (b - shift[0])^2.  *nb_out partials.
+void launch_rhs_blk(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
+                    const double* uz, const double* S, const double* sbar, int smode, double* b, const double* shift,
+                    double* partials, int* nb_out, hipStream_t s);
+void launch_vc_blk(const Dims& d, double inv_h, const double* cc, const double* beta0, const double* phi, double* ux,
+                   double* uy, double* uz, hipStream_t s);
+int proj_blk_reduce_blocks(const Dims& d);
+
 // ---- FP64 level-0 operations --------------------------------------------
 // y = M x = -(A x).
 void launch_apply64(const Dims& d, const double* x, const Coef<double>& c, double inv_h2, double* y, hipStream_t s);
