@@ -41,6 +41,67 @@ void launch_rbgs(const Dims& d, T* phi, const T* rhs, const Coef<T>& c, T h2, in
         hipLaunchKernelGGL((k_rbgs<T, false>), sh.grid, sh.block, 0, s, d, phi, rhs, c, h2, colour, zero_init);
 }
 
+// The two colour passes that follow a prolongation, with the prolongation
+// folded in (ec: coarse correction; piecewise constant, parent of (i,j,k) is
+// (i/2, j/2, k/2)).  ALL (first colour): every value read, neighbours and
+// own, is x + e of its parent, the values the separate prolongation would
+// have stored; the other colour is left as stored.  Otherwise (second
+// colour): the neighbours, just updated, are read as stored and the cell's
+// own value as x + e.  Together they equal launch_prolong followed by two
+// plain passes, bit for bit.
+__device__ __forceinline__ long long parent_of(const Dims& d, int i, int j, int k)
+{
+    return ((long long)(k >> 1) * (d.ny >> 1) + (j >> 1)) * (d.nx >> 1) + (i >> 1);
+}
+
+template <typename T, bool CELL, bool ALL>
+__global__ __launch_bounds__(256) void k_rbgs_e(Dims d, T* __restrict__ x, const T* __restrict__ b, Coef<T> C, T h2,
+                                                int colour, const T* __restrict__ ec)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (p >= (d.nx + 1) / 2 || j >= d.ny || k >= d.nz) return;
+    const int i = 2 * p + ((j + k + colour) & 1);
+    if (i >= d.nx) return;
+    const long long q = ((long long)k * d.ny + j) * d.nx + i;
+    const Nbr nb = neighbours(d, q, i, j, k);
+    T c0, c1, c2, c3, c4, c5;
+    coef6<T, CELL>(C, d, q, nb, i, j, k, c0, c1, c2, c3, c4, c5);
+    const T own = x[q] + ec[parent_of(d, i, j, k)];
+    if constexpr (ALL) {
+        // neighbour coordinates (a wall neighbour is the cell itself)
+        const int im = i > 0 ? i - 1 : (d.px ? d.nx - 1 : i), ip = i < d.nx - 1 ? i + 1 : (d.px ? 0 : i);
+        const int jm = j > 0 ? j - 1 : (d.py ? d.ny - 1 : j), jp = j < d.ny - 1 ? j + 1 : (d.py ? 0 : j);
+        const int km = k > 0 ? k - 1 : (d.pz ? d.nz - 1 : k), kp = k < d.nz - 1 ? k + 1 : (d.pz ? 0 : k);
+        const T xm = x[nb.xm] + ec[parent_of(d, im, j, k)], xp = x[nb.xp] + ec[parent_of(d, ip, j, k)];
+        const T ym = x[nb.ym] + ec[parent_of(d, i, jm, k)], yp = x[nb.yp] + ec[parent_of(d, i, jp, k)];
+        const T zm = x[nb.zm] + ec[parent_of(d, i, j, km)], zp = x[nb.zp] + ec[parent_of(d, i, j, kp)];
+        x[q] = gs_value<T>(c0, c1, c2, c3, c4, c5, xm, xp, ym, yp, zm, zp, b[q], h2, own);
+    } else {
+        x[q] = gs_value<T>(c0, c1, c2, c3, c4, c5, x[nb.xm], x[nb.xp], x[nb.ym], x[nb.yp], x[nb.zm], x[nb.zp], b[q],
+                           h2, own);
+    }
+}
+
+template <typename T>
+void launch_rbgs_e(const Dims& d, T* phi, const T* rhs, const Coef<T>& c, T h2, int colour, int first,
+                   const T* ec, hipStream_t s)
+{
+    const Shape3 sh = cells3((d.nx + 1) / 2, d.ny, d.nz);
+    if (c.cell) {
+        if (first)
+            hipLaunchKernelGGL((k_rbgs_e<T, true, true>), sh.grid, sh.block, 0, s, d, phi, rhs, c, h2, colour, ec);
+        else
+            hipLaunchKernelGGL((k_rbgs_e<T, true, false>), sh.grid, sh.block, 0, s, d, phi, rhs, c, h2, colour, ec);
+    } else {
+        if (first)
+            hipLaunchKernelGGL((k_rbgs_e<T, false, true>), sh.grid, sh.block, 0, s, d, phi, rhs, c, h2, colour, ec);
+        else
+            hipLaunchKernelGGL((k_rbgs_e<T, false, false>), sh.grid, sh.block, 0, s, d, phi, rhs, c, h2, colour, ec);
+    }
+}
+
 // --------------------------------------------------------- transfer operators
 
 template <typename T, bool CELL>
@@ -343,6 +404,7 @@ void launch_ir_update(long long n, double* phi, const float* e, const double* s,
 
 #define MP_INST(T)                                                                                                    \
     template void launch_rbgs<T>(const Dims&, T*, const T*, const Coef<T>&, T, int, int, hipStream_t);                \
+    template void launch_rbgs_e<T>(const Dims&, T*, const T*, const Coef<T>&, T, int, int, const T*, hipStream_t);    \
     template void launch_resid_restrict<T>(const Dims&, const T*, const T*, const Coef<T>&, T, T*, hipStream_t);      \
     template void launch_prolong<T>(const Dims&, T*, const T*, hipStream_t);                                          \
     template void launch_bottom<T>(const Dims&, const T*, T*, const T*, const T*, const T*, double, double, int, int, \

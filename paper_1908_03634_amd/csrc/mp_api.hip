@@ -441,14 +441,17 @@ void smooth(mp_ctx* c, int l, bool zero_init, const T* ec, bool last = false)
         }
         return;
     }
-    if (ec) mp::launch_prolong<T>(L.d, (T*)L.x, ec, c->stream);
     for (int colour = 0; colour < 2; colour++) {
         // per colour: x (both colours share every line; not read when zero),
-        // coefficients (3 face words, or 1 cell word), b and x of one colour
+        // coefficients (3 face words, or 1 cell word), b and x of one colour;
+        // after a prolongation it is folded into the two passes (1/8 word of e)
         const bool zi = zero_init && colour == 0;
-        const double words = (zi ? 0.0 : 1.0) + (C.cell ? 1.0 : 3.0) + 0.5 + (zi ? 1.0 : 0.5);
+        const double words = (zi ? 0.0 : 1.0) + (C.cell ? 1.0 : 3.0) + 0.5 + (zi ? 1.0 : 0.5) + (ec ? 0.125 : 0.0);
         timed_begin(c, tm);
-        mp::launch_rbgs<T>(L.d, (T*)L.x, (const T*)L.b, C, h2, colour, zi ? 1 : 0, c->stream);
+        if (ec)
+            mp::launch_rbgs_e<T>(L.d, (T*)L.x, (const T*)L.b, C, h2, colour, colour == 0 ? 1 : 0, ec, c->stream);
+        else
+            mp::launch_rbgs<T>(L.d, (T*)L.x, (const T*)L.b, C, h2, colour, zi ? 1 : 0, c->stream);
         timed_end(c, tm, words * sizeof(T) * cells);
     }
 }

@@ -97,6 +97,13 @@ void launch_coef_grad(const Dims& d, double inv_h2, const double* lam, const dou
 template <typename T>
 void launch_rbgs(const Dims& d, T* phi, const T* rhs, const Coef<T>& c, T h2, int colour, int zero_init,
                  hipStream_t s);
+// The two colour passes after a prolongation with the prolongation folded in
+// (ec: the coarse correction): first = 1 for the first colour (every value
+// read as x + e of its parent cell), 0 for the second (own value x + e).
+// Equal bit for bit to launch_prolong and two launch_rbgs passes; even extents.
+template <typename T>
+void launch_rbgs_e(const Dims& d, T* phi, const T* rhs, const Coef<T>& c, T h2, int colour, int first, const T* ec,
+                   hipStream_t s);
 // Both colours in one launch, out of place (xo -> xn).  zero_init: xo is
 // taken as zero.  ec: coarse correction added to xo while reading
 // (prolongation fused into the sweep), or nullptr.
