@@ -297,6 +297,89 @@ __global__ __launch_bounds__(256) void k_nd_col(NDims d, int lz, T* __restrict__
     }
 }
 
+// The nodal right-hand side b = L(beta0 S - m) - D(beta0 U) (or, with
+// squares, its sum of squares alone) by threads that walk node columns: the
+// 2 x 2 cell columns around the column keep the cell plane below the node in
+// registers, so each node loads one new plane of 4 cells.  Same operands in
+// the same order as k_nd_rhs (bitwise equal); per-block partial sums.
+__global__ __launch_bounds__(256) void k_nd_rhs_col(NDims d, int lz, double inv4h, const double* __restrict__ beta0,
+                                                    const double* __restrict__ ux, const double* __restrict__ uy,
+                                                    const double* __restrict__ uz, const double* __restrict__ S,
+                                                    const double* __restrict__ mean, double* __restrict__ out,
+                                                    int squares, double* part)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k0 = blockIdx.z * lz;
+    const int k1 = min(k0 + lz, d.mz);
+    double acc = 0.0;
+    if (i < d.mx && j < d.my) {
+        const double m = mean[0];
+        const Axis ax = axis_of(i, d.nx, d.px), ay = axis_of(j, d.ny, d.py);
+        const long long cy = d.nx, cz = (long long)d.nx * d.ny;
+        long long ccol[2][2];
+        bool ccok[2][2];
+#pragma unroll
+        for (int oy = 0; oy < 2; oy++)
+#pragma unroll
+            for (int ox = 0; ox < 2; ox++) {
+                ccol[oy][ox] = ay.ce[oy] * cy + ax.ce[ox];
+                ccok[oy][ox] = ax.cok[ox] && ay.cok[oy];
+            }
+        // the five cell fields of the 2 x 2 columns in cell plane kc
+        struct CP {
+            double b0[2][2], s[2][2], u[2][2], v[2][2], w[2][2];
+            bool ok;
+        };
+        auto ld = [&](int kc, CP& c) {
+            bool okz = true;
+            if (d.pz) kc = kc < 0 ? kc + d.nz : kc;
+            else okz = kc >= 0 && kc < d.nz;
+            c.ok = okz;
+#pragma unroll
+            for (int oy = 0; oy < 2; oy++)
+#pragma unroll
+                for (int ox = 0; ox < 2; ox++) {
+                    const bool ok = okz && ccok[oy][ox];
+                    const long long e = (long long)(okz ? kc : 0) * cz + ccol[oy][ox];
+                    c.b0[oy][ox] = ok ? beta0[e] : 0.0;
+                    c.s[oy][ox] = ok ? S[e] : 0.0;
+                    c.u[oy][ox] = ok ? ux[e] : 0.0;
+                    c.v[oy][ox] = ok ? uy[e] : 0.0;
+                    c.w[oy][ox] = ok ? uz[e] : 0.0;
+                }
+        };
+        CP lo, hi;
+        ld(k0 - 1, lo);
+        for (int k = k0; k < k1; k++) {
+            ld(k, hi);
+            double src = 0.0, div = 0.0;
+#pragma unroll
+            for (int oz = 0; oz < 2; oz++) {
+                const CP& c = oz ? hi : lo;
+#pragma unroll
+                for (int oy = 0; oy < 2; oy++)
+#pragma unroll
+                    for (int ox = 0; ox < 2; ox++) {
+                        if (!(c.ok && ccok[oy][ox])) continue;
+                        const double b0 = c.b0[oy][ox];
+                        src += fma(b0, c.s[oy][ox], -m);
+                        const double vx = b0 * c.u[oy][ox], vy = b0 * c.v[oy][ox], vz = b0 * c.w[oy][ox];
+                        div += (ox ? -vx : vx) + (oy ? -vy : vy) + (oz ? -vz : vz);
+                    }
+            }
+            const double bn = 0.125 * src + inv4h * div;
+            if (out) out[((long long)k * d.my + j) * d.mx + i] = bn;
+            acc = squares ? fma(bn, bn, acc) : acc + bn;
+            lo = hi;
+        }
+    }
+    __shared__ double sh[kBlock / kWave];
+    const double sblk = block_sum(acc, sh);
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+        part[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = sblk;
+}
+
 namespace {
 
 // Columns (ni x nj) in 64 x 4 blocks, planes in chunks of lz: the largest lz
@@ -354,6 +437,16 @@ void launch_nd_resid64_col(const NDims& d, const double* x, const double* b, con
     *nb_out = (int)(c.grid.x * c.grid.y * c.grid.z);
     hipLaunchKernelGGL((k_nd_col<double, ND_RESID64>), c.grid, c.block, 0, s, d, c.lz, const_cast<double*>(x), b,
                        sg, 0.0, inv_h12, 0, (double*)nullptr, r32, inv_s, partials);
+}
+
+void launch_nd_rhs_col(const NDims& d, double inv4h, const double* beta0, const double* ux, const double* uy,
+                       const double* uz, const double* S, const double* mean, double* out, int squares,
+                       double* partials, int* nb_out, hipStream_t s)
+{
+    const ColShape c = col_shape(d.mx, d.my, d.mz, 1024, kMaxRedBlocks);
+    *nb_out = (int)(c.grid.x * c.grid.y * c.grid.z);
+    hipLaunchKernelGGL(k_nd_rhs_col, c.grid, c.block, 0, s, d, c.lz, inv4h, beta0, ux, uy, uz, S, mean, out, squares,
+                       partials);
 }
 
 template void launch_nd_gs_col<float>(const NDims&, float*, const float*, const float*, float, int, hipStream_t);

@@ -1367,10 +1367,16 @@ int mp_nodal_project(mp_ctx* c, double* ux, double* uy, double* uz, const double
     // mean of beta0 S over the cells, then b = L(beta0 S - m) - D(beta0 U)
     mp::launch_nd_src_sum(c->n0, c->beta0, S, c->partials, nbc, c->stream);
     mp::launch_final_sum(c->partials, nbc, c->dscal + S_MEAN, 1.0 / (double)c->n0, nullptr, 0.0, c->stream);
-    mp::launch_nd_rhs(d, inv4h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, N.b64, 0, N.partials, N.nb, c->stream);
+    const bool col = N.lv[0].col;
+    int nbr = N.nb;
+    if (col)
+        mp::launch_nd_rhs_col(d, inv4h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, N.b64, 0, N.partials, &nbr,
+                              c->stream);
+    else
+        mp::launch_nd_rhs(d, inv4h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, N.b64, 0, N.partials, N.nb, c->stream);
     // remove the node mean (rounding only, in exact arithmetic the sum is 0):
     // b then lies in the range of A, which is orthogonal to the constants
-    mp::launch_final_sum(N.partials, N.nb, c->dscal + S_NMEAN, 1.0 / (double)nn, nullptr, 0.0, c->stream);
+    mp::launch_final_sum(N.partials, nbr, c->dscal + S_NMEAN, 1.0 / (double)nn, nullptr, 0.0, c->stream);
     mp::launch_sub_mean_sumsq(N.b64, nn, c->dscal + S_NMEAN, N.partials, N.nb, c->stream);
     mp::launch_final_sum(N.partials, N.nb, c->dscal + S_NB2, 1.0, c->dscal + S_PAIR0, (double)nn, c->stream);
     st = sync_read(c, S_MEAN, 2);
@@ -1386,9 +1392,14 @@ int mp_nodal_project(mp_ctx* c, double* ux, double* uy, double* uz, const double
     if (solve_st != MP_OK && solve_st != MP_ERR_NOT_CONVERGED) return solve_st;
     HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
     mp::launch_nd_correct(d, inv4h, c->ccell, c->beta0, phi, ux, uy, uz, c->stream);
-    mp::launch_nd_rhs(d, inv4h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, nullptr, 1, N.partials, N.nb,
-                      c->stream);
-    mp::launch_final_sum(N.partials, N.nb, c->dscal + S_DEF, 1.0, nullptr, 0.0, c->stream);
+    int nbd = N.nb;
+    if (col)
+        mp::launch_nd_rhs_col(d, inv4h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, nullptr, 1, N.partials, &nbd,
+                              c->stream);
+    else
+        mp::launch_nd_rhs(d, inv4h, c->beta0, ux, uy, uz, S, c->dscal + S_MEAN, nullptr, 1, N.partials, N.nb,
+                          c->stream);
+    mp::launch_final_sum(N.partials, nbd, c->dscal + S_DEF, 1.0, nullptr, 0.0, c->stream);
     HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
     st = sync_read(c, S_DEF, 1);
     if (st) return st;

@@ -261,6 +261,11 @@ void launch_nd_prolong(const NDims& f, const NDims& c, T* xf, const T* ec, hipSt
 bool nd_col_supported(const NDims& d);
 // Partials written by launch_nd_resid64_col on these dims.
 int nd_col_reduce_blocks(const NDims& d);
+// As launch_nd_rhs by node columns (bitwise equal); *nb_out partials
+// (<= nd_col_reduce_blocks(d)).
+void launch_nd_rhs_col(const NDims& d, double inv4h, const double* beta0, const double* ux, const double* uy,
+                       const double* uz, const double* S, const double* mean, double* out, int squares,
+                       double* partials, int* nb_out, hipStream_t s);
 template <typename T>
 void launch_nd_gs_col(const NDims& d, T* x, const T* b, const T* sg, T h12, int colour, hipStream_t s);
 template <typename T>
