@@ -388,6 +388,28 @@ void launch_resid64(const Dims& d, const double* phi, const double* b, const Coe
                            partials);
 }
 
+// First refinement step from a zero iterate: the residual is b itself, so
+// r32 = float(b * pair_in[1]) (the value the residual kernel would write) and
+// the scale pair of the next step is the one of b.
+__global__ __launch_bounds__(256) void k_scale32(long long n, const double* __restrict__ b, float* __restrict__ r32,
+                                                 const double* __restrict__ pair_in, double* __restrict__ pair_out)
+{
+    const double is = pair_in[1];
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q == 0) {
+        pair_out[0] = pair_in[0];
+        pair_out[1] = pair_in[1];
+    }
+    if (r32 && q < n) r32[q] = (float)(b[q] * is);
+}
+
+void launch_scale32(long long n, const double* b, float* r32, const double* pair_in, double* pair_out, hipStream_t st)
+{
+    const long long work = r32 ? n : 1;
+    hipLaunchKernelGGL(k_scale32, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, st, n, b, r32, pair_in,
+                       pair_out);
+}
+
 __global__ __launch_bounds__(256) void k_ir_update(long long n, double* __restrict__ x, const float* __restrict__ e,
                                                    const double* __restrict__ s)
 {

@@ -567,16 +567,23 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
         double* sp = c->dscal + S_PAIR0 + 2 * p;
         double* sq = c->dscal + S_PAIR0 + 2 * (1 - p);
         int nbr = 0;
-        if (use_blk(c, 0))
-            mp::launch_resid64_blk(c->d0, phi, c->b64, c->ccell, inv_h2, mx ? (float*)c->lv[0].b : nullptr, sp + 1,
+        if (it == 0 && !use_guess) {
+            // zero iterate: the residual is b (relative residual 1), so the
+            // residual pass and its read-back are skipped
+            mp::launch_scale32(n, c->b64, mx ? (float*)c->lv[0].b : nullptr, sp, sq, c->stream);
+            rel = 1.0;
+        } else {
+            if (use_blk(c, 0))
+                mp::launch_resid64_blk(c->d0, phi, c->b64, c->ccell, inv_h2, mx ? (float*)c->lv[0].b : nullptr,
+                                       sp + 1, c->partials, &nbr, c->stream);
+            else
+                mp::launch_resid64(c->d0, phi, c->b64, coef64(c), inv_h2, mx ? (float*)c->lv[0].b : nullptr, sp + 1,
                                    c->partials, &nbr, c->stream);
-        else
-            mp::launch_resid64(c->d0, phi, c->b64, coef64(c), inv_h2, mx ? (float*)c->lv[0].b : nullptr, sp + 1,
-                               c->partials, &nbr, c->stream);
-        mp::launch_final_sum(c->partials, nbr, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
-        int st = sync_read(c, S_RR, 1);
-        if (st) return st;
-        rel = sqrt(c->hscal[S_RR] / nb2);
+            mp::launch_final_sum(c->partials, nbr, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
+            int st = sync_read(c, S_RR, 1);
+            if (st) return st;
+            rel = sqrt(c->hscal[S_RR] / nb2);
+        }
         if (it < 64) {
             hist[it] = rel;
             if (info) info->resid_hist[it] = rel;
@@ -793,16 +800,22 @@ int nd_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
         double* sp = c->dscal + S_PAIR0 + 2 * p;
         double* sq = c->dscal + S_PAIR0 + 2 * (1 - p);
         int nbr = N.nb;
-        if (L0.col)
-            mp::launch_nd_resid64_col(L0.d, phi, N.b64, sig64, inv_h12, mx ? (float*)L0.b : nullptr, sp + 1,
-                                      N.partials, &nbr, c->stream);
-        else
-            mp::launch_nd_resid64(L0.d, phi, N.b64, sig64, inv_h12, mx ? (float*)L0.b : nullptr, sp + 1, N.partials,
-                                  N.nb, c->stream);
-        mp::launch_final_sum(N.partials, nbr, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
-        int st = sync_read(c, S_RR, 1);
-        if (st) return st;
-        rel = sqrt(c->hscal[S_RR] / nb2);
+        if (it == 0 && !use_guess) {
+            // zero iterate: the residual is b (relative residual 1)
+            mp::launch_scale32(n, N.b64, mx ? (float*)L0.b : nullptr, sp, sq, c->stream);
+            rel = 1.0;
+        } else {
+            if (L0.col)
+                mp::launch_nd_resid64_col(L0.d, phi, N.b64, sig64, inv_h12, mx ? (float*)L0.b : nullptr, sp + 1,
+                                          N.partials, &nbr, c->stream);
+            else
+                mp::launch_nd_resid64(L0.d, phi, N.b64, sig64, inv_h12, mx ? (float*)L0.b : nullptr, sp + 1,
+                                      N.partials, N.nb, c->stream);
+            mp::launch_final_sum(N.partials, nbr, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
+            int st = sync_read(c, S_RR, 1);
+            if (st) return st;
+            rel = sqrt(c->hscal[S_RR] / nb2);
+        }
         if (it < 64) {
             hist[it] = rel;
             if (info) info->resid_hist[it] = rel;

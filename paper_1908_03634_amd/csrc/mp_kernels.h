@@ -225,6 +225,9 @@ void launch_resid64(const Dims& d, const double* phi, const double* b, const Coe
                     float* r32, const double* inv_s, double* partials, int* nb_out, hipStream_t s);
 // phi += s[0] * e.
 void launch_ir_update(long long n, double* phi, const float* e, const double* s, hipStream_t st);
+// First refinement step from a zero iterate (residual = b): r32 =
+// float(b * pair_in[1]) when r32 != nullptr; pair_out = pair_in.
+void launch_scale32(long long n, const double* b, float* r32, const double* pair_in, double* pair_out, hipStream_t st);
 
 // ---- irregular radial base state ------------------------------------------
 // Lateral average over radii m = 0 .. nm-1: cells[offs[m] .. offs[m+1]) lists
