@@ -459,15 +459,12 @@ template void launch_nd_resid_col<double>(const NDims&, const double*, const dou
 
 // ------------------------------------------------------------- transfers
 
-// Coarse right-hand side = (1/8) P^T r: the fine nodes 2I-1, 2I, 2I+1 per
-// axis with weights 1/2, 1, 1/2 (wrapped when periodic, dropped beyond a wall).
+// Coarse right-hand side = (1/8) P^T r at coarse node (I, J, K): the fine
+// nodes 2I-1, 2I, 2I+1 per axis with weights 1/2, 1, 1/2 (wrapped when
+// periodic, dropped beyond a wall).
 template <typename T>
-__global__ __launch_bounds__(256) void k_nd_restrict(NDims f, NDims c, const T* __restrict__ rf, T* __restrict__ bc)
+__device__ __forceinline__ T nd_restrict_node(const NDims& f, const T* __restrict__ rf, int I, int J, int K)
 {
-    const int I = blockIdx.x * blockDim.x + threadIdx.x;
-    const int J = blockIdx.y * blockDim.y + threadIdx.y;
-    const int K = blockIdx.z * blockDim.z + threadIdx.z;
-    if (I >= c.mx || J >= c.my || K >= c.mz) return;
     const Axis ax = axis_of(2 * I, f.nx, f.px), ay = axis_of(2 * J, f.ny, f.py), az = axis_of(2 * K, f.nz, f.pz);
     const long long sy = f.mx, sz = (long long)f.mx * f.my;
     T acc = T(0);
@@ -487,25 +484,15 @@ __global__ __launch_bounds__(256) void k_nd_restrict(NDims f, NDims c, const T* 
         }
         acc += cc == 1 ? row : T(0.5) * row;
     }
-    bc[((long long)K * c.my + J) * c.mx + I] = T(0.125) * acc;
+    return T(0.125) * acc;
 }
 
+// P e_c at fine node (i, j, k), trilinear: an even fine index takes coarse
+// node i/2, an odd one the mean of coarse nodes (i-1)/2 and (i+1)/2 (wrapped
+// when periodic).
 template <typename T>
-void launch_nd_restrict(const NDims& f, const NDims& c, const T* rf, T* bc, hipStream_t s)
+__device__ __forceinline__ T nd_prolong_node(const NDims& c, const T* __restrict__ ec, int i, int j, int k)
 {
-    const Shape3 sh = cells3(c.mx, c.my, c.mz);
-    hipLaunchKernelGGL((k_nd_restrict<T>), sh.grid, sh.block, 0, s, f, c, rf, bc);
-}
-
-// x_f += P e_c, trilinear: an even fine index takes coarse node i/2, an odd
-// one the mean of coarse nodes (i-1)/2 and (i+1)/2 (wrapped when periodic).
-template <typename T>
-__global__ __launch_bounds__(256) void k_nd_prolong(NDims f, NDims c, T* __restrict__ xf, const T* __restrict__ ec)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z * blockDim.z + threadIdx.z;
-    if (i >= f.mx || j >= f.my || k >= f.mz) return;
     int I[2], J[2], K[2];
     I[0] = i >> 1;
     I[1] = (i & 1) ? ((i + 1) >> 1 == c.mx ? 0 : (i + 1) >> 1) : I[0];
@@ -525,7 +512,35 @@ __global__ __launch_bounds__(256) void k_nd_prolong(NDims f, NDims c, T* __restr
         }
         acc += row;
     }
-    xf[((long long)k * f.my + j) * f.mx + i] += T(0.125) * acc;
+    return T(0.125) * acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_nd_restrict(NDims f, NDims c, const T* __restrict__ rf, T* __restrict__ bc)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (I >= c.mx || J >= c.my || K >= c.mz) return;
+    bc[((long long)K * c.my + J) * c.mx + I] = nd_restrict_node<T>(f, rf, I, J, K);
+}
+
+template <typename T>
+void launch_nd_restrict(const NDims& f, const NDims& c, const T* rf, T* bc, hipStream_t s)
+{
+    const Shape3 sh = cells3(c.mx, c.my, c.mz);
+    hipLaunchKernelGGL((k_nd_restrict<T>), sh.grid, sh.block, 0, s, f, c, rf, bc);
+}
+
+// x_f += P e_c.
+template <typename T>
+__global__ __launch_bounds__(256) void k_nd_prolong(NDims f, NDims c, T* __restrict__ xf, const T* __restrict__ ec)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= f.mx || j >= f.my || k >= f.mz) return;
+    xf[((long long)k * f.my + j) * f.mx + i] += nd_prolong_node<T>(c, ec, i, j, k);
 }
 
 template <typename T>
@@ -738,11 +753,9 @@ void launch_nd_correct(const NDims& d, double inv4h, const double* sg, const dou
 // tolerance is then relative to the initial residual), and is returned
 // mean-zero.  Stops at ||r|| <= rtol ||r0|| or maxit.  work holds 4 n doubles.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_nd_bottom(NDims d, const T* __restrict__ bin, T* __restrict__ xout,
-                                                    const T* __restrict__ sg, double inv_h12, double rtol, int maxit,
-                                                    int use_x0, double* __restrict__ work)
+__device__ void nd_block_cg(const NDims& d, const T* __restrict__ bin, T* __restrict__ xout, const T* __restrict__ sg,
+                            double inv_h12, double rtol, int maxit, int use_x0, double* __restrict__ work, double* sh)
 {
-    __shared__ double sh[16];
     const int n = d.mx * d.my * d.mz;
     const int tid = threadIdx.x, nt = blockDim.x;
     double* x = work;
@@ -825,6 +838,15 @@ __global__ __launch_bounds__(1024) void k_nd_bottom(NDims d, const T* __restrict
 }
 
 template <typename T>
+__global__ __launch_bounds__(1024) void k_nd_bottom(NDims d, const T* __restrict__ bin, T* __restrict__ xout,
+                                                    const T* __restrict__ sg, double inv_h12, double rtol, int maxit,
+                                                    int use_x0, double* __restrict__ work)
+{
+    __shared__ double sh[16];
+    nd_block_cg<T>(d, bin, xout, sg, inv_h12, rtol, maxit, use_x0, work, sh);
+}
+
+template <typename T>
 void launch_nd_bottom(const NDims& d, const T* b, T* x, const T* sg, double inv_h12, double rtol, int maxit,
                       int use_x0, double* work, hipStream_t s)
 {
@@ -833,6 +855,142 @@ void launch_nd_bottom(const NDims& d, const T* b, T* x, const T* sg, double inv_
     if (nt > 1024) nt = 1024;
     hipLaunchKernelGGL((k_nd_bottom<T>), dim3(1), dim3(nt), 0, s, d, b, x, sg, inv_h12, rtol, maxit, use_x0, work);
 }
+
+// ------------------------------------------------------------- coarse cycle
+
+// The coarse end of a nodal V-cycle in one 1024-thread workgroup with every
+// array in LDS: per level the iterate, right-hand side and residual on the
+// nodes and sigma on the cells, then the FP64 work of the bottom solve.  The
+// per-node arithmetic is that of the one-launch kernels (node_sums,
+// nd_restrict_node, nd_prolong_node, nd_block_cg), so both agree bit for bit.
+template <typename T>
+__device__ __forceinline__ long long nd_lds_off(const NdCoarseArgs<T>& a, int l)
+{
+    long long off = 0;
+    for (int q = 0; q < l; q++) {
+        const NDims& d = a.lv[q].d;
+        off += 3LL * d.mx * d.my * d.mz + (long long)d.nx * d.ny * d.nz;
+    }
+    return off;
+}
+
+template <typename T>
+__device__ __forceinline__ void nd_cc_gs(const NDims& d, T* x, const T* b, const T* sg, T h12, int colour)
+{
+    const int cx = colour & 1, cy = colour >> 1;
+    const int ni = (d.mx - cx + 1) / 2, nj = (d.my - cy + 1) / 2;
+    const int cnt = ni * nj * d.mz;
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const int ti = e % ni, t = e / ni, tj = t % nj, k = t / nj;
+        const int i = 2 * ti + cx, j = 2 * tj + cy;
+        T ssig, ss;
+        node_sums<T>(d, x, sg, i, j, k, ssig, ss);
+        const long long q = node_index(d, i, j, k);
+        x[q] = (ss + h12 * b[q]) / (T(4) * ssig);
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_nd_coarse(NdCoarseArgs<T> a)
+{
+    __shared__ T lds[kCoarseLdsBytes / sizeof(T)];
+    __shared__ double sh[16];
+    const int nl = a.nlev;
+    // stage sigma of every level and the right-hand side of the top level;
+    // every level starts from zero
+    for (int l = 0; l < nl; l++) {
+        const NDims& d = a.lv[l].d;
+        const int nn = d.mx * d.my * d.mz, nc = d.nx * d.ny * d.nz;
+        T* base = lds + nd_lds_off(a, l);
+        for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+            base[e] = T(0);
+            base[nn + e] = l == 0 ? a.lv[0].b[e] : T(0);
+        }
+        for (int e = threadIdx.x; e < nc; e += blockDim.x) base[3 * nn + e] = a.lv[l].sig[e];
+    }
+    __syncthreads();
+    // down
+    for (int l = 0; l < nl - 1; l++) {
+        const NDims& d = a.lv[l].d;
+        const int nn = d.mx * d.my * d.mz;
+        T* x = lds + nd_lds_off(a, l);
+        T* b = x + nn;
+        T* r = b + nn;
+        const T* sg = r + nn;
+        for (int s = 0; s < a.nu1; s++)
+            for (int colour = 0; colour < 4; colour++) nd_cc_gs<T>(d, x, b, sg, a.lv[l].h12, colour);
+        for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+            const int i = e % d.mx, t = e / d.mx, j = t % d.my, k = t / d.my;
+            T ssig, ss;
+            node_sums<T>(d, x, sg, i, j, k, ssig, ss);
+            r[e] = b[e] - (T(4) * ssig * x[e] - ss) * a.lv[l].inv_h12;
+        }
+        __syncthreads();
+        const NDims& c = a.lv[l + 1].d;
+        const int nnc = c.mx * c.my * c.mz;
+        T* bc = lds + nd_lds_off(a, l + 1) + nnc;
+        for (int e = threadIdx.x; e < nnc; e += blockDim.x) {
+            const int I = e % c.mx, t = e / c.mx, J = t % c.my, K = t / c.my;
+            bc[e] = nd_restrict_node<T>(d, r, I, J, K);
+        }
+        __syncthreads();
+    }
+    // bottom: FP64 conjugate gradients by the whole workgroup, work in LDS
+    {
+        const NDims& d = a.lv[nl - 1].d;
+        const int nn = d.mx * d.my * d.mz;
+        T* x = lds + nd_lds_off(a, nl - 1);
+        long long wo = nd_lds_off(a, nl) * (long long)sizeof(T);
+        wo = (wo + 7) / 8;  // in doubles, 8-byte aligned
+        double* work = reinterpret_cast<double*>(lds) + wo;
+        nd_block_cg<T>(d, x + nn, x, x + 3 * nn, a.bottom_inv_h12, a.bottom_rtol, a.bottom_maxit, 0, work, sh);
+        __syncthreads();
+    }
+    // up
+    for (int l = nl - 2; l >= 0; l--) {
+        const NDims& d = a.lv[l].d;
+        const int nn = d.mx * d.my * d.mz;
+        T* x = lds + nd_lds_off(a, l);
+        const T* b = x + nn;
+        const T* sg = x + 3 * nn;
+        const T* xc = lds + nd_lds_off(a, l + 1);
+        for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+            const int i = e % d.mx, t = e / d.mx, j = t % d.my, k = t / d.my;
+            x[e] += nd_prolong_node<T>(a.lv[l + 1].d, xc, i, j, k);
+        }
+        __syncthreads();
+        for (int s = 0; s < a.nu2; s++)
+            for (int colour = 3; colour >= 0; colour--) nd_cc_gs<T>(d, x, b, sg, a.lv[l].h12, colour);
+    }
+    {
+        const NDims& d = a.lv[0].d;
+        const int nn = d.mx * d.my * d.mz;
+        const T* x = lds;
+        for (int e = threadIdx.x; e < nn; e += blockDim.x) a.lv[0].x[e] = x[e];
+    }
+}
+
+template <typename T>
+long long nd_coarse_lds_bytes(const NDims* lv, int nlev)
+{
+    long long words = 0;
+    for (int q = 0; q < nlev; q++) words += 3LL * lv[q].mx * lv[q].my * lv[q].mz + (long long)lv[q].nx * lv[q].ny * lv[q].nz;
+    long long bytes = ((words * (long long)sizeof(T) + 7) / 8) * 8;
+    const NDims& bt = lv[nlev - 1];
+    return bytes + 4LL * bt.mx * bt.my * bt.mz * 8;
+}
+
+template <typename T>
+void launch_nd_coarse(const NdCoarseArgs<T>& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_nd_coarse<T>), dim3(1), dim3(1024), 0, s, a);
+}
+
+template long long nd_coarse_lds_bytes<float>(const NDims*, int);
+template long long nd_coarse_lds_bytes<double>(const NDims*, int);
+template void launch_nd_coarse<float>(const NdCoarseArgs<float>&, hipStream_t);
+template void launch_nd_coarse<double>(const NdCoarseArgs<double>&, hipStream_t);
 
 #define ND_INST(T)                                                                                        \
     template void launch_nd_gs<T>(const NDims&, T*, const T*, const T*, T, int, hipStream_t);             \

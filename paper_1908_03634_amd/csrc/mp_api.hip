@@ -74,6 +74,7 @@ struct NodalState {
     double* b64 = nullptr;          // FP64 right-hand side on the finest nodes
     double* bottom_work = nullptr;  // 4 * coarsest nodes
     double* partials = nullptr;     // per-block partial sums of the nodal reductions
+    int coarse_start = -1;          // first level of the single-workgroup coarse cycle, -1 = off
     long long sig_serial = -1;      // mapping the sigma pyramid was built from
     int nb = 1;                     // blocks of the grid-stride reductions over the finest nodes
 };
@@ -698,6 +699,20 @@ int nd_setup(mp_ctx* c)
     }
     N->b64 = (double*)alloc(sizeof(double) * N->lv[0].nn);
     if (!mx) N->lv[0].b = N->b64;
+    // single-workgroup coarse cycle: the trailing levels whose arrays fit LDS
+    if (c->cfg.coarse_cycle) {
+        const int nlev = (int)N->lv.size();
+        std::vector<mp::NDims> dims;
+        for (const auto& L : N->lv) dims.push_back(L.d);
+        auto fits = [&](int from) {
+            const long long b = mx ? mp::nd_coarse_lds_bytes<float>(dims.data() + from, nlev - from)
+                                   : mp::nd_coarse_lds_bytes<double>(dims.data() + from, nlev - from);
+            return nlev - from <= mp::kMaxCoarse && b <= mp::kCoarseLdsBytes;
+        };
+        int lc = nlev - 1;
+        while (lc > 1 && fits(lc - 1)) lc--;
+        N->coarse_start = (nlev >= 3 && fits(lc) && lc < nlev - 1) ? lc : -1;
+    }
     N->bottom_work = (double*)alloc(sizeof(double) * 4 * N->lv.back().nn);
     N->nb = mp::red_blocks(N->lv[0].nn);
     if (!good) {
@@ -743,6 +758,28 @@ void nd_vcycle(mp_ctx* c, int l)
     NLevel& L = N.lv[l];
     const int nlev = (int)N.lv.size();
     const double h2 = L.h * L.h;
+    if (l == N.coarse_start) {
+        mp::NdCoarseArgs<T> a;
+        memset(&a, 0, sizeof(a));
+        a.nlev = nlev - l;
+        a.nu1 = c->cfg.nu1;
+        a.nu2 = c->cfg.nu2;
+        a.bottom_rtol = c->cfg.bottom_rtol;
+        a.bottom_maxit = c->cfg.bottom_max_iter;
+        const double hb = N.lv[nlev - 1].h;
+        a.bottom_inv_h12 = 1.0 / (12.0 * hb * hb);
+        for (int q = 0; q < a.nlev; q++) {
+            const NLevel& Q = N.lv[l + q];
+            a.lv[q].d = Q.d;
+            a.lv[q].h12 = (T)(12.0 * Q.h * Q.h);
+            a.lv[q].inv_h12 = (T)(1.0 / (12.0 * Q.h * Q.h));
+            a.lv[q].x = (T*)Q.x;
+            a.lv[q].b = (const T*)Q.b;
+            a.lv[q].sig = (const T*)Q.sig;
+        }
+        mp::launch_nd_coarse<T>(a, c->stream);
+        return;
+    }
     if (l == nlev - 1) {
         // on a one-level grid the finest iterate carries the previous steps
         mp::launch_nd_bottom<T>(L.d, (const T*)L.b, (T*)L.x, (const T*)L.sig, 1.0 / (12.0 * h2),
@@ -763,7 +800,7 @@ void nd_vcycle(mp_ctx* c, int l)
     else
         mp::launch_nd_resid<T>(L.d, (const T*)L.x, (const T*)L.b, (const T*)L.sig, inv_h12, (T*)L.r, c->stream);
     mp::launch_nd_restrict<T>(L.d, C.d, (const T*)L.r, (T*)C.b, c->stream);
-    if (l + 1 < nlev - 1) (void)hipMemsetAsync(C.x, 0, sizeof(T) * C.nn, c->stream);
+    if (l + 1 < nlev - 1 && l + 1 != N.coarse_start) (void)hipMemsetAsync(C.x, 0, sizeof(T) * C.nn, c->stream);
     nd_vcycle<T>(c, l + 1);
     mp::launch_nd_prolong<T>(L.d, C.d, (T*)L.x, (const T*)C.x, c->stream);
     for (int s = 0; s < c->cfg.nu2; s++)

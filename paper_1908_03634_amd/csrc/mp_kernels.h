@@ -285,6 +285,29 @@ void launch_nd_sigma(int nx, int ny, int nz, const Tin* sf, Tout* sc, int coarse
 template <typename T>
 void launch_nd_bottom(const NDims& d, const T* b, T* x, const T* sg, double inv_h12, double rtol, int maxit,
                       int use_x0, double* work, hipStream_t s);
+// The coarse end of a nodal V-cycle in one workgroup, every array in LDS
+// (levels lv[0..nlev), all starting from zero; lv[0].b in, lv[0].x out).
+template <typename T>
+struct NdCoarseLevel {
+    NDims d;
+    T h12, inv_h12;  // 12 h^2 and its inverse
+    T* x;            // global iterate of lv[0] (written at the end)
+    const T* b;      // global right-hand side of lv[0]
+    const T* sig;    // global cell sigma
+};
+template <typename T>
+struct NdCoarseArgs {
+    int nlev, nu1, nu2;
+    double bottom_rtol;
+    int bottom_maxit;
+    double bottom_inv_h12;
+    NdCoarseLevel<T> lv[kMaxCoarse];
+};
+// LDS bytes the coarse set lv[0..nlev) needs (must be <= kCoarseLdsBytes).
+template <typename T>
+long long nd_coarse_lds_bytes(const NDims* lv, int nlev);
+template <typename T>
+void launch_nd_coarse(const NdCoarseArgs<T>& a, hipStream_t s);
 // partials (nb blocks) = per-block sum of beta0 * S over the cells.
 void launch_nd_src_sum(long long n, const double* beta0, const double* S, double* partials, int nb, hipStream_t s);
 // b = L(beta0 S - mean[0]) - D(beta0 U) on the nodes (out may be nullptr);

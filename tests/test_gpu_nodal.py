@@ -192,3 +192,23 @@ def test_column_kernels_equal_the_one_node_kernels(shape, bc, precision):
         ctx.close()
     assert outs[0][2] == outs[1][2]
     assert rel(outs[0][0], outs[1][0]) < 1e-8 and rel(outs[0][1], outs[1][1]) < 1e-8
+
+
+@pytest.mark.parametrize("shape,bc", [((32, 32, 32), (0, 0, 1)), ((48, 32, 40), (1, 1, 1)), ((64, 64, 64), (0, 0, 0)),
+                                      ((24, 16, 20), (1, 0, 1))])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_nodal_coarse_cycle_equals_per_level_launches(shape, bc, precision):
+    """The single-workgroup coarse cycle (every coarse array in LDS) runs the
+    same per-node arithmetic as one launch per operation: the same bits."""
+    nx, ny, nz = shape
+    say("nodal coarse cycle", shape, bc, precision)
+    p = W.planar_problem(nx=nx, ny=ny, nz=nz, contrast=1e4, bc=bc, seed=7900 + nx + nz, velocity="cells")
+    outs = []
+    for cc in (True, False):
+        ctx = _mapped(p, precision, rtol=1e-11, coarse_cycle=cc)
+        ux = T(p.ux)
+        phi, info = ctx.nodal_project(ux, T(p.uy), T(p.uz), T(p.S))
+        outs.append((N(phi), N(ux), info["vcycles"]))
+        ctx.close()
+    assert outs[0][2] == outs[1][2]
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
