@@ -164,20 +164,25 @@ def main():
     main_prec = args.only or "mixed"
     dt, steps, infos = res[main_prec]
     value = steps / dt
-    # dominant kernel: the finest-level red-black smoother pass.  In the last
-    # timed step the library timestamps each of its launches (HIP events
-    # recorded by the dispatch on the library's stream) and adds up the
-    # algorithmic bytes of each launch: x read (not in the zero-start pass)
-    # and written, b and the cell coefficients read, one word each per cell,
-    # plus 1/8 word of coarse correction after prolongation and 16 bytes per
-    # cell where the refinement update rides on the pass.
+    # dominant kernel: the finest-level red-black smoother (in mixed precision
+    # on rows of 128 or 256 cells both colours of a sweep in one launch,
+    # otherwise one launch per colour).  In the last timed step the library
+    # timestamps each of its launches (HIP events recorded by the dispatch on
+    # the library's stream) and adds up the algorithmic bytes of each launch:
+    # x read (not from a zero start) and written, b and the cell coefficients
+    # read, one word each per cell, plus 1/8 word of coarse correction after
+    # prolongation and 16 bytes per cell where the refinement update rides on
+    # the launch.
     tot_ms = sum(i["smooth_ms_total"] for i in infos)
     cnt = sum(i["smooth_launches"] for i in infos)
     tot_bytes = sum(i["smooth_bytes"] for i in infos)
     avg_s = tot_ms / cnt / 1e3 if cnt else float("nan")
     bytes_per_launch = tot_bytes / cnt if cnt else float("nan")
     achieved = bytes_per_launch / avg_s / 1e9
-    kname = "k_gs_blk<float>" if main_prec == "mixed" else "k_gs_blk<double>"
+    if main_prec == "mixed":
+        kname = "k_fsw_lds<float>" if infos[-1].get("smooth_form") == 1 else "k_gs_blk<float>"
+    else:
+        kname = "k_gs_blk<double>"
     rec = _traffic_record(f"{args.workload}:{kname}")
     traffic = None
     if rec:

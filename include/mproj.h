@@ -85,15 +85,15 @@ typedef struct mp_config {
     int demean;              /* 1: remove the mean of the rhs; 0: require mean ~ 0 */
     int kernel_timing;       /* 1: time the finest-level smoother launches with
                                 HIP events (mp_info.smooth_*) */
-    int smoother;            /* MP_SMOOTH_AUTO: one launch per colour, except
-                                both colours in one launch on finest levels of
-                                >= 4M cells with stored face coefficients;
+    int smoother;            /* MP_SMOOTH_AUTO: both colours of a sweep in one
+                                launch on the register-blocked finest level
+                                in MIXED when nx is 128 or 256, and on finest
+                                levels of >= 4M cells with stored face
+                                coefficients; one launch per colour elsewhere.
                                 MP_SMOOTH_PER_COLOUR: one launch per colour on
-                                every level; MP_SMOOTH_FUSED: both colours in one
-                                launch wherever the grid allows (also the
-                                register-blocked finest level in MIXED when
-                                nx is 128 or 256).  All three give the same
-                                bits. */
+                                every level; MP_SMOOTH_FUSED: both colours in
+                                one launch wherever the grid allows.  All
+                                three give the same bits. */
     int coarse_cycle;        /* 1: run levels of <= 512 cells in one workgroup
                                 (bottom <= 256 cells by one wavefront); 0: one
                                 launch per operation on every level */
@@ -125,6 +125,9 @@ typedef struct mp_info {
     double smooth_ms_total;  /* summed finest-level smoother time (kernel_timing) */
     int smooth_launches;     /* number of launches summed above */
     double smooth_bytes;     /* algorithmic HBM bytes of those launches */
+    int smooth_form;         /* finest-level smoother: 0 = one launch per
+                                colour, 1 = both colours of a sweep in one
+                                launch */
     int flags;               /* bit 0: stagnation detected */
 } mp_info;
 

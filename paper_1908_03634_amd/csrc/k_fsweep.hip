@@ -1,25 +1,35 @@
 // k_fsweep.hip -- both colours of a red-black Gauss-Seidel sweep in one pass
-// over the finest level (register-blocked strips, out of place).
+// over the finest level (whole rows, out of place, rows exchanged in LDS).
 //
 // A sweep updates every red cell (i + j + k even) from the old black values,
-// then every black cell from the new red values.  Done as two passes, each
-// pass streams the iterate, the right-hand side and the coefficients through
-// HBM once; here one pass does both.  A wavefront owns R rows of a plane and
-// marches along z, updating red on plane k+1 and then black on plane k:
-//   * black on plane k needs new red values in its own rows, in the rows
-//     just outside them (owned by other wavefronts) and on planes k-1 and
-//     k+1; the wavefront therefore computes red for R + 2 rows (one halo row
-//     on each side, recomputed rather than exchanged), which needs the old
-//     values of R + 4 rows;
-//   * the planes it keeps in registers are k-1 (final), k (new red), k+1
-//     (old, then new red) and k+2 (old, loaded at the top of the step);
-//   * a plane chunk starts by computing red on its first two planes.
-// The sweep reads the old iterate `xo` and writes `xn`: a wavefront reads
-// old values of rows and planes that other wavefronts write.  Every cell is
-// evaluated with the shared per-cell arithmetic (`harm`, `gs_value`), in the
-// operand order of the one-cell kernels, so the result equals two colour
-// passes bit for bit.  Used when one wavefront spans a row (nx = 128 M,
-// M <= 2).
+// then every black cell from the new red values.  As two colour passes it
+// streams the iterate, the right-hand side and the coefficients through HBM
+// twice (32 bytes per cell in FP32); here one pass does both (16 bytes).
+//
+// Wavefront w of a workgroup holds row j0 - 2 + w of every plane (a whole
+// row: nx = 128 M, 2M cells per lane), so the R + 4 wavefronts span the R
+// owned rows, one row on each side whose red is recomputed and one more on
+// each side that only supplies old values.  The workgroup marches along z
+// through a chunk of planes; each wavefront keeps its own cells of planes
+// k-1 .. k+2 (and the planes being prefetched) in registers, and a row's y
+// neighbours come from the other wavefronts through three LDS plane buffers
+// (x and c), used in turn.  Plane step k (planes z0-2 .. z1-1 of the chunk):
+//   1. prefetch x and c of plane k+2+D and b of plane k+1+D;
+//   2. publish the old x and c of plane k+1 in its buffer; barrier;
+//   3. red on plane k+1 (rows j0-1 .. j0+R), written back to the buffer: the
+//      other red rows read only the black cells of the row, which keep their
+//      values;
+//   4. black on plane k (rows j0 .. j0+R-1) from the new red of plane k (the
+//      neighbour rows, published in step 3 of the previous plane step and
+//      made visible by this step's barrier) and of planes k-1 and k+1 (own
+//      registers); stored to xn.
+// A buffer is filled again two plane steps after its black reads, with a
+// barrier between, so one barrier per plane step suffices.  The chunk starts
+// two planes early (red only on planes z0-1 and z0).  The sweep reads the old
+// iterate xo and writes xn: other workgroups read old values of the rows and
+// planes this one writes.  Each cell is evaluated with the shared per-cell
+// arithmetic (harm, gs_value) in the operand order of the colour passes, so
+// the result equals two colour passes bit for bit.
 #include "mp_blk.h"
 #include "mp_device.h"
 #include "mp_kernels.h"
@@ -30,257 +40,389 @@ namespace mp {
 
 bool fsw_supported(const Dims& d) { return blk_supported(d) && (d.nx == 128 || d.nx == 256); }
 
-// Red (colour 0) update of rows 1 .. R+2 of plane P, in place in x.
-// x, c: rows j0-2 .. j0+R+1 of plane P.  xb/cb (below, plane P-1) and xa/ca
-// (above, plane P+1) hold row j0-2+t at index t-1+OB / t-1+OA.  bq: rows
-// j0-1 .. j0+R.
-template <typename T, int M, int R, int OB, int NB, int OA, int NA>
-__device__ __forceinline__ void fs_red(const Dims& d, const BlkGeo& g, int P, T h2, Strip<T, M> (&x)[R + 4],
-                                       const Strip<T, M> (&c)[R + 4], const Strip<T, M> (&xb)[NB],
-                                       const Strip<T, M> (&cb)[NB], const Strip<T, M> (&xa)[NA],
-                                       const Strip<T, M> (&ca)[NA], const Strip<T, M> (&bq)[R + 2])
+// The M cells of one parity (q even or q odd) of a lane's strip.
+template <typename T, int M>
+struct Half {
+    T v[M];
+};
+
+// One colour (par 0: red, 1: black) of row j of plane P, in place in x.
+// xlo/xhi, clo/chi: the cells of the colour's parity in rows j-1 and j+1 of
+// plane P (the update of cell q reads element q / 2); xb and xa: this row on
+// planes P-1 and P+1.  fx: the x faces of the row (x_faces); fzl and fzh: its
+// z faces below and above (z_faces of planes P-1 and P).
+template <typename T, int M>
+__device__ __forceinline__ void fs_row(const Dims& d, const BlkGeo& g, int j, int P, int par, T h2, Strip<T, M>& x,
+                                       const Half<T, M>& xlo, const Half<T, M>& xhi, const Strip<T, M>& xb,
+                                       const Strip<T, M>& xa, const T (&fx)[2 * M + 1], const Strip<T, M>& c,
+                                       const Half<T, M>& clo, const Half<T, M>& chi, const Strip<T, M>& fzl,
+                                       const Strip<T, M>& fzh, const Strip<T, M>& bq)
 {
-    constexpr int NH = R + 4;
     const bool hzm = P > 0 || d.pz, hzp = P < d.nz - 1 || d.pz;
-    T fy[NH][2 * M];  // fy[t]: face between rows t-1 and t
+    const bool fyl = (j > 0 || d.py) && (j < d.ny || d.py);
+    const bool fyh = (j + 1 > 0 || d.py) && (j + 1 < d.ny || d.py);
+    const bool ywl = !(j > 0 || d.py), ywh = !(j < d.ny - 1 || d.py);
+    T vl, vr;
+    x_edges<T, M>(g, x, T(0), vl, vr);
+    Strip<T, M> out = x;
+    auto upd = [&](int q) {
+        const T own = x.v[q];
+        const T fl = fyl ? harm(clo.v[q >> 1], c.v[q]) : T(0);
+        const T fh = fyh ? harm(c.v[q], chi.v[q >> 1]) : T(0);
+        const T xm = q > 0 ? x.v[q > 0 ? q - 1 : 0] : (g.wl ? own : vl);
+        const T xp = q < 2 * M - 1 ? x.v[q < 2 * M - 1 ? q + 1 : 0] : (g.wr ? own : vr);
+        const T ym = ywl ? own : xlo.v[q >> 1];
+        const T yp = ywh ? own : xhi.v[q >> 1];
+        const T zm = hzm ? xb.v[q] : own;
+        const T zp = hzp ? xa.v[q] : own;
+        out.v[q] = gs_value<T>(fx[q], fx[q + 1], fl, fh, fzl.v[q], fzh.v[q], xm, xp, ym, yp, zm, zp, bq.v[q], h2,
+                               own);
+    };
+    if (((j + P + par) & 1) == 0) {
 #pragma unroll
-    for (int t = 1; t < NH; t++) {
-        const int j = g.j0 - 2 + t;
-        const bool has = (j > 0 || d.py) && (j < d.ny || d.py);
+        for (int q = 0; q < 2 * M; q += 2) upd(q);
+    } else {
 #pragma unroll
-        for (int q = 0; q < 2 * M; q++) fy[t][q] = has ? harm(c[t - 1].v[q], c[t].v[q]) : T(0);
+        for (int q = 1; q < 2 * M; q += 2) upd(q);
     }
-#pragma unroll
-    for (int t = 1; t <= R + 2; t++) {
-        const int j = g.j0 - 2 + t;
-        T fx[2 * M + 1];
-        x_faces<T, M>(g, c[t], T(0), fx);
-        T vl, vr;
-        x_edges<T, M>(g, x[t], T(0), vl, vr);
-        const bool ywl = !(j > 0 || d.py), ywh = !(j < d.ny - 1 || d.py);
-        Strip<T, M> out = x[t];
-        auto upd = [&](int q) {
-            const T own = x[t].v[q];
-            const T c4 = hzm ? harm(cb[t - 1 + OB].v[q], c[t].v[q]) : T(0);
-            const T c5 = hzp ? harm(c[t].v[q], ca[t - 1 + OA].v[q]) : T(0);
-            const T xm = q > 0 ? x[t].v[q > 0 ? q - 1 : 0] : (g.wl ? own : vl);
-            const T xp = q < 2 * M - 1 ? x[t].v[q < 2 * M - 1 ? q + 1 : 0] : (g.wr ? own : vr);
-            const T ym = ywl ? own : x[t - 1].v[q];
-            const T yp = ywh ? own : x[t + 1].v[q];
-            const T zm = hzm ? xb[t - 1 + OB].v[q] : own;
-            const T zp = hzp ? xa[t - 1 + OA].v[q] : own;
-            out.v[q] = gs_value<T>(fx[q], fx[q + 1], fy[t][q], fy[t + 1][q], c4, c5, xm, xp, ym, yp, zm, zp,
-                                   bq[t - 1].v[q], h2, own);
-        };
-        if (((j + P) & 1) == 0) {
-#pragma unroll
-            for (int q = 0; q < 2 * M; q += 2) upd(q);
-        } else {
-#pragma unroll
-            for (int q = 1; q < 2 * M; q += 2) upd(q);
-        }
-        x[t] = out;  // rows t+1.. read only black cells of row t
-    }
+    x = out;
 }
 
-// FS_ZERO: the old iterate is zero (not read).  FS_PROLONG: every old value
-// is taken as x + e of its parent coarse cell (ec: coarse correction), i.e.
-// the prolongation is applied on the fly.  IRU (FP32): also phi += irs[0] x.
-template <typename T, int MODE, int M, int R, bool IRU>
-__global__ __launch_bounds__(BK_T) void k_fsw_blk(Dims d, int lz, const T* __restrict__ xo, T* __restrict__ xn,
-                                                  const T* __restrict__ b, const T* __restrict__ cc, T h2,
-                                                  const T* __restrict__ ec, double* __restrict__ phi,
-                                                  const double* __restrict__ irs)
+// Coefficients of the z faces between planes P and P+1 of a row (0 where
+// either side lies beyond a wall).  A cell of plane P takes them as its face
+// above, a cell of plane P+1 as its face below: in the colour passes the same
+// harmonic mean of the same two values.
+template <typename T, int M>
+__device__ __forceinline__ Strip<T, M> z_faces(const Dims& d, int P, const Strip<T, M>& lo, const Strip<T, M>& hi)
 {
-    using S = Strip<T, M>;
-    constexpr bool ZI = MODE == FS_ZERO;
-    constexpr bool EC = MODE == FS_PROLONG;
-    constexpr int NH = R + 4;
-    const BlkGeo g = blk_geo<M, R>(d, lz);
-    if (!g.live) return;
-    const long long sz = (long long)d.nx * d.ny;
-    const int nxc = d.nx >> 1;
-    const long long szc = (long long)nxc * (d.ny >> 1);
-    int rows[NH];
-    long long roff[NH];
+    const bool has = (P >= 0 || d.pz) && (P < d.nz - 1 || d.pz);
+    Strip<T, M> f;
 #pragma unroll
-    for (int t = 0; t < NH; t++) {
-        rows[t] = wrap_row(d, g.j0 - 2 + t);
-        roff[t] = (long long)rows[t] * d.nx;
+    for (int q = 0; q < 2 * M; q++) f.v[q] = has ? harm(lo.v[q], hi.v[q]) : T(0);
+    return f;
+}
+
+// A row of a plane buffer holds the even cells of every lane's strip, then
+// the odd ones: lane l's cells 2e (e < M) at l M + e, its cells 2e + 1 at
+// NX / 2 + l M + e.  A colour reads the cells of one parity of a neighbour
+// row in one access of M consecutive words per lane, free of bank conflicts.
+// (par selects by value: an index computed at run time would move the
+// caller's register slots to scratch memory)
+template <typename T, int M>
+__device__ __forceinline__ void lds_put_half(T* p, const Strip<T, M>& s, int par)
+{
+    T h[M];
+#pragma unroll
+    for (int e = 0; e < M; e++) h[e] = par ? s.v[2 * e + 1] : s.v[2 * e];
+    if constexpr (M == 2) {
+        *reinterpret_cast<typename V2<T>::type*>(p) = typename V2<T>::type{h[0], h[1]};
+    } else {
+#pragma unroll
+        for (int e = 0; e < M; e++) p[e] = h[e];
     }
-    auto ldx = [&](int kk, int t) -> S {
-        if constexpr (ZI) {
+}
+// p: the row's first word plus lane l M.
+template <typename T, int M, int NX>
+__device__ __forceinline__ void lds_put_row(T* p, const Strip<T, M>& s)
+{
+    lds_put_half<T, M>(p, s, 0);
+    lds_put_half<T, M>(p + NX / 2, s, 1);
+}
+template <typename T, int M>
+__device__ __forceinline__ Half<T, M> lds_get_half(const T* p)
+{
+    Half<T, M> h;
+    if constexpr (M == 2) {
+        const typename V2<T>::type v = *reinterpret_cast<const typename V2<T>::type*>(p);
+        h.v[0] = v.x;
+        h.v[1] = v.y;
+    } else {
+#pragma unroll
+        for (int e = 0; e < M; e++) h.v[e] = p[e];
+    }
+    return h;
+}
+
+// Per-wavefront state of the LDS-tiled sweep.  Plane p of the chunk lives in
+// register slot (p - z0 + 2) mod NS of x, c and b, so that a plane step
+// names its planes by compile-time slots and no values move between
+// registers (a move would wait for the prefetch in flight).  The x faces of
+// a plane and the z faces above it are computed once, for its red update,
+// and kept for the black update of the same plane and the red update of the
+// next (slots of fx and fz).
+template <typename T, int M, int NS>
+struct FsCol {
+    Strip<T, M> x[NS], c[NS], b[NS], fz[NS];
+    T fx[NS][2 * M + 1];
+};
+
+template <typename T, int MODE, int M, int R, int D, bool IRU>
+struct FsLds {
+    static constexpr int NW = R + 4, NX = 128 * M, NS = D + 4;
+    static_assert(D >= 0 && D <= 3, "the plane loop is unrolled for at most 7 slots");
+    using S = Strip<T, M>;
+    using H = Half<T, M>;
+    const Dims& d;
+    const BlkGeo& g;
+    int j, jw;
+    bool red_row, black_row;
+    long long sz, roff;
+    int nxc;
+    long long szc;
+    int so;
+    const T* __restrict__ xo;
+    T* __restrict__ xn;
+    const T* __restrict__ b;
+    const T* __restrict__ cc;
+    const T* __restrict__ ec;
+    double* __restrict__ phi;
+    const double* __restrict__ irs;
+    T h2;
+    T (*sx)[NW * NX];
+    T (*sc)[NW * NX];
+
+    __device__ __forceinline__ S ldx(int kk) const
+    {
+        if constexpr (MODE == FS_ZERO) {
             return zero_strip<T, M>();
         } else {
-            S v = ld_strip<T, M>(xo, (long long)kk * sz + roff[t] + g.xi);
-            if constexpr (EC) {
-                const long long o = (long long)(kk >> 1) * szc + (long long)(rows[t] >> 1) * nxc + (g.xi >> 1);
+            S v = ld_strip<T, M>(xo, (long long)kk * sz + roff);
+            if constexpr (MODE == FS_PROLONG) {
+                const long long o = (long long)(kk >> 1) * szc + (long long)(jw >> 1) * nxc + (g.xi >> 1);
 #pragma unroll
                 for (int q = 0; q < 2 * M; q++) v.v[q] = v.v[q] + ec[o + (q >> 1)];
             }
             return v;
         }
-    };
-    auto ldc = [&](int kk, int t) -> S { return ld_strip<T, M>(cc, (long long)kk * sz + roff[t] + g.xi); };
-    auto ldb = [&](int kk, int t) -> S { return ld_strip<T, M>(b, (long long)kk * sz + roff[t] + g.xi); };
-
-    // ---- prologue: red on planes z0-1 and z0
-    S xC[R], cC[R], xB[R + 2], cB[R + 2], bB[R], xA[NH], cA[NH];
-    {
-        const int pm2 = wrap_plane(d, g.z0 - 2), pm1 = wrap_plane(d, g.z0 - 1), p0 = g.z0,
-                  p1 = wrap_plane(d, g.z0 + 1);
-        S x2[R + 2], c2[R + 2], x1[NH], c1[NH], b1[R + 2], x0[NH], c0[NH], b0[R + 2];
-#pragma unroll
-        for (int t = 0; t < R + 2; t++) {
-            x2[t] = ldx(pm2, t + 1);
-            c2[t] = ldc(pm2, t + 1);
-            b1[t] = ldb(pm1, t + 1);
-            b0[t] = ldb(p0, t + 1);
-        }
-#pragma unroll
-        for (int t = 0; t < NH; t++) {
-            x1[t] = ldx(pm1, t);
-            c1[t] = ldc(pm1, t);
-            x0[t] = ldx(p0, t);
-            c0[t] = ldc(p0, t);
-            xA[t] = ldx(p1, t);
-            cA[t] = ldc(p1, t);
-        }
-        fs_red<T, M, R, 0, R + 2, 1, NH>(d, g, g.z0 - 1, h2, x1, c1, x2, c2, x0, c0, b1);
-        fs_red<T, M, R, 1, NH, 1, NH>(d, g, g.z0, h2, x0, c0, x1, c1, xA, cA, b0);
-#pragma unroll
-        for (int t = 0; t < R; t++) {
-            xC[t] = x1[t + 2];
-            cC[t] = c1[t + 2];
-            bB[t] = b0[t + 1];
-        }
-#pragma unroll
-        for (int t = 0; t < R + 2; t++) {
-            xB[t] = x0[t + 1];
-            cB[t] = c0[t + 1];
-        }
     }
+    __device__ __forceinline__ S ldc(int kk) const { return ld_strip<T, M>(cc, (long long)kk * sz + roff); }
+    __device__ __forceinline__ S ldb(int kk) const { return ld_strip<T, M>(b, (long long)kk * sz + roff); }
 
-    for (int k = g.z0; k < g.z1; k++) {
-        const int k1 = wrap_plane(d, k + 1), k2 = wrap_plane(d, k + 2);
-        S xD[NH], cD[NH], bA[R + 2];
-#pragma unroll
-        for (int t = 0; t < NH; t++) {
-            xD[t] = ldx(k2, t);
-            cD[t] = ldc(k2, t);
+    // Plane step k; P0 is the slot of plane k.  i0, i1: LDS buffers of planes
+    // k and k+1.
+    template <int P0>
+    __device__ __forceinline__ void step(FsCol<T, M, NS>& s, int k, int i0, int i1) const
+    {
+        constexpr int PM = (P0 + NS - 1) % NS, P1 = (P0 + 1) % NS, P2 = (P0 + 2) % NS;
+        constexpr int PL = (P0 + 2 + D) % NS, PB = (P0 + 1 + D) % NS;
+        // unconditional loads (the last planes of a chunk load the last
+        // plane it needs again): a skipped load would leave the count of
+        // loads in flight unknown to the compiler, which then waits for all
+        const int pl = wrap_plane(d, min(k + 2 + D, g.z1 + 1));
+        s.x[PL] = ldx(pl);
+        s.c[PL] = ldc(pl);
+        s.b[PB] = ldb(wrap_plane(d, min(k + 1 + D, g.z1)));
+        lds_put_row<T, M, NX>(&sx[i1][so], s.x[P1]);
+        lds_put_row<T, M, NX>(&sc[i1][so], s.c[P1]);
+        __syncthreads();
+        if (red_row) {
+            // red cells of row j on plane k+1: cell q with (q + j + k + 1) even
+            const int ho = ((j + k + 1) & 1) * (NX / 2);
+            x_faces<T, M>(g, s.c[P1], T(0), s.fx[P1]);
+            s.fz[P1] = z_faces<T, M>(d, k + 1, s.c[P1], s.c[P2]);
+            const H xlo = lds_get_half<T, M>(&sx[i1][so + ho - NX]), xhi = lds_get_half<T, M>(&sx[i1][so + ho + NX]);
+            const H clo = lds_get_half<T, M>(&sc[i1][so + ho - NX]), chi = lds_get_half<T, M>(&sc[i1][so + ho + NX]);
+            fs_row<T, M>(d, g, j, k + 1, 0, h2, s.x[P1], xlo, xhi, s.x[P0], s.x[P2], s.fx[P1], s.c[P1], clo, chi,
+                         s.fz[P0], s.fz[P1], s.b[P1]);
+            // only the red half changed
+            lds_put_half<T, M>(&sx[i1][so + ho], s.x[P1], (j + k + 1) & 1);
         }
-#pragma unroll
-        for (int t = 0; t < R + 2; t++) bA[t] = ldb(k1, t + 1);
-        // red on plane k+1 (old black of planes k, k+1, k+2)
-        fs_red<T, M, R, 0, R + 2, 1, NH>(d, g, k + 1, h2, xA, cA, xB, cB, xD, cD, bA);
-        // black on plane k (new red of planes k-1, k, k+1)
-        const bool hzm = k > 0 || d.pz, hzp = k < d.nz - 1 || d.pz;
-        const long long bk = (long long)k * sz;
-        T fy[R + 2][2 * M];  // fy[t]: face between rows t-1 and t of xB (row j0-1+t)
-#pragma unroll
-        for (int t = 1; t <= R + 1; t++) {
-            const int j = g.j0 - 1 + t;
-            const bool has = (j > 0 || d.py) && (j < d.ny || d.py);
-#pragma unroll
-            for (int q = 0; q < 2 * M; q++) fy[t][q] = has ? harm(cB[t - 1].v[q], cB[t].v[q]) : T(0);
-        }
-#pragma unroll
-        for (int t = 1; t <= R; t++) {
-            const int j = g.j0 - 1 + t;
-            T fx[2 * M + 1];
-            x_faces<T, M>(g, cB[t], T(0), fx);
-            T vl, vr;
-            x_edges<T, M>(g, xB[t], T(0), vl, vr);
-            const bool ywl = !(j > 0 || d.py), ywh = !(j < d.ny - 1 || d.py);
-            S out = xB[t];
-            auto upd = [&](int q) {
-                const T own = xB[t].v[q];
-                const T c4 = hzm ? harm(cC[t - 1].v[q], cB[t].v[q]) : T(0);
-                const T c5 = hzp ? harm(cB[t].v[q], cA[t + 1].v[q]) : T(0);
-                const T xm = q > 0 ? xB[t].v[q > 0 ? q - 1 : 0] : (g.wl ? own : vl);
-                const T xp = q < 2 * M - 1 ? xB[t].v[q < 2 * M - 1 ? q + 1 : 0] : (g.wr ? own : vr);
-                const T ym = ywl ? own : xB[t - 1].v[q];
-                const T yp = ywh ? own : xB[t + 1].v[q];
-                const T zm = hzm ? xC[t - 1].v[q] : own;
-                const T zp = hzp ? xA[t + 1].v[q] : own;
-                out.v[q] = gs_value<T>(fx[q], fx[q + 1], fy[t][q], fy[t + 1][q], c4, c5, xm,
-                                       xp, ym, yp, zm, zp, bB[t - 1].v[q], h2, own);
-            };
-            if (((1 + j + k) & 1) == 0) {
-#pragma unroll
-                for (int q = 0; q < 2 * M; q += 2) upd(q);
-            } else {
-#pragma unroll
-                for (int q = 1; q < 2 * M; q += 2) upd(q);
-            }
-            xB[t] = out;
-            st_strip<T, M>(xn, bk + roff[t + 1] + g.xi, out);
+        if (black_row && k >= g.z0) {
+            // black cells of row j on plane k: (q + j + k) odd
+            const int ho = ((j + k + 1) & 1) * (NX / 2);
+            const H xlo = lds_get_half<T, M>(&sx[i0][so + ho - NX]), xhi = lds_get_half<T, M>(&sx[i0][so + ho + NX]);
+            const H clo = lds_get_half<T, M>(&sc[i0][so + ho - NX]), chi = lds_get_half<T, M>(&sc[i0][so + ho + NX]);
+            fs_row<T, M>(d, g, j, k, 1, h2, s.x[P0], xlo, xhi, s.x[PM], s.x[P1], s.fx[P0], s.c[P0], clo, chi,
+                         s.fz[PM], s.fz[P0], s.b[P0]);
+            const long long o = (long long)k * sz + roff;
+            st_strip<T, M>(xn, o, s.x[P0]);
             if constexpr (IRU) {
-                const double sc = irs[0];
-                double* pp = phi + bk + roff[t + 1] + g.xi;
+                const double sc0 = irs[0];
+                double* pp = phi + o;
 #pragma unroll
                 for (int q = 0; q < M; q++) {
                     const double2 pv = *reinterpret_cast<const double2*>(pp + 2 * q);
-                    *reinterpret_cast<double2*>(pp + 2 * q) = make_double2(fma(sc, (double)out.v[2 * q], pv.x),
-                                                                           fma(sc, (double)out.v[2 * q + 1], pv.y));
+                    *reinterpret_cast<double2*>(pp + 2 * q) = make_double2(fma(sc0, (double)s.x[P0].v[2 * q], pv.x),
+                                                                           fma(sc0, (double)s.x[P0].v[2 * q + 1], pv.y));
                 }
             }
         }
-        // rotate: k-1 <- k (own rows, final), k <- k+1, k+1 <- k+2
+    }
+};
+
+// D: planes loaded ahead of the three a plane step works on (x, c), and of
+// the two it takes b from.
+template <typename T, int MODE, int M, int R, int D, bool IRU>
+__global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const T* __restrict__ xo,
+                                                            T* __restrict__ xn, const T* __restrict__ b,
+                                                            const T* __restrict__ cc, T h2,
+                                                            const T* __restrict__ ec, double* __restrict__ phi,
+                                                            const double* __restrict__ irs)
+{
+    using F = FsLds<T, MODE, M, R, D, IRU>;
+    constexpr int NS = F::NS;
+    __shared__ __align__(16) T sx[3][F::NW * F::NX];
+    __shared__ __align__(16) T sc[3][F::NW * F::NX];
+    unsigned bx, by, bz;
+    blk_tile(bx, by, bz);
+    BlkGeo g;
+    g.lane = threadIdx.x & (kWave - 1);
+    g.xi = 2 * M * g.lane;
+    g.j0 = (int)by * R;
+    g.z0 = (int)bz * lz;
+    g.z1 = min(g.z0 + lz, d.nz);
+    g.hal = false;
+    g.hcol = 0;
+    g.wl = g.xi == 0 && !d.px;
+    g.wr = g.xi + 2 * M == d.nx && !d.px;
+    g.live = true;
+    g.yfirst = g.ylast = true;
+    const int t = threadIdx.x / kWave;  // row of the workgroup
+    F f{d, g};
+    f.j = g.j0 - 2 + t;
+    f.jw = wrap_row(d, f.j);
+    f.red_row = t >= 1 && t <= R + 2;
+    f.black_row = t >= 2 && t <= R + 1 && f.j < d.ny;
+    f.sz = (long long)d.nx * d.ny;
+    f.roff = (long long)f.jw * d.nx + g.xi;
+    f.nxc = d.nx >> 1;
+    f.szc = (long long)f.nxc * (d.ny >> 1);
+    f.so = t * F::NX + M * g.lane;  // the lane's words in row t of a buffer
+    f.xo = xo;
+    f.xn = xn;
+    f.b = b;
+    f.cc = cc;
+    f.ec = ec;
+    f.phi = phi;
+    f.irs = irs;
+    f.h2 = h2;
+    f.sx = sx;
+    f.sc = sc;
+
+    // planes z0-2 .. z0+D+1 (x, c) and z0-1 .. z0+D-2 (b) before the first step
+    const int zs = g.z0 - 2;
+    FsCol<T, M, NS> s;
 #pragma unroll
-        for (int t = 0; t < R; t++) {
-            xC[t] = xB[t + 1];
-            cC[t] = cB[t + 1];
-            bB[t] = bA[t + 1];
-        }
+    for (int q = 0; q < NS; q++) {
+        s.x[q] = s.c[q] = s.b[q] = s.fz[q] = zero_strip<T, M>();
 #pragma unroll
-        for (int t = 0; t < R + 2; t++) {
-            xB[t] = xA[t + 1];
-            cB[t] = cA[t + 1];
-        }
+        for (int e = 0; e <= 2 * M; e++) s.fx[q][e] = T(0);
+    }
 #pragma unroll
-        for (int t = 0; t < NH; t++) {
-            xA[t] = xD[t];
-            cA[t] = cD[t];
+    for (int q = 0; q < D + 2; q++) {
+        const int pl = wrap_plane(d, zs + q);
+        s.x[q] = f.ldx(pl);
+        s.c[q] = f.ldc(pl);
+    }
+#pragma unroll
+    for (int q = 1; q <= D; q++) s.b[q] = f.ldb(wrap_plane(d, zs + q));
+    s.fz[0] = z_faces<T, M>(d, zs, s.c[0], s.c[1]);  // below the first red plane
+    int i0 = 0, i1 = 1;  // LDS buffers of planes k and k+1
+    auto adv = [&]() {
+        i0 = i1;
+        i1 = i1 == 2 ? 0 : i1 + 1;
+    };
+    // whole groups of NS plane steps, then the rest one at a time
+    int k = zs;
+    for (; k + NS <= g.z1; k += NS) {
+        f.template step<0>(s, k, i0, i1);
+        adv();
+        f.template step<1>(s, k + 1, i0, i1);
+        adv();
+        f.template step<2>(s, k + 2, i0, i1);
+        adv();
+        f.template step<3>(s, k + 3, i0, i1);
+        adv();
+        if constexpr (NS > 4) {
+            f.template step<4 % NS>(s, k + 4, i0, i1);
+            adv();
         }
+        if constexpr (NS > 5) {
+            f.template step<5 % NS>(s, k + 5, i0, i1);
+            adv();
+        }
+        if constexpr (NS > 6) {
+            f.template step<6 % NS>(s, k + 6, i0, i1);
+            adv();
+        }
+    }
+    if (k < g.z1) f.template step<0>(s, k, i0, i1);
+    adv();
+    if (k + 1 < g.z1) f.template step<1>(s, k + 1, i0, i1);
+    adv();
+    if (k + 2 < g.z1) f.template step<2>(s, k + 2, i0, i1);
+    adv();
+    if constexpr (NS > 4) {
+        if (k + 3 < g.z1) f.template step<3 % NS>(s, k + 3, i0, i1);
+        adv();
+    }
+    if constexpr (NS > 5) {
+        if (k + 4 < g.z1) f.template step<4 % NS>(s, k + 4, i0, i1);
+        adv();
+    }
+    if constexpr (NS > 6) {
+        if (k + 5 < g.z1) f.template step<5 % NS>(s, k + 5, i0, i1);
+        adv();
     }
 }
 
-// Rows per wavefront: 2 for pairs, 1 for strips of 4 (register budget).
-template <int M>
-constexpr int fsw_rows()
+// Rows owned by a workgroup, and planes loaded ahead.
+constexpr int kFswRows = 8;
+constexpr int kFswAhead = 1;
+
+// Planes per chunk: the shortest chunk for which the whole grid is resident at
+// once (workgroups per CU from the kernel's occupancy), lengthened until its
+// plane steps (lz + 2) are whole groups of the unrolled plane loop.  A second
+// round of workgroups would double the time of the few that run in it.
+template <typename T, int MODE, int M, bool IRU>
+static int fsw_chunk(const Dims& d, long long gy)
 {
-    return M == 1 ? 2 : 1;
+    constexpr int NS = kFswAhead + 4;
+    static int resident = 0;  // workgroups resident on the device at once
+    if (resident == 0) {
+        int dev = 0, ncu = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(k_fsw_lds<T, MODE, M, kFswRows, kFswAhead, IRU>),
+                kWave * (kFswRows + 4), 0) != hipSuccess)
+            return 16;
+        resident = max(1, ncu * max(per_cu, 1));
+    }
+    const long long chunks = max(1LL, resident / gy);
+    int lz = (int)((d.nz + chunks - 1) / chunks);
+    lz += (NS - (lz + 2) % NS) % NS;
+    return lz;
 }
 
 template <typename T, int MODE, int M, bool IRU>
 static void fsw_launch(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, T h2, const T* ec, double* phi,
                        const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
 {
-    constexpr int R = fsw_rows<M>();
-    int lz;
-    const dim3 grid = blk_grid(d, M, R, kBlkMinBlocks, 1LL << 30, lz);
+    constexpr int R = kFswRows;
+    const long long gy = (d.ny + R - 1) / R;
+    const int lz = fsw_chunk<T, MODE, M, IRU>(d, gy);
+    const dim3 grid(1, (unsigned)gy, (unsigned)((d.nz + lz - 1) / lz));
+    const dim3 block(kWave * (R + 4));
     if (ev0)
-        hipExtLaunchKernelGGL((k_fsw_blk<T, MODE, M, R, IRU>), grid, dim3(BK_T), 0, s, ev0, ev1, 0, d, lz, xo, xn, b,
-                              cc, h2, ec, phi, irs);
+        hipExtLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, kFswAhead, IRU>), grid, block, 0, s, ev0, ev1, 0, d, lz, xo,
+                              xn, b, cc, h2, ec, phi, irs);
     else
-        hipLaunchKernelGGL((k_fsw_blk<T, MODE, M, R, IRU>), grid, dim3(BK_T), 0, s, d, lz, xo, xn, b, cc, h2, ec, phi,
-                           irs);
+        hipLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, kFswAhead, IRU>), grid, block, 0, s, d, lz, xo, xn, b, cc, h2,
+                           ec, phi, irs);
 }
 
 template <typename T, int M>
 static void fsw_mode(int mode, const Dims& d, const T* xo, T* xn, const T* b, const T* cc, T h2, const T* ec,
                      double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
 {
-    if constexpr (sizeof(T) == 4) {
-        if (phi) {
-            // the refinement update rides on the last sweep of a V-cycle
-            if (mode == FS_PROLONG)
-                fsw_launch<T, FS_PROLONG, M, true>(d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s);
-            else
-                fsw_launch<T, FS_PLAIN, M, true>(d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s);
-            return;
-        }
+    if (phi) {
+        // the refinement update rides on the last sweep of a V-cycle
+        if (mode == FS_PROLONG)
+            fsw_launch<T, FS_PROLONG, M, true>(d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s);
+        else
+            fsw_launch<T, FS_PLAIN, M, true>(d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s);
+        return;
     }
     switch (mode) {
     case FS_ZERO: fsw_launch<T, FS_ZERO, M, false>(d, xo, xn, b, cc, h2, ec, nullptr, nullptr, ev0, ev1, s); break;

@@ -925,6 +925,7 @@ void finish_timing(mp_ctx* c, mp_info* info)
         info->smooth_launches = cnt;
         info->smooth_bytes = bytes;
     }
+    info->smooth_form = c->lv[0].fsw ? 1 : 0;
 }
 
 void reset_info(mp_info* info)
@@ -1078,10 +1079,9 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
             c->coarse_start = lc;
         }
         c->lv[0].blk = cfg->blocked && nlev >= 2 && mp::blk_supported(c->d0);
-        // the one-pass sweep recomputes halo rows and keeps four planes in
-        // registers; on gfx950 two colour passes are faster, so it runs on
-        // request only
-        c->lv[0].fsw = c->lv[0].blk && mx && mp::fsw_supported(c->d0) && cfg->smoother == MP_SMOOTH_FUSED;
+        // both colours of a finest-level sweep in one pass (half the bytes of
+        // two colour passes; bitwise the same), unless colour passes are asked for
+        c->lv[0].fsw = c->lv[0].blk && mx && mp::fsw_supported(c->d0) && cfg->smoother != MP_SMOOTH_PER_COLOUR;
         if (c->lv[0].fsw) {
             void* p = nullptr;
             e = hipMalloc(&p, tsz * c->n0);

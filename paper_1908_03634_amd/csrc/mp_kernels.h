@@ -177,7 +177,8 @@ template <typename T>
 void launch_gs_blk(const Dims& d, T* x, const T* b, const T* cc, T h2, int colour, int mode, const T* ec,
                    double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
 // Both colours of one red-black sweep in one pass, out of place (xo -> xn),
-// in FP32 when fsw_supported(d) (blocked layout, nx = 128 or 256).  Modes:
+// in FP32 when fsw_supported(d) (blocked layout, nx = 128 or 256; whole rows
+// per wavefront, rows exchanged through LDS).  Modes:
 //   FS_PLAIN:   xo as stored;
 //   FS_ZERO:    xo is zero (not read);
 //   FS_PROLONG: xo + e of each cell's parent coarse cell (ec), i.e. the

@@ -76,6 +76,7 @@ class Info(ctypes.Structure):
         ("smooth_ms_total", ctypes.c_double),
         ("smooth_launches", ctypes.c_int),
         ("smooth_bytes", ctypes.c_double),
+        ("smooth_form", ctypes.c_int),
         ("flags", ctypes.c_int),
     ]
 
@@ -85,7 +86,8 @@ class Info(ctypes.Structure):
                     rel_resid=self.rel_resid, div_defect=self.div_defect, rhs_norm=self.rhs_norm,
                     rhs_mean=self.rhs_mean, resid_hist=list(self.resid_hist[:n]), ms_rhs=self.ms_rhs,
                     ms_solve=self.ms_solve, ms_correct=self.ms_correct, smooth_ms_total=self.smooth_ms_total,
-                    smooth_launches=self.smooth_launches, smooth_bytes=self.smooth_bytes, flags=self.flags)
+                    smooth_launches=self.smooth_launches, smooth_bytes=self.smooth_bytes,
+                    smooth_form=self.smooth_form, flags=self.flags)
 
 
 # Every exported symbol of include/mproj.h.
