@@ -47,11 +47,16 @@ struct Half {
 };
 
 // One colour (par 0: red, 1: black) of row j of plane P, in place in x.
-// xlo/xhi, clo/chi: the cells of the colour's parity in rows j-1 and j+1 of
-// plane P (the update of cell q reads element q / 2); xb and xa: this row on
-// planes P-1 and P+1.  fx: the x faces of the row (x_faces); fzl and fzh: its
-// z faces below and above (z_faces of planes P-1 and P).
-template <typename T, int M>
+// xlo/xhi: the cells of the colour's parity in rows j-1 and j+1 of plane P
+// (the update of cell q reads element q / 2); xb and xa: this row on planes
+// P-1 and P+1; fx: the x faces of the row.
+// CELL (cell coefficients): c is the row's coefficients, clo/chi those of
+// rows j-1 and j+1 (colour parity), fzl/fzh the z faces below and above
+// (z_faces of planes P-1 and P).
+// Stored faces: c is the row's low y faces, chi the low y faces of row j+1
+// (colour parity), fzl/fzh the low z faces of planes P and P+1; a high face
+// across a wall is 0 (fyh, zh), the low faces are taken as stored.
+template <typename T, int M, bool CELL>
 __device__ __forceinline__ void fs_row(const Dims& d, const BlkGeo& g, int j, int P, int par, T h2, Strip<T, M>& x,
                                        const Half<T, M>& xlo, const Half<T, M>& xhi, const Strip<T, M>& xb,
                                        const Strip<T, M>& xa, const T (&fx)[2 * M + 1], const Strip<T, M>& c,
@@ -67,16 +72,23 @@ __device__ __forceinline__ void fs_row(const Dims& d, const BlkGeo& g, int j, in
     Strip<T, M> out = x;
     auto upd = [&](int q) {
         const T own = x.v[q];
-        const T fl = fyl ? harm(clo.v[q >> 1], c.v[q]) : T(0);
-        const T fh = fyh ? harm(c.v[q], chi.v[q >> 1]) : T(0);
+        T fl, fh, c5;
+        if constexpr (CELL) {
+            fl = fyl ? harm(clo.v[q >> 1], c.v[q]) : T(0);
+            fh = fyh ? harm(c.v[q], chi.v[q >> 1]) : T(0);
+            c5 = fzh.v[q];
+        } else {
+            fl = c.v[q];
+            fh = fyh ? chi.v[q >> 1] : T(0);
+            c5 = hzp ? fzh.v[q] : T(0);
+        }
         const T xm = q > 0 ? x.v[q > 0 ? q - 1 : 0] : (g.wl ? own : vl);
         const T xp = q < 2 * M - 1 ? x.v[q < 2 * M - 1 ? q + 1 : 0] : (g.wr ? own : vr);
         const T ym = ywl ? own : xlo.v[q >> 1];
         const T yp = ywh ? own : xhi.v[q >> 1];
         const T zm = hzm ? xb.v[q] : own;
         const T zp = hzp ? xa.v[q] : own;
-        out.v[q] = gs_value<T>(fx[q], fx[q + 1], fl, fh, fzl.v[q], fzh.v[q], xm, xp, ym, yp, zm, zp, bq.v[q], h2,
-                               own);
+        out.v[q] = gs_value<T>(fx[q], fx[q + 1], fl, fh, fzl.v[q], c5, xm, xp, ym, yp, zm, zp, bq.v[q], h2, own);
     };
     if (((j + P + par) & 1) == 0) {
 #pragma unroll
@@ -86,6 +98,17 @@ __device__ __forceinline__ void fs_row(const Dims& d, const BlkGeo& g, int j, in
         for (int q = 1; q < 2 * M; q += 2) upd(q);
     }
     x = out;
+}
+
+// x faces of a row from its stored low x faces: the face above the strip's
+// last cell is the next strip's first (0 at a wall).  All lanes must call (DPP).
+template <typename T, int M>
+__device__ __forceinline__ void x_faces_stored(const BlkGeo& g, const Strip<T, M>& cx, T (&f)[2 * M + 1])
+{
+    const T nr = from_next(cx.v[0]);
+#pragma unroll
+    for (int q = 0; q < 2 * M; q++) f[q] = cx.v[q];
+    f[2 * M] = g.wr ? T(0) : nr;
 }
 
 // Coefficients of the z faces between planes P and P+1 of a row (0 where
@@ -150,13 +173,14 @@ __device__ __forceinline__ Half<T, M> lds_get_half(const T* p)
 // a plane and the z faces above it are computed once, for its red update,
 // and kept for the black update of the same plane and the red update of the
 // next (slots of fx and fz).
+// With stored faces, c holds the low y faces and cx, cz the low x and z faces.
 template <typename T, int M, int NS>
 struct FsCol {
-    Strip<T, M> x[NS], c[NS], b[NS], fz[NS];
+    Strip<T, M> x[NS], c[NS], b[NS], fz[NS], cx[NS], cz[NS];
     T fx[NS][2 * M + 1];
 };
 
-template <typename T, int MODE, int M, int R, int D, bool IRU>
+template <typename T, int MODE, int M, int R, int D, bool IRU, bool CELL>
 struct FsLds {
     static constexpr int NW = R + 4, NX = 128 * M, NS = D + 4;
     static_assert(D >= 0 && D <= 3, "the plane loop is unrolled for at most 7 slots");
@@ -173,7 +197,9 @@ struct FsLds {
     const T* __restrict__ xo;
     T* __restrict__ xn;
     const T* __restrict__ b;
-    const T* __restrict__ cc;
+    const T* __restrict__ cc;  // cell coefficients, or the low y faces
+    const T* __restrict__ cxa;  // low x and z faces (stored faces only)
+    const T* __restrict__ cza;
     const T* __restrict__ ec;
     double* __restrict__ phi;
     const double* __restrict__ irs;
@@ -197,6 +223,17 @@ struct FsLds {
     }
     __device__ __forceinline__ S ldc(int kk) const { return ld_strip<T, M>(cc, (long long)kk * sz + roff); }
     __device__ __forceinline__ S ldb(int kk) const { return ld_strip<T, M>(b, (long long)kk * sz + roff); }
+    // everything of plane kk a plane step needs, into slot Q
+    template <int Q>
+    __device__ __forceinline__ void ld_plane(FsCol<T, M, NS>& s, int kk) const
+    {
+        s.x[Q] = ldx(kk);
+        s.c[Q] = ldc(kk);
+        if constexpr (!CELL) {
+            s.cx[Q] = ld_strip<T, M>(cxa, (long long)kk * sz + roff);
+            s.cz[Q] = ld_strip<T, M>(cza, (long long)kk * sz + roff);
+        }
+    }
 
     // Plane step k; P0 is the slot of plane k.  i0, i1: LDS buffers of planes
     // k and k+1.
@@ -208,9 +245,7 @@ struct FsLds {
         // unconditional loads (the last planes of a chunk load the last
         // plane it needs again): a skipped load would leave the count of
         // loads in flight unknown to the compiler, which then waits for all
-        const int pl = wrap_plane(d, min(k + 2 + D, g.z1 + 1));
-        s.x[PL] = ldx(pl);
-        s.c[PL] = ldc(pl);
+        ld_plane<PL>(s, wrap_plane(d, min(k + 2 + D, g.z1 + 1)));
         s.b[PB] = ldb(wrap_plane(d, min(k + 1 + D, g.z1)));
         lds_put_row<T, M, NX>(&sx[i1][so], s.x[P1]);
         lds_put_row<T, M, NX>(&sc[i1][so], s.c[P1]);
@@ -218,12 +253,17 @@ struct FsLds {
         if (red_row) {
             // red cells of row j on plane k+1: cell q with (q + j + k + 1) even
             const int ho = ((j + k + 1) & 1) * (NX / 2);
-            x_faces<T, M>(g, s.c[P1], T(0), s.fx[P1]);
-            s.fz[P1] = z_faces<T, M>(d, k + 1, s.c[P1], s.c[P2]);
+            if constexpr (CELL) {
+                x_faces<T, M>(g, s.c[P1], T(0), s.fx[P1]);
+                s.fz[P1] = z_faces<T, M>(d, k + 1, s.c[P1], s.c[P2]);
+            } else {
+                x_faces_stored<T, M>(g, s.cx[P1], s.fx[P1]);
+            }
             const H xlo = lds_get_half<T, M>(&sx[i1][so + ho - NX]), xhi = lds_get_half<T, M>(&sx[i1][so + ho + NX]);
-            const H clo = lds_get_half<T, M>(&sc[i1][so + ho - NX]), chi = lds_get_half<T, M>(&sc[i1][so + ho + NX]);
-            fs_row<T, M>(d, g, j, k + 1, 0, h2, s.x[P1], xlo, xhi, s.x[P0], s.x[P2], s.fx[P1], s.c[P1], clo, chi,
-                         s.fz[P0], s.fz[P1], s.b[P1]);
+            const H clo = CELL ? lds_get_half<T, M>(&sc[i1][so + ho - NX]) : H{};
+            const H chi = lds_get_half<T, M>(&sc[i1][so + ho + NX]);
+            fs_row<T, M, CELL>(d, g, j, k + 1, 0, h2, s.x[P1], xlo, xhi, s.x[P0], s.x[P2], s.fx[P1], s.c[P1], clo,
+                               chi, CELL ? s.fz[P0] : s.cz[P1], CELL ? s.fz[P1] : s.cz[P2], s.b[P1]);
             // only the red half changed
             lds_put_half<T, M>(&sx[i1][so + ho], s.x[P1], (j + k + 1) & 1);
         }
@@ -231,9 +271,10 @@ struct FsLds {
             // black cells of row j on plane k: (q + j + k) odd
             const int ho = ((j + k + 1) & 1) * (NX / 2);
             const H xlo = lds_get_half<T, M>(&sx[i0][so + ho - NX]), xhi = lds_get_half<T, M>(&sx[i0][so + ho + NX]);
-            const H clo = lds_get_half<T, M>(&sc[i0][so + ho - NX]), chi = lds_get_half<T, M>(&sc[i0][so + ho + NX]);
-            fs_row<T, M>(d, g, j, k, 1, h2, s.x[P0], xlo, xhi, s.x[PM], s.x[P1], s.fx[P0], s.c[P0], clo, chi,
-                         s.fz[PM], s.fz[P0], s.b[P0]);
+            const H clo = CELL ? lds_get_half<T, M>(&sc[i0][so + ho - NX]) : H{};
+            const H chi = lds_get_half<T, M>(&sc[i0][so + ho + NX]);
+            fs_row<T, M, CELL>(d, g, j, k, 1, h2, s.x[P0], xlo, xhi, s.x[PM], s.x[P1], s.fx[P0], s.c[P0], clo, chi,
+                               CELL ? s.fz[PM] : s.cz[P0], CELL ? s.fz[P0] : s.cz[P1], s.b[P0]);
             const long long o = (long long)k * sz + roff;
             st_strip<T, M>(xn, o, s.x[P0]);
             if constexpr (IRU) {
@@ -252,14 +293,17 @@ struct FsLds {
 
 // D: planes loaded ahead of the three a plane step works on (x, c), and of
 // the two it takes b from.
-template <typename T, int MODE, int M, int R, int D, bool IRU>
+// CELL: cc holds cell coefficients; otherwise cc, cxa, cza hold the low y,
+// x and z faces.
+template <typename T, int MODE, int M, int R, int D, bool IRU, bool CELL>
 __global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const T* __restrict__ xo,
                                                             T* __restrict__ xn, const T* __restrict__ b,
-                                                            const T* __restrict__ cc, T h2,
+                                                            const T* __restrict__ cc, const T* __restrict__ cxa,
+                                                            const T* __restrict__ cza, T h2,
                                                             const T* __restrict__ ec, double* __restrict__ phi,
                                                             const double* __restrict__ irs)
 {
-    using F = FsLds<T, MODE, M, R, D, IRU>;
+    using F = FsLds<T, MODE, M, R, D, IRU, CELL>;
     constexpr int NS = F::NS;
     __shared__ __align__(16) T sx[3][F::NW * F::NX];
     __shared__ __align__(16) T sc[3][F::NW * F::NX];
@@ -292,6 +336,8 @@ __global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const
     f.xn = xn;
     f.b = b;
     f.cc = cc;
+    f.cxa = cxa;
+    f.cza = cza;
     f.ec = ec;
     f.phi = phi;
     f.irs = irs;
@@ -299,24 +345,24 @@ __global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const
     f.sx = sx;
     f.sc = sc;
 
-    // planes z0-2 .. z0+D+1 (x, c) and z0-1 .. z0+D-2 (b) before the first step
+    // planes z0-2 .. z0+D-1 (x and coefficients) and z0-1 .. z0+D-2 (b)
+    // before the first step
     const int zs = g.z0 - 2;
     FsCol<T, M, NS> s;
 #pragma unroll
     for (int q = 0; q < NS; q++) {
-        s.x[q] = s.c[q] = s.b[q] = s.fz[q] = zero_strip<T, M>();
+        s.x[q] = s.c[q] = s.b[q] = s.fz[q] = s.cx[q] = s.cz[q] = zero_strip<T, M>();
 #pragma unroll
         for (int e = 0; e <= 2 * M; e++) s.fx[q][e] = T(0);
     }
-#pragma unroll
-    for (int q = 0; q < D + 2; q++) {
-        const int pl = wrap_plane(d, zs + q);
-        s.x[q] = f.ldx(pl);
-        s.c[q] = f.ldc(pl);
-    }
+    f.template ld_plane<0>(s, wrap_plane(d, zs));
+    f.template ld_plane<1 % NS>(s, wrap_plane(d, zs + 1));
+    if constexpr (D >= 1) f.template ld_plane<2 % NS>(s, wrap_plane(d, zs + 2));
+    if constexpr (D >= 2) f.template ld_plane<3 % NS>(s, wrap_plane(d, zs + 3));
+    if constexpr (D >= 3) f.template ld_plane<4 % NS>(s, wrap_plane(d, zs + 4));
 #pragma unroll
     for (int q = 1; q <= D; q++) s.b[q] = f.ldb(wrap_plane(d, zs + q));
-    s.fz[0] = z_faces<T, M>(d, zs, s.c[0], s.c[1]);  // below the first red plane
+    if constexpr (CELL) s.fz[0] = z_faces<T, M>(d, zs, s.c[0], s.c[1]);  // below the first red plane
     int i0 = 0, i1 = 1;  // LDS buffers of planes k and k+1
     auto adv = [&]() {
         i0 = i1;
@@ -366,15 +412,18 @@ __global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const
     }
 }
 
-// Rows owned by a workgroup, and planes loaded ahead.
+// Rows owned by a workgroup, planes loaded ahead, and the shortest chunk.
 constexpr int kFswRows = 8;
 constexpr int kFswAhead = 1;
+constexpr int kFswMinPlanes = 8;
 
-// Planes per chunk: the shortest chunk for which the whole grid is resident at
-// once (workgroups per CU from the kernel's occupancy), lengthened until its
-// plane steps (lz + 2) are whole groups of the unrolled plane loop.  A second
-// round of workgroups would double the time of the few that run in it.
-template <typename T, int MODE, int M, bool IRU>
+// Planes per chunk: the shortest chunk (at least kFswMinPlanes, which bounds
+// the share of the four planes a chunk reads beyond its own) for which the
+// whole grid is resident at once (workgroups per CU from the kernel's
+// occupancy), lengthened until its plane steps (lz + 2) are whole groups of
+// the unrolled plane loop.  A second round of workgroups would double the
+// time of the few that run in it.
+template <typename T, int MODE, int M, bool IRU, bool CELL>
 static int fsw_chunk(const Dims& d, long long gy)
 {
     constexpr int NS = kFswAhead + 4;
@@ -384,32 +433,32 @@ static int fsw_chunk(const Dims& d, long long gy)
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(k_fsw_lds<T, MODE, M, kFswRows, kFswAhead, IRU>),
+                &per_cu, reinterpret_cast<const void*>(k_fsw_lds<T, MODE, M, kFswRows, kFswAhead, IRU, CELL>),
                 kWave * (kFswRows + 4), 0) != hipSuccess)
             return 16;
         resident = max(1, ncu * max(per_cu, 1));
     }
     const long long chunks = max(1LL, resident / gy);
-    int lz = (int)((d.nz + chunks - 1) / chunks);
+    int lz = max((int)((d.nz + chunks - 1) / chunks), kFswMinPlanes);
     lz += (NS - (lz + 2) % NS) % NS;
     return lz;
 }
 
-template <typename T, int MODE, int M, bool IRU>
-static void fsw_launch(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, T h2, const T* ec, double* phi,
-                       const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
+template <typename T, int MODE, int M, bool IRU, bool CELL>
+static void fsw_launch(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, const T* cxa, const T* cza, T h2,
+                       const T* ec, double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
 {
     constexpr int R = kFswRows;
     const long long gy = (d.ny + R - 1) / R;
-    const int lz = fsw_chunk<T, MODE, M, IRU>(d, gy);
+    const int lz = fsw_chunk<T, MODE, M, IRU, CELL>(d, gy);
     const dim3 grid(1, (unsigned)gy, (unsigned)((d.nz + lz - 1) / lz));
     const dim3 block(kWave * (R + 4));
     if (ev0)
-        hipExtLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, kFswAhead, IRU>), grid, block, 0, s, ev0, ev1, 0, d, lz, xo,
-                              xn, b, cc, h2, ec, phi, irs);
+        hipExtLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, kFswAhead, IRU, CELL>), grid, block, 0, s, ev0, ev1, 0, d, lz,
+                              xo, xn, b, cc, cxa, cza, h2, ec, phi, irs);
     else
-        hipLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, kFswAhead, IRU>), grid, block, 0, s, d, lz, xo, xn, b, cc, h2,
-                           ec, phi, irs);
+        hipLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, kFswAhead, IRU, CELL>), grid, block, 0, s, d, lz, xo, xn, b, cc,
+                           cxa, cza, h2, ec, phi, irs);
 }
 
 template <typename T, int M>
@@ -419,17 +468,25 @@ static void fsw_mode(int mode, const Dims& d, const T* xo, T* xn, const T* b, co
     if (phi) {
         // the refinement update rides on the last sweep of a V-cycle
         if (mode == FS_PROLONG)
-            fsw_launch<T, FS_PROLONG, M, true>(d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s);
+            fsw_launch<T, FS_PROLONG, M, true, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, phi, irs, ev0, ev1,
+                                                     s);
         else
-            fsw_launch<T, FS_PLAIN, M, true>(d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s);
+            fsw_launch<T, FS_PLAIN, M, true, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, phi, irs, ev0, ev1, s);
         return;
     }
     switch (mode) {
-    case FS_ZERO: fsw_launch<T, FS_ZERO, M, false>(d, xo, xn, b, cc, h2, ec, nullptr, nullptr, ev0, ev1, s); break;
-    case FS_PROLONG:
-        fsw_launch<T, FS_PROLONG, M, false>(d, xo, xn, b, cc, h2, ec, nullptr, nullptr, ev0, ev1, s);
+    case FS_ZERO:
+        fsw_launch<T, FS_ZERO, M, false, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, nullptr, nullptr, ev0, ev1,
+                                               s);
         break;
-    default: fsw_launch<T, FS_PLAIN, M, false>(d, xo, xn, b, cc, h2, ec, nullptr, nullptr, ev0, ev1, s); break;
+    case FS_PROLONG:
+        fsw_launch<T, FS_PROLONG, M, false, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, nullptr, nullptr, ev0,
+                                                  ev1, s);
+        break;
+    default:
+        fsw_launch<T, FS_PLAIN, M, false, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, nullptr, nullptr, ev0, ev1,
+                                                s);
+        break;
     }
 }
 
@@ -441,7 +498,37 @@ void launch_fsw_blk(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, 
     else fsw_mode<T, 1>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s);
 }
 
+template <typename T, int M>
+static void fswf_mode(int mode, const Dims& d, const T* xo, T* xn, const T* b, const Coef<T>& c, T h2, const T* ec,
+                      hipStream_t s)
+{
+    switch (mode) {
+    case FS_ZERO:
+        fsw_launch<T, FS_ZERO, M, false, false>(d, xo, xn, b, c.y, c.x, c.z, h2, ec, nullptr, nullptr, nullptr,
+                                                nullptr, s);
+        break;
+    case FS_PROLONG:
+        fsw_launch<T, FS_PROLONG, M, false, false>(d, xo, xn, b, c.y, c.x, c.z, h2, ec, nullptr, nullptr, nullptr,
+                                                   nullptr, s);
+        break;
+    default:
+        fsw_launch<T, FS_PLAIN, M, false, false>(d, xo, xn, b, c.y, c.x, c.z, h2, ec, nullptr, nullptr, nullptr,
+                                                 nullptr, s);
+        break;
+    }
+}
+
+template <typename T>
+void launch_fsw_blkf(const Dims& d, const T* xo, T* xn, const T* b, const Coef<T>& c, T h2, int mode, const T* ec,
+                     hipStream_t s)
+{
+    if (d.nx == 256) fswf_mode<T, 2>(mode, d, xo, xn, b, c, h2, ec, s);
+    else fswf_mode<T, 1>(mode, d, xo, xn, b, c, h2, ec, s);
+}
+
 template void launch_fsw_blk<float>(const Dims&, const float*, float*, const float*, const float*, float, int,
                                     const float*, double*, const double*, hipEvent_t, hipEvent_t, hipStream_t);
+template void launch_fsw_blkf<float>(const Dims&, const float*, float*, const float*, const Coef<float>&, float, int,
+                                     const float*, hipStream_t);
 
 }  // namespace mp

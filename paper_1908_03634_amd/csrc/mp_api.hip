@@ -376,6 +376,18 @@ void smooth(mp_ctx* c, int l, bool zero_init, const T* ec, bool last = false)
     const bool tm = c->cfg.kernel_timing && l == 0;
     const double cells = (double)L.d.n();
     const mp::Coef<T> C = level_coef<T>(c, l);
+    if (use_blkf(c, l) && L.fsw) {
+        // both colours in one pass, out of place: x read (not when zero) and
+        // written, b and the three faces read; 1/8 word of coarse correction
+        const double words = (zero_init ? 5.0 : 6.0) + (ec ? 0.125 : 0.0);
+        timed_begin(c, tm);
+        if constexpr (sizeof(T) == 4)
+            mp::launch_fsw_blkf<T>(L.d, (const T*)L.x, (T*)L.x2, (const T*)L.b, C, h2,
+                                   zero_init ? mp::FS_ZERO : ec ? mp::FS_PROLONG : mp::FS_PLAIN, ec, c->stream);
+        timed_end(c, tm, words * sizeof(T) * cells);
+        std::swap(L.x, L.x2);
+        return;
+    }
     if (use_blkf(c, l)) {
         for (int colour = 0; colour < 2; colour++) {
             const bool zi = zero_init && colour == 0;
@@ -1094,10 +1106,12 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
             if (c->coarse_start >= 0 && l >= c->coarse_start) break;
             // FP32 levels only: the FP64 variants need too many registers
             L.blkf = cfg->blocked && mx && mp::blk_supported(L.d);
+            // both colours of a sweep in one pass where rows are 128 or 256 cells
+            if (l > 0) L.fsw = L.blkf && mp::fsw_supported(L.d) && cfg->smoother != MP_SMOOTH_PER_COLOUR;
             L.fused = !L.blkf && mp::sweep_supported(L.d) &&
                       (cfg->smoother == MP_SMOOTH_FUSED ||
                        (cfg->smoother == MP_SMOOTH_AUTO && L.d.n() >= kFusedMinCells));
-            if (L.fused) {
+            if (L.fused || (l > 0 && L.fsw)) {
                 void* p = nullptr;
                 e = hipMalloc(&p, tsz * L.d.n());
                 good &= e == hipSuccess;

@@ -190,6 +190,11 @@ bool fsw_supported(const Dims& d);
 template <typename T>
 void launch_fsw_blk(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, T h2, int mode, const T* ec,
                     double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
+// The same sweep on a level with stored low-face coefficients c (FP32; equal
+// bit for bit to two launch_gs_blkf colour passes).
+template <typename T>
+void launch_fsw_blkf(const Dims& d, const T* xo, T* xn, const T* b, const Coef<T>& c, T h2, int mode, const T* ec,
+                     hipStream_t s);
 // The same two kernels on a level with stored low-face coefficients c.
 template <typename T>
 void launch_gs_blkf(const Dims& d, T* x, const T* b, const Coef<T>& c, T h2, int colour, int mode, const T* ec,
