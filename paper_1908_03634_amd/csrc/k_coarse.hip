@@ -133,14 +133,36 @@ __device__ void wave_cg(const Dims& d, const T* __restrict__ bin, T* __restrict_
         if (live[u]) xout[lane + kWave * u] = (T)(x[u] - xm);
 }
 
+// Quotient by a divisor fixed for a loop: q = (e * m) >> 32 with
+// m = ceil(2^32 / d), exact whenever e * d < 2^32 (the levels of the coarse
+// cycle hold at most 4096 cells), in place of the generic integer division.
+// (ceil(2^32 / d) = floor((2^32 - 1) / d) + 1 for d >= 2, a 32-bit division
+// once per loop; d = 1 divides by itself.)
+struct FastDiv {
+    unsigned m, d;
+    __device__ __forceinline__ explicit FastDiv(unsigned dv) : m(dv > 1 ? 0xFFFFFFFFu / dv + 1u : 0u), d(dv) {}
+    __device__ __forceinline__ unsigned div(unsigned e) const { return d > 1 ? __umulhi(e, m) : e; }
+};
+
+// (a, b, c) of e = a + na (b + nb c).
+__device__ __forceinline__ void split3(unsigned e, const FastDiv& na, const FastDiv& nb, int& a, int& b, int& c)
+{
+    const unsigned t = na.div(e), u = nb.div(t);
+    a = (int)(e - t * na.d);
+    b = (int)(t - u * nb.d);
+    c = (int)u;
+}
+
 template <typename T>
 __device__ void cg_smooth(const CoarseLevel<T>& L, const Dims& d, int zero_init)
 {
     const int nxh = (d.nx + 1) / 2;
     const int cnt = nxh * d.ny * d.nz;
+    const FastDiv fa((unsigned)nxh), fb((unsigned)d.ny);
     for (int colour = 0; colour < 2; colour++) {
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-            const int p = e % nxh, t = e / nxh, j = t % d.ny, k = t / d.ny;
+            int p, j, k;
+            split3((unsigned)e, fa, fb, p, j, k);
             rbgs_cell<T, false>(d, L.x, L.b, Coef<T>{L.cx, L.cy, L.cz, nullptr}, L.h2, colour,
                                 zero_init && colour == 0, p, j, k);
         }
@@ -240,13 +262,16 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(CoarseArgs<T> a)
         // the order of restrict_cell (the same bits)
         const int nf = (int)f.n();
         const Coef<T> C{L.cx, L.cy, L.cz, nullptr};
+        const FastDiv fx((unsigned)f.nx), fy((unsigned)f.ny), fxc((unsigned)nxc), fyc((unsigned)nyc);
         for (int e = threadIdx.x; e < nf; e += blockDim.x) {
-            const int i = e % f.nx, t = e / f.nx, j = t % f.ny, k = t / f.ny;
+            int i, j, k;
+            split3((unsigned)e, fx, fy, i, j, k);
             rs[e] = resid_cell<T, false>(f, L.x, L.b, C, L.inv_h2, i, j, k);
         }
         __syncthreads();
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-            const int I = e % nxc, t = e / nxc, J = t % nyc, K = t / nyc;
+            int I, J, K;
+            split3((unsigned)e, fxc, fyc, I, J, K);
             T acc = T(0);
 #pragma unroll
             for (int c = 0; c < 2; c++)
@@ -272,8 +297,10 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(CoarseArgs<T> a)
         const int nxc = f.nx / 2, nyc = f.ny / 2;
         const int cnt = f.nx * f.ny * f.nz;
         const T* ec = lds_level(a, l + 1, lds).x;
+        const FastDiv fx((unsigned)f.nx), fy((unsigned)f.ny);
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-            const int i = e % f.nx, t = e / f.nx, j = t % f.ny, k = t / f.ny;
+            int i, j, k;
+            split3((unsigned)e, fx, fy, i, j, k);
             L.x[e] += ec[((k >> 1) * nyc + (j >> 1)) * nxc + (i >> 1)];
         }
         __syncthreads();
