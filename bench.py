@@ -43,6 +43,9 @@ def _parse():
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None, help="time one precision only")
     ap.add_argument("--no-nodal", action="store_true", help="skip the nodal-projection timing")
     ap.add_argument("--nodal-steps", type=int, default=10)
+    ap.add_argument("--smoother", choices=["auto", "per_colour"], default="auto",
+                    help="per_colour: one launch per colour on every level (the default runs both colours of a "
+                         "finest-level sweep in one launch where rows are 128 or 256 cells)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB streaming copy (reference for the HBM traffic counters)")
     return ap.parse_args()
@@ -112,7 +115,8 @@ def main():
     K, Wm = args.steps, args.warmup
 
     def run(precision, steps, warmup):
-        ctx = mproj.Context(p.nx, p.ny, p.nz, h=p.h, bc=p.bc, precision=precision, rtol=1e-10)
+        ctx = mproj.Context(p.nx, p.ny, p.nz, h=p.h, bc=p.bc, precision=precision, rtol=1e-10,
+                            smoother=args.smoother)
         total = steps + warmup
         # every step projects its own copy of the unprojected velocity
         copies = [[u.clone() for u in U0] for _ in range(total)]
