@@ -247,12 +247,24 @@ struct FsLds {
         // loads in flight unknown to the compiler, which then waits for all
         ld_plane<PL>(s, wrap_plane(d, min(k + 2 + D, g.z1 + 1)));
         s.b[PB] = ldb(wrap_plane(d, min(k + 1 + D, g.z1)));
+
         lds_put_row<T, M, NX>(&sx[i1][so], s.x[P1]);
         lds_put_row<T, M, NX>(&sc[i1][so], s.c[P1]);
         __syncthreads();
+        // red cells of row j on plane k+1 and black cells on plane k: cell q
+        // with (q + j + k + 1) even, the same half of a buffer row
+        const int ho = ((j + k + 1) & 1) * (NX / 2);
+        const bool blk = black_row && k >= g.z0;
+        // the black update's neighbour rows first, so that their LDS latency
+        // overlaps the red update (it writes only plane k+1's buffer)
+        H bxlo{}, bxhi{}, bclo{}, bchi{};
+        if (blk) {
+            bxlo = lds_get_half<T, M>(&sx[i0][so + ho - NX]);
+            bxhi = lds_get_half<T, M>(&sx[i0][so + ho + NX]);
+            if constexpr (CELL) bclo = lds_get_half<T, M>(&sc[i0][so + ho - NX]);
+            bchi = lds_get_half<T, M>(&sc[i0][so + ho + NX]);
+        }
         if (red_row) {
-            // red cells of row j on plane k+1: cell q with (q + j + k + 1) even
-            const int ho = ((j + k + 1) & 1) * (NX / 2);
             if constexpr (CELL) {
                 x_faces<T, M>(g, s.c[P1], T(0), s.fx[P1]);
                 s.fz[P1] = z_faces<T, M>(d, k + 1, s.c[P1], s.c[P2]);
@@ -267,14 +279,9 @@ struct FsLds {
             // only the red half changed
             lds_put_half<T, M>(&sx[i1][so + ho], s.x[P1], (j + k + 1) & 1);
         }
-        if (black_row && k >= g.z0) {
-            // black cells of row j on plane k: (q + j + k) odd
-            const int ho = ((j + k + 1) & 1) * (NX / 2);
-            const H xlo = lds_get_half<T, M>(&sx[i0][so + ho - NX]), xhi = lds_get_half<T, M>(&sx[i0][so + ho + NX]);
-            const H clo = CELL ? lds_get_half<T, M>(&sc[i0][so + ho - NX]) : H{};
-            const H chi = lds_get_half<T, M>(&sc[i0][so + ho + NX]);
-            fs_row<T, M, CELL>(d, g, j, k, 1, h2, s.x[P0], xlo, xhi, s.x[PM], s.x[P1], s.fx[P0], s.c[P0], clo, chi,
-                               CELL ? s.fz[PM] : s.cz[P0], CELL ? s.fz[P0] : s.cz[P1], s.b[P0]);
+        if (blk) {
+            fs_row<T, M, CELL>(d, g, j, k, 1, h2, s.x[P0], bxlo, bxhi, s.x[PM], s.x[P1], s.fx[P0], s.c[P0], bclo,
+                               bchi, CELL ? s.fz[PM] : s.cz[P0], CELL ? s.fz[P0] : s.cz[P1], s.b[P0]);
             const long long o = (long long)k * sz + roff;
             st_strip<T, M>(xn, o, s.x[P0]);
             if constexpr (IRU) {
