@@ -133,26 +133,6 @@ __device__ void wave_cg(const Dims& d, const T* __restrict__ bin, T* __restrict_
         if (live[u]) xout[lane + kWave * u] = (T)(x[u] - xm);
 }
 
-// Quotient by a divisor fixed for a loop: q = (e * m) >> 32 with
-// m = ceil(2^32 / d), exact whenever e * d < 2^32 (the levels of the coarse
-// cycle hold at most 4096 cells), in place of the generic integer division.
-// (ceil(2^32 / d) = floor((2^32 - 1) / d) + 1 for d >= 2, a 32-bit division
-// once per loop; d = 1 divides by itself.)
-struct FastDiv {
-    unsigned m, d;
-    __device__ __forceinline__ explicit FastDiv(unsigned dv) : m(dv > 1 ? 0xFFFFFFFFu / dv + 1u : 0u), d(dv) {}
-    __device__ __forceinline__ unsigned div(unsigned e) const { return d > 1 ? __umulhi(e, m) : e; }
-};
-
-// (a, b, c) of e = a + na (b + nb c).
-__device__ __forceinline__ void split3(unsigned e, const FastDiv& na, const FastDiv& nb, int& a, int& b, int& c)
-{
-    const unsigned t = na.div(e), u = nb.div(t);
-    a = (int)(e - t * na.d);
-    b = (int)(t - u * nb.d);
-    c = (int)u;
-}
-
 template <typename T>
 __device__ void cg_smooth(const CoarseLevel<T>& L, const Dims& d, int zero_init)
 {

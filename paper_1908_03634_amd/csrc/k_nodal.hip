@@ -880,8 +880,10 @@ __device__ __forceinline__ void nd_cc_gs(const NDims& d, T* x, const T* b, const
     const int cx = colour & 1, cy = colour >> 1;
     const int ni = (d.mx - cx + 1) / 2, nj = (d.my - cy + 1) / 2;
     const int cnt = ni * nj * d.mz;
+    const FastDiv fi((unsigned)ni), fj((unsigned)nj);
     for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-        const int ti = e % ni, t = e / ni, tj = t % nj, k = t / nj;
+        int ti, tj, k;
+        split3((unsigned)e, fi, fj, ti, tj, k);
         const int i = 2 * ti + cx, j = 2 * tj + cy;
         T ssig, ss;
         node_sums<T>(d, x, sg, i, j, k, ssig, ss);
@@ -920,8 +922,10 @@ __global__ __launch_bounds__(1024) void k_nd_coarse(NdCoarseArgs<T> a)
         const T* sg = r + nn;
         for (int s = 0; s < a.nu1; s++)
             for (int colour = 0; colour < 4; colour++) nd_cc_gs<T>(d, x, b, sg, a.lv[l].h12, colour);
+        const FastDiv fx((unsigned)d.mx), fy((unsigned)d.my);
         for (int e = threadIdx.x; e < nn; e += blockDim.x) {
-            const int i = e % d.mx, t = e / d.mx, j = t % d.my, k = t / d.my;
+            int i, j, k;
+            split3((unsigned)e, fx, fy, i, j, k);
             T ssig, ss;
             node_sums<T>(d, x, sg, i, j, k, ssig, ss);
             r[e] = b[e] - (T(4) * ssig * x[e] - ss) * a.lv[l].inv_h12;
@@ -930,8 +934,10 @@ __global__ __launch_bounds__(1024) void k_nd_coarse(NdCoarseArgs<T> a)
         const NDims& c = a.lv[l + 1].d;
         const int nnc = c.mx * c.my * c.mz;
         T* bc = lds + nd_lds_off(a, l + 1) + nnc;
+        const FastDiv fxc((unsigned)c.mx), fyc((unsigned)c.my);
         for (int e = threadIdx.x; e < nnc; e += blockDim.x) {
-            const int I = e % c.mx, t = e / c.mx, J = t % c.my, K = t / c.my;
+            int I, J, K;
+            split3((unsigned)e, fxc, fyc, I, J, K);
             bc[e] = nd_restrict_node<T>(d, r, I, J, K);
         }
         __syncthreads();
@@ -955,8 +961,10 @@ __global__ __launch_bounds__(1024) void k_nd_coarse(NdCoarseArgs<T> a)
         const T* b = x + nn;
         const T* sg = x + 3 * nn;
         const T* xc = lds + nd_lds_off(a, l + 1);
+        const FastDiv fx((unsigned)d.mx), fy((unsigned)d.my);
         for (int e = threadIdx.x; e < nn; e += blockDim.x) {
-            const int i = e % d.mx, t = e / d.mx, j = t % d.my, k = t / d.my;
+            int i, j, k;
+            split3((unsigned)e, fx, fy, i, j, k);
             x[e] += nd_prolong_node<T>(a.lv[l + 1].d, xc, i, j, k);
         }
         __syncthreads();

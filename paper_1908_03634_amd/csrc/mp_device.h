@@ -29,6 +29,26 @@ struct Dims {
 };
 
 // Neighbour offsets and high-face coefficients of cell (i,j,k) at linear index q.
+// Quotient by a divisor fixed for a loop: q = (e * m) >> 32 with
+// m = ceil(2^32 / d), exact whenever e * d < 2^32 (the single-workgroup
+// coarse cycles index at most a few thousand cells), in place of the generic
+// integer division.  ceil(2^32 / d) = floor((2^32 - 1) / d) + 1 for d >= 2,
+// one 32-bit division per loop; d = 1 divides by itself.
+struct FastDiv {
+    unsigned m, d;
+    __device__ __forceinline__ explicit FastDiv(unsigned dv) : m(dv > 1 ? 0xFFFFFFFFu / dv + 1u : 0u), d(dv) {}
+    __device__ __forceinline__ unsigned div(unsigned e) const { return d > 1 ? __umulhi(e, m) : e; }
+};
+
+// (a, b, c) of e = a + na (b + nb c).
+__device__ __forceinline__ void split3(unsigned e, const FastDiv& na, const FastDiv& nb, int& a, int& b, int& c)
+{
+    const unsigned t = na.div(e), u = nb.div(t);
+    a = (int)(e - t * na.d);
+    b = (int)(t - u * nb.d);
+    c = (int)u;
+}
+
 struct Nbr {
     long long xm, xp, ym, yp, zm, zp;  // neighbour linear indices (self at a wall)
     long long cxp, cyp, czp;            // index of the high-face coefficient, -1 at a wall
