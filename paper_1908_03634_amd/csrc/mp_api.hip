@@ -66,7 +66,9 @@ struct NLevel {
     void* r = nullptr;
     void* sig = nullptr;  // cell sigma in the V-cycle's precision
     bool own_x = false, own_b = false, own_sig = false;
-    bool col = false;  // z-marching column kernels
+    bool col = false;    // z-marching column kernels
+    bool pair = false;   // two colours per pass (out of place: x2)
+    void* x2 = nullptr;
 };
 
 struct NodalState {
@@ -206,6 +208,7 @@ void free_all(mp_ctx* c)
     if (c->nd) {
         for (auto& L : c->nd->lv) {
             if (L.own_x) (void)hipFree(L.x);
+            if (L.x2) (void)hipFree(L.x2);
             if (L.own_b) (void)hipFree(L.b);
             (void)hipFree(L.r);
             if (L.own_sig) (void)hipFree(L.sig);
@@ -700,6 +703,8 @@ int nd_setup(mp_ctx* c)
             L.own_sig = true;
         }
         L.col = c->cfg.blocked && mp::nd_col_supported(L.d);
+        L.pair = mx && L.col && mp::nd_pair_supported(L.d) && c->cfg.smoother != MP_SMOOTH_PER_COLOUR;
+        if (L.pair) L.x2 = alloc(tsz * L.nn);
         N->lv.push_back(L);
         if (!can_coarsen(d.nx, d.ny, d.nz)) break;
         d = Dims{d.nx / 2, d.ny / 2, d.nz / 2, d.px, d.py, d.pz};
@@ -804,8 +809,28 @@ void nd_vcycle(mp_ctx* c, int l)
         if (L.col) mp::launch_nd_gs_col<T>(L.d, (T*)L.x, (const T*)L.b, (const T*)L.sig, h12, colour, c->stream);
         else mp::launch_nd_gs<T>(L.d, (T*)L.x, (const T*)L.b, (const T*)L.sig, h12, colour, c->stream);
     };
-    for (int s = 0; s < c->cfg.nu1; s++)
-        for (int colour = 0; colour < 4; colour++) gs(colour);
+    // a sweep as two passes of two colours (rows of one parity each), out of
+    // place: the second pass reads the rows the first wrote
+    auto sweep = [&](bool down) {
+        if constexpr (sizeof(T) == 4) {
+            if (L.pair) {
+                // down: colours 0, 1 (even rows, x parity 0 first), then 2, 3;
+                // up: colours 3, 2 (odd rows, x parity 1 first), then 1, 0
+                const int r0 = down ? 0 : 1, lead = down ? 0 : 1;
+                mp::launch_nd_pair<T>(L.d, (const T*)L.x, (const T*)L.x, (T*)L.x2, (const T*)L.b, (const T*)L.sig, h12,
+                                      r0, lead, c->stream);
+                mp::launch_nd_pair<T>(L.d, (const T*)L.x, (const T*)L.x2, (T*)L.x2, (const T*)L.b, (const T*)L.sig,
+                                      h12, 1 - r0, lead, c->stream);
+                std::swap(L.x, L.x2);
+                return;
+            }
+        }
+        if (down)
+            for (int colour = 0; colour < 4; colour++) gs(colour);
+        else
+            for (int colour = 3; colour >= 0; colour--) gs(colour);
+    };
+    for (int s = 0; s < c->cfg.nu1; s++) sweep(true);
     NLevel& C = N.lv[l + 1];
     if (L.col)
         mp::launch_nd_resid_col<T>(L.d, (const T*)L.x, (const T*)L.b, (const T*)L.sig, inv_h12, (T*)L.r, c->stream);
@@ -815,8 +840,7 @@ void nd_vcycle(mp_ctx* c, int l)
     if (l + 1 < nlev - 1 && l + 1 != N.coarse_start) (void)hipMemsetAsync(C.x, 0, sizeof(T) * C.nn, c->stream);
     nd_vcycle<T>(c, l + 1);
     mp::launch_nd_prolong<T>(L.d, C.d, (T*)L.x, (const T*)C.x, c->stream);
-    for (int s = 0; s < c->cfg.nu2; s++)
-        for (int colour = 3; colour >= 0; colour--) gs(colour);
+    for (int s = 0; s < c->cfg.nu2; s++) sweep(false);
 }
 
 // Solve A phi = N.b64 on the nodes (||b||^2 in hscal[S_NB2], its rms pair in

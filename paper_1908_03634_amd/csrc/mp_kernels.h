@@ -255,6 +255,14 @@ struct NDims {
 // One colour (0..3, by i and j parity) of Gauss-Seidel on A x = b; h12 = 12 h^2.
 template <typename T>
 void launch_nd_gs(const NDims& d, T* x, const T* b, const T* sg, T h12, int colour, hipStream_t s);
+// The two colours of the rows of parity rowpar (x parity lead first), out of
+// place: own rows read from xo, rows of the other parity from xnb, own rows
+// written to xn (FP32, nd_pair_supported: periodic x and y, 128 or 256 nodes
+// per row).  Equal bit for bit to the two launch_nd_gs colours.
+bool nd_pair_supported(const NDims& d);
+template <typename T>
+void launch_nd_pair(const NDims& d, const T* xo, const T* xnb, T* xn, const T* b, const T* sg, T h12, int rowpar,
+                    int lead, hipStream_t s);
 // r = b - A x; inv_h12 = 1 / (12 h^2).
 template <typename T>
 void launch_nd_resid(const NDims& d, const T* x, const T* b, const T* sg, T inv_h12, T* r, hipStream_t s);

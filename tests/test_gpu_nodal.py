@@ -212,3 +212,28 @@ def test_nodal_coarse_cycle_equals_per_level_launches(shape, bc, precision):
         ctx.close()
     assert outs[0][2] == outs[1][2]
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("shape,bc", [((128, 16, 12), (0, 0, 1)), ((128, 8, 18), (0, 0, 0)), ((128, 8, 34), (0, 0, 1)),
+                                      ((256, 12, 10), (0, 0, 1)), ((256, 32, 16), (0, 0, 1)),
+                                      ((256, 256, 24), (0, 0, 1))])
+def test_two_colour_passes_equal_four_colour_passes(shape, bc):
+    """On rows of 128 or 256 nodes (periodic x and y) the mixed-precision
+    smoother runs the two colours of each row parity in one out-of-place pass
+    (first colour one plane ahead of the second); with one pass per colour
+    (smoother="per_colour") the projection is the same bit for bit, through
+    plane chunks of ragged length and on the 128-node level below a 256-node
+    grid."""
+    nx, ny, nz = shape
+    say("nodal two-colour passes", shape, bc)
+    p = W.planar_problem(nx=nx, ny=ny, nz=nz, contrast=1e4, bc=bc, seed=8100 + nx + ny + nz, velocity="cells")
+    outs = []
+    for sm in ("auto", "per_colour"):
+        ctx = _mapped(p, "mixed", rtol=1e-11, smoother=sm)
+        ux, uy, uz = T(p.ux), T(p.uy), T(p.uz)
+        phi, info = ctx.nodal_project(ux, uy, uz, T(p.S))
+        outs.append((N(phi), N(ux), N(uz), info["vcycles"], info["rel_resid"]))
+        ctx.close()
+    assert outs[0][3] == outs[1][3] and outs[0][4] <= 1e-11
+    for a, b in zip(outs[0][:3], outs[1][:3]):
+        assert np.array_equal(a, b)
