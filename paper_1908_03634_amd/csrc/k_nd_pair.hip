@@ -33,8 +33,6 @@ bool nd_pair_supported(const NDims& d)
     return d.px && d.py && (d.mx == 128 || d.mx == 256) && d.my % 2 == 0 && d.mz >= 2;
 }
 
-namespace {
-
 // Register slots of one wavefront: plane p of the chunk in slot
 // (p - z0 + 2) mod NS (node values of rows j-1, j, j+1; sigma of the cell rows
 // below and above row j; b of row j).  Compile-time slot names keep values
@@ -265,12 +263,15 @@ __global__ __launch_bounds__(256) void k_nd_pair(NDims d, int lz, const T* __res
         if (k + 5 < f.z1) f.template step<5 % NS>(s, k + 5);
 }
 
+namespace {
+
 constexpr int kNpAhead = 1;
-constexpr int kNpMinPlanes = 8;
+constexpr int kNpMinPlanes = 3;
 
 // Planes per chunk: the shortest (at least kNpMinPlanes) for which the grid
 // is resident at once, lengthened until its plane steps are whole groups of
-// the unrolled loop.
+// the unrolled loop.  Short chunks read four extra planes each, but from L2:
+// at 256 x 256 nodes the resident grid wins over longer chunks.
 template <typename T, int M>
 int np_chunk(const NDims& d, long long gx)
 {
