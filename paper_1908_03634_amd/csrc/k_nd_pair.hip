@@ -6,10 +6,11 @@
 // only in its own row, one node along x and one plane along z (a face of a
 // cell spans x and z).  Rows of the other parity are not touched by either
 // colour.  So one pass can update both colours of every row of one parity:
-// each wavefront owns a whole row (nx = 128 M nodes, 2M per lane, x neighbours
-// across lanes by DPP rotation) and marches along z, updating the first colour
-// on plane k+1 and then the second on plane k.  No data moves between
-// wavefronts, so there is no barrier and no LDS.
+// each wavefront owns whole rows (nx = 256, 128, 64 or 32 nodes on 64, 64,
+// 32 or 16 lanes, 4 or 2 nodes per lane, x neighbours across the lanes of a
+// row by rotation) and marches along z, updating the first colour on plane
+// k+1 and then the second on plane k.  No data moves between wavefronts, so
+// there is no barrier and no LDS.
 //
 // A chunk of planes [z0, z1) starts two planes early and ends one late: the
 // first colour is recomputed on planes z0-1 and z1 (from old values, as the
@@ -30,7 +31,7 @@ namespace mp {
 
 bool nd_pair_supported(const NDims& d)
 {
-    return d.px && d.py && (d.mx == 128 || d.mx == 256) && d.my % 2 == 0 && d.mz >= 2;
+    return d.px && d.py && (d.mx == 32 || d.mx == 64 || d.mx == 128 || d.mx == 256) && d.my % 2 == 0 && d.mz >= 2;
 }
 
 // Register slots of one wavefront: plane p of the chunk in slot
@@ -49,14 +50,44 @@ struct Ext {
     T v[2 * M + 2];  // v[q + 1]
 };
 
-template <typename T, int M>
+// Rotations within a row of LPR lanes (a wavefront holds 64 / LPR rows):
+// lane l receives lane l - 1 (prev) or l + 1 (next) of its row, wrapping.
+// 64: wave rotation (DPP); 16: row rotation (DPP row_ror); 32: ds_bpermute.
+template <int LPR>
+__device__ __forceinline__ float row_prev(float v)
+{
+    if constexpr (LPR == 64) {
+        return from_prev(v);
+    } else if constexpr (LPR == 16) {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x121, 0xf, 0xf, false));
+    } else {
+        static_assert(LPR == 32, "rows of 16, 32 or 64 lanes");
+        const int l = (int)(threadIdx.x & (kWave - 1));
+        return __int_as_float(__builtin_amdgcn_ds_bpermute(((l & 32) | ((l + 31) & 31)) << 2, __float_as_int(v)));
+    }
+}
+template <int LPR>
+__device__ __forceinline__ float row_next(float v)
+{
+    if constexpr (LPR == 64) {
+        return from_next(v);
+    } else if constexpr (LPR == 16) {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x12F, 0xf, 0xf, false));
+    } else {
+        static_assert(LPR == 32, "rows of 16, 32 or 64 lanes");
+        const int l = (int)(threadIdx.x & (kWave - 1));
+        return __int_as_float(__builtin_amdgcn_ds_bpermute(((l & 32) | ((l + 1) & 31)) << 2, __float_as_int(v)));
+    }
+}
+
+template <typename T, int M, int LPR>
 __device__ __forceinline__ Ext<T, M> ext(const Strip<T, M>& s)
 {
     Ext<T, M> e;
-    e.v[0] = from_prev(s.v[2 * M - 1]);
+    e.v[0] = row_prev<LPR>(s.v[2 * M - 1]);
 #pragma unroll
     for (int q = 0; q < 2 * M; q++) e.v[q + 1] = s.v[q];
-    e.v[2 * M + 1] = from_next(s.v[0]);
+    e.v[2 * M + 1] = row_next<LPR>(s.v[0]);
     return e;
 }
 
@@ -88,7 +119,7 @@ __device__ __forceinline__ T np_update(int q, const Ext<T, M> (&lo)[3], const Ex
     return (a2 + h12 * bq) / (T(4) * a1);
 }
 
-template <typename T, int M, int D>
+template <typename T, int M, int D, int LPR>
 struct NpPass {
     static constexpr int NS = D + 4;
     static_assert(D >= 0 && D <= 3, "the plane loop is unrolled for at most 7 slots");
@@ -104,7 +135,8 @@ struct NpPass {
     const T* __restrict__ b;
     const T* __restrict__ sg;
     T h12;
-    int lead;  // x parity of the first colour
+    int lead;   // x parity of the first colour
+    bool live;  // the lane's row lies inside the grid (else it only loads)
 
     // node plane P: in range (or wrapped when periodic), else zeros; the load
     // itself is always issued, at a clamped plane
@@ -158,11 +190,11 @@ struct NpPass {
         ld_cells<PB>(s, min(k + 1 + D, z1));
         // first colour on plane k+1: planes k, k+1, k+2; cells k, k+1
         if (node_ok(k + 1)) {
-            const Ext<T, M> lo[3] = {ext<T, M>(s.xl[P0]), ext<T, M>(s.xo[P0]), ext<T, M>(s.xh[P0])};
-            const Ext<T, M> mid[3] = {ext<T, M>(s.xl[P1]), ext<T, M>(s.xo[P1]), ext<T, M>(s.xh[P1])};
-            const Ext<T, M> hi[3] = {ext<T, M>(s.xl[P2]), ext<T, M>(s.xo[P2]), ext<T, M>(s.xh[P2])};
-            const Ext<T, M> cb[2] = {ext<T, M>(s.sl[P0]), ext<T, M>(s.sh[P0])};
-            const Ext<T, M> ca[2] = {ext<T, M>(s.sl[P1]), ext<T, M>(s.sh[P1])};
+            const Ext<T, M> lo[3] = {ext<T, M, LPR>(s.xl[P0]), ext<T, M, LPR>(s.xo[P0]), ext<T, M, LPR>(s.xh[P0])};
+            const Ext<T, M> mid[3] = {ext<T, M, LPR>(s.xl[P1]), ext<T, M, LPR>(s.xo[P1]), ext<T, M, LPR>(s.xh[P1])};
+            const Ext<T, M> hi[3] = {ext<T, M, LPR>(s.xl[P2]), ext<T, M, LPR>(s.xo[P2]), ext<T, M, LPR>(s.xh[P2])};
+            const Ext<T, M> cb[2] = {ext<T, M, LPR>(s.sl[P0]), ext<T, M, LPR>(s.sh[P0])};
+            const Ext<T, M> ca[2] = {ext<T, M, LPR>(s.sl[P1]), ext<T, M, LPR>(s.sh[P1])};
             S out = s.xo[P1];
             if (lead == 0) {
 #pragma unroll
@@ -175,11 +207,11 @@ struct NpPass {
         }
         // second colour on plane k: planes k-1, k, k+1; cells k-1, k
         if (k >= z0 && node_ok(k)) {
-            const Ext<T, M> lo[3] = {ext<T, M>(s.xl[PM]), ext<T, M>(s.xo[PM]), ext<T, M>(s.xh[PM])};
-            const Ext<T, M> mid[3] = {ext<T, M>(s.xl[P0]), ext<T, M>(s.xo[P0]), ext<T, M>(s.xh[P0])};
-            const Ext<T, M> hi[3] = {ext<T, M>(s.xl[P1]), ext<T, M>(s.xo[P1]), ext<T, M>(s.xh[P1])};
-            const Ext<T, M> cb[2] = {ext<T, M>(s.sl[PM]), ext<T, M>(s.sh[PM])};
-            const Ext<T, M> ca[2] = {ext<T, M>(s.sl[P0]), ext<T, M>(s.sh[P0])};
+            const Ext<T, M> lo[3] = {ext<T, M, LPR>(s.xl[PM]), ext<T, M, LPR>(s.xo[PM]), ext<T, M, LPR>(s.xh[PM])};
+            const Ext<T, M> mid[3] = {ext<T, M, LPR>(s.xl[P0]), ext<T, M, LPR>(s.xo[P0]), ext<T, M, LPR>(s.xh[P0])};
+            const Ext<T, M> hi[3] = {ext<T, M, LPR>(s.xl[P1]), ext<T, M, LPR>(s.xo[P1]), ext<T, M, LPR>(s.xh[P1])};
+            const Ext<T, M> cb[2] = {ext<T, M, LPR>(s.sl[PM]), ext<T, M, LPR>(s.sh[PM])};
+            const Ext<T, M> ca[2] = {ext<T, M, LPR>(s.sl[P0]), ext<T, M, LPR>(s.sh[P0])};
             S out = s.xo[P0];
             if (lead == 0) {
 #pragma unroll
@@ -189,26 +221,30 @@ struct NpPass {
                 for (int q = 0; q < 2 * M; q += 2) out.v[q] = np_update<T, M>(q, lo, mid, hi, cb, ca, s.b[P0].v[q], h12);
             }
             s.xo[P0] = out;
-            st_strip<T, M>(xn, (long long)k * sz + ro, out);
+            if (live) st_strip<T, M>(xn, (long long)k * sz + ro, out);
         }
     }
 };
 
-// One wavefront per row j = 2 w + rowpar; blocks of four rows; blockIdx.y is
-// the plane chunk.
-template <typename T, int M, int D>
+// Row r = 2 (w * 64 / LPR + lane / LPR) + rowpar for wavefront w (LPR lanes
+// per row, nx = 2 M LPR nodes); blocks of four wavefronts; blockIdx.y is the
+// plane chunk.
+template <typename T, int M, int D, int LPR>
 __global__ __launch_bounds__(256) void k_nd_pair(NDims d, int lz, const T* __restrict__ xo,
                                                  const T* __restrict__ xnb, T* __restrict__ xn,
                                                  const T* __restrict__ b, const T* __restrict__ sg, T h12, int rowpar,
                                                  int lead)
 {
-    using F = NpPass<T, M, D>;
+    using F = NpPass<T, M, D, LPR>;
     constexpr int NS = F::NS;
+    constexpr int RPW = kWave / LPR;
     const int lane = threadIdx.x & (kWave - 1);
     const int w = (int)blockIdx.x * (blockDim.x / kWave) + (int)threadIdx.x / kWave;
-    const int j = 2 * w + rowpar;
-    if (j >= d.my) return;  // whole wavefronts only
-    const int xi = 2 * M * lane;
+    if (2 * w * RPW + rowpar >= d.my) return;  // the wavefront's first row is beyond the grid
+    int j = 2 * (w * RPW + lane / LPR) + rowpar;
+    const bool live = j < d.my;
+    if (!live) j = rowpar;  // rows beyond the grid load a row inside it and store nothing
+    const int xi = 2 * M * (lane % LPR);
     const int jl = j > 0 ? j - 1 : d.my - 1, jh = j + 1 < d.my ? j + 1 : 0;  // periodic y
     F f{d};
     f.z0 = (int)blockIdx.y * lz;
@@ -227,6 +263,7 @@ __global__ __launch_bounds__(256) void k_nd_pair(NDims d, int lz, const T* __res
     f.sg = sg;
     f.h12 = h12;
     f.lead = lead;
+    f.live = live;
 
     const int zs = f.z0 - 2;
     NpCol<T, M, NS> s;
@@ -272,7 +309,7 @@ constexpr int kNpMinPlanes = 3;
 // is resident at once, lengthened until its plane steps are whole groups of
 // the unrolled loop.  Short chunks read four extra planes each, but from L2:
 // at 256 x 256 nodes the resident grid wins over longer chunks.
-template <typename T, int M>
+template <typename T, int M, int LPR>
 int np_chunk(const NDims& d, long long gx)
 {
     constexpr int NS = kNpAhead + 4;
@@ -282,7 +319,7 @@ int np_chunk(const NDims& d, long long gx)
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
-                                                         reinterpret_cast<const void*>(k_nd_pair<T, M, kNpAhead>),
+                                                         reinterpret_cast<const void*>(k_nd_pair<T, M, kNpAhead, LPR>),
                                                          256, 0) != hipSuccess)
             return 13;
         resident = max(1, ncu * max(per_cu, 1));
@@ -293,16 +330,17 @@ int np_chunk(const NDims& d, long long gx)
     return lz;
 }
 
-template <typename T, int M>
+template <typename T, int M, int LPR>
 void np_launch(const NDims& d, const T* xo, const T* xnb, T* xn, const T* b, const T* sg, T h12, int rowpar,
                int lead, hipStream_t s)
 {
     const int rows = (d.my - rowpar + 1) / 2;
-    const long long gx = (rows + 3) / 4;
-    const int lz = np_chunk<T, M>(d, gx);
+    const int per_block = 4 * (kWave / LPR);
+    const long long gx = (rows + per_block - 1) / per_block;
+    const int lz = np_chunk<T, M, LPR>(d, gx);
     const dim3 grid((unsigned)gx, (unsigned)((d.mz + lz - 1) / lz));
-    hipLaunchKernelGGL((k_nd_pair<T, M, kNpAhead>), grid, dim3(256), 0, s, d, lz, xo, xnb, xn, b, sg, h12, rowpar,
-                       lead);
+    hipLaunchKernelGGL((k_nd_pair<T, M, kNpAhead, LPR>), grid, dim3(256), 0, s, d, lz, xo, xnb, xn, b, sg, h12,
+                       rowpar, lead);
 }
 
 }  // namespace
@@ -311,8 +349,12 @@ template <typename T>
 void launch_nd_pair(const NDims& d, const T* xo, const T* xnb, T* xn, const T* b, const T* sg, T h12, int rowpar,
                     int lead, hipStream_t s)
 {
-    if (d.mx == 256) np_launch<T, 2>(d, xo, xnb, xn, b, sg, h12, rowpar, lead, s);
-    else np_launch<T, 1>(d, xo, xnb, xn, b, sg, h12, rowpar, lead, s);
+    switch (d.mx) {
+    case 256: np_launch<T, 2, 64>(d, xo, xnb, xn, b, sg, h12, rowpar, lead, s); break;
+    case 128: np_launch<T, 1, 64>(d, xo, xnb, xn, b, sg, h12, rowpar, lead, s); break;
+    case 64: np_launch<T, 1, 32>(d, xo, xnb, xn, b, sg, h12, rowpar, lead, s); break;
+    default: np_launch<T, 1, 16>(d, xo, xnb, xn, b, sg, h12, rowpar, lead, s); break;
+    }
 }
 
 template void launch_nd_pair<float>(const NDims&, const float*, const float*, float*, const float*, const float*,

@@ -216,14 +216,16 @@ def test_nodal_coarse_cycle_equals_per_level_launches(shape, bc, precision):
 
 @pytest.mark.parametrize("shape,bc", [((128, 16, 12), (0, 0, 1)), ((128, 8, 18), (0, 0, 0)), ((128, 8, 34), (0, 0, 1)),
                                       ((256, 12, 10), (0, 0, 1)), ((256, 32, 16), (0, 0, 1)),
-                                      ((256, 256, 24), (0, 0, 1))])
+                                      ((256, 256, 24), (0, 0, 1)), ((64, 16, 12), (0, 0, 1)), ((64, 6, 10), (0, 0, 0)),
+                                      ((32, 8, 10), (0, 0, 1)), ((32, 10, 6), (0, 0, 0))])
 def test_two_colour_passes_equal_four_colour_passes(shape, bc):
-    """On rows of 128 or 256 nodes (periodic x and y) the mixed-precision
-    smoother runs the two colours of each row parity in one out-of-place pass
-    (first colour one plane ahead of the second); with one pass per colour
+    """On rows of 32, 64, 128 or 256 nodes (periodic x and y) the
+    mixed-precision smoother runs the two colours of each row parity in one
+    out-of-place pass (first colour one plane ahead of the second; a
+    wavefront holds one, two or four rows); with one pass per colour
     (smoother="per_colour") the projection is the same bit for bit, through
-    plane chunks of ragged length and on the 128-node level below a 256-node
-    grid."""
+    plane chunks of ragged length, row counts that leave part of a wavefront
+    empty, and the coarser levels below a 256-node grid."""
     nx, ny, nz = shape
     say("nodal two-colour passes", shape, bc)
     p = W.planar_problem(nx=nx, ny=ny, nz=nz, contrast=1e4, bc=bc, seed=8100 + nx + ny + nz, velocity="cells")
