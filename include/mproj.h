@@ -80,21 +80,26 @@ typedef struct mp_config {
                                 V-cycles per refinement step in MIXED);
                                 0: predicted from the last step's
                                 contraction (1 to 4) */
-    double bottom_rtol;      /* BiCGStab tolerance on the coarsest grid */
-    int bottom_max_iter;     /* BiCGStab iteration cap */
+    double bottom_rtol;      /* bottom-solver tolerance on the coarsest grid
+                                (conjugate gradients in one wavefront up to
+                                256 cells, BiCGStab in one workgroup above) */
+    int bottom_max_iter;     /* bottom-solver iteration cap */
     int demean;              /* 1: remove the mean of the rhs; 0: require mean ~ 0 */
     int kernel_timing;       /* 1: time the finest-level smoother launches with
                                 HIP events (mp_info.smooth_*) */
     int smoother;            /* MP_SMOOTH_AUTO: both colours of a sweep in one
-                                launch on the register-blocked finest level
-                                in MIXED when nx is 128 or 256, and on finest
-                                levels of >= 4M cells with stored face
-                                coefficients; one launch per colour elsewhere.
+                                launch wherever it pays: register-blocked
+                                levels in MIXED whose rows are 128 or 256
+                                cells, face-coefficient levels of >= 4M cells
+                                (tiled), and the other levels below the
+                                finest with even extents (one red and one
+                                black cell per thread); one launch per colour
+                                elsewhere.
                                 MP_SMOOTH_PER_COLOUR: one launch per colour on
                                 every level; MP_SMOOTH_FUSED: both colours in
                                 one launch wherever the grid allows.  All
                                 three give the same bits. */
-    int coarse_cycle;        /* 1: run levels of <= 512 cells in one workgroup
+    int coarse_cycle;        /* 1: run levels of <= 4096 cells in one workgroup
                                 (bottom <= 256 cells by one wavefront); 0: one
                                 launch per operation on every level */
     int blocked;             /* 1: on the finest level, register-blocked

@@ -133,6 +133,22 @@ __device__ void wave_cg(const Dims& d, const T* __restrict__ bin, T* __restrict_
         if (live[u]) xout[lane + kWave * u] = (T)(x[u] - xm);
 }
 
+// The six low/high face coefficients of cell q (the values of coef6 in face
+// mode: a high face on a wall is 0).
+template <typename T>
+__device__ __forceinline__ void cc_coef(const CoarseLevel<T>& L, int q, const Nb32& b, T (&c)[6])
+{
+    const T xh = L.cx[b.xp], yh = L.cy[b.yp], zh = L.cz[b.zp];
+    c[0] = L.cx[q];
+    c[1] = b.hx ? xh : T(0);
+    c[2] = L.cy[q];
+    c[3] = b.hy ? yh : T(0);
+    c[4] = L.cz[q];
+    c[5] = b.hz ? zh : T(0);
+}
+
+// One red-black sweep of a level in LDS: the cell arithmetic of rbgs_cell
+// (gs_value on the same operands), with 32-bit indexing.
 template <typename T>
 __device__ void cg_smooth(const CoarseLevel<T>& L, const Dims& d, int zero_init)
 {
@@ -140,14 +156,51 @@ __device__ void cg_smooth(const CoarseLevel<T>& L, const Dims& d, int zero_init)
     const int cnt = nxh * d.ny * d.nz;
     const FastDiv fa((unsigned)nxh), fb((unsigned)d.ny);
     for (int colour = 0; colour < 2; colour++) {
+        const bool zi = zero_init && colour == 0;
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
             int p, j, k;
             split3((unsigned)e, fa, fb, p, j, k);
-            rbgs_cell<T, false>(d, L.x, L.b, Coef<T>{L.cx, L.cy, L.cz, nullptr}, L.h2, colour,
-                                zero_init && colour == 0, p, j, k);
+            const int par = (j + k + colour) & 1;
+            const int i = 2 * p + par;
+            const int rbase = (k * d.ny + j) * d.nx;
+            if (zi) {
+                // x is zero on entry: clear the other cell of the pair
+                const int io = 2 * p + (1 - par);
+                if (io < d.nx) L.x[rbase + io] = T(0);
+            }
+            if (i >= d.nx) continue;
+            const int q = rbase + i;
+            const Nb32 nb = nb32(d, q, i, j, k);
+            T c[6];
+            cc_coef<T>(L, q, nb, c);
+            if (zi)
+                L.x[q] = gs_value<T>(c[0], c[1], c[2], c[3], c[4], c[5], T(0), T(0), T(0), T(0), T(0), T(0), L.b[q],
+                                     L.h2, T(0));
+            else
+                L.x[q] = gs_value<T>(c[0], c[1], c[2], c[3], c[4], c[5], L.x[nb.xm], L.x[nb.xp], L.x[nb.ym],
+                                     L.x[nb.yp], L.x[nb.zm], L.x[nb.zp], L.b[q], L.h2, L.x[q]);
         }
         __syncthreads();
     }
+}
+
+// Residual of cell q = (i, j, k): the arithmetic of resid_cell.
+template <typename T>
+__device__ __forceinline__ T cc_resid(const CoarseLevel<T>& L, const Dims& d, int q, int i, int j, int k)
+{
+    const Nb32 nb = nb32(d, q, i, j, k);
+    T c[6];
+    cc_coef<T>(L, q, nb, c);
+    return resid_value<T>(c[0], c[1], c[2], c[3], c[4], c[5], L.x[nb.xm], L.x[nb.xp], L.x[nb.ym], L.x[nb.yp],
+                          L.x[nb.zm], L.x[nb.zp], L.x[q], L.b[q], L.inv_h2);
+}
+
+// Extents of coarse level l (from the kernel arguments: an array of them in
+// the kernel would live in scratch memory, indexed at run time).
+template <typename T>
+__device__ __forceinline__ Dims cdims(const CoarseArgs<T>& a, int l)
+{
+    return Dims{a.lv[l].nx, a.lv[l].ny, a.lv[l].nz, a.px, a.py, a.pz};
 }
 
 // The arrays of every coarse level (x, b and the three low-face
@@ -187,16 +240,14 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(CoarseArgs<T> a)
 {
     __shared__ T lds[kCoarseLdsBytes / sizeof(T)];
     const int nl = a.nlev;
-    Dims dims[kMaxCoarse];
-    for (int l = 0; l < nl; l++) dims[l] = Dims{a.lv[l].nx, a.lv[l].ny, a.lv[l].nz, a.px, a.py, a.pz};
     // residual scratch for the restrictions, after the last level
-    T* rs = lds_level(a, nl - 1, lds).x + 5 * dims[nl - 1].n();
+    T* rs = lds_level(a, nl - 1, lds).x + 5 * cdims(a, nl - 1).n();
     // stage the coefficients of every level and the right-hand side (and,
     // unless it starts from zero, the iterate) of the top level, 16 bytes
     // per access where the level allows it
     for (int l = 0; l < nl; l++) {
         const CoarseLevel<T> S = lds_level(a, l, lds);
-        const int n = (int)dims[l].n();
+        const int n = (int)cdims(a, l).n();
         const bool top = l == 0, xin = l == 0 && !a.zero_init;
         if (n % (int)V16<T>::k == 0) {
             using V = typename V16<T>::type;
@@ -228,12 +279,12 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(CoarseArgs<T> a)
         const CoarseLevel<T> L = lds_level(a, l, lds);
         const int zi = (l > 0) || a.zero_init;
         if (zi && a.nu1 == 0) {
-            const int cnt0 = dims[l].nx * dims[l].ny * dims[l].nz;
+            const int cnt0 = a.lv[l].nx * a.lv[l].ny * a.lv[l].nz;
             for (int e = threadIdx.x; e < cnt0; e += blockDim.x) L.x[e] = T(0);
             __syncthreads();
         }
-        for (int s = 0; s < a.nu1; s++) cg_smooth<T>(L, dims[l], zi && s == 0);
-        const Dims& f = dims[l];
+        const Dims f = cdims(a, l);
+        for (int s = 0; s < a.nu1; s++) cg_smooth<T>(L, f, zi && s == 0);
         const int nxc = f.nx / 2, nyc = f.ny / 2, nzc = f.nz / 2;
         const int cnt = nxc * nyc * nzc;
         T* bc = lds_level(a, l + 1, lds).b;
@@ -241,12 +292,11 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(CoarseArgs<T> a)
         // into the scratch, then the 8 children of each coarse cell summed in
         // the order of restrict_cell (the same bits)
         const int nf = (int)f.n();
-        const Coef<T> C{L.cx, L.cy, L.cz, nullptr};
         const FastDiv fx((unsigned)f.nx), fy((unsigned)f.ny), fxc((unsigned)nxc), fyc((unsigned)nyc);
         for (int e = threadIdx.x; e < nf; e += blockDim.x) {
             int i, j, k;
             split3((unsigned)e, fx, fy, i, j, k);
-            rs[e] = resid_cell<T, false>(f, L.x, L.b, C, L.inv_h2, i, j, k);
+            rs[e] = cc_resid<T>(L, f, e, i, j, k);
         }
         __syncthreads();
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
@@ -267,13 +317,13 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(CoarseArgs<T> a)
     // bottom: first wavefront only; the others wait at the barrier below
     if (threadIdx.x < kWave) {
         const CoarseLevel<T> B = lds_level(a, nl - 1, lds);
-        wave_cg<T, NS>(dims[nl - 1], B.b, B.x, B.cx, B.cy, B.cz, B.h2d, a.bottom_rtol, a.bottom_maxit);
+        wave_cg<T, NS>(cdims(a, nl - 1), B.b, B.x, B.cx, B.cy, B.cz, B.h2d, a.bottom_rtol, a.bottom_maxit);
     }
     __syncthreads();
     // up
     for (int l = nl - 2; l >= 0; l--) {
         const CoarseLevel<T> L = lds_level(a, l, lds);
-        const Dims& f = dims[l];
+        const Dims f = cdims(a, l);
         const int nxc = f.nx / 2, nyc = f.ny / 2;
         const int cnt = f.nx * f.ny * f.nz;
         const T* ec = lds_level(a, l + 1, lds).x;
@@ -289,7 +339,7 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(CoarseArgs<T> a)
     // the top level's iterate goes back to the finer level's prolongation
     {
         const CoarseLevel<T> L = lds_level(a, 0, lds);
-        const int n = (int)dims[0].n();
+        const int n = (int)cdims(a, 0).n();
         for (int e = threadIdx.x; e < n; e += blockDim.x) a.lv[0].x[e] = L.x[e];
     }
 }

@@ -56,7 +56,9 @@ struct Half {
 // Stored faces: c is the row's low y faces, chi the low y faces of row j+1
 // (colour parity), fzl/fzh the low z faces of planes P and P+1; a high face
 // across a wall is 0 (fyh, zh), the low faces are taken as stored.
-template <typename T, int M, bool CELL>
+// PXY: x and y periodic (no wall in the row or between rows; the selects
+// for walls drop out at compile time).
+template <typename T, int M, bool CELL, bool PXY>
 __device__ __forceinline__ void fs_row(const Dims& d, const BlkGeo& g, int j, int P, int par, T h2, Strip<T, M>& x,
                                        const Half<T, M>& xlo, const Half<T, M>& xhi, const Strip<T, M>& xb,
                                        const Strip<T, M>& xa, const T (&fx)[2 * M + 1], const Strip<T, M>& c,
@@ -64,9 +66,9 @@ __device__ __forceinline__ void fs_row(const Dims& d, const BlkGeo& g, int j, in
                                        const Strip<T, M>& fzh, const Strip<T, M>& bq)
 {
     const bool hzm = P > 0 || d.pz, hzp = P < d.nz - 1 || d.pz;
-    const bool fyl = (j > 0 || d.py) && (j < d.ny || d.py);
-    const bool fyh = (j + 1 > 0 || d.py) && (j + 1 < d.ny || d.py);
-    const bool ywl = !(j > 0 || d.py), ywh = !(j < d.ny - 1 || d.py);
+    const bool fyl = PXY || ((j > 0 || d.py) && (j < d.ny || d.py));
+    const bool fyh = PXY || ((j + 1 > 0 || d.py) && (j + 1 < d.ny || d.py));
+    const bool ywl = !PXY && !(j > 0 || d.py), ywh = !PXY && !(j < d.ny - 1 || d.py);
     T vl, vr;
     x_edges<T, M>(g, x, T(0), vl, vr);
     Strip<T, M> out = x;
@@ -82,8 +84,8 @@ __device__ __forceinline__ void fs_row(const Dims& d, const BlkGeo& g, int j, in
             fh = fyh ? chi.v[q >> 1] : T(0);
             c5 = hzp ? fzh.v[q] : T(0);
         }
-        const T xm = q > 0 ? x.v[q > 0 ? q - 1 : 0] : (g.wl ? own : vl);
-        const T xp = q < 2 * M - 1 ? x.v[q < 2 * M - 1 ? q + 1 : 0] : (g.wr ? own : vr);
+        const T xm = q > 0 ? x.v[q > 0 ? q - 1 : 0] : (!PXY && g.wl ? own : vl);
+        const T xp = q < 2 * M - 1 ? x.v[q < 2 * M - 1 ? q + 1 : 0] : (!PXY && g.wr ? own : vr);
         const T ym = ywl ? own : xlo.v[q >> 1];
         const T yp = ywh ? own : xhi.v[q >> 1];
         const T zm = hzm ? xb.v[q] : own;
@@ -102,13 +104,30 @@ __device__ __forceinline__ void fs_row(const Dims& d, const BlkGeo& g, int j, in
 
 // x faces of a row from its stored low x faces: the face above the strip's
 // last cell is the next strip's first (0 at a wall).  All lanes must call (DPP).
-template <typename T, int M>
+template <typename T, int M, bool PXY>
 __device__ __forceinline__ void x_faces_stored(const BlkGeo& g, const Strip<T, M>& cx, T (&f)[2 * M + 1])
 {
     const T nr = from_next(cx.v[0]);
 #pragma unroll
     for (int q = 0; q < 2 * M; q++) f[q] = cx.v[q];
-    f[2 * M] = g.wr ? T(0) : nr;
+    f[2 * M] = !PXY && g.wr ? T(0) : nr;
+}
+
+// x faces of a row from cell coefficients (x_faces).  Periodic in x, the
+// face above the strip's last cell is the next lane's face below its first
+// cell, the harmonic mean of the same two values in the same order: it is
+// taken from that lane instead of formed again.  All lanes must call (DPP).
+template <typename T, int M, bool PXY>
+__device__ __forceinline__ void x_faces_cell(const BlkGeo& g, const Strip<T, M>& c, T (&f)[2 * M + 1])
+{
+    if constexpr (PXY) {
+        f[0] = harm(from_prev(c.v[2 * M - 1]), c.v[0]);
+#pragma unroll
+        for (int q = 1; q < 2 * M; q++) f[q] = harm(c.v[q - 1], c.v[q]);
+        f[2 * M] = from_next(f[0]);
+    } else {
+        x_faces<T, M>(g, c, T(0), f);
+    }
 }
 
 // Coefficients of the z faces between planes P and P+1 of a row (0 where
@@ -180,7 +199,7 @@ struct FsCol {
     T fx[NS][2 * M + 1];
 };
 
-template <typename T, int MODE, int M, int R, int D, bool IRU, bool CELL>
+template <typename T, int MODE, int M, int R, int D, bool IRU, bool CELL, bool PXY>
 struct FsLds {
     static constexpr int NW = R + 4, NX = 128 * M, NS = D + 4;
     static_assert(D >= 0 && D <= 3, "the plane loop is unrolled for at most 7 slots");
@@ -266,21 +285,21 @@ struct FsLds {
         }
         if (red_row) {
             if constexpr (CELL) {
-                x_faces<T, M>(g, s.c[P1], T(0), s.fx[P1]);
+                x_faces_cell<T, M, PXY>(g, s.c[P1], s.fx[P1]);
                 s.fz[P1] = z_faces<T, M>(d, k + 1, s.c[P1], s.c[P2]);
             } else {
-                x_faces_stored<T, M>(g, s.cx[P1], s.fx[P1]);
+                x_faces_stored<T, M, PXY>(g, s.cx[P1], s.fx[P1]);
             }
             const H xlo = lds_get_half<T, M>(&sx[i1][so + ho - NX]), xhi = lds_get_half<T, M>(&sx[i1][so + ho + NX]);
             const H clo = CELL ? lds_get_half<T, M>(&sc[i1][so + ho - NX]) : H{};
             const H chi = lds_get_half<T, M>(&sc[i1][so + ho + NX]);
-            fs_row<T, M, CELL>(d, g, j, k + 1, 0, h2, s.x[P1], xlo, xhi, s.x[P0], s.x[P2], s.fx[P1], s.c[P1], clo,
+            fs_row<T, M, CELL, PXY>(d, g, j, k + 1, 0, h2, s.x[P1], xlo, xhi, s.x[P0], s.x[P2], s.fx[P1], s.c[P1], clo,
                                chi, CELL ? s.fz[P0] : s.cz[P1], CELL ? s.fz[P1] : s.cz[P2], s.b[P1]);
             // only the red half changed
             lds_put_half<T, M>(&sx[i1][so + ho], s.x[P1], (j + k + 1) & 1);
         }
         if (blk) {
-            fs_row<T, M, CELL>(d, g, j, k, 1, h2, s.x[P0], bxlo, bxhi, s.x[PM], s.x[P1], s.fx[P0], s.c[P0], bclo,
+            fs_row<T, M, CELL, PXY>(d, g, j, k, 1, h2, s.x[P0], bxlo, bxhi, s.x[PM], s.x[P1], s.fx[P0], s.c[P0], bclo,
                                bchi, CELL ? s.fz[PM] : s.cz[P0], CELL ? s.fz[P0] : s.cz[P1], s.b[P0]);
             const long long o = (long long)k * sz + roff;
             st_strip<T, M>(xn, o, s.x[P0]);
@@ -301,8 +320,8 @@ struct FsLds {
 // D: planes loaded ahead of the three a plane step works on (x, c), and of
 // the two it takes b from.
 // CELL: cc holds cell coefficients; otherwise cc, cxa, cza hold the low y,
-// x and z faces.
-template <typename T, int MODE, int M, int R, int D, bool IRU, bool CELL>
+// x and z faces.  PXY: x and y periodic.
+template <typename T, int MODE, int M, int R, int D, bool IRU, bool CELL, bool PXY>
 __global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const T* __restrict__ xo,
                                                             T* __restrict__ xn, const T* __restrict__ b,
                                                             const T* __restrict__ cc, const T* __restrict__ cxa,
@@ -310,7 +329,7 @@ __global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const
                                                             const T* __restrict__ ec, double* __restrict__ phi,
                                                             const double* __restrict__ irs)
 {
-    using F = FsLds<T, MODE, M, R, D, IRU, CELL>;
+    using F = FsLds<T, MODE, M, R, D, IRU, CELL, PXY>;
     constexpr int NS = F::NS;
     __shared__ __align__(16) T sx[3][F::NW * F::NX];
     __shared__ __align__(16) T sc[3][F::NW * F::NX];
@@ -324,8 +343,8 @@ __global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const
     g.z1 = min(g.z0 + lz, d.nz);
     g.hal = false;
     g.hcol = 0;
-    g.wl = g.xi == 0 && !d.px;
-    g.wr = g.xi + 2 * M == d.nx && !d.px;
+    g.wl = !PXY && g.xi == 0 && !d.px;
+    g.wr = !PXY && g.xi + 2 * M == d.nx && !d.px;
     g.live = true;
     g.yfirst = g.ylast = true;
     const int t = threadIdx.x / kWave;  // row of the workgroup
@@ -430,7 +449,7 @@ constexpr int kFswMinPlanes = 8;
 // occupancy), lengthened until its plane steps (lz + 2) are whole groups of
 // the unrolled plane loop.  A second round of workgroups would double the
 // time of the few that run in it.
-template <typename T, int MODE, int M, bool IRU, bool CELL>
+template <typename T, int MODE, int M, bool IRU, bool CELL, bool PXY>
 static int fsw_chunk(const Dims& d, long long gy)
 {
     constexpr int NS = kFswAhead + 4;
@@ -440,7 +459,7 @@ static int fsw_chunk(const Dims& d, long long gy)
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(k_fsw_lds<T, MODE, M, kFswRows, kFswAhead, IRU, CELL>),
+                &per_cu, reinterpret_cast<const void*>(k_fsw_lds<T, MODE, M, kFswRows, kFswAhead, IRU, CELL, PXY>),
                 kWave * (kFswRows + 4), 0) != hipSuccess)
             return 16;
         resident = max(1, ncu * max(per_cu, 1));
@@ -451,21 +470,33 @@ static int fsw_chunk(const Dims& d, long long gy)
     return lz;
 }
 
+template <typename T, int MODE, int M, bool IRU, bool CELL, bool PXY>
+static void fsw_launch_p(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, const T* cxa, const T* cza,
+                         T h2, const T* ec, double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1,
+                         hipStream_t s)
+{
+    constexpr int R = kFswRows;
+    const long long gy = (d.ny + R - 1) / R;
+    const int lz = fsw_chunk<T, MODE, M, IRU, CELL, PXY>(d, gy);
+    const dim3 grid(1, (unsigned)gy, (unsigned)((d.nz + lz - 1) / lz));
+    const dim3 block(kWave * (R + 4));
+    if (ev0)
+        hipExtLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, kFswAhead, IRU, CELL, PXY>), grid, block, 0, s, ev0, ev1, 0, d,
+                              lz, xo, xn, b, cc, cxa, cza, h2, ec, phi, irs);
+    else
+        hipLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, kFswAhead, IRU, CELL, PXY>), grid, block, 0, s, d, lz, xo, xn, b,
+                           cc, cxa, cza, h2, ec, phi, irs);
+}
+
+// the variant without wall selects when x and y are both periodic
 template <typename T, int MODE, int M, bool IRU, bool CELL>
 static void fsw_launch(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, const T* cxa, const T* cza, T h2,
                        const T* ec, double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
 {
-    constexpr int R = kFswRows;
-    const long long gy = (d.ny + R - 1) / R;
-    const int lz = fsw_chunk<T, MODE, M, IRU, CELL>(d, gy);
-    const dim3 grid(1, (unsigned)gy, (unsigned)((d.nz + lz - 1) / lz));
-    const dim3 block(kWave * (R + 4));
-    if (ev0)
-        hipExtLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, kFswAhead, IRU, CELL>), grid, block, 0, s, ev0, ev1, 0, d, lz,
-                              xo, xn, b, cc, cxa, cza, h2, ec, phi, irs);
+    if (d.px && d.py)
+        fsw_launch_p<T, MODE, M, IRU, CELL, true>(d, xo, xn, b, cc, cxa, cza, h2, ec, phi, irs, ev0, ev1, s);
     else
-        hipLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, kFswAhead, IRU, CELL>), grid, block, 0, s, d, lz, xo, xn, b, cc,
-                           cxa, cza, h2, ec, phi, irs);
+        fsw_launch_p<T, MODE, M, IRU, CELL, false>(d, xo, xn, b, cc, cxa, cza, h2, ec, phi, irs, ev0, ev1, s);
 }
 
 template <typename T, int M>

@@ -102,6 +102,133 @@ void launch_rbgs_e(const Dims& d, T* phi, const T* rhs, const Coef<T>& c, T h2, 
     }
 }
 
+// Both colours of a sweep in one launch, out of place, for levels with stored
+// faces and even extents, where a launch costs more than its cells: thread
+// (p, j, k) owns cells 2p and 2p+1 of row j of plane k, one red and one black.
+// It updates the red cell from old values, then the black cell from the new
+// red values of its six neighbours, evaluating the five that lie outside the
+// pair again from old values.  A red value depends on old values only, so the
+// repeated evaluation gives the bits of the colour pass and no thread waits
+// on another.  Old values (MODE): FS_ZERO 0 (first sweep from a zero
+// iterate), FS_PLAIN x as stored, FS_PROLONG x + e of the parent cell (first
+// sweep after prolongation).  Every cell takes the operands of rbgs_cell /
+// k_rbgs_e: a black cell's neighbour behind a wall is its value as the
+// colour pass finds it stored (x, without e).
+template <typename T, int MODE>
+struct RbPair {
+    Dims d;
+    const T* __restrict__ xo;
+    const T* __restrict__ b;
+    const T* __restrict__ cx;
+    const T* __restrict__ cy;
+    const T* __restrict__ cz;
+    const T* __restrict__ ec;
+    T h2;
+
+    __device__ __forceinline__ int parent(int i, int j, int k) const
+    {
+        return ((k >> 1) * (d.ny >> 1) + (j >> 1)) * (d.nx >> 1) + (i >> 1);
+    }
+    __device__ __forceinline__ T old_at(int q, int i, int j, int k) const
+    {
+        if constexpr (MODE == FS_ZERO) return T(0);
+        else if constexpr (MODE == FS_PLAIN) return xo[q];
+        else return xo[q] + ec[parent(i, j, k)];
+    }
+    // face coefficients of cell q in stencil order (coef6, face mode)
+    __device__ __forceinline__ void coefs(int q, const Nb32& nb, T (&c)[6]) const
+    {
+        const T xh = cx[nb.xp], yh = cy[nb.yp], zh = cz[nb.zp];
+        c[0] = cx[q];
+        c[1] = nb.hx ? xh : T(0);
+        c[2] = cy[q];
+        c[3] = nb.hy ? yh : T(0);
+        c[4] = cz[q];
+        c[5] = nb.hz ? zh : T(0);
+    }
+    // new value of red cell (i, j, k) (coordinates inside the grid)
+    __device__ __forceinline__ T red(int i, int j, int k) const
+    {
+        const int q = (k * d.ny + j) * d.nx + i;
+        const Nb32 nb = nb32(d, q, i, j, k);
+        T c[6];
+        coefs(q, nb, c);
+        T v[6], own;
+        if constexpr (MODE == FS_ZERO) {
+            own = v[0] = v[1] = v[2] = v[3] = v[4] = v[5] = T(0);
+        } else {
+            // neighbour coordinates (a wall neighbour is the cell itself)
+            const int im = i > 0 ? i - 1 : (d.px ? d.nx - 1 : i), ip = i < d.nx - 1 ? i + 1 : (d.px ? 0 : i);
+            const int jm = j > 0 ? j - 1 : (d.py ? d.ny - 1 : j), jp = j < d.ny - 1 ? j + 1 : (d.py ? 0 : j);
+            const int km = k > 0 ? k - 1 : (d.pz ? d.nz - 1 : k), kp = k < d.nz - 1 ? k + 1 : (d.pz ? 0 : k);
+            own = old_at(q, i, j, k);
+            v[0] = old_at(nb.xm, im, j, k);
+            v[1] = old_at(nb.xp, ip, j, k);
+            v[2] = old_at(nb.ym, i, jm, k);
+            v[3] = old_at(nb.yp, i, jp, k);
+            v[4] = old_at(nb.zm, i, j, km);
+            v[5] = old_at(nb.zp, i, j, kp);
+        }
+        return gs_value<T>(c[0], c[1], c[2], c[3], c[4], c[5], v[0], v[1], v[2], v[3], v[4], v[5], b[q], h2, own);
+    }
+};
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_rb_pair(Dims d, const T* __restrict__ xo, T* __restrict__ xn,
+                                                 const T* __restrict__ b, const T* __restrict__ cx,
+                                                 const T* __restrict__ cy, const T* __restrict__ cz, T h2,
+                                                 const T* __restrict__ ec)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (p >= d.nx / 2 || j >= d.ny || k >= d.nz) return;
+    const RbPair<T, MODE> s{d, xo, b, cx, cy, cz, ec, h2};
+    const int par = (j + k) & 1;  // the red cell is 2p + par
+    const int ir = 2 * p + par, ib = 2 * p + 1 - par;
+    const int row = (k * d.ny + j) * d.nx;
+    const T rv = s.red(ir, j, k);
+    const int q = row + ib;
+    const Nb32 nb = nb32(d, q, ib, j, k);
+    // the black cell as the second colour pass finds it stored
+    const T stored = MODE == FS_ZERO ? T(0) : xo[q];
+    // red neighbours: one x neighbour is the pair's red cell; the other, and
+    // those in y and z, are evaluated here (-1: behind a wall)
+    const int io = par ? (ib > 0 ? ib - 1 : (d.px ? d.nx - 1 : -1)) : (ib < d.nx - 1 ? ib + 1 : (d.px ? 0 : -1));
+    const int jm = j > 0 ? j - 1 : (d.py ? d.ny - 1 : -1), jp = j < d.ny - 1 ? j + 1 : (d.py ? 0 : -1);
+    const int km = k > 0 ? k - 1 : (d.pz ? d.nz - 1 : -1), kp = k < d.nz - 1 ? k + 1 : (d.pz ? 0 : -1);
+    const T vo = io >= 0 ? s.red(io, j, k) : stored;
+    const T ym = jm >= 0 ? s.red(ib, jm, k) : stored;
+    const T yp = jp >= 0 ? s.red(ib, jp, k) : stored;
+    const T zm = km >= 0 ? s.red(ib, j, km) : stored;
+    const T zp = kp >= 0 ? s.red(ib, j, kp) : stored;
+    T c[6];
+    s.coefs(q, nb, c);
+    const T xm = par ? vo : rv, xp = par ? rv : vo;
+    const T bv = gs_value<T>(c[0], c[1], c[2], c[3], c[4], c[5], xm, xp, ym, yp, zm, zp, b[q], h2,
+                             s.old_at(q, ib, j, k));
+    xn[row + ir] = rv;
+    xn[q] = bv;
+}
+
+bool rb_pair_supported(const Dims& d)
+{
+    return d.nx % 2 == 0 && d.ny % 2 == 0 && d.nz % 2 == 0 && d.n() < (1LL << 31);
+}
+
+template <typename T>
+void launch_rb_pair(const Dims& d, const T* xo, T* xn, const T* b, const Coef<T>& c, T h2, int mode, const T* ec,
+                    hipStream_t s)
+{
+    const Shape3 sh = cells3(d.nx / 2, d.ny, d.nz);
+    if (mode == FS_ZERO)
+        hipLaunchKernelGGL((k_rb_pair<T, FS_ZERO>), sh.grid, sh.block, 0, s, d, xo, xn, b, c.x, c.y, c.z, h2, ec);
+    else if (mode == FS_PROLONG)
+        hipLaunchKernelGGL((k_rb_pair<T, FS_PROLONG>), sh.grid, sh.block, 0, s, d, xo, xn, b, c.x, c.y, c.z, h2, ec);
+    else
+        hipLaunchKernelGGL((k_rb_pair<T, FS_PLAIN>), sh.grid, sh.block, 0, s, d, xo, xn, b, c.x, c.y, c.z, h2, ec);
+}
+
 // --------------------------------------------------------- transfer operators
 
 template <typename T, bool CELL>
@@ -427,6 +554,8 @@ void launch_ir_update(long long n, double* phi, const float* e, const double* s,
 #define MP_INST(T)                                                                                                    \
     template void launch_rbgs<T>(const Dims&, T*, const T*, const Coef<T>&, T, int, int, hipStream_t);                \
     template void launch_rbgs_e<T>(const Dims&, T*, const T*, const Coef<T>&, T, int, int, const T*, hipStream_t);    \
+    template void launch_rb_pair<T>(const Dims&, const T*, T*, const T*, const Coef<T>&, T, int, const T*,           \
+                                    hipStream_t);                                                                     \
     template void launch_resid_restrict<T>(const Dims&, const T*, const T*, const Coef<T>&, T, T*, hipStream_t);      \
     template void launch_prolong<T>(const Dims&, T*, const T*, hipStream_t);                                          \
     template void launch_bottom<T>(const Dims&, const T*, T*, const T*, const T*, const T*, double, double, int, int, \

@@ -42,6 +42,7 @@ struct Level {
     bool blk = false;    // register-blocked kernels (finest level, cell mode)
     bool fsw = false;    // ... with both colours of a sweep in one pass
     bool blkf = false;   // register-blocked kernels with stored face coefficients
+    bool pair = false;   // both colours in one launch, one red and one black cell per thread
 };
 
 constexpr long long kCoarseCells = 4096;  // levels at or below may run in one workgroup (LDS permitting)
@@ -401,6 +402,17 @@ void smooth(mp_ctx* c, int l, bool zero_init, const T* ec, bool last = false)
             mp::launch_gs_blkf<T>(L.d, (T*)L.x, (const T*)L.b, C, h2, colour, mode, ec, c->stream);
             timed_end(c, tm, words * sizeof(T) * cells);
         }
+        return;
+    }
+    if (L.pair && !C.cell) {
+        // words per cell: x_old (unless zero), b, 3 coefficients, x_new, 1/8
+        // coarse e; the red neighbours evaluated again are read from cache
+        const double words = (zero_init ? 0.0 : 1.0) + 1.0 + 3.0 + 1.0 + (ec ? 0.125 : 0.0);
+        timed_begin(c, tm);
+        mp::launch_rb_pair<T>(L.d, (const T*)L.x, (T*)L.x2, (const T*)L.b, C, h2,
+                              zero_init ? mp::FS_ZERO : ec ? mp::FS_PROLONG : mp::FS_PLAIN, ec, c->stream);
+        timed_end(c, tm, words * sizeof(T) * cells);
+        std::swap(L.x, L.x2);
         return;
     }
     if (L.fused && !C.cell) {
@@ -1140,7 +1152,13 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
             L.fused = !L.blkf && mp::sweep_supported(L.d) &&
                       (cfg->smoother == MP_SMOOTH_FUSED ||
                        (cfg->smoother == MP_SMOOTH_AUTO && L.d.n() >= kFusedMinCells));
-            if (L.fused || (l > 0 && L.fsw)) {
+            // the remaining coarser levels (below the workgroup's coarse
+            // set): both colours in one launch with the red cells around each
+            // black cell evaluated again, where a launch costs more than the
+            // level's cells
+            L.pair = l > 0 && !L.blkf && !L.fused && mp::rb_pair_supported(L.d) &&
+                     cfg->smoother != MP_SMOOTH_PER_COLOUR;
+            if (L.fused || L.pair || (l > 0 && L.fsw)) {
                 void* p = nullptr;
                 e = hipMalloc(&p, tsz * L.d.n());
                 good &= e == hipSuccess;

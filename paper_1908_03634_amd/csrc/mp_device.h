@@ -79,6 +79,30 @@ __device__ __forceinline__ Nbr neighbours(const Dims& d, long long q, int i, int
     return b;
 }
 
+// The neighbours of neighbours() in 32-bit arithmetic, for levels of fewer
+// than 2^31 cells (a neighbour behind a wall is the cell itself; hx, hy, hz:
+// the high face lies inside the domain, else its coefficient is 0).
+struct Nb32 {
+    int xm, xp, ym, yp, zm, zp;
+    bool hx, hy, hz;
+};
+
+__device__ __forceinline__ Nb32 nb32(const Dims& d, int q, int i, int j, int k)
+{
+    const int sy = d.nx, sz = d.nx * d.ny;
+    Nb32 b;
+    b.xm = i > 0 ? q - 1 : (d.px ? q + (d.nx - 1) : q);
+    b.xp = i < d.nx - 1 ? q + 1 : (d.px ? q - (d.nx - 1) : q);
+    b.ym = j > 0 ? q - sy : (d.py ? q + (d.ny - 1) * sy : q);
+    b.yp = j < d.ny - 1 ? q + sy : (d.py ? q - (d.ny - 1) * sy : q);
+    b.zm = k > 0 ? q - sz : (d.pz ? q + (d.nz - 1) * sz : q);
+    b.zp = k < d.nz - 1 ? q + sz : (d.pz ? q - (d.nz - 1) * sz : q);
+    b.hx = i < d.nx - 1 || d.px;
+    b.hy = j < d.ny - 1 || d.py;
+    b.hz = k < d.nz - 1 || d.pz;
+    return b;
+}
+
 template <typename Tc>
 __device__ __forceinline__ Tc ld_or0(const Tc* a, long long q)
 {

@@ -186,6 +186,15 @@ void launch_gs_blk(const Dims& d, T* x, const T* b, const T* cc, T h2, int colou
 // phi != nullptr (FP32): also phi += irs[0] * xn.  Equal bit for bit to two
 // launch_gs_blk colour passes.
 enum { FS_PLAIN = 0, FS_ZERO = 1, FS_PROLONG = 2 };
+// Both colours of one red-black sweep in one launch, out of place (xo -> xn),
+// on a level with stored faces and even extents (rb_pair_supported), in the
+// modes above: a thread updates one red and one black cell, evaluating the
+// black cell's other red neighbours again from old values.  Equal bit for bit
+// to two launch_rbgs / launch_rbgs_e colour passes.
+bool rb_pair_supported(const Dims& d);
+template <typename T>
+void launch_rb_pair(const Dims& d, const T* xo, T* xn, const T* b, const Coef<T>& c, T h2, int mode, const T* ec,
+                    hipStream_t s);
 bool fsw_supported(const Dims& d);
 template <typename T>
 void launch_fsw_blk(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, T h2, int mode, const T* ec,

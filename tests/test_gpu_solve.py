@@ -173,21 +173,31 @@ def test_wrong_shapes_are_rejected():
 @pytest.mark.parametrize("shape,bc", [((32, 32, 32), (0, 0, 1)), ((40, 24, 16), (0, 0, 1)), ((48, 48, 48), (1, 1, 1)),
                                       ((128, 64, 64), (0, 0, 1)), ((24, 40, 32), (0, 1, 0))])
 def test_fused_sweep_is_bitwise_equal_to_per_colour_launches(precision, shape, bc):
-    """Both colours in one launch (x_old staged in LDS, red recomputed on a
-    halo ring, prolongation folded into the first post-smoothing sweep) give
-    exactly the bits of one launch per colour."""
+    """Both colours in one launch give exactly the bits of one launch per
+    colour: the tiled sweep (x_old staged in LDS, red recomputed on a halo
+    ring) with smoother="fused", and with "auto" the coarser levels' sweep
+    with one red and one black cell per thread (the black cell's other red
+    neighbours evaluated again), also on the smallest levels when the coarse
+    cycle is off; the prolongation folded into the first post-smoothing
+    sweep either way."""
     nx, ny, nz = shape
-    say("fused vs per-colour", shape, bc, precision)
     p = W.planar_problem(nz, nx=nx, ny=ny, bc=bc, contrast=1e3, seed=606)
-    outs = []
-    for sm in ("fused", "per_colour"):
-        r = gpu_project(p, precision, rtol=1e-10, smoother=sm)
-        outs.append((N(r["phi"]), N(r["uz"]), r["info"]["outer_iters"], r["info"]["resid_hist"]))
+
+    def run(sm, cc):
+        say("smoother", sm, "coarse cycle", cc, shape, bc, precision)
+        r = gpu_project(p, precision, rtol=1e-10, smoother=sm, coarse_cycle=cc)
+        out = (N(r["phi"]), N(r["uz"]), r["info"]["outer_iters"], r["info"]["resid_hist"])
         r["ctx"].close()
-    assert outs[0][2] == outs[1][2]
-    assert outs[0][3] == outs[1][3]
-    assert np.array_equal(outs[0][0], outs[1][0])
-    assert np.array_equal(outs[0][1], outs[1][1])
+        return out
+
+    for cc in (True, False):
+        ref = run("per_colour", cc)
+        for sm in ("fused", "auto") if cc else ("auto",):
+            out = run(sm, cc)
+            assert out[2] == ref[2]
+            assert out[3] == ref[3]
+            assert np.array_equal(out[0], ref[0])
+            assert np.array_equal(out[1], ref[1])
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
@@ -209,21 +219,23 @@ def test_coarse_cycle_kernel_matches_per_level_launches(precision):
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 @pytest.mark.parametrize("shape,bc", [((64, 64, 64), (0, 0, 1)), ((128, 32, 48), (1, 1, 1)), ((40, 24, 16), (0, 1, 0))])
 def test_fused_sweep_bitwise_with_face_coefficients(precision, shape, bc):
-    """Caller face coefficients (face mode on every level): the fused sweep on
-    every level against one launch per colour."""
+    """Caller face coefficients (face mode on every level): the fused sweeps
+    ("fused", and "auto" with its one-launch sweep on the coarser levels)
+    against one launch per colour."""
     nx, ny, nz = shape
     say("fused vs per-colour, face mode", shape, bc, precision)
     cx, cy, cz = W.random_coefs(nx, ny, nz, bc, 909)
     rhs = W.random_cells(nx, ny, nz, 910)
     outs = []
-    for sm in ("fused", "per_colour"):
+    for sm in ("per_colour", "fused", "auto"):
         ctx = mproj.Context(nx, ny, nz, h=1.0 / nz, bc=bc, precision=precision, rtol=1e-10, smoother=sm)
         ctx.set_coefs(T(cx), T(cy), T(cz))
         x, info = ctx.solve(T(rhs))
         outs.append((N(x), info["resid_hist"]))
         ctx.close()
-    assert outs[0][1] == outs[1][1]
-    assert np.array_equal(outs[0][0], outs[1][0])
+    for o in outs[1:]:
+        assert o[1] == outs[0][1]
+        assert np.array_equal(o[0], outs[0][0])
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
