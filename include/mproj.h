@@ -91,10 +91,10 @@ typedef struct mp_config {
                                 launch wherever it pays: register-blocked
                                 levels in MIXED whose rows are 128 or 256
                                 cells, face-coefficient levels of >= 4M cells
-                                (tiled), and the other levels below the
-                                finest with even extents (one red and one
-                                black cell per thread); one launch per colour
-                                elsewhere.
+                                (tiled), and the other FP32 levels below the
+                                finest of <= 64^3 cells with even extents (one
+                                red and one black cell per thread); one launch
+                                per colour elsewhere.
                                 MP_SMOOTH_PER_COLOUR: one launch per colour on
                                 every level; MP_SMOOTH_FUSED: both colours in
                                 one launch wherever the grid allows.  All

@@ -105,15 +105,17 @@ void launch_rbgs_e(const Dims& d, T* phi, const T* rhs, const Coef<T>& c, T h2, 
 // Both colours of a sweep in one launch, out of place, for levels with stored
 // faces and even extents, where a launch costs more than its cells: thread
 // (p, j, k) owns cells 2p and 2p+1 of row j of plane k, one red and one black.
-// It updates the red cell from old values, then the black cell from the new
-// red values of its six neighbours, evaluating the five that lie outside the
-// pair again from old values.  A red value depends on old values only, so the
-// repeated evaluation gives the bits of the colour pass and no thread waits
-// on another.  Old values (MODE): FS_ZERO 0 (first sweep from a zero
-// iterate), FS_PLAIN x as stored, FS_PROLONG x + e of the parent cell (first
-// sweep after prolongation).  Every cell takes the operands of rbgs_cell /
-// k_rbgs_e: a black cell's neighbour behind a wall is its value as the
-// colour pass finds it stored (x, without e).
+// It updates the red cell from old values and publishes it in LDS; after one
+// barrier it updates the black cell from the new red values of its six
+// neighbours, which are the red cells of the neighbouring threads (the pair
+// p -/+ 1 along x, the same p on the rows and planes beside it): taken from
+// LDS inside the workgroup, evaluated again from old values at its edges.  A
+// red value depends on old values only, so the repeated evaluation gives the
+// bits of the colour pass.  Old values (MODE): FS_ZERO 0 (first sweep from a
+// zero iterate), FS_PLAIN x as stored, FS_PROLONG x + e of the parent cell
+// (first sweep after prolongation).  Every cell takes the operands of
+// rbgs_cell / k_rbgs_e: a black cell's neighbour behind a wall is its value as
+// the colour pass finds it stored (x, without e).
 template <typename T, int MODE>
 struct RbPair {
     Dims d;
@@ -179,29 +181,41 @@ __global__ __launch_bounds__(256) void k_rb_pair(Dims d, const T* __restrict__ x
                                                  const T* __restrict__ cy, const T* __restrict__ cz, T h2,
                                                  const T* __restrict__ ec)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
-    const int k = blockIdx.z * blockDim.z + threadIdx.z;
-    if (p >= d.nx / 2 || j >= d.ny || k >= d.nz) return;
+    __shared__ T sred[256];
+    const int bx = (int)blockDim.x, by = (int)blockDim.y, bz = (int)blockDim.z;
+    const int p0 = (int)blockIdx.x * bx, j0 = (int)blockIdx.y * by, k0 = (int)blockIdx.z * bz;
+    const int p = p0 + (int)threadIdx.x, j = j0 + (int)threadIdx.y, k = k0 + (int)threadIdx.z;
+    const bool live = p < d.nx / 2 && j < d.ny && k < d.nz;
     const RbPair<T, MODE> s{d, xo, b, cx, cy, cz, ec, h2};
     const int par = (j + k) & 1;  // the red cell is 2p + par
     const int ir = 2 * p + par, ib = 2 * p + 1 - par;
+    const T rv = live ? s.red(ir, j, k) : T(0);
+    sred[((int)threadIdx.z * by + (int)threadIdx.y) * bx + (int)threadIdx.x] = rv;
+    __syncthreads();
+    if (!live) return;
+    // the red cell of pair (pn, jn, kn): from LDS when that thread is in this
+    // workgroup, else evaluated here
+    auto red_of = [&](int pn, int jn, int kn) -> T {
+        const int u = pn - p0, v = jn - j0, w = kn - k0;
+        if (u >= 0 && u < bx && v >= 0 && v < by && w >= 0 && w < bz) return sred[(w * by + v) * bx + u];
+        return s.red(2 * pn + ((jn + kn) & 1), jn, kn);
+    };
     const int row = (k * d.ny + j) * d.nx;
-    const T rv = s.red(ir, j, k);
     const int q = row + ib;
     const Nb32 nb = nb32(d, q, ib, j, k);
     // the black cell as the second colour pass finds it stored
     const T stored = MODE == FS_ZERO ? T(0) : xo[q];
-    // red neighbours: one x neighbour is the pair's red cell; the other, and
-    // those in y and z, are evaluated here (-1: behind a wall)
-    const int io = par ? (ib > 0 ? ib - 1 : (d.px ? d.nx - 1 : -1)) : (ib < d.nx - 1 ? ib + 1 : (d.px ? 0 : -1));
+    // one x neighbour is the pair's red cell; the other is the red cell of
+    // the pair beside it (-1: behind a wall)
+    const int np = d.nx / 2;
+    const int po = par ? (p > 0 ? p - 1 : (d.px ? np - 1 : -1)) : (p < np - 1 ? p + 1 : (d.px ? 0 : -1));
     const int jm = j > 0 ? j - 1 : (d.py ? d.ny - 1 : -1), jp = j < d.ny - 1 ? j + 1 : (d.py ? 0 : -1);
     const int km = k > 0 ? k - 1 : (d.pz ? d.nz - 1 : -1), kp = k < d.nz - 1 ? k + 1 : (d.pz ? 0 : -1);
-    const T vo = io >= 0 ? s.red(io, j, k) : stored;
-    const T ym = jm >= 0 ? s.red(ib, jm, k) : stored;
-    const T yp = jp >= 0 ? s.red(ib, jp, k) : stored;
-    const T zm = km >= 0 ? s.red(ib, j, km) : stored;
-    const T zp = kp >= 0 ? s.red(ib, j, kp) : stored;
+    const T vo = po >= 0 ? red_of(po, j, k) : stored;
+    const T ym = jm >= 0 ? red_of(p, jm, k) : stored;
+    const T yp = jp >= 0 ? red_of(p, jp, k) : stored;
+    const T zm = km >= 0 ? red_of(p, j, km) : stored;
+    const T zp = kp >= 0 ? red_of(p, j, kp) : stored;
     T c[6];
     s.coefs(q, nb, c);
     const T xm = par ? vo : rv, xp = par ? rv : vo;
@@ -216,17 +230,25 @@ bool rb_pair_supported(const Dims& d)
     return d.nx % 2 == 0 && d.ny % 2 == 0 && d.nz % 2 == 0 && d.n() < (1LL << 31);
 }
 
+// Workgroup of whole rows of pairs (up to 64 pairs wide) by a few rows and
+// planes, so that most red neighbours of a black cell lie inside it.
 template <typename T>
 void launch_rb_pair(const Dims& d, const T* xo, T* xn, const T* b, const Coef<T>& c, T h2, int mode, const T* ec,
                     hipStream_t s)
 {
-    const Shape3 sh = cells3(d.nx / 2, d.ny, d.nz);
+    const int np = d.nx / 2;
+    const int bx = pow2_at_least(np, 64);
+    const int rem = 256 / bx;
+    const int bz = pow2_at_least(d.nz, rem >= 16 ? 4 : rem >= 4 ? 2 : 1);
+    const int by = pow2_at_least(d.ny, rem / bz);
+    const dim3 block(bx, by, bz);
+    const dim3 grid((np + bx - 1) / bx, (d.ny + by - 1) / by, (d.nz + bz - 1) / bz);
     if (mode == FS_ZERO)
-        hipLaunchKernelGGL((k_rb_pair<T, FS_ZERO>), sh.grid, sh.block, 0, s, d, xo, xn, b, c.x, c.y, c.z, h2, ec);
+        hipLaunchKernelGGL((k_rb_pair<T, FS_ZERO>), grid, block, 0, s, d, xo, xn, b, c.x, c.y, c.z, h2, ec);
     else if (mode == FS_PROLONG)
-        hipLaunchKernelGGL((k_rb_pair<T, FS_PROLONG>), sh.grid, sh.block, 0, s, d, xo, xn, b, c.x, c.y, c.z, h2, ec);
+        hipLaunchKernelGGL((k_rb_pair<T, FS_PROLONG>), grid, block, 0, s, d, xo, xn, b, c.x, c.y, c.z, h2, ec);
     else
-        hipLaunchKernelGGL((k_rb_pair<T, FS_PLAIN>), sh.grid, sh.block, 0, s, d, xo, xn, b, c.x, c.y, c.z, h2, ec);
+        hipLaunchKernelGGL((k_rb_pair<T, FS_PLAIN>), grid, block, 0, s, d, xo, xn, b, c.x, c.y, c.z, h2, ec);
 }
 
 // --------------------------------------------------------- transfer operators

@@ -48,6 +48,7 @@ struct Level {
 constexpr long long kCoarseCells = 4096;  // levels at or below may run in one workgroup (LDS permitting)
 constexpr long long kWaveBottomCells = 256;
 constexpr long long kFusedMinCells = 1LL << 22;  // fused sweeps on levels at least this large
+constexpr long long kPairMaxCells = 1LL << 18;   // one-launch pair sweeps on levels at most this large
 
 // Multigrid coarsening: halve every axis while all extents are even and
 // at least 4 (the coarsest grid keeps >= 2 cells per axis).
@@ -1155,9 +1156,12 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
             // the remaining coarser levels (below the workgroup's coarse
             // set): both colours in one launch with the red cells around each
             // black cell evaluated again, where a launch costs more than the
-            // level's cells
+            // level's cells.  On larger levels, and in FP64 (a true division
+            // per evaluation), the repeated evaluations cost as much as the
+            // second launch: there only when asked for (MP_SMOOTH_FUSED)
             L.pair = l > 0 && !L.blkf && !L.fused && mp::rb_pair_supported(L.d) &&
-                     cfg->smoother != MP_SMOOTH_PER_COLOUR;
+                     (cfg->smoother == MP_SMOOTH_FUSED ||
+                      (cfg->smoother == MP_SMOOTH_AUTO && mx && L.d.n() <= kPairMaxCells));
             if (L.fused || L.pair || (l > 0 && L.fsw)) {
                 void* p = nullptr;
                 e = hipMalloc(&p, tsz * L.d.n());
