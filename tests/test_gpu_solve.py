@@ -171,15 +171,18 @@ def test_wrong_shapes_are_rejected():
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 @pytest.mark.parametrize("shape,bc", [((32, 32, 32), (0, 0, 1)), ((40, 24, 16), (0, 0, 1)), ((48, 48, 48), (1, 1, 1)),
-                                      ((128, 64, 64), (0, 0, 1)), ((24, 40, 32), (0, 1, 0))])
+                                      ((128, 64, 64), (0, 0, 1)), ((24, 40, 32), (0, 1, 0)), ((384, 8, 8), (0, 0, 1)),
+                                      ((384, 8, 8), (1, 0, 1))])
 def test_fused_sweep_is_bitwise_equal_to_per_colour_launches(precision, shape, bc):
     """Both colours in one launch give exactly the bits of one launch per
     colour: the tiled sweep (x_old staged in LDS, red recomputed on a halo
     ring) with smoother="fused", and with "auto" the coarser levels' sweep
     with one red and one black cell per thread (the black cell's other red
     neighbours evaluated again), also on the smallest levels when the coarse
-    cycle is off; the prolongation folded into the first post-smoothing
-    sweep either way."""
+    cycle is off (rows of 96 pairs span two workgroups of the one-launch
+    sweep at 384 cells: their x neighbours across the edge are evaluated
+    again); the prolongation folded into the first post-smoothing sweep
+    either way."""
     nx, ny, nz = shape
     p = W.planar_problem(nz, nx=nx, ny=ny, bc=bc, contrast=1e3, seed=606)
 
