@@ -752,12 +752,29 @@ void launch_nd_correct(const NDims& d, double inv4h, const double* sg, const dou
 // mean-zero; x starts at zero, or at the x passed in when use_x0 (the
 // tolerance is then relative to the initial residual), and is returned
 // mean-zero.  Stops at ||r|| <= rtol ||r0|| or maxit.  work holds 4 n doubles.
-template <typename T>
+// WAVE: run by the first wavefront alone (n <= 64), synchronised within it
+// (the other wavefronts of the workgroup wait at a later barrier); a sum is
+// lane 0's wavefront sum either way, so both forms give the same bits.
+template <typename T, bool WAVE = false>
 __device__ void nd_block_cg(const NDims& d, const T* __restrict__ bin, T* __restrict__ xout, const T* __restrict__ sg,
                             double inv_h12, double rtol, int maxit, int use_x0, double* __restrict__ work, double* sh)
 {
     const int n = d.mx * d.my * d.mz;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = WAVE ? (int)(threadIdx.x & (kWave - 1)) : (int)threadIdx.x;
+    const int nt = WAVE ? kWave : (int)blockDim.x;
+    auto sync = [&]() {
+        if constexpr (WAVE) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        } else {
+            __syncthreads();
+        }
+    };
+    auto total = [&](double v) {
+        if constexpr (WAVE) return wave_sum_bcast(v);
+        else return block_sum(v, sh);
+    };
     double* x = work;
     double* r = work + n;
     double* p = work + 2 * n;
@@ -765,7 +782,7 @@ __device__ void nd_block_cg(const NDims& d, const T* __restrict__ bin, T* __rest
     const long long sy = d.mx, sz = (long long)d.mx * d.my, cy = d.nx, cz = (long long)d.nx * d.ny;
     // out = A y (sigma in T, y in FP64); returns sum of y . out
     auto apply = [&](const double* y, double* out) {
-        __syncthreads();
+        sync();
         double acc = 0.0;
         for (int q = tid; q < n; q += nt) {
             int i, j, k;
@@ -789,16 +806,16 @@ __device__ void nd_block_cg(const NDims& d, const T* __restrict__ bin, T* __rest
             out[q] = v;
             acc = fma(y[q], v, acc);
         }
-        return block_sum(acc, sh);
+        return total(acc);
     };
     double part = 0.0;
     for (int q = tid; q < n; q += nt) part += (double)bin[q];
-    const double mb = block_sum(part, sh) / n;
+    const double mb = total(part) / n;
     for (int q = tid; q < n; q += nt) x[q] = use_x0 ? (double)xout[q] : 0.0;
     if (use_x0) (void)apply(x, ap);
     part = 0.0;
     for (int q = tid; q < n; q += nt) part += ((double)bin[q] - mb) - (use_x0 ? ap[q] : 0.0);
-    const double m0 = block_sum(part, sh) / n;
+    const double m0 = total(part) / n;
     part = 0.0;
     for (int q = tid; q < n; q += nt) {
         const double rq = ((double)bin[q] - mb) - (use_x0 ? ap[q] : 0.0) - m0;
@@ -806,7 +823,7 @@ __device__ void nd_block_cg(const NDims& d, const T* __restrict__ bin, T* __rest
         p[q] = rq;
         part = fma(rq, rq, part);
     }
-    double rr = block_sum(part, sh);
+    double rr = total(part);
     const double tol2 = rtol * rtol * rr;
     for (int it = 0; it < maxit && rr > tol2 && rr > 0.0; it++) {
         const double pap = apply(p, ap);
@@ -818,22 +835,22 @@ __device__ void nd_block_cg(const NDims& d, const T* __restrict__ bin, T* __rest
             r[q] = fma(-alpha, ap[q], r[q]);
             part += r[q];
         }
-        const double mr = block_sum(part, sh) / n;
+        const double mr = total(part) / n;
         part = 0.0;
         for (int q = tid; q < n; q += nt) {
             const double rq = r[q] - mr;
             r[q] = rq;
             part = fma(rq, rq, part);
         }
-        const double rr1 = block_sum(part, sh);
+        const double rr1 = total(part);
         const double beta = rr1 / rr;
         rr = rr1;
         for (int q = tid; q < n; q += nt) p[q] = fma(beta, p[q], r[q]);
     }
-    __syncthreads();
+    sync();
     part = 0.0;
     for (int q = tid; q < n; q += nt) part += x[q];
-    const double mx = block_sum(part, sh) / n;
+    const double mx = total(part) / n;
     for (int q = tid; q < n; q += nt) xout[q] = (T)(x[q] - mx);
 }
 
@@ -950,7 +967,15 @@ __global__ __launch_bounds__(1024) void k_nd_coarse(NdCoarseArgs<T> a)
         long long wo = nd_lds_off(a, nl) * (long long)sizeof(T);
         wo = (wo + 7) / 8;  // in doubles, 8-byte aligned
         double* work = reinterpret_cast<double*>(lds) + wo;
-        nd_block_cg<T>(d, x + nn, x, x + 3 * nn, a.bottom_inv_h12, a.bottom_rtol, a.bottom_maxit, 0, work, sh);
+        // a bottom of one wavefront's nodes runs in the first wavefront alone
+        // (no workgroup barriers inside the iteration)
+        if (nn <= kWave) {
+            if (threadIdx.x < kWave)
+                nd_block_cg<T, true>(d, x + nn, x, x + 3 * nn, a.bottom_inv_h12, a.bottom_rtol, a.bottom_maxit, 0,
+                                     work, sh);
+        } else {
+            nd_block_cg<T>(d, x + nn, x, x + 3 * nn, a.bottom_inv_h12, a.bottom_rtol, a.bottom_maxit, 0, work, sh);
+        }
         __syncthreads();
     }
     // up
