@@ -543,9 +543,57 @@ __global__ __launch_bounds__(256) void k_nd_prolong(NDims f, NDims c, T* __restr
     xf[((long long)k * f.my + j) * f.mx + i] += nd_prolong_node<T>(c, ec, i, j, k);
 }
 
+// x_f += P e_c for a column of fine nodes per thread: the sum over the two
+// coarse rows of a coarse plane (the inner two loops of nd_prolong_node) is
+// formed once per coarse plane and serves the two or three fine planes that
+// read it; each node then adds the sums of its planes in the order of
+// nd_prolong_node (bitwise equal).
 template <typename T>
-void launch_nd_prolong(const NDims& f, const NDims& c, T* xf, const T* ec, hipStream_t s)
+__global__ __launch_bounds__(256) void k_nd_prolong_col(NDims f, NDims c, int lz, T* __restrict__ xf,
+                                                        const T* __restrict__ ec)
 {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k0 = blockIdx.z * lz;
+    const int k1 = min(k0 + lz, f.mz);
+    if (i >= f.mx || j >= f.my) return;
+    const int I0 = i >> 1, I1 = (i & 1) ? ((i + 1) >> 1 == c.mx ? 0 : (i + 1) >> 1) : I0;
+    const int J0 = j >> 1, J1 = (j & 1) ? ((j + 1) >> 1 == c.my ? 0 : (j + 1) >> 1) : J0;
+    const long long sy = c.mx, sz = (long long)c.mx * c.my;
+    auto plane_sum = [&](int K) {
+        T row = T(0);
+        row += ec[K * sz + J0 * sy + I0] + ec[K * sz + J0 * sy + I1];
+        row += ec[K * sz + J1 * sy + I0] + ec[K * sz + J1 * sy + I1];
+        return row;
+    };
+    int kc = -1;  // coarse plane whose sum is held in rc
+    T rc = T(0);
+    auto sum_of = [&](int K) {
+        if (K != kc) {
+            rc = plane_sum(K);
+            kc = K;
+        }
+        return rc;
+    };
+    const long long fsy = f.mx, fsz = (long long)f.mx * f.my;
+    for (int k = k0; k < k1; k++) {
+        const int K0 = k >> 1, K1 = (k & 1) ? ((k + 1) >> 1 == c.mz ? 0 : (k + 1) >> 1) : K0;
+        T acc = T(0);
+        acc += sum_of(K0);
+        acc += sum_of(K1);
+        const long long q = k * fsz + j * fsy + i;
+        xf[q] += T(0.125) * acc;
+    }
+}
+
+template <typename T>
+void launch_nd_prolong(const NDims& f, const NDims& c, T* xf, const T* ec, int col, hipStream_t s)
+{
+    if (col && f.mz >= 2) {
+        const ColShape cs = col_shape(f.mx, f.my, f.mz, 1024, 1LL << 30);
+        hipLaunchKernelGGL((k_nd_prolong_col<T>), cs.grid, cs.block, 0, s, f, c, cs.lz, xf, ec);
+        return;
+    }
     const Shape3 sh = cells3(f.mx, f.my, f.mz);
     hipLaunchKernelGGL((k_nd_prolong<T>), sh.grid, sh.block, 0, s, f, c, xf, ec);
 }
@@ -1029,7 +1077,7 @@ template void launch_nd_coarse<double>(const NdCoarseArgs<double>&, hipStream_t)
     template void launch_nd_gs<T>(const NDims&, T*, const T*, const T*, T, int, hipStream_t);             \
     template void launch_nd_resid<T>(const NDims&, const T*, const T*, const T*, T, T*, hipStream_t);     \
     template void launch_nd_restrict<T>(const NDims&, const NDims&, const T*, T*, hipStream_t);           \
-    template void launch_nd_prolong<T>(const NDims&, const NDims&, T*, const T*, hipStream_t);            \
+    template void launch_nd_prolong<T>(const NDims&, const NDims&, T*, const T*, int, hipStream_t);       \
     template void launch_nd_bottom<T>(const NDims&, const T*, T*, const T*, double, double, int, int,     \
                                       double*, hipStream_t);
 ND_INST(float)

@@ -857,7 +857,7 @@ void nd_vcycle(mp_ctx* c, int l)
     mp::launch_nd_restrict<T>(L.d, C.d, (const T*)L.r, (T*)C.b, c->stream);
     if (l + 1 < nlev - 1 && l + 1 != N.coarse_start) (void)hipMemsetAsync(C.x, 0, sizeof(T) * C.nn, c->stream);
     nd_vcycle<T>(c, l + 1);
-    mp::launch_nd_prolong<T>(L.d, C.d, (T*)L.x, (const T*)C.x, c->stream);
+    mp::launch_nd_prolong<T>(L.d, C.d, (T*)L.x, (const T*)C.x, L.col ? 1 : 0, c->stream);
     for (int s = 0; s < c->cfg.nu2; s++) sweep(false);
 }
 

@@ -278,9 +278,10 @@ void launch_nd_resid(const NDims& d, const T* x, const T* b, const T* sg, T inv_
 // bc = (1/8) P^T rf (P trilinear interpolation from the grid coarsened by 2).
 template <typename T>
 void launch_nd_restrict(const NDims& f, const NDims& c, const T* rf, T* bc, hipStream_t s);
-// xf += P ec.
+// xf += P ec; col != 0: a column of fine nodes per thread, each coarse
+// plane's sum formed once (the same bits as one thread per node).
 template <typename T>
-void launch_nd_prolong(const NDims& f, const NDims& c, T* xf, const T* ec, hipStream_t s);
+void launch_nd_prolong(const NDims& f, const NDims& c, T* xf, const T* ec, int col, hipStream_t s);
 // The smoother colour and the residuals above by threads that walk node
 // columns along z (registers carry the neighbour planes); bitwise equal to
 // the one-node kernels.  Valid when nd_col_supported(d).
