@@ -558,15 +558,24 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
 // count; 0 predicts it from the contraction of the last step,
 // rho = (rel / rel_prev)^(1 / m_prev): about log(rtol / rel) / log(rho)
 // cycles, at least 1 and at most 4 (FP32 corrections gain nothing beyond).
+// From a zero iterate the first step runs the most, kFirstCycles, instead of
+// one measuring cycle: the first cycle contracts most (~1e-2), so 4 cycles
+// end near 1e-6, still above the FP32 floor.  The nodal solves at 256^3 then
+// reach 1e-10 in two steps (4 + 3 cycles) instead of three; the MAC solves
+// take 4 + 3 + 1 cycles instead of 1 + 4 + 3 (the prediction after the first
+// step, from its mean rate, falls a cycle short by a hair).
 // The contraction per cycle weakens as the smooth error components remain
 // (on the stratified workloads ~0.03 for the second cycle, ~0.08 for the
 // eighth), so the mean rate of the last step is discounted by a fifth: a
 // prediction one cycle short costs a whole refinement step (an FP64 residual
 // and a read-back) to run the missing cycle.
-int cycles_this_step(const mp_ctx* c, int it, double rel, double rel_prev, int m_prev)
+constexpr int kFirstCycles = 4;
+
+int cycles_this_step(const mp_ctx* c, int it, double rel, double rel_prev, int m_prev, bool from_zero)
 {
     if (c->cfg.cycles_per_outer > 0) return c->cfg.cycles_per_outer;
-    if (it == 0 || !(rel_prev > 0.0) || !(rel > 0.0)) return 1;
+    if (it == 0) return from_zero ? kFirstCycles : 1;
+    if (!(rel_prev > 0.0) || !(rel > 0.0)) return 1;
     const double rho = pow(rel / rel_prev, 1.0 / m_prev);
     if (!(rho > 0.0) || rho >= 0.5) return 1;
     const double need = log(c->cfg.rtol / rel) / (0.8 * log(rho));
@@ -641,7 +650,7 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
             fail(c, MP_ERR_NOT_CONVERGED, "stagnated at step %d (rel. residual %.3e)", it, rel);
             break;
         }
-        const int m = cycles_this_step(c, it, rel, rel_prev, m_prev);
+        const int m = cycles_this_step(c, it, rel, rel_prev, m_prev, it == 0 && !use_guess);
         rel_prev = rel;
         m_prev = m;
         if (mx) {
@@ -930,7 +939,7 @@ int nd_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
             fail(c, MP_ERR_NOT_CONVERGED, "nodal solve stagnated at step %d (rel. residual %.3e)", it, rel);
             break;
         }
-        const int m = cycles_this_step(c, it, rel, rel_prev, m_prev);
+        const int m = cycles_this_step(c, it, rel, rel_prev, m_prev, it == 0 && !use_guess);
         rel_prev = rel;
         m_prev = m;
         if (mx) {
