@@ -560,10 +560,10 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
 // cycles, at least 1 and at most 4 (FP32 corrections gain nothing beyond).
 // From a zero iterate the first step runs the most, kFirstCycles, instead of
 // one measuring cycle: the first cycle contracts most (~1e-2), so 4 cycles
-// end near 1e-6, still above the FP32 floor.  The nodal solves at 256^3 then
-// reach 1e-10 in two steps (4 + 3 cycles) instead of three; the MAC solves
-// take 4 + 3 + 1 cycles instead of 1 + 4 + 3 (the prediction after the first
-// step, from its mean rate, falls a cycle short by a hair).
+// end near 1e-6, still above the FP32 floor.  The mean rate of such a step
+// includes that first cycle, so the prediction aims at half the tolerance:
+// the MAC and nodal solves at 256^3 then reach 1e-10 in two steps (4 + 4 and
+// 4 + 3 cycles) instead of three.
 // The contraction per cycle weakens as the smooth error components remain
 // (on the stratified workloads ~0.03 for the second cycle, ~0.08 for the
 // eighth), so the mean rate of the last step is discounted by a fifth: a
@@ -578,7 +578,7 @@ int cycles_this_step(const mp_ctx* c, int it, double rel, double rel_prev, int m
     if (!(rel_prev > 0.0) || !(rel > 0.0)) return 1;
     const double rho = pow(rel / rel_prev, 1.0 / m_prev);
     if (!(rho > 0.0) || rho >= 0.5) return 1;
-    const double need = log(c->cfg.rtol / rel) / (0.8 * log(rho));
+    const double need = log(0.5 * c->cfg.rtol / rel) / (0.8 * log(rho));
     const int m = (int)ceil(need - 0.25);
     return m < 1 ? 1 : m > 4 ? 4 : m;
 }
