@@ -38,7 +38,10 @@
 
 namespace mp {
 
-bool fsw_supported(const Dims& d) { return blk_supported(d) && (d.nx == 128 || d.nx == 256); }
+bool fsw_supported(const Dims& d)
+{
+    return blk_supported(d) && (d.nx == 128 || d.nx == 256 || d.nx == 384 || d.nx == 512);
+}
 
 // The M cells of one parity (q even or q odd) of a lane's strip.
 template <typename T, int M>
@@ -158,6 +161,8 @@ __device__ __forceinline__ void lds_put_half(T* p, const Strip<T, M>& s, int par
     for (int e = 0; e < M; e++) h[e] = par ? s.v[2 * e + 1] : s.v[2 * e];
     if constexpr (M == 2) {
         *reinterpret_cast<typename V2<T>::type*>(p) = typename V2<T>::type{h[0], h[1]};
+    } else if constexpr (M == 4 && sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(h[0], h[1], h[2], h[3]);
     } else {
 #pragma unroll
         for (int e = 0; e < M; e++) p[e] = h[e];
@@ -178,6 +183,12 @@ __device__ __forceinline__ Half<T, M> lds_get_half(const T* p)
         const typename V2<T>::type v = *reinterpret_cast<const typename V2<T>::type*>(p);
         h.v[0] = v.x;
         h.v[1] = v.y;
+    } else if constexpr (M == 4 && sizeof(T) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        h.v[0] = v.x;
+        h.v[1] = v.y;
+        h.v[2] = v.z;
+        h.v[3] = v.w;
     } else {
 #pragma unroll
         for (int e = 0; e < M; e++) h.v[e] = p[e];
@@ -438,36 +449,56 @@ __global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const
     }
 }
 
-// Rows owned by a workgroup, planes loaded ahead, and the shortest chunk.
-constexpr int kFswRows = 8;
-constexpr int kFswAhead = 1;
+// Launch shape by strip width M (2M cells per lane, rows of 128 M cells):
+// rows owned by a workgroup (R + 4 wavefronts) and planes loaded ahead (D).
+// Rows of up to 256 cells: 8 rows, 12 wavefronts, three per SIMD.  Rows of
+// 384 and 512 cells hold 6 or 8 cells per lane in every plane slot: 4 rows,
+// 8 wavefronts, two per SIMD, which the larger strips need for registers.
+template <int M>
+struct FswShape {
+    static constexpr int R = M <= 2 ? 8 : 4;
+    static constexpr int D = M <= 3 ? 1 : 0;
+};
 constexpr int kFswMinPlanes = 8;
 
-// Planes per chunk: the shortest chunk (at least kFswMinPlanes, which bounds
-// the share of the four planes a chunk reads beyond its own) for which the
-// whole grid is resident at once (workgroups per CU from the kernel's
-// occupancy), lengthened until its plane steps (lz + 2) are whole groups of
-// the unrolled plane loop.  A second round of workgroups would double the
-// time of the few that run in it.
+// Planes per chunk.  Each workgroup marches lz + 2 plane steps, and the
+// per-plane critical path (barrier, LDS round trips, the two updates) rather
+// than HBM bounds a workgroup, so the sweep takes about (rounds of resident
+// workgroups) x (lz + 2) plane steps: the chunk count minimising that is
+// taken (at least kFswMinPlanes planes, which bounds the share of the four
+// planes a chunk reads beyond its own), each chunk lengthened until its plane
+// steps are whole groups of the unrolled plane loop.  256^3 (32 row blocks):
+// 8 chunks of 33 planes in one round; 512^3 (128 row blocks): 2 of 258;
+// 384^3 (96 row blocks): 8 chunks of 48 planes in three rounds rather than 2
+// chunks of 192 on three quarters of the CUs.
 template <typename T, int MODE, int M, bool IRU, bool CELL, bool PXY>
 static int fsw_chunk(const Dims& d, long long gy)
 {
-    constexpr int NS = kFswAhead + 4;
+    constexpr int R = FswShape<M>::R, D = FswShape<M>::D, NS = D + 4;
     static int resident = 0;  // workgroups resident on the device at once
     if (resident == 0) {
         int dev = 0, ncu = 0, per_cu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(k_fsw_lds<T, MODE, M, kFswRows, kFswAhead, IRU, CELL, PXY>),
-                kWave * (kFswRows + 4), 0) != hipSuccess)
+                &per_cu, reinterpret_cast<const void*>(k_fsw_lds<T, MODE, M, R, D, IRU, CELL, PXY>), kWave * (R + 4),
+                0) != hipSuccess)
             return 16;
         resident = max(1, ncu * max(per_cu, 1));
     }
-    const long long chunks = max(1LL, resident / gy);
-    int lz = max((int)((d.nz + chunks - 1) / chunks), kFswMinPlanes);
-    lz += (NS - (lz + 2) % NS) % NS;
-    return lz;
+    int best = d.nz;
+    long long best_cost = -1;
+    for (int c = 1; c == 1 || d.nz / c >= kFswMinPlanes; c++) {
+        int lz = max((d.nz + c - 1) / c, kFswMinPlanes);
+        lz += (NS - (lz + 2) % NS) % NS;
+        const long long wgs = gy * ((d.nz + lz - 1) / lz);
+        const long long cost = (wgs + resident - 1) / resident * (lz + 2);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = lz;
+        }
+    }
+    return best;
 }
 
 template <typename T, int MODE, int M, bool IRU, bool CELL, bool PXY>
@@ -475,16 +506,16 @@ static void fsw_launch_p(const Dims& d, const T* xo, T* xn, const T* b, const T*
                          T h2, const T* ec, double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1,
                          hipStream_t s)
 {
-    constexpr int R = kFswRows;
+    constexpr int R = FswShape<M>::R, D = FswShape<M>::D;
     const long long gy = (d.ny + R - 1) / R;
     const int lz = fsw_chunk<T, MODE, M, IRU, CELL, PXY>(d, gy);
     const dim3 grid(1, (unsigned)gy, (unsigned)((d.nz + lz - 1) / lz));
     const dim3 block(kWave * (R + 4));
     if (ev0)
-        hipExtLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, kFswAhead, IRU, CELL, PXY>), grid, block, 0, s, ev0, ev1, 0, d,
+        hipExtLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, D, IRU, CELL, PXY>), grid, block, 0, s, ev0, ev1, 0, d,
                               lz, xo, xn, b, cc, cxa, cza, h2, ec, phi, irs);
     else
-        hipLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, kFswAhead, IRU, CELL, PXY>), grid, block, 0, s, d, lz, xo, xn, b,
+        hipLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, D, IRU, CELL, PXY>), grid, block, 0, s, d, lz, xo, xn, b,
                            cc, cxa, cza, h2, ec, phi, irs);
 }
 
@@ -532,8 +563,12 @@ template <typename T>
 void launch_fsw_blk(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, T h2, int mode, const T* ec,
                     double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
 {
-    if (d.nx == 256) fsw_mode<T, 2>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s);
-    else fsw_mode<T, 1>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s);
+    switch (d.nx) {
+    case 512: fsw_mode<T, 4>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s); break;
+    case 384: fsw_mode<T, 3>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s); break;
+    case 256: fsw_mode<T, 2>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s); break;
+    default: fsw_mode<T, 1>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s); break;
+    }
 }
 
 template <typename T, int M>
@@ -560,8 +595,12 @@ template <typename T>
 void launch_fsw_blkf(const Dims& d, const T* xo, T* xn, const T* b, const Coef<T>& c, T h2, int mode, const T* ec,
                      hipStream_t s)
 {
-    if (d.nx == 256) fswf_mode<T, 2>(mode, d, xo, xn, b, c, h2, ec, s);
-    else fswf_mode<T, 1>(mode, d, xo, xn, b, c, h2, ec, s);
+    switch (d.nx) {
+    case 512: fswf_mode<T, 4>(mode, d, xo, xn, b, c, h2, ec, s); break;
+    case 384: fswf_mode<T, 3>(mode, d, xo, xn, b, c, h2, ec, s); break;
+    case 256: fswf_mode<T, 2>(mode, d, xo, xn, b, c, h2, ec, s); break;
+    default: fswf_mode<T, 1>(mode, d, xo, xn, b, c, h2, ec, s); break;
+    }
 }
 
 template void launch_fsw_blk<float>(const Dims&, const float*, float*, const float*, const float*, float, int,

@@ -146,12 +146,14 @@ def test_unaligned_solution_array_uses_one_cell_kernels():
 
 
 @pytest.mark.parametrize("bc", BCS)
-@pytest.mark.parametrize("shape", [(128, 12, 6), (128, 36, 32), (256, 20, 10), (256, 48, 64)])
+@pytest.mark.parametrize("shape", [(128, 12, 6), (128, 36, 32), (256, 20, 10), (256, 48, 64), (384, 12, 10),
+                                   (384, 20, 36), (512, 8, 6), (512, 36, 36)])
 def test_fused_blocked_sweep_equals_colour_passes(shape, bc):
     """Both colours of a sweep in one out-of-place pass (rows wider than the
     owned ones recomputed, plane chunks started two planes early) equal the two
     in-place colour passes bit for bit, through a refinement step and over a
-    full solve."""
+    full solve: rows of 128 and 256 cells (8 owned rows per workgroup) and of
+    384 and 512 cells (6 and 8 cells per lane, 4 owned rows)."""
     say("fused blocked sweep", shape, bc)
     p = _problem(shape, bc, 5000 + sum(shape))
     rhs = W.random_cells(*shape, 5100 + sum(shape))
