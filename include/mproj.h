@@ -89,8 +89,8 @@ typedef struct mp_config {
                                 HIP events (mp_info.smooth_*) */
     int smoother;            /* MP_SMOOTH_AUTO: both colours of a sweep in one
                                 launch wherever it pays: register-blocked
-                                levels in MIXED whose rows are 128 or 256
-                                cells, face-coefficient levels of >= 4M cells
+                                levels in MIXED whose rows are 128, 256, 384
+                                or 512 cells, face-coefficient levels of >= 4M cells
                                 (tiled), and the other FP32 levels below the
                                 finest of <= 64^3 cells with even extents (one
                                 red and one black cell per thread); one launch
@@ -119,13 +119,18 @@ typedef struct mp_info {
     int outer_iters;         /* residual checks after the first (refinement
                                 steps in MIXED) */
     int vcycles;             /* V-cycles run */
-    int bottom_iters_total;  /* reserved (BiCGStab counts stay on the device) */
+    int bottom_iters_total;  /* iterations of every coarsest-grid solve of the
+                                call (conjugate gradients or BiCGStab),
+                                counted on the device */
     int levels;              /* multigrid levels, finest included */
     double rel_resid;        /* final ||rhs - M phi||_2 / ||rhs||_2 in FP64 */
     double div_defect;       /* ||D(beta0 U_new) - beta0 S - m||_2 / ||rhs||_2 */
     double rhs_norm;         /* ||rhs||_2 after the mean is removed */
     double rhs_mean;         /* mean removed from div(beta0 U) - beta0 S */
     double resid_hist[64];   /* relative residual at each check */
+    double ms_setup;         /* duration of the last mp_map_base_state or
+                                mp_set_coefs on this context (fill, faces,
+                                coefficient hierarchy; HIP events) */
     double ms_rhs, ms_solve, ms_correct;   /* phase times (HIP events) */
     double smooth_ms_total;  /* summed finest-level smoother time (kernel_timing) */
     int smooth_launches;     /* number of launches summed above */

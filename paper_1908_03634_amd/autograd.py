@@ -15,15 +15,22 @@ import torch
 from .mproj import Context
 
 
-def _key(ts):
-    return tuple((t.data_ptr(), t._version) for t in ts)
+def _key(solver: Context, ts):
+    return (solver.coef_generation,) + tuple((t.data_ptr(), t._version) for t in ts)
 
 
 def _ensure_coefs(solver: Context, cx, cy, cz):
-    k = _key((cx, cy, cz))
-    if getattr(solver, "_coef_key", None) != k:
+    """Load (cx, cy, cz) into the solver unless exactly these values are
+    loaded already.  The key holds the solver's coefficient generation (bumped
+    by every map_base_state and set_coefs, so coefficients replaced by any
+    other call are loaded again), and the address and version counter of
+    each tensor (an in-place change bumps the version; views and detached
+    tensors share it).  The cached tensors are kept alive with the key, so
+    no other tensor can take their memory and match it by address."""
+    if getattr(solver, "_coef_key", None) != _key(solver, (cx, cy, cz)):
         solver.set_coefs(cx, cy, cz)
-        solver._coef_key = k
+        solver._coef_key = _key(solver, (cx, cy, cz))
+        solver._coef_refs = (cx, cy, cz)
 
 
 class MacSolve(torch.autograd.Function):

@@ -37,7 +37,7 @@ __device__ __forceinline__ double wave_get(const double (&v)[NS], int nq)
 template <typename T, int NS>
 __device__ void wave_cg(const Dims& d, const T* __restrict__ bin, T* __restrict__ xout,
                               const T* __restrict__ cx, const T* __restrict__ cy, const T* __restrict__ cz, double h2,
-                              double rtol, int maxit)
+                              double rtol, int maxit, double* __restrict__ iters)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int n = (int)d.n();
@@ -103,7 +103,8 @@ __device__ void wave_cg(const Dims& d, const T* __restrict__ bin, T* __restrict_
     // the residual is kept mean-zero against rounding
     double rr = dot(r, r);
     const double tol2 = rtol * rtol * rr;
-    for (int it = 0; it < maxit && rr > tol2 && rr > 0.0; it++) {
+    int it = 0;
+    for (; it < maxit && rr > tol2 && rr > 0.0; it++) {
         apply(p, v);
         const double pv = dot(p, v);
         if (!(pv > 0.0)) break;
@@ -124,6 +125,9 @@ __device__ void wave_cg(const Dims& d, const T* __restrict__ bin, T* __restrict_
 #pragma unroll
         for (int u = 0; u < NS; u++) p[u] = fma(beta, p[u], r[u]);
     }
+    // iterations of this solve added to the caller's running count (one
+    // lane; the solves of a stream run one after another)
+    if (iters && lane == 0) iters[0] += (double)it;
     part = 0.0;
 #pragma unroll
     for (int u = 0; u < NS; u++) part += live[u] ? x[u] : 0.0;
@@ -317,7 +321,8 @@ __global__ __launch_bounds__(1024) void k_coarse_cycle(CoarseArgs<T> a)
     // bottom: first wavefront only; the others wait at the barrier below
     if (threadIdx.x < kWave) {
         const CoarseLevel<T> B = lds_level(a, nl - 1, lds);
-        wave_cg<T, NS>(cdims(a, nl - 1), B.b, B.x, B.cx, B.cy, B.cz, B.h2d, a.bottom_rtol, a.bottom_maxit);
+        wave_cg<T, NS>(cdims(a, nl - 1), B.b, B.x, B.cx, B.cy, B.cz, B.h2d, a.bottom_rtol, a.bottom_maxit,
+                       a.bottom_iters);
     }
     __syncthreads();
     // up

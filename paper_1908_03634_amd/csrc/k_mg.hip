@@ -309,7 +309,7 @@ template <typename T>
 __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ bin, T* __restrict__ xout,
                                                  const T* __restrict__ cx, const T* __restrict__ cy,
                                                  const T* __restrict__ cz, double h2, double rtol, int maxit,
-                                                 int use_x0, double* __restrict__ work)
+                                                 int use_x0, double* __restrict__ work, double* __restrict__ iters)
 {
     __shared__ double sh[16];
     const int n = (int)d.n();
@@ -356,8 +356,9 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
     const double tol2 = rtol * rtol * bnorm2;
     double rho = 1.0, alpha = 1.0, omega = 1.0;
 
+    int it = 0;  // iterations begun (each ends in a break or a full step)
     if (bnorm2 > 0.0) {
-        for (int it = 0; it < maxit; it++) {
+        for (; it < maxit; it++) {
             part = 0.0;
             for (int q = tid; q < n; q += nt) part = fma(rh[q], r[q], part);
             const double rho1 = block_sum(part, sh);
@@ -405,6 +406,7 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
             if (rr <= tol2 || omega == 0.0) break;
         }
     }
+    if (iters && tid == 0) iters[0] += (double)(it < maxit ? it + (bnorm2 > 0.0 ? 1 : 0) : it);
     __syncthreads();
     part = 0.0;
     for (int q = tid; q < n; q += nt) part += x[q];
@@ -414,13 +416,13 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
 
 template <typename T>
 void launch_bottom(const Dims& d, const T* rhs, T* phi, const T* cx, const T* cy, const T* cz, double h2, double rtol,
-                   int maxit, int use_x0, double* work, hipStream_t s)
+                   int maxit, int use_x0, double* work, double* iters, hipStream_t s)
 {
     long long n = d.n();
     int nt = (int)((n + 63) / 64) * 64;
     if (nt > 1024) nt = 1024;
     hipLaunchKernelGGL((k_bottom<T>), dim3(1), dim3(nt), 0, s, d, rhs, phi, cx, cy, cz, h2, rtol, maxit, use_x0,
-                       work);
+                       work, iters);
 }
 
 // --------------------------------------------------------- FP64 level 0
@@ -581,7 +583,7 @@ void launch_ir_update(long long n, double* phi, const float* e, const double* s,
     template void launch_resid_restrict<T>(const Dims&, const T*, const T*, const Coef<T>&, T, T*, hipStream_t);      \
     template void launch_prolong<T>(const Dims&, T*, const T*, hipStream_t);                                          \
     template void launch_bottom<T>(const Dims&, const T*, T*, const T*, const T*, const T*, double, double, int, int, \
-                                   double*, hipStream_t);
+                                   double*, double*, hipStream_t);
 MP_INST(float)
 MP_INST(double)
 

@@ -805,7 +805,8 @@ void launch_nd_correct(const NDims& d, double inv4h, const double* sg, const dou
 // lane 0's wavefront sum either way, so both forms give the same bits.
 template <typename T, bool WAVE = false>
 __device__ void nd_block_cg(const NDims& d, const T* __restrict__ bin, T* __restrict__ xout, const T* __restrict__ sg,
-                            double inv_h12, double rtol, int maxit, int use_x0, double* __restrict__ work, double* sh)
+                            double inv_h12, double rtol, int maxit, int use_x0, double* __restrict__ work, double* sh,
+                            double* __restrict__ iters = nullptr)
 {
     const int n = d.mx * d.my * d.mz;
     const int tid = WAVE ? (int)(threadIdx.x & (kWave - 1)) : (int)threadIdx.x;
@@ -873,7 +874,8 @@ __device__ void nd_block_cg(const NDims& d, const T* __restrict__ bin, T* __rest
     }
     double rr = total(part);
     const double tol2 = rtol * rtol * rr;
-    for (int it = 0; it < maxit && rr > tol2 && rr > 0.0; it++) {
+    int it = 0;
+    for (; it < maxit && rr > tol2 && rr > 0.0; it++) {
         const double pap = apply(p, ap);
         if (!(pap > 0.0)) break;
         const double alpha = rr / pap;
@@ -895,6 +897,8 @@ __device__ void nd_block_cg(const NDims& d, const T* __restrict__ bin, T* __rest
         rr = rr1;
         for (int q = tid; q < n; q += nt) p[q] = fma(beta, p[q], r[q]);
     }
+    // iterations of this solve added to the caller's running count
+    if (iters && tid == 0) iters[0] += (double)it;
     sync();
     part = 0.0;
     for (int q = tid; q < n; q += nt) part += x[q];
@@ -905,20 +909,21 @@ __device__ void nd_block_cg(const NDims& d, const T* __restrict__ bin, T* __rest
 template <typename T>
 __global__ __launch_bounds__(1024) void k_nd_bottom(NDims d, const T* __restrict__ bin, T* __restrict__ xout,
                                                     const T* __restrict__ sg, double inv_h12, double rtol, int maxit,
-                                                    int use_x0, double* __restrict__ work)
+                                                    int use_x0, double* __restrict__ work, double* __restrict__ iters)
 {
     __shared__ double sh[16];
-    nd_block_cg<T>(d, bin, xout, sg, inv_h12, rtol, maxit, use_x0, work, sh);
+    nd_block_cg<T>(d, bin, xout, sg, inv_h12, rtol, maxit, use_x0, work, sh, iters);
 }
 
 template <typename T>
 void launch_nd_bottom(const NDims& d, const T* b, T* x, const T* sg, double inv_h12, double rtol, int maxit,
-                      int use_x0, double* work, hipStream_t s)
+                      int use_x0, double* work, double* iters, hipStream_t s)
 {
     const int n = d.mx * d.my * d.mz;
     int nt = ((n + 63) / 64) * 64;
     if (nt > 1024) nt = 1024;
-    hipLaunchKernelGGL((k_nd_bottom<T>), dim3(1), dim3(nt), 0, s, d, b, x, sg, inv_h12, rtol, maxit, use_x0, work);
+    hipLaunchKernelGGL((k_nd_bottom<T>), dim3(1), dim3(nt), 0, s, d, b, x, sg, inv_h12, rtol, maxit, use_x0, work,
+                       iters);
 }
 
 // ------------------------------------------------------------- coarse cycle
@@ -1020,9 +1025,10 @@ __global__ __launch_bounds__(1024) void k_nd_coarse(NdCoarseArgs<T> a)
         if (nn <= kWave) {
             if (threadIdx.x < kWave)
                 nd_block_cg<T, true>(d, x + nn, x, x + 3 * nn, a.bottom_inv_h12, a.bottom_rtol, a.bottom_maxit, 0,
-                                     work, sh);
+                                     work, sh, a.bottom_iters);
         } else {
-            nd_block_cg<T>(d, x + nn, x, x + 3 * nn, a.bottom_inv_h12, a.bottom_rtol, a.bottom_maxit, 0, work, sh);
+            nd_block_cg<T>(d, x + nn, x, x + 3 * nn, a.bottom_inv_h12, a.bottom_rtol, a.bottom_maxit, 0, work, sh,
+                           a.bottom_iters);
         }
         __syncthreads();
     }
@@ -1079,7 +1085,7 @@ template void launch_nd_coarse<double>(const NdCoarseArgs<double>&, hipStream_t)
     template void launch_nd_restrict<T>(const NDims&, const NDims&, const T*, T*, hipStream_t);           \
     template void launch_nd_prolong<T>(const NDims&, const NDims&, T*, const T*, int, hipStream_t);       \
     template void launch_nd_bottom<T>(const NDims&, const T*, T*, const T*, double, double, int, int,     \
-                                      double*, hipStream_t);
+                                      double*, double*, hipStream_t);
 ND_INST(float)
 ND_INST(double)
 template void launch_nd_sigma<double, float>(int, int, int, const double*, float*, int, hipStream_t);

@@ -69,7 +69,7 @@ __device__ __forceinline__ void zpart_store(double* part, double s)
 // ---------------------------------------------------------------- reductions
 
 __global__ __launch_bounds__(1024) void k_final_sum(const double* __restrict__ part, int nb, double* out, double scale,
-                                                    double* rms_out, double count)
+                                                    double* rms_out, double count, double* zero_out)
 {
     __shared__ double sh[16];
     double v = 0.0;
@@ -77,6 +77,7 @@ __global__ __launch_bounds__(1024) void k_final_sum(const double* __restrict__ p
     double s = block_sum(v, sh);
     if (threadIdx.x == 0) {
         out[0] = scale * s;
+        if (zero_out) zero_out[0] = 0.0;
         if (rms_out) {
             double r = sqrt(s / count);
             rms_out[0] = r > 0.0 ? r : 1.0;
@@ -86,9 +87,9 @@ __global__ __launch_bounds__(1024) void k_final_sum(const double* __restrict__ p
 }
 
 void launch_final_sum(const double* partials, int nb, double* out, double scale, double* rms_out, double count,
-                      hipStream_t s)
+                      hipStream_t s, double* zero_out)
 {
-    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(1024), 0, s, partials, nb, out, scale, rms_out, count);
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(1024), 0, s, partials, nb, out, scale, rms_out, count, zero_out);
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum(const double* __restrict__ x, long long n, double* part)

@@ -26,7 +26,20 @@ using mp::Dims;
 constexpr int kMaxBottomCells = 16384;
 constexpr int kScal = 64;  // device scalar slots
 // scalar slots
-enum { S_MEAN = 0, S_NB2 = 1, S_RR = 2, S_DEF = 3, S_BAD = 4, S_GAUGE = 5, S_ZERO = 6, S_NMEAN = 7, S_PAIR0 = 8 };
+// (S_BIT, the running count of bottom-solve iterations of a solve, follows
+// S_RR so that one read-back per residual check takes both)
+enum {
+    S_MEAN = 0,
+    S_NB2 = 1,
+    S_RR = 2,
+    S_BIT = 3,
+    S_BAD = 4,
+    S_GAUGE = 5,
+    S_ZERO = 6,
+    S_NMEAN = 7,
+    S_PAIR0 = 8,
+    S_DEF = 12
+};
 
 struct Level {
     Dims d;
@@ -104,6 +117,8 @@ struct mp_ctx {
     double *partials = nullptr, *dscal = nullptr, *bottom_work = nullptr;
     double* hscal = nullptr;  // pinned host
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t evm[2] = {nullptr, nullptr};  // around the last mapping / coefficient import
+    double ms_setup = 0.0;                   // its duration
     std::vector<hipEvent_t> kev;
     std::vector<double> kev_bytes;
     int kev_used = 0;
@@ -149,6 +164,15 @@ int fail(mp_ctx* c, int code, const char* fmt, ...)
     } while (0)
 
 bool log_on() { return getenv("MP_LOG") && getenv("MP_LOG")[0] == '1'; }
+
+// Error-path testing: MP_TEST_FAIL_ALLOC=<name> makes the named workspace
+// allocation report failure (after it has been made), so that the recovery
+// path runs without exhausting device memory.
+bool test_fail_alloc(const char* name)
+{
+    const char* v = getenv("MP_TEST_FAIL_ALLOC");
+    return v && strcmp(v, name) == 0;
+}
 
 template <typename T>
 T* dalloc(long long n, hipError_t& e)
@@ -203,6 +227,8 @@ void free_all(mp_ctx* c)
     if (c->rad_cells) (void)hipFree(c->rad_cells);
     if (c->hscal) (void)hipHostFree(c->hscal);
     for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : c->evm)
         if (e) (void)hipEventDestroy(e);
     for (auto& e : c->kev)
         if (e) (void)hipEventDestroy(e);
@@ -296,9 +322,9 @@ int build_radius_list(mp_ctx* c)
         }
     hipError_t e1 = hipMalloc((void**)&c->rad_offs, sizeof(long long) * offs.size());
     hipError_t e2 = hipMalloc((void**)&c->rad_cells, sizeof(unsigned) * cells.size());
+    if (test_fail_alloc("radius_list")) e2 = hipErrorOutOfMemory;
     if (e1 != hipSuccess || e2 != hipSuccess) {
-        if (c->sbar) (void)hipFree(c->sbar);
-    if (c->rad_offs) (void)hipFree(c->rad_offs);
+        if (c->rad_offs) (void)hipFree(c->rad_offs);
         if (c->rad_cells) (void)hipFree(c->rad_cells);
         c->rad_offs = nullptr;
         c->rad_cells = nullptr;
@@ -500,6 +526,7 @@ void coarse_cycle(mp_ctx* c, bool zero_init)
     a.zero_init = zero_init ? 1 : 0;
     a.bottom_rtol = c->cfg.bottom_rtol;
     a.bottom_maxit = c->cfg.bottom_max_iter;
+    a.bottom_iters = c->dscal + S_BIT;
     for (int q = 0; q < a.nlev; q++) {
         const Level& L = c->lv[l0 + q];
         mp::CoarseLevel<T>& C = a.lv[q];
@@ -530,7 +557,7 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
     if (l == nlev - 1) {
         mp::launch_bottom<T>(L.d, (const T*)L.b, (T*)L.x, (const T*)L.cx, (const T*)L.cy, (const T*)L.cz, L.h * L.h,
                              c->cfg.bottom_rtol, c->cfg.bottom_max_iter, zero_init ? 0 : 1, c->bottom_work,
-                             c->stream);
+                             c->dscal + S_BIT, c->stream);
         return;
     }
     if (zero_init && c->cfg.nu1 == 0) (void)hipMemsetAsync(L.x, 0, sizeof(T) * L.d.n(), c->stream);
@@ -623,9 +650,10 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
                 mp::launch_resid64(c->d0, phi, c->b64, coef64(c), inv_h2, mx ? (float*)c->lv[0].b : nullptr, sp + 1,
                                    c->partials, &nbr, c->stream);
             mp::launch_final_sum(c->partials, nbr, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
-            int st = sync_read(c, S_RR, 1);
+            int st = sync_read(c, S_RR, 2);
             if (st) return st;
             rel = sqrt(c->hscal[S_RR] / nb2);
+            if (info) info->bottom_iters_total = (int)c->hscal[S_BIT];
         }
         if (it < 64) {
             hist[it] = rel;
@@ -812,6 +840,7 @@ void nd_vcycle(mp_ctx* c, int l)
         a.bottom_maxit = c->cfg.bottom_max_iter;
         const double hb = N.lv[nlev - 1].h;
         a.bottom_inv_h12 = 1.0 / (12.0 * hb * hb);
+        a.bottom_iters = c->dscal + S_BIT;
         for (int q = 0; q < a.nlev; q++) {
             const NLevel& Q = N.lv[l + q];
             a.lv[q].d = Q.d;
@@ -828,7 +857,7 @@ void nd_vcycle(mp_ctx* c, int l)
         // on a one-level grid the finest iterate carries the previous steps
         mp::launch_nd_bottom<T>(L.d, (const T*)L.b, (T*)L.x, (const T*)L.sig, 1.0 / (12.0 * h2),
                                 c->cfg.bottom_rtol, c->cfg.bottom_max_iter, l == 0 ? 1 : 0, N.bottom_work,
-                                c->stream);
+                                c->dscal + S_BIT, c->stream);
         return;
     }
     const T h12 = (T)(12.0 * h2), inv_h12 = (T)(1.0 / (12.0 * h2));
@@ -912,9 +941,10 @@ int nd_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
                 mp::launch_nd_resid64(L0.d, phi, N.b64, sig64, inv_h12, mx ? (float*)L0.b : nullptr, sp + 1,
                                       N.partials, N.nb, c->stream);
             mp::launch_final_sum(N.partials, nbr, c->dscal + S_RR, 1.0, sq, (double)n, c->stream);
-            int st = sync_read(c, S_RR, 1);
+            int st = sync_read(c, S_RR, 2);
             if (st) return st;
             rel = sqrt(c->hscal[S_RR] / nb2);
+            if (info) info->bottom_iters_total = (int)c->hscal[S_BIT];
         }
         if (it < 64) {
             hist[it] = rel;
@@ -967,9 +997,18 @@ int nd_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
     return status;
 }
 
+// Duration of the mapping or coefficient import just completed (its events
+// have been passed: the caller read a scalar back after the second).
+void record_setup_time(mp_ctx* c)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->evm[0], c->evm[1]) == hipSuccess) c->ms_setup = ms;
+}
+
 void finish_timing(mp_ctx* c, mp_info* info)
 {
     if (!info) return;
+    info->ms_setup = c->ms_setup;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) info->ms_rhs = ms;
     if (hipEventElapsedTime(&ms, c->ev[1], c->ev[2]) == hipSuccess) info->ms_solve = ms;
@@ -1184,6 +1223,8 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
         good = false;
     for (auto& ev : c->ev)
         if (good && hipEventCreate(&ev) != hipSuccess) good = false;
+    for (auto& ev : c->evm)
+        if (good && hipEventCreate(&ev) != hipSuccess) good = false;
     if (good && cfg->kernel_timing && make_timing_events(c) != MP_OK) good = false;
     if (!good) {
         free_all(c);
@@ -1245,7 +1286,7 @@ int mp_map_base_state(mp_ctx* c, int geometry, const double* beta0_1d, int n1d, 
     }
     (void)hipSetDevice(c->cfg.device);
 
-    HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    HIPCHK(c, hipEventRecord(c->evm[0], c->stream));
     // cell mode whenever the finest level is not also the coarsest
     c->cell_mode = c->lv.size() >= 2;
     Level& L0 = c->lv[0];
@@ -1261,8 +1302,10 @@ int mp_map_base_state(mp_ctx* c, int geometry, const double* beta0_1d, int n1d, 
         mp::launch_faces_from_cells(c->d0, c->ccell, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, cx, cy, cz,
                                     c->stream);
     build_pyramid(c);
+    HIPCHK(c, hipEventRecord(c->evm[1], c->stream));
     int st = sync_read(c, S_BAD, 1);
     if (st) return st;
+    record_setup_time(c);
     if (c->hscal[S_BAD] != 0.0) {
         c->have_base = c->have_coefs = false;
         return fail(c, MP_ERR_NONFINITE, "%.0f cells with rho <= 0, beta0 <= 0 or non-finite values",
@@ -1280,6 +1323,7 @@ int mp_set_coefs(mp_ctx* c, const double* cx, const double* cy, const double* cz
     if (!cx || !cy || !cz) return fail(c, MP_ERR_ARG, "cx, cy, cz are required");
     (void)hipSetDevice(c->cfg.device);
 
+    HIPCHK(c, hipEventRecord(c->evm[0], c->stream));
     Level& L0 = c->lv[0];
     const bool mx = mixed(c);
     c->cell_mode = false;
@@ -1287,8 +1331,10 @@ int mp_set_coefs(mp_ctx* c, const double* cx, const double* cy, const double* cz
                             mx ? (float*)L0.cy : nullptr, mx ? (float*)L0.cz : nullptr, c->partials, c->stream);
     mp::launch_final_sum(c->partials, c->nbz, c->dscal + S_BAD, 1.0, nullptr, 0.0, c->stream);
     build_pyramid(c);
+    HIPCHK(c, hipEventRecord(c->evm[1], c->stream));
     int st = sync_read(c, S_BAD, 1);
     if (st) return st;
+    record_setup_time(c);
     if (c->hscal[S_BAD] != 0.0) {
         c->have_coefs = false;
         return fail(c, MP_ERR_NONFINITE, "%.0f negative or non-finite face coefficients", c->hscal[S_BAD]);
@@ -1305,7 +1351,8 @@ static int finish_rhs(mp_ctx* c, int nb_sum, int nb)
     const long long n = c->n0;
     mp::launch_final_sum(c->partials, nb_sum, c->dscal + S_MEAN, 1.0 / (double)n, nullptr, 0.0, c->stream);
     mp::launch_sub_mean_sumsq(c->b64, n, c->dscal + S_MEAN, c->partials, nb, c->stream);
-    mp::launch_final_sum(c->partials, nb, c->dscal + S_NB2, 1.0, c->dscal + S_PAIR0, (double)n, c->stream);
+    mp::launch_final_sum(c->partials, nb, c->dscal + S_NB2, 1.0, c->dscal + S_PAIR0, (double)n, c->stream,
+                         c->dscal + S_BIT);
     int st = sync_read(c, S_MEAN, 2);
     if (st) return st;
     if (!isfinite(c->hscal[S_MEAN]) || !isfinite(c->hscal[S_NB2]))
@@ -1502,7 +1549,8 @@ int mp_nodal_project(mp_ctx* c, double* ux, double* uy, double* uz, const double
     // b then lies in the range of A, which is orthogonal to the constants
     mp::launch_final_sum(N.partials, nbr, c->dscal + S_NMEAN, 1.0 / (double)nn, nullptr, 0.0, c->stream);
     mp::launch_sub_mean_sumsq(N.b64, nn, c->dscal + S_NMEAN, N.partials, N.nb, c->stream);
-    mp::launch_final_sum(N.partials, N.nb, c->dscal + S_NB2, 1.0, c->dscal + S_PAIR0, (double)nn, c->stream);
+    mp::launch_final_sum(N.partials, N.nb, c->dscal + S_NB2, 1.0, c->dscal + S_PAIR0, (double)nn, c->stream,
+                         c->dscal + S_BIT);
     st = sync_read(c, S_MEAN, 2);
     if (st) return st;
     if (!isfinite(c->hscal[S_MEAN]) || !isfinite(c->hscal[S_NB2]))

@@ -34,8 +34,9 @@ int zred_blocks(const Dims& d);
 // ---- reductions ---------------------------------------------------------
 // out[0] = scale * sum(partials[0..nb)); when rms_out != nullptr also
 // rms_out[0] = sqrt(sum / count), rms_out[1] = 1 / rms_out[0] (1 if the sum is 0).
+// zero_out (or nullptr): a device scalar set to 0 by the same launch.
 void launch_final_sum(const double* partials, int nb, double* out, double scale, double* rms_out, double count,
-                      hipStream_t s);
+                      hipStream_t s, double* zero_out = nullptr);
 // partials[b] = per-block sum of x (grid-stride, fixed order).
 void launch_sum(const double* x, long long n, double* partials, int nb, hipStream_t s);
 // x[q] -= mean[0]; partials = per-block sum of x^2 after the update.
@@ -118,9 +119,10 @@ template <typename T>
 void launch_prolong(const Dims& fine, T* phi, const T* coarse_phi, hipStream_t s);
 // BiCGStab in FP64 on the coarsest grid (one workgroup); work = 7 * n doubles.
 // use_x0: start from phi (tolerance relative to the initial residual).
+// iters: device counter the iterations are added to, or nullptr.
 template <typename T>
 void launch_bottom(const Dims& d, const T* rhs, T* phi, const T* cx, const T* cy, const T* cz, double h2, double rtol,
-                   int maxit, int use_x0, double* work, hipStream_t s);
+                   int maxit, int use_x0, double* work, double* iters, hipStream_t s);
 
 // The coarse end of a V-cycle in one workgroup (levels lv[0..nlev), the last
 // one solved by one-wavefront conjugate gradients; it must hold <= 256 cells).
@@ -148,6 +150,7 @@ struct CoarseArgs {
     int zero_init;  // x of lv[0] is zero on entry
     double bottom_rtol;
     int bottom_maxit;
+    double* bottom_iters;  // device counter the bottom solve adds its iterations to, or nullptr
     CoarseLevel<T> lv[kMaxCoarse];
 };
 template <typename T>
@@ -305,10 +308,11 @@ void launch_nd_resid64_col(const NDims& d, const double* x, const double* b, con
 template <typename Tin, typename Tout>
 void launch_nd_sigma(int nx, int ny, int nz, const Tin* sf, Tout* sc, int coarsen, hipStream_t s);
 // FP64 conjugate gradients on the coarsest nodes (one workgroup); x from 0
-// (or from x when use_x0), returned mean-zero; work = 4 * nodes doubles.
+// (or from x when use_x0), returned mean-zero; work = 4 * nodes doubles;
+// iters: device counter the iterations are added to, or nullptr.
 template <typename T>
 void launch_nd_bottom(const NDims& d, const T* b, T* x, const T* sg, double inv_h12, double rtol, int maxit,
-                      int use_x0, double* work, hipStream_t s);
+                      int use_x0, double* work, double* iters, hipStream_t s);
 // The coarse end of a nodal V-cycle in one workgroup, every array in LDS
 // (levels lv[0..nlev), all starting from zero; lv[0].b in, lv[0].x out).
 template <typename T>
@@ -325,6 +329,7 @@ struct NdCoarseArgs {
     double bottom_rtol;
     int bottom_maxit;
     double bottom_inv_h12;
+    double* bottom_iters;  // device counter the bottom solve adds its iterations to, or nullptr
     NdCoarseLevel<T> lv[kMaxCoarse];
 };
 // LDS bytes the coarse set lv[0..nlev) needs (must be <= kCoarseLdsBytes).

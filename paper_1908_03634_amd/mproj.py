@@ -72,6 +72,7 @@ class Info(ctypes.Structure):
         ("rhs_norm", ctypes.c_double),
         ("rhs_mean", ctypes.c_double),
         ("resid_hist", ctypes.c_double * 64),
+        ("ms_setup", ctypes.c_double),
         ("ms_rhs", ctypes.c_double), ("ms_solve", ctypes.c_double), ("ms_correct", ctypes.c_double),
         ("smooth_ms_total", ctypes.c_double),
         ("smooth_launches", ctypes.c_int),
@@ -83,6 +84,7 @@ class Info(ctypes.Structure):
     def as_dict(self):
         n = min(max(self.outer_iters + 1, 0), 64)
         return dict(outer_iters=self.outer_iters, vcycles=self.vcycles, levels=self.levels,
+                    bottom_iters_total=self.bottom_iters_total, ms_setup=self.ms_setup,
                     rel_resid=self.rel_resid, div_defect=self.div_defect, rhs_norm=self.rhs_norm,
                     rhs_mean=self.rhs_mean, resid_hist=list(self.resid_hist[:n]), ms_rhs=self.ms_rhs,
                     ms_solve=self.ms_solve, ms_correct=self.ms_correct, smooth_ms_total=self.smooth_ms_total,
@@ -174,6 +176,8 @@ class Context:
                  max_outer=100, nu1=2, nu2=2, cycles_per_outer=0, bottom_rtol=1e-8, bottom_max_iter=400,
                  demean=True, kernel_timing=False, smoother="auto", coarse_cycle=True, blocked=True, device=None, stream=None):
         self.lib = load_library()
+        self._args = []
+        self.coef_generation = 0  # bumped whenever the library's coefficients change
         if not torch.cuda.is_available():
             raise MprojError(2, "no GPU visible to torch")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -222,7 +226,30 @@ class Context:
             raise ValueError(f"{name} must be a contiguous float64 tensor on {self.device}")
         if shape is not None and tuple(t.shape) != tuple(shape):
             raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        self._args.append(t)
         return ctypes.c_void_p(t.data_ptr())
+
+    def _run(self, fn, *args):
+        """Call the library on this context with the tensors marshalled since
+        the last call, in stream order with the caller's current stream: when
+        that is not the context's stream, the context's stream first waits
+        for the work queued on the caller's (which produced the inputs), the
+        caller's stream then waits for the context's (so that it sees the
+        outputs), and each tensor is recorded as used on the context's stream
+        (the caching allocator does not hand its memory out again before
+        that work ends)."""
+        ts, self._args = self._args, []
+        cur = torch.cuda.current_stream(self.device)
+        cross = cur.cuda_stream != self.stream.cuda_stream
+        if cross:
+            self.stream.wait_stream(cur)
+            for t in ts:
+                t.record_stream(self.stream)
+        try:
+            return fn(self._h, *args)
+        finally:
+            if cross:
+                cur.wait_stream(self.stream)
 
     def _check(self, code, what, info=None):
         if code != MP_OK:
@@ -250,13 +277,16 @@ class Context:
         else:
             ptrs = [None, None, None]
         c = (ctypes.c_double * 3)(*(center if center is not None else (0.0, 0.0, 0.0)))
-        code = self.lib.mp_map_base_state(self._h, int(geometry), tab, n1d, float(dr), c, rp, *ptrs)
+        code = self._run(self.lib.mp_map_base_state, int(geometry), tab, n1d, float(dr), c, rp, *ptrs)
+        self.coef_generation += 1
         self._check(code, "mp_map_base_state")
         return faces
 
     def set_coefs(self, cx, cy, cz):
         ps = [self._ptr(f, s, n) for f, s, n in zip((cx, cy, cz), self.face_shapes(), ("cx", "cy", "cz"))]
-        self._check(self.lib.mp_set_coefs(self._h, *ps), "mp_set_coefs")
+        code = self._run(self.lib.mp_set_coefs, *ps)
+        self.coef_generation += 1
+        self._check(code, "mp_set_coefs")
 
     def mac_project(self, ux, uy, uz, S, phi=None, use_initial_guess=False, allow_not_converged=False,
                     split=False, sbar=None):
@@ -273,10 +303,10 @@ class Context:
         info = Info()
         if split:
             pb = self._ptr(sbar, None, "sbar") if sbar is not None else None
-            code = self.lib.mp_mac_project_split(self._h, *pu, ps, pp, int(bool(use_initial_guess)), pb,
+            code = self._run(self.lib.mp_mac_project_split, *pu, ps, pp, int(bool(use_initial_guess)), pb,
                                                  ctypes.byref(info))
         else:
-            code = self.lib.mp_mac_project(self._h, *pu, ps, pp, int(bool(use_initial_guess)), ctypes.byref(info))
+            code = self._run(self.lib.mp_mac_project, *pu, ps, pp, int(bool(use_initial_guess)), ctypes.byref(info))
         d = info.as_dict()
         if not (allow_not_converged and code == MP_ERR_NOT_CONVERGED):
             self._check(code, "mp_mac_project_split" if split else "mp_mac_project", d)
@@ -291,7 +321,7 @@ class Context:
             use_initial_guess = False
         px = self._ptr(x, self.shape, "x")
         info = Info()
-        code = self.lib.mp_solve(self._h, pr, px, int(bool(use_initial_guess)), ctypes.byref(info))
+        code = self._run(self.lib.mp_solve, pr, px, int(bool(use_initial_guess)), ctypes.byref(info))
         d = info.as_dict()
         if not (allow_not_converged and code == MP_ERR_NOT_CONVERGED):
             self._check(code, "mp_solve", d)
@@ -313,7 +343,7 @@ class Context:
         cnt = torch.empty(nm, dtype=torch.float64, device=self.device) if count else None
         pa = self._ptr(avg, (nm,), "avg")
         pc = self._ptr(cnt, (nm,), "count") if count else None
-        self._check(self.lib.mp_average(self._h, pp, pa, pc), "mp_average")
+        self._check(self._run(self.lib.mp_average, pp, pa, pc), "mp_average")
         return avg, cnt
 
     def set_kernel_timing(self, on):
@@ -323,7 +353,7 @@ class Context:
     def apply(self, x, out=None):
         """M x = div(c grad x) with the FP64 finest-level coefficients."""
         y = out if out is not None else self.empty_cells()
-        self._check(self.lib.mp_apply(self._h, self._ptr(x, self.shape, "x"), self._ptr(y, self.shape, "y")),
+        self._check(self._run(self.lib.mp_apply, self._ptr(x, self.shape, "x"), self._ptr(y, self.shape, "y")),
                     "mp_apply")
         return y
 
@@ -331,7 +361,7 @@ class Context:
         """(G lam)(G phi) on every face (walls 0)."""
         g = out if out is not None else self.empty_faces()
         ps = [self._ptr(f, s, "g") for f, s in zip(g, self.face_shapes())]
-        self._check(self.lib.mp_coef_grad(self._h, self._ptr(lam, self.shape, "lam"),
+        self._check(self._run(self.lib.mp_coef_grad, self._ptr(lam, self.shape, "lam"),
                                           self._ptr(phi, self.shape, "phi"), *ps), "mp_coef_grad")
         return g
 
@@ -357,7 +387,7 @@ class Context:
             use_initial_guess = False
         pp = self._ptr(phi, self.node_shape, "phi")
         info = Info()
-        code = self.lib.mp_nodal_project(self._h, *pu, ps, pp, int(bool(use_initial_guess)), ctypes.byref(info))
+        code = self._run(self.lib.mp_nodal_project, *pu, ps, pp, int(bool(use_initial_guess)), ctypes.byref(info))
         d = info.as_dict()
         if not (allow_not_converged and code == MP_ERR_NOT_CONVERGED):
             self._check(code, "mp_nodal_project", d)
@@ -368,7 +398,7 @@ class Context:
         """M x on the nodes (finite-element div(sigma grad x)), FP64."""
         y = out if out is not None else self.empty_nodes()
         ns = self.node_shape
-        self._check(self.lib.mp_nodal_apply(self._h, self._ptr(x, ns, "x"), self._ptr(y, ns, "y")), "mp_nodal_apply")
+        self._check(self._run(self.lib.mp_nodal_apply, self._ptr(x, ns, "x"), self._ptr(y, ns, "y")), "mp_nodal_apply")
         return y
 
     # -- one-dimensional base state ----------------------------------------
@@ -379,7 +409,7 @@ class Context:
         """(centres, edges) of the irregular base state of this grid."""
         nm = self.radius_count()
         rc, re = self._vec(nm), self._vec(nm + 1)
-        self._check(self.lib.mp_base_radii(self._h, self._ptr(rc, (nm,), "rc"), self._ptr(re, (nm + 1,), "re")),
+        self._check(self._run(self.lib.mp_base_radii, self._ptr(rc, (nm,), "rc"), self._ptr(re, (nm + 1,), "re")),
                     "mp_base_radii")
         return rc, re
 
@@ -388,7 +418,7 @@ class Context:
         n = int(rc.shape[0])
         p0 = out if out is not None else self._vec(n)
         jc = ctypes.c_longlong()
-        code = self.lib.mp_enforce_hse(self._h, n, self._ptr(rc, (n,), "rc"), self._ptr(rho0, (n,), "rho0"),
+        code = self._run(self.lib.mp_enforce_hse, n, self._ptr(rc, (n,), "rc"), self._ptr(rho0, (n,), "rho0"),
                                        self._ptr(g_edge, (n + 1,), "g_edge"), float(p0_base), float(rho_cutoff),
                                        self._ptr(p0, (n,), "p0"), ctypes.byref(jc))
         self._check(code, "mp_enforce_hse")
@@ -398,7 +428,7 @@ class Context:
         """beta0 = rho0(0) exp(int dp0 / (Gamma1 p0)) on the base state."""
         n = int(p0.shape[0])
         b = out if out is not None else self._vec(n)
-        self._check(self.lib.mp_beta0_from_p0(self._h, n, float(rho0_centre), self._ptr(p0, (n,), "p0"),
+        self._check(self._run(self.lib.mp_beta0_from_p0, n, float(rho0_centre), self._ptr(p0, (n,), "p0"),
                                               self._ptr(gamma1, (n,), "gamma1"), self._ptr(b, (n,), "beta0")),
                     "mp_beta0_from_p0")
         return b
@@ -408,7 +438,7 @@ class Context:
         n = int(rc.shape[0])
         w = out if out is not None else self._vec(n + 1)
         pp = self._ptr(psi, (n,), "psi") if psi is not None else None
-        self._check(self.lib.mp_w0(self._h, int(geometry), n, self._ptr(rc, (n,), "rc"),
+        self._check(self._run(self.lib.mp_w0, int(geometry), n, self._ptr(rc, (n,), "rc"),
                                    self._ptr(re, (n + 1,), "re"), self._ptr(beta0, (n,), "beta0"),
                                    self._ptr(sbar, (n,), "sbar"), pp, self._ptr(w, (n + 1,), "w0")), "mp_w0")
         return w

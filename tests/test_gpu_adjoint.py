@@ -123,3 +123,65 @@ def test_c5_adjoint_properties_at_full_size():
         ref = (lam[k, j, i] - lam[k - 1, j, i]) * (phin[k, j, i] - phin[k - 1, j, i]) / p.h ** 2
         assert gz[k, j, i] == pytest.approx(ref, rel=1e-12, abs=1e-300)
     ctx.close()
+
+
+def test_c5_gradients_match_oracle():
+    """512^3 mixed, forward + backward through the autograd function with both
+    sides solved to 1e-12: phi and grad_rhs = lam within 1e-9, the face-
+    coefficient gradients (G lam)(G phi) within 1e-6 relative L2 of the
+    oracle's; the errors at the production tolerance 1e-10 are reported."""
+    p = W.config_problem("c5")
+    g, rhs, coefs = _setup(p)
+    say("c5 oracle solves to 1e-12")
+    phi_o, io = oracle.solve(g, *coefs, rhs, tol=1e-12)
+    lam_o, il = oracle.solve(g, *coefs, p.w, tol=1e-12)
+    assert io["converged"] and il["converged"]
+    gref = oracle.coef_grad(g, lam_o, phi_o)
+    for rtol in (1e-12, 1e-10):
+        say(f"c5 gpu forward + backward, rtol {rtol:g}")
+        r = _gpu_grads(p, rhs, coefs, "mixed", rtol)
+        e_phi, e_lam = rel(r["phi"], phi_o), rel(r["grad_rhs"], lam_o)
+        e_c = [rel(a, b) for a, b in zip(r["grad_c"], gref)]
+        say(f"  phi {e_phi:.3e}  grad_rhs {e_lam:.3e}  grad_c {e_c[0]:.3e} {e_c[1]:.3e} {e_c[2]:.3e}")
+        if rtol == 1e-12:
+            assert e_phi < 1e-9 and e_lam < 1e-9
+            assert max(e_c) < 1e-6
+            assert not r["grad_c"][2][0].any() and not r["grad_c"][2][-1].any()
+        r["ctx"].close()
+        del r
+
+
+def test_coefficients_replaced_between_forward_and_backward():
+    """A mapping (or any other coefficient change) on the solver between the
+    forward solve and the backward pass, or between two forward solves with
+    the same tensors, must not leave the library's coefficients in place of
+    the ones the autograd function was given: the solve and the adjoint use
+    (cx, cy, cz) and match the oracle's gradients."""
+    p = W.planar_problem(32, contrast=1e3, seed=7100)
+    g, rhs, coefs = _setup(p)
+    q = W.planar_problem(32, contrast=1e5, seed=7101)  # another base state
+    w = W.random_cells(32, 32, 32, 7102)
+    phi_o, _ = oracle.solve(g, *coefs, rhs, tol=1e-12)
+    lam_o, _ = oracle.solve(g, *coefs, w, tol=1e-12)
+    gref = oracle.coef_grad(g, lam_o, phi_o)
+    ctx = mproj.Context(p.nx, p.ny, p.nz, h=p.h, bc=p.bc, precision="fp64", rtol=1e-12)
+    cs = [T(c).requires_grad_(True) for c in coefs]
+    r = T(rhs).requires_grad_(True)
+    phi = mac_solve(ctx, r, *cs)
+    ctx.map_base_state(q.geometry, T(q.beta0_1d), T(q.rho), q.dr, q.center, want_coefs=False)
+    (phi * T(w)).sum().backward()
+    assert rel(N(phi), phi_o) < 1e-9
+    assert rel(N(r.grad), lam_o) < 1e-9
+    for a, b in zip(cs, gref):
+        assert rel(N(a.grad), b) < 1e-6
+    # a second forward with the same tensors after another mapping
+    ctx.map_base_state(q.geometry, T(q.beta0_1d), T(q.rho), q.dr, q.center, want_coefs=False)
+    phi2 = mac_solve(ctx, r.detach(), *[c.detach() for c in cs])
+    assert rel(N(phi2), phi_o) < 1e-9
+    # an in-place change of a cached coefficient tensor is seen
+    with torch.no_grad():
+        cs[0].mul_(2.0)
+    phi3 = mac_solve(ctx, r.detach(), *[c.detach() for c in cs])
+    phi3_o, _ = oracle.solve(g, 2.0 * coefs[0], coefs[1], coefs[2], rhs, tol=1e-12)
+    assert rel(N(phi3), phi3_o) < 1e-9
+    ctx.close()

@@ -156,3 +156,35 @@ def test_split_needs_a_planar_or_irregular_mapping():
         ctx.mac_project(T(p.ux), T(p.uy), T(p.uz), T(p.S), split=True)
     assert e.value.code == 7
     ctx.close()
+
+
+def test_radius_list_allocation_failure_leaves_the_context_usable(monkeypatch):
+    """When the radius list cannot be allocated, a split projection after an
+    irregular mapping fails with MP_ERR_NOMEM and frees only the list: the
+    context's lateral-average buffer stays owned and valid, so the next split
+    projection writes into it (not into memory the failure released, which a
+    caller's tensor may now occupy), gives the same bits as a fresh context,
+    and mp_free releases every buffer once."""
+    p = W.spherical_problem(32, contrast=1e5, seed=6800, base="irregular")
+    ctx = context_for(p, "fp64", rtol=1e-12)
+    ctx.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center, want_coefs=False)
+    monkeypatch.setenv("MP_TEST_FAIL_ALLOC", "radius_list")
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.mac_project(T(p.ux), T(p.uy), T(p.uz), T(p.S), split=True)
+    assert e.value.code == 3
+    monkeypatch.delenv("MP_TEST_FAIL_ALLOC")
+    nm = ctx.radius_count()
+    guards = [torch.full((nm,), 7.0, dtype=torch.float64, device="cuda:0") for _ in range(8)]
+    ux, uy, uz = T(p.ux), T(p.uy), T(p.uz)
+    phi, _ = ctx.mac_project(ux, uy, uz, T(p.S), split=True)
+    torch.cuda.synchronize()
+    for gd in guards:
+        assert bool((gd == 7.0).all())
+    fresh = context_for(p, "fp64", rtol=1e-12)
+    fresh.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center, want_coefs=False)
+    vx, vy, vz = T(p.ux), T(p.uy), T(p.uz)
+    phi2, _ = fresh.mac_project(vx, vy, vz, T(p.S), split=True)
+    assert np.array_equal(N(phi), N(phi2))
+    assert np.array_equal(N(uz), N(vz))
+    fresh.close()
+    ctx.close()

@@ -96,3 +96,35 @@ def test_bad_coefficients_are_reported():
         ctx.set_coefs(T(cx), T(cy), T(cz))
     assert e.value.code == 5
     ctx.close()
+
+
+def test_calls_from_another_stream_are_ordered():
+    """A context bound to one stream, called while the caller works on
+    another: inputs produced on the caller's stream are read after they are
+    written, and the caller's stream sees the outputs of calls that return
+    without waiting (operator, coefficient gradient)."""
+    nx, ny, nz, bc = 64, 48, 40, (0, 0, 1)
+    g = oracle.Grid(nx, ny, nz, 1.0 / nz, bc)
+    cx, cy, cz = W.random_coefs(nx, ny, nz, bc, 121)
+    x = W.random_cells(nx, ny, nz, 122)
+    lam = W.random_cells(nx, ny, nz, 123)
+    ctx = mproj.Context(nx, ny, nz, h=1.0 / nz, bc=bc, precision="fp64", stream=torch.cuda.Stream())
+    ctx.set_coefs(T(cx), T(cy), T(cz))
+    ref_y = oracle.apply(g, cx, cy, cz, x)
+    ref_g = oracle.coef_grad(g, lam, x)
+    other = torch.cuda.Stream()
+    big = torch.ones(1 << 26, dtype=torch.float64, device="cuda:0")
+    with torch.cuda.stream(other):
+        for _ in range(3):
+            xd = T(np.zeros_like(x))
+            big.mul_(1.0)  # queue work ahead of the input on the caller's stream
+            xd.copy_(T(x))
+            y = ctx.apply(xd)
+            s_y = y * 1.0  # read on the caller's stream, no explicit wait
+            gx, gy, gz = ctx.coef_grad(T(lam), xd)
+            s_g = [a * 1.0 for a in (gx, gy, gz)]
+        torch.cuda.synchronize()
+    assert np.abs(N(s_y) - ref_y).max() <= 1e-13 * np.abs(ref_y).max()
+    for a, b in zip(s_g, ref_g):
+        assert np.abs(N(a) - b).max() <= 1e-13 * np.abs(b).max()
+    ctx.close()
