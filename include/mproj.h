@@ -261,9 +261,12 @@ int mp_radius_count(const mp_ctx *ctx, long long *nm);
 int mp_average(mp_ctx *ctx, const double *phi, double *avg, double *count);
 
 /* ---- one-dimensional base state (Sec. 3.2 modules, Appendix A) ----------
- * Arrays are device arrays of doubles owned by the caller; each call runs one
- * workgroup on the context's stream and returns without waiting unless it
- * reports a scalar.  Sums run in a fixed order (reproducible).  */
+ * Arrays are device arrays of doubles owned by the caller; each call is a
+ * multi-block scan on the context's stream (tiles of 4096 values: tile
+ * totals, their prefix, every tile again from it) and returns without
+ * waiting unless it reports a scalar.  Sums run in a fixed association
+ * (reproducible).  Beyond about 2.8 million values a call may allocate a
+ * scratch buffer of 24 bytes per 4096 values the first time (MP_ERR_NOMEM).  */
 
 /* Centres rc (mp_radius_count entries) and edges re (one more) of the
  * irregular base state (Sec. 3.1): rc[m] = h sqrt(0.75 + 2m), re[m] =

@@ -6,6 +6,7 @@
 // the caller's stream.  The only device->host transfers are small scalar
 // read-backs (norms, counts) into pinned memory.
 #include "../../include/mproj.h"
+#include "mp_base.h"
 #include "mp_device.h"
 #include "mp_kernels.h"
 
@@ -115,6 +116,9 @@ struct mp_ctx {
     double *c64x = nullptr, *c64y = nullptr, *c64z = nullptr;
     double *beta0 = nullptr, *ccell = nullptr, *b64 = nullptr;
     double *partials = nullptr, *dscal = nullptr, *bottom_work = nullptr;
+    long long npartials = 0;     // doubles in partials
+    double* scanw = nullptr;     // scratch of the one-dimensional scans when partials is too small
+    long long scanw_cap = 0;
     double* hscal = nullptr;  // pinned host
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t evm[2] = {nullptr, nullptr};  // around the last mapping / coefficient import
@@ -223,6 +227,7 @@ void free_all(mp_ctx* c)
         if (p) (void)hipFree(p);
     if (c->ccell32) (void)hipFree(c->ccell32);
     if (c->sbar) (void)hipFree(c->sbar);
+    if (c->scanw) (void)hipFree(c->scanw);
     if (c->rad_offs) (void)hipFree(c->rad_offs);
     if (c->rad_cells) (void)hipFree(c->rad_cells);
     if (c->hscal) (void)hipHostFree(c->hscal);
@@ -333,6 +338,30 @@ int build_radius_list(mp_ctx* c)
     }
     HIPCHK(c, hipMemcpy(c->rad_offs, offs.data(), sizeof(long long) * offs.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->rad_cells, cells.data(), sizeof(unsigned) * cells.size(), hipMemcpyHostToDevice));
+    return MP_OK;
+}
+
+// Scratch of a one-dimensional scan over n values: the reduction partials
+// when they hold it, else a buffer of the context grown to fit.
+int scan_scratch(mp_ctx* c, long long n, double** out)
+{
+    const long long need = mp::scan_work_doubles(n);
+    if (need <= c->npartials) {
+        *out = c->partials;
+        return MP_OK;
+    }
+    if (need > c->scanw_cap) {
+        if (c->scanw) (void)hipFree(c->scanw);
+        c->scanw = nullptr;
+        c->scanw_cap = 0;
+        if (hipMalloc((void**)&c->scanw, sizeof(double) * (size_t)need) != hipSuccess) {
+            c->scanw = nullptr;
+            (void)hipGetLastError();
+            return fail(c, MP_ERR_NOMEM, "no device memory for the scan of %lld values", n);
+        }
+        c->scanw_cap = need;
+    }
+    *out = c->scanw;
     return MP_OK;
 }
 
@@ -1117,6 +1146,7 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
         if (mp::proj_blk_supported(c->d0) && mp::proj_blk_reduce_blocks(c->d0) > np)
             np = mp::proj_blk_reduce_blocks(c->d0);
         c->partials = dalloc<double>(np, e), good &= ok(c->partials);
+        c->npartials = np;
     }
     c->dscal = dalloc<double>(kScal, e), good &= ok(c->dscal);
     // levels
@@ -1613,7 +1643,11 @@ int mp_enforce_hse(mp_ctx* c, long long n, const double* rc, const double* rho0,
     if (n < 1 || !rc || !rho0 || !g_edge || !p0) return fail(c, MP_ERR_ARG, "n >= 1, rc, rho0, g_edge, p0 required");
     if (!isfinite(p0_base) || isnan(rho_cutoff)) return fail(c, MP_ERR_ARG, "p0_base must be finite");
     (void)hipSetDevice(c->cfg.device);
-    mp::launch_enforce_hse(n, rc, rho0, g_edge, p0_base, rho_cutoff, p0, c->dscal + S_ZERO, c->stream);
+    double* work = nullptr;
+    int st0 = scan_scratch(c, n, &work);
+    if (st0) return st0;
+    mp::launch_enforce_hse(n, rc, rho0, g_edge, p0_base, rho_cutoff, p0, work, c->dscal + S_ZERO, nullptr,
+                           c->stream);
     HIPCHK(c, hipGetLastError());
     if (cutoff_index) {
         int st = sync_read(c, S_ZERO, 1);
@@ -1630,7 +1664,10 @@ int mp_beta0_from_p0(mp_ctx* c, long long n, double rho0_centre, const double* p
     if (n < 1 || !p0 || !gamma1 || !beta0) return fail(c, MP_ERR_ARG, "n >= 1, p0, gamma1, beta0 required");
     if (!(rho0_centre > 0.0) || !isfinite(rho0_centre)) return fail(c, MP_ERR_ARG, "rho0_centre must be positive");
     (void)hipSetDevice(c->cfg.device);
-    mp::launch_beta0_from_p0(n, rho0_centre, p0, gamma1, beta0, c->dscal + S_ZERO, c->stream);
+    double* work = nullptr;
+    int st0 = scan_scratch(c, n, &work);
+    if (st0) return st0;
+    mp::launch_beta0_from_p0(n, rho0_centre, p0, gamma1, beta0, work, c->dscal + S_ZERO, c->stream);
     int st = sync_read(c, S_ZERO, 1);
     if (st) return st;
     if (c->hscal[S_ZERO] != 0.0)
@@ -1648,7 +1685,10 @@ int mp_w0(mp_ctx* c, int geometry, long long n, const double* rc, const double* 
     if (n < 1 || !rc || !re || !beta0 || !sbar || !w0)
         return fail(c, MP_ERR_ARG, "n >= 1, rc, re, beta0, sbar, w0 required");
     (void)hipSetDevice(c->cfg.device);
-    mp::launch_w0(geometry == MP_PLANAR ? 0 : 1, n, rc, re, beta0, sbar, psi, w0, c->stream);
+    double* work = nullptr;
+    int st0 = scan_scratch(c, n, &work);
+    if (st0) return st0;
+    mp::launch_w0(geometry == MP_PLANAR ? 0 : 1, n, rc, re, beta0, sbar, psi, w0, work, c->stream);
     HIPCHK(c, hipGetLastError());
     return MP_OK;
 }

@@ -247,13 +247,6 @@ void launch_ir_update(long long n, double* phi, const float* e, const double* s,
 // float(b * pair_in[1]) when r32 != nullptr; pair_out = pair_in.
 void launch_scale32(long long n, const double* b, float* r32, const double* pair_in, double* pair_out, hipStream_t st);
 
-// ---- irregular radial base state ------------------------------------------
-// Lateral average over radii m = 0 .. nm-1: cells[offs[m] .. offs[m+1]) lists
-// the cells at radius m (memory order); avg[m] = their mean (0 if none),
-// count[m] = their number (count may be nullptr).
-void launch_average(long long nm, const long long* offs, const unsigned* cells, const double* phi, double* avg,
-                    double* count, hipStream_t s);
-
 // ---- nodal projection (node-based phi, cell-centred U and sigma) --------
 // Cells nx x ny x nz with per-axis periodicity; nodes mx = nx + (1 - px) etc.
 // Node arrays [mz][my][mx], cell arrays [nz][ny][nx].  A is the trilinear
@@ -354,20 +347,6 @@ void launch_nd_apply64(const NDims& d, const double* x, const double* sg, double
 // U -= (sigma / beta0) G phi on every cell (cell-average gradient of phi_h).
 void launch_nd_correct(const NDims& d, double inv4h, const double* sg, const double* beta0, const double* phi,
                        double* ux, double* uy, double* uz, hipStream_t s);
-
-// ---- one-dimensional base state (one workgroup each; deterministic scans) --
-// Centres rc (nm) and edges re (nm + 1) of the irregular base state.
-void launch_irregular_radii(long long nm, double h, double* rc, double* re, hipStream_t s);
-// Enforce HSE (trapezoidal across centres, cutoff density); jc_out[0] = the
-// first centre at or below rho_cutoff (n if none), as a double.
-void launch_enforce_hse(long long n, const double* rc, const double* rho0, const double* g_edge, double p0_base,
-                        double rho_cutoff, double* p0, double* jc_out, hipStream_t s);
-// beta0 from p0 and Gamma1 (definition of beta0); bad[0] counts invalid inputs.
-void launch_beta0_from_p0(long long n, double rho0_centre, const double* p0, const double* gamma1, double* beta0,
-                          double* bad, hipStream_t s);
-// w0 on the n + 1 edges from div(beta0 w0 e_r) = beta0 (sbar - psi) (psi may be nullptr).
-void launch_w0(int spherical, long long n, const double* rc, const double* re, const double* beta0, const double* sbar,
-               const double* psi, double* w0, hipStream_t s);
 
 // Plain device copy (bandwidth calibration of the traffic counters).
 void launch_copy(const double* src, double* dst, long long n, hipStream_t s);

@@ -50,7 +50,7 @@ def test_enforce_hse_matches_the_oracle(n, cut):
     ctx.close()
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4095, 4096, 4097, 100003, 1000003])
+@pytest.mark.parametrize("n", [1, 2, 3, 4095, 4096, 4097, 100003, 1000003, 4096 * 4096 + 5])
 def test_scans_across_tiles(n):
     say("scan", n)
     rng = np.random.default_rng(n)
