@@ -286,6 +286,29 @@ int mp_base_radii(mp_ctx *ctx, double *rc, double *re);
 int mp_enforce_hse(mp_ctx *ctx, long long n, const double *rc, const double *rho0, const double *g_edge,
                    double p0_base, double rho_cutoff, double *p0, long long *cutoff_index);
 
+/* Allocation-free Enforce HSE, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the computation of mp_enforce_hse (same kernels, same bits),
+ * without a context.  Its scan scratch is a static device array of the
+ * library (about 96 KiB per device, held until the process ends): n is at
+ * most 16777216 centres (MP_ERR_ARG beyond, before any device work).  The
+ * call allocates nothing: no hipMalloc, hipFree or allocating routine; the
+ * first call on a device looks the array's address up with that device
+ * current.  Every call on a device shares that device's array, and every
+ * scratch value a call reads it writes first; calls that overlap on one
+ * device (other streams, other threads) race and must be ordered by the
+ * caller.
+ * stream: hipStream_t of the launches (NULL = null stream), on the current
+ *   device; returns without waiting.
+ * rc, rho0 (n), g_edge (n + 1), p0 (n, out): device arrays as in
+ *   mp_enforce_hse.  cutoff_index: DEVICE pointer to one long long receiving
+ *   the first centre with rho0 <= rho_cutoff (n if none), or NULL.
+ * Errors: MP_ERR_ARG (NULL arrays, n < 1 or too large, non-finite p0_base),
+ * MP_ERR_DEVICE (no current device, a failed launch); mp_last_error(NULL)
+ * gives the text. */
+int mp_enforce_hse_noalloc(void *stream, long long n, const double *rc, const double *rho0, const double *g_edge,
+                           double p0_base, double rho_cutoff, double *p0, long long *cutoff_index);
+
 /* beta0 from its definition (Sec. 2), beta0 = rho0(0) exp(int dp0 / (Gamma1 p0)),
  * on n centres: beta0[0] = rho0_centre and across each pair of centres the
  * integral is ln(p0[j] / p0[j-1]) / ((gamma1[j-1] + gamma1[j]) / 2) (exact
@@ -323,7 +346,9 @@ int mp_coef_grad(mp_ctx *ctx, const double *lam, const double *phi, double *gx, 
 /* Release a context and its device memory; NULL is accepted. */
 int mp_free(mp_ctx *ctx);
 
-/* Text of the last failure on ctx (never NULL; "" if none). */
+/* Text of the last failure on ctx (never NULL; "" if none).  With ctx NULL:
+ * the last failure of a context-free call (mp_enforce_hse_noalloc) on the
+ * calling thread. */
 const char *mp_last_error(const mp_ctx *ctx);
 
 /* Library version string. */

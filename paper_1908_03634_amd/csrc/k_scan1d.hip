@@ -1,6 +1,7 @@
 // k_scan1d.hip -- the one-dimensional base state by multi-block scans:
 // Enforce HSE, beta0 from its definition, and w0 of the velocity split (the
-// base-state modules of Sec. 3.2 and Appendix A).
+// base-state modules of Sec. 3.2 and Appendix A), plus the allocation-free
+// form of Enforce HSE for callers that cannot allocate device memory.
 //
 // Each quantity is a prefix sum over the base-state cells.  The values are cut
 // into tiles of kScanTile = 4096 (one 1024-thread workgroup per tile, four
@@ -15,8 +16,14 @@
 // threads' totals, and the wavefront totals are added in order; step 2 uses
 // the same pattern over the tile totals.  The association is fixed, so the
 // results are reproducible bit for bit.
+#include "../../include/mproj.h"
 #include "mp_base.h"
 #include "mp_device.h"
+
+#include <stdio.h>
+
+#include <cmath>
+#include <mutex>
 
 namespace mp {
 
@@ -310,4 +317,75 @@ void launch_w0(int spherical, long long n, const double* rc, const double* re, c
     run_scan(n, op, work, nullptr, s);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free Enforce HSE.  The scan's scratch lives in `scratch`, one
+// copy per device for the life of the process, sized for kNoAllocMaxRadii
+// centres.  Host code never uses the array's name as a device address: the
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current.
+
+constexpr long long kNoAllocMaxRadii = 1LL << 24;  // 4096 tiles
+constexpr long long kScratchDoubles = 3 * ((kNoAllocMaxRadii + kScanTile - 1) / kScanTile) + 8;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up on first use).
+hipError_t scratch_for(int dev, double** out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+thread_local char g_noalloc_err[256] = "";
+
+int na_fail(int code, const char* msg)
+{
+    snprintf(g_noalloc_err, sizeof g_noalloc_err, "%s", msg);
+    return code;
+}
+
+}  // namespace
+
+const char* noalloc_last_error() { return g_noalloc_err; }
+
 }  // namespace mp
+
+extern "C" int mp_enforce_hse_noalloc(void* stream, long long n, const double* rc, const double* rho0,
+                                      const double* g_edge, double p0_base, double rho_cutoff, double* p0,
+                                      long long* cutoff_index)
+{
+    using namespace mp;
+    if (n < 1 || !rc || !rho0 || !g_edge || !p0)
+        return na_fail(MP_ERR_ARG, "mp_enforce_hse_noalloc: n >= 1, rc, rho0, g_edge and p0 are required");
+    if (n > kNoAllocMaxRadii)
+        return na_fail(MP_ERR_ARG, "mp_enforce_hse_noalloc: n exceeds the static scratch (at most 16777216 centres)");
+    if (!std::isfinite(p0_base) || std::isnan(rho_cutoff))
+        return na_fail(MP_ERR_ARG, "mp_enforce_hse_noalloc: p0_base must be finite");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return na_fail(MP_ERR_DEVICE, "mp_enforce_hse_noalloc: no current HIP device");
+    double* work = nullptr;
+    if (scratch_for(dev, &work) != hipSuccess) {
+        (void)hipGetLastError();
+        return na_fail(MP_ERR_DEVICE, "mp_enforce_hse_noalloc: hipGetSymbolAddress of the scratch array failed");
+    }
+    launch_enforce_hse(n, rc, rho0, g_edge, p0_base, rho_cutoff, p0, work, nullptr, cutoff_index,
+                       (hipStream_t)stream);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return na_fail(MP_ERR_DEVICE, hipGetErrorString(e));
+    g_noalloc_err[0] = '\0';
+    return MP_OK;
+}

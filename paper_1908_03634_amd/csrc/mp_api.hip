@@ -1285,7 +1285,7 @@ int mp_free(mp_ctx* c)
     return MP_OK;
 }
 
-const char* mp_last_error(const mp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* mp_last_error(const mp_ctx* c) { return c ? c->err.c_str() : mp::noalloc_last_error(); }
 
 int mp_map_base_state(mp_ctx* c, int geometry, const double* beta0_1d, int n1d, double dr, const double* center,
                       const double* rho, double* cx, double* cy, double* cz)

@@ -37,4 +37,7 @@ void launch_beta0_from_p0(long long n, double rho0_centre, const double* p0, con
 void launch_w0(int spherical, long long n, const double* rc, const double* re, const double* beta0, const double* sbar,
                const double* psi, double* w0, double* work, hipStream_t s);
 
+// Text of the last failure of mp_enforce_hse_noalloc on the calling thread.
+const char* noalloc_last_error();
+
 }  // namespace mp

@@ -96,7 +96,7 @@ class Info(ctypes.Structure):
 EXPORTS = ["mp_config_default", "mp_init", "mp_map_base_state", "mp_set_coefs", "mp_mac_project", "mp_solve",
            "mp_mac_project_split", "mp_radius_count", "mp_average", "mp_set_kernel_timing", "mp_apply", "mp_coef_grad",
            "mp_nodal_shape", "mp_nodal_project", "mp_nodal_apply", "mp_base_radii", "mp_enforce_hse",
-           "mp_beta0_from_p0", "mp_w0", "mp_free", "mp_last_error", "mp_version"]
+           "mp_beta0_from_p0", "mp_w0", "mp_enforce_hse_noalloc", "mp_free", "mp_last_error", "mp_version"]
 
 _lib = None
 
@@ -148,6 +148,8 @@ def load_library(path=None):
     lib.mp_base_radii.restype = I
     lib.mp_enforce_hse.argtypes = [P, L, P, P, P, D, D, P, ctypes.POINTER(L)]
     lib.mp_enforce_hse.restype = I
+    lib.mp_enforce_hse_noalloc.argtypes = [P, L, P, P, P, D, D, P, P]
+    lib.mp_enforce_hse_noalloc.restype = I
     lib.mp_beta0_from_p0.argtypes = [P, L, D, P, P, P]
     lib.mp_beta0_from_p0.restype = I
     lib.mp_w0.argtypes = [P, I, L, P, P, P, P, P, P]
@@ -460,6 +462,31 @@ class Context:
     def __exit__(self, *exc):
         self.close()
         return False
+
+
+def enforce_hse_noalloc(rc, rho0, g_edge, p0_base, rho_cutoff, p0, cutoff_index=None, stream=None):
+    """mp_enforce_hse_noalloc: Enforce HSE without a context and without any
+    device allocation (the library's static scratch); p0 (out) and
+    cutoff_index (a one-element int64 tensor, out, or None) are device
+    tensors on the current device.  Returns without waiting; runs on
+    `stream` (default: torch's current stream)."""
+    lib = load_library()
+    n = int(rc.shape[0])
+    dev = rc.device
+    for t, shape, name in ((rc, (n,), "rc"), (rho0, (n,), "rho0"), (g_edge, (n + 1,), "g_edge"), (p0, (n,), "p0")):
+        if t.device != dev or t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError(f"{name} must be a contiguous float64 tensor of shape {shape} on {dev}")
+    if cutoff_index is not None and (cutoff_index.dtype != torch.int64 or cutoff_index.numel() != 1
+                                     or cutoff_index.device != dev):
+        raise ValueError("cutoff_index must be a one-element int64 tensor on the same device")
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    code = lib.mp_enforce_hse_noalloc(ctypes.c_void_p(st.cuda_stream), n, ctypes.c_void_p(rc.data_ptr()),
+                                      ctypes.c_void_p(rho0.data_ptr()), ctypes.c_void_p(g_edge.data_ptr()),
+                                      float(p0_base), float(rho_cutoff), ctypes.c_void_p(p0.data_ptr()),
+                                      ctypes.c_void_p(cutoff_index.data_ptr()) if cutoff_index is not None else None)
+    if code != MP_OK:
+        raise MprojError(code, f"mp_enforce_hse_noalloc: {lib.mp_last_error(None).decode()}")
+    return p0
 
 
 def version():
