@@ -65,6 +65,12 @@ def _declare(lib):
     lib.or_plane_average.argtypes = [_I, _I, _I, _D, _D]
     lib.or_split_source.argtypes = [_I, _I, _I, _I, _D, _D, _D]
     lib.or_split_source.restype = _I
+    lib.or_average_uniform.argtypes = [_I, _I, _I, _F, _D, _I, _F, _D]
+    lib.or_average_uniform.restype = _I
+    lib.or_split_source_uniform.argtypes = [_I, _I, _I, _F, _I, _I, _F, _D, _D, _D]
+    lib.or_split_source_uniform.restype = _I
+    lib.or_add_w0.argtypes = _GRID + [_I, _D, _D, ctypes.c_long, _D, _D, _D, _D]
+    lib.or_add_w0.restype = _I
     lib.or_radius_count.argtypes = [_I, _I, _I]
     lib.or_radius_count.restype = ctypes.c_long
     lib.or_radius_index.argtypes = [_I, _I, _I, ctypes.POINTER(ctypes.c_long)]
@@ -225,17 +231,50 @@ def plane_average(phi):
     return out
 
 
-def split_source(geometry, S):
+def average_uniform(phi, h, n1d, dr):
+    """Lateral average onto the uniform base state r_j = (j + 1/2) dr (Sec. 3.1):
+    the averages over the irregular radii, quadratically interpolated (the
+    three reached radii around the nearest one; end values held)."""
+    nz, ny, nx = phi.shape
+    a = np.ascontiguousarray(phi, dtype=np.float64)
+    out = np.zeros(int(n1d))
+    if _load().or_average_uniform(nx, ny, nz, float(h), _p(a), int(n1d), float(dr), _p(out)):
+        raise ValueError("the uniform Average needs even extents and dr > 0")
+    return out
+
+
+def split_source(geometry, S, h=None, n1d=None, dr=None):
     """(S - Sbar on the cells, Sbar): the source of the velocity-split
     constraint div(beta0 U~) = beta0 (S - Sbar) of Appendix A, Sbar the
-    lateral average (planes for geometry 0, irregular radii for geometry 2)."""
+    lateral average: per plane (geometry 0), per irregular radius (2), or on
+    the uniform table of n1d entries at spacing dr filled back linearly (1) or
+    quadratically (3) (h the cell size; the star centred on the middle node)."""
     nz, ny, nx = S.shape
     a = np.ascontiguousarray(S, dtype=np.float64)
     out = np.zeros_like(a)
+    if geometry in (1, 3):
+        sbar = np.zeros(int(n1d))
+        if _load().or_split_source_uniform(nx, ny, nz, float(h), int(geometry), int(n1d), float(dr), _p(a), _p(out),
+                                           _p(sbar)):
+            raise ValueError("the uniform split source needs even extents and dr > 0")
+        return out, sbar
     sbar = np.zeros(nz if geometry == 0 else max(radius_count(nx, ny, nz), 1))
     if _load().or_split_source(nx, ny, nz, int(geometry), _p(a), _p(out), _p(sbar)):
-        raise ValueError("the split source needs a planar or irregular spherical base state")
+        raise ValueError("the split source needs a planar or spherical base state")
     return out, sbar
+
+
+def add_w0(g, geometry, w0_edges, re, center, ux, uy, uz):
+    """U = U~ + w0 e_r on the faces (Appendix A): planar (geometry 0) adds
+    w0[k] to the interior z faces; spherical adds w0(r_f) e_r . n_f on every
+    non-wall face, w0 linear between the edges re.  Returns copies."""
+    ux, uy, uz = (np.array(a, dtype=np.float64, order="C") for a in (ux, uy, uz))
+    w = np.ascontiguousarray(w0_edges, dtype=np.float64)
+    e = np.ascontiguousarray(re if re is not None else np.zeros(len(w)), dtype=np.float64)
+    c = np.ascontiguousarray(center if center is not None else (0.0, 0.0, 0.0), dtype=np.float64)
+    if _load().or_add_w0(*g.args(), int(geometry), _p(w), _p(e), len(w), _p(c), _p(ux), _p(uy), _p(uz)):
+        raise ValueError("w0 on faces: planar needs Neumann z and nz + 1 edge values")
+    return ux, uy, uz
 
 
 def irregular_radii(nm, h):
@@ -371,7 +410,7 @@ def mac_project(prob, tol=1e-12, maxcycles=200, split=False):
     S = prob.S
     sbar = None
     if split:
-        S, sbar = split_source(prob.geometry, prob.S)
+        S, sbar = split_source(prob.geometry, prob.S, h=prob.h, n1d=len(prob.beta0_1d), dr=prob.dr)
     rhs, m = mac_rhs(g, beta0_cc, prob.ux, prob.uy, prob.uz, S)
     phi, info = solve(g, cx, cy, cz, rhs, tol=tol, maxcycles=maxcycles)
     ux, uy, uz = velocity_correct(g, cx, cy, cz, beta0_cc, phi, prob.ux, prob.uy, prob.uz)

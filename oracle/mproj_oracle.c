@@ -15,8 +15,10 @@
  *    uniform radial grid r_j = (j + 1/2) dr), or, for the irregular base state,
  *    by the index m of the radius h sqrt(0.75 + 2m) of each cell centre;
  *  - the lateral Average (Sec. 3.1 and the Average module of Sec. 3.2) over
- *    those irregular radii, or over the planes of a planar atmosphere, and the
- *    source S - Sbar of the velocity-split constraint of Appendix A;
+ *    those irregular radii, onto a uniform radial base state (quadratic
+ *    interpolation of the radius averages), or over the planes of a planar
+ *    atmosphere; the source S - Sbar of the velocity-split constraint of
+ *    Appendix A, and the full velocity U = U~ + w0 e_r on the faces;
  *  - the one-dimensional base state: centres and edges of the irregular radii,
  *    Enforce HSE (p0 from rho0), beta0 from its definition in Sec. 2, and the
  *    base-state velocity w0 of the velocity split (Appendix A);
@@ -224,6 +226,166 @@ int or_split_source(int nx, int ny, int nz, int geometry, const double *S, doubl
         return 0;
     }
     return 1;
+}
+
+/* Lagrange polynomial through the points (x[q], y[q]), q < np (np = 1, 2
+ * or 3), evaluated at r. */
+static double lagrange(const double *x, const double *y, int np, double r)
+{
+    double v = 0.0;
+    for (int q = 0; q < np; q++) {
+        double w = 1.0;
+        for (int s = 0; s < np; s++)
+            if (s != q) w *= (r - x[s]) / (x[q] - x[s]);
+        v += w * y[q];
+    }
+    return v;
+}
+
+/* Lateral average onto the uniform base state r_j = (j + 1/2) dr, j < n1d
+ * (Sec. 3.1; Delta r = Delta x / 5 before the irregular base state): first
+ * the arithmetic average over the cells of each radius h sqrt(0.75 + 2m)
+ * (or_average_irregular), then quadratic interpolation of those averages onto
+ * r_j.  Only radii that cell centres reach carry data.  The parabola runs
+ * through the reached radius nearest r_j and the reached radii just below and
+ * above it (shifted inward at the first and last reached radius); below the
+ * smallest and beyond the largest reached radius the first and last averages
+ * are held.  The centre of the star is the node in the middle of the box.
+ * Returns 1 when an extent is odd. */
+int or_average_uniform(int nx, int ny, int nz, double h, const double *phi, int n1d, double dr, double *avg)
+{
+    long nm = or_radius_count(nx, ny, nz);
+    if (nm == 0 || n1d < 1 || !(dr > 0.0)) return 1;
+    double *a = (double *)malloc(sizeof(double) * (size_t)nm);
+    double *cnt = (double *)malloc(sizeof(double) * (size_t)nm);
+    double *R = (double *)malloc(sizeof(double) * (size_t)nm);
+    double *A = (double *)malloc(sizeof(double) * (size_t)nm);
+    or_average_irregular(nx, ny, nz, phi, nm, a, cnt);
+    long P = 0; /* the reached radii, in increasing order */
+    for (long m = 0; m < nm; m++)
+        if (cnt[m] > 0.0) {
+            R[P] = h * sqrt(0.75 + 2.0 * (double)m);
+            A[P] = a[m];
+            P++;
+        }
+    for (int j = 0; j < n1d; j++) {
+        double r = (j + 0.5) * dr;
+        if (r <= R[0]) {
+            avg[j] = A[0];
+        } else if (r >= R[P - 1]) {
+            avg[j] = A[P - 1];
+        } else {
+            long lo = 0, hi = P - 1; /* R[lo] <= r < R[hi] */
+            while (hi - lo > 1) {
+                long mid = (lo + hi) / 2;
+                if (R[mid] <= r)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            long q = (r - R[lo] <= R[hi] - r) ? lo : hi;
+            int np = P < 3 ? (int)P : 3;
+            long first = q - 1;
+            if (first > P - np) first = P - np;
+            if (first < 0) first = 0;
+            avg[j] = lagrange(R + first, A + first, np, r);
+        }
+    }
+    free(a);
+    free(cnt);
+    free(R);
+    free(A);
+    return 0;
+}
+
+/* Velocity-split source for a uniform spherical base state (Appendix A with
+ * the uniform Average of Sec. 3.1): Sbar on the table r_j = (j + 1/2) dr
+ * (or_average_uniform of S), filled back onto the cells with the fill of the
+ * mapping (geometry 1: linear, 3: quadratic, about the middle node of the
+ * box), s_out = S - Sbar(cell).  sbar: n1d entries.  Returns 1 on a bad
+ * geometry or odd extents. */
+int or_split_source_uniform(int nx, int ny, int nz, double h, int geometry, int n1d, double dr, const double *S,
+                            double *s_out, double *sbar)
+{
+    if (geometry != 1 && geometry != 3) return 1;
+    if (or_average_uniform(nx, ny, nz, h, S, n1d, dr, sbar)) return 1;
+    grid_t g = mkgrid(nx, ny, nz, h, 0, 0, 0);
+    double c[3] = {0.5 * nx * h, 0.5 * ny * h, 0.5 * nz * h};
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                double r = cell_radius(&g, c, i, j, k);
+                double sb = geometry == 1 ? radial_lookup(sbar, n1d, dr, r) : radial_quadratic(sbar, n1d, dr, r);
+                s_out[cell(&g, i, j, k)] = S[cell(&g, i, j, k)] - sb;
+            }
+    return 0;
+}
+
+/* w0 at radius r from its values on the base-state edges re[0..ne) (sorted
+ * increasing): linear in r between the two edges around r, the last value
+ * held beyond the last edge. */
+static double w0_at(const double *w0, const double *re, long ne, double r)
+{
+    if (r >= re[ne - 1]) return w0[ne - 1];
+    if (r <= re[0]) return w0[0];
+    long lo = 0, hi = ne - 1; /* re[lo] <= r < re[hi] */
+    while (hi - lo > 1) {
+        long mid = (lo + hi) / 2;
+        if (re[mid] <= r)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    double t = (r - re[lo]) / (re[hi] - re[lo]);
+    return w0[lo] + t * (w0[hi] - w0[lo]);
+}
+
+/* Full velocity of the velocity split (Appendix A): U = U~ + w0 e_r on the MAC
+ * faces, in place on (ux, uy, uz) holding U~.  geometry 0 (planar, e_r = e_z,
+ * base-state edges on the z faces): z face k (the low face of cell k) gains
+ * w0[k]; x and y faces are unchanged; ne = nz + 1 and re is not used.
+ * Spherical geometries: every face gains w0(r_f) (e_r . n_f), r_f the distance
+ * of the face centre from `center`, e_r . n_f the component of (x_f -
+ * center) / r_f along the face's axis (0 at r_f = 0), w0(r) linear between
+ * the edges re[0..ne).  Wall faces (Neumann axes) are left unchanged.
+ * Returns 1 on bad arguments (planar with a periodic z axis or ne != nz + 1). */
+int or_add_w0(int nx, int ny, int nz, double h, int bx, int by, int bz, int geometry, const double *w0,
+              const double *re, long ne, const double *center, double *ux, double *uy, double *uz)
+{
+    grid_t g = mkgrid(nx, ny, nz, h, bx, by, bz);
+    if (geometry == 0) {
+        if (!bz || ne != nz + 1) return 1;
+        for (int f = 1; f < nz; f++)
+            for (int j = 0; j < ny; j++)
+                for (int i = 0; i < nx; i++) uz[zface(&g, i, j, f)] += w0[f];
+        return 0;
+    }
+    if (ne < 1) return 1;
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int f = 0; f < nx + bx; f++) {
+                if (bx && (f == 0 || f == nx)) continue;
+                double x = f * h - center[0], y = (j + 0.5) * h - center[1], z = (k + 0.5) * h - center[2];
+                double r = sqrt(x * x + y * y + z * z);
+                if (r > 0.0) ux[xface(&g, f, j, k)] += w0_at(w0, re, ne, r) * (x / r);
+            }
+    for (int k = 0; k < nz; k++)
+        for (int f = 0; f < ny + by; f++)
+            for (int i = 0; i < nx; i++) {
+                if (by && (f == 0 || f == ny)) continue;
+                double x = (i + 0.5) * h - center[0], y = f * h - center[1], z = (k + 0.5) * h - center[2];
+                double r = sqrt(x * x + y * y + z * z);
+                if (r > 0.0) uy[yface(&g, i, f, k)] += w0_at(w0, re, ne, r) * (y / r);
+            }
+    for (int f = 0; f < nz + bz; f++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                if (bz && (f == 0 || f == nz)) continue;
+                double x = (i + 0.5) * h - center[0], y = (j + 0.5) * h - center[1], z = f * h - center[2];
+                double r = sqrt(x * x + y * y + z * z);
+                if (r > 0.0) uz[zface(&g, i, j, f)] += w0_at(w0, re, ne, r) * (z / r);
+            }
+    return 0;
 }
 
 /* ---------------------------------------------------------------------- */

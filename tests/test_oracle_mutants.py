@@ -188,6 +188,42 @@ def pin_w0_rate():
     return all(_passes(B.test_w0_with_a_stratified_beta0_converges_at_second_order, s) for s in ("uniform", "irregular"))
 
 
+def pin_uniform_quadratic():
+    from tests import test_oracle_uniform as U
+
+    return all(_passes(U.test_uniform_average_reproduces_quadratic_profiles, s) for s in U.SHAPES)
+
+
+def pin_uniform_stencil():
+    from tests import test_oracle_uniform as U
+
+    return all(_passes(U.test_uniform_average_takes_the_three_reached_radii_around_the_nearest, s) for s in U.SHAPES)
+
+
+def pin_uniform_split():
+    from tests import test_oracle_uniform as U
+
+    return all(_passes(U.test_uniform_split_source, g) for g in (1, 3))
+
+
+def pin_w0_planar_faces():
+    from tests import test_oracle_uniform as U
+
+    return _passes(U.test_planar_full_velocity_meets_the_constraint, (0, 0, 1))
+
+
+def pin_w0_linear_faces():
+    from tests import test_oracle_uniform as U
+
+    return _passes(U.test_spherical_w0_faces_for_a_linear_w0_are_exact)
+
+
+def pin_w0_face_interpolation():
+    from tests import test_oracle_uniform as U
+
+    return _passes(U.test_spherical_w0_faces_interpolate_between_edges)
+
+
 MUTANTS = [
     ("harmonic mean replaced by arithmetic mean", "v = 2.0 * a * b / (a + b);", "v = 0.5 * (a + b);",
      pin_series_conductance),
@@ -233,6 +269,25 @@ MUTANTS = [
      "re[j + 1] * re[j + 1] * (re[j + 1] - re[j]);", pin_w0_exact),
     ("w0 edge beta0 taken from the inner centre", "    return beta0[a] + t * (beta0[b] - beta0[a]);",
      "    return beta0[a];", pin_w0_rate),
+    ("uniform Average interpolated linearly", "int np = P < 3 ? (int)P : 3;", "int np = P < 2 ? (int)P : 2;",
+     pin_uniform_quadratic),
+    ("uniform Average stencil around the radius below", "long q = (r - R[lo] <= R[hi] - r) ? lo : hi;",
+     "long q = lo;", pin_uniform_stencil),
+    ("uniform Average interpolates through unreached radii", "if (cnt[m] > 0.0) {", "if (m >= 0) {",
+     pin_uniform_quadratic),
+    ("uniform Average ends set to zero", "            avg[j] = A[0];", "            avg[j] = 0.0;",
+     pin_uniform_quadratic),
+    ("uniform split source filled linearly after a quadratic mapping",
+     "double sb = geometry == 1 ? radial_lookup(sbar, n1d, dr, r) : radial_quadratic(sbar, n1d, dr, r);",
+     "double sb = radial_lookup(sbar, n1d, dr, r);", pin_uniform_split),
+    ("planar w0 put on the face above its edge", "uz[zface(&g, i, j, f)] += w0[f];",
+     "uz[zface(&g, i, j, f)] += w0[f + 1];", pin_w0_planar_faces),
+    ("spherical w0 added without the e_r . n factor", "ux[xface(&g, f, j, k)] += w0_at(w0, re, ne, r) * (x / r);",
+     "ux[xface(&g, f, j, k)] += w0_at(w0, re, ne, r);", pin_w0_linear_faces),
+    ("x-face radius measured at the cell centre", "double x = f * h - center[0], y = (j + 0.5) * h - center[1],",
+     "double x = (f + 0.5) * h - center[0], y = (j + 0.5) * h - center[1],", pin_w0_linear_faces),
+    ("w0 taken at the edge below instead of interpolated", "    return w0[lo] + t * (w0[hi] - w0[lo]);",
+     "    return w0[lo];", pin_w0_face_interpolation),
 ]
 
 
