@@ -194,12 +194,18 @@ int mp_mac_project(mp_ctx *ctx, double *ux, double *uy, double *uz, const double
 
 /* Velocity-split MAC projection (Appendix A): as mp_mac_project with the
  * source S replaced by S - Sbar, Sbar being the lateral average of S
- * (Sec. 3.1): the plane averages after an MP_PLANAR mapping, the averages
- * over the irregular radii after an MP_SPHERICAL_IRREGULAR mapping.  The
- * projected velocity U~ then satisfies div(beta0 U~) = beta0 (S - Sbar) up to
- * the solve residual; the base-state velocity w0 of the split is not computed
- * here.  sbar: device array receiving Sbar (nz, or mp_radius_count entries),
- * or NULL.  Errors as mp_mac_project; MP_ERR_STATE after any other mapping. */
+ * (Sec. 3.1): the plane averages after an MP_PLANAR mapping; the averages
+ * over the irregular radii after an MP_SPHERICAL_IRREGULAR mapping; after an
+ * MP_SPHERICAL or MP_SPHERICAL_QUADRATIC mapping the radius averages
+ * interpolated onto the mapping's table r_j = (j + 1/2) dr (as
+ * mp_average_uniform) and filled back onto the cells with the mapping's
+ * interpolation.  The projected velocity U~ then satisfies
+ * div(beta0 U~) = beta0 (S - Sbar) up to the solve residual; the base-state
+ * velocity w0 (mp_w0) is added by mp_add_w0.  sbar: device array receiving
+ * Sbar (nz, mp_radius_count or n1d entries), or NULL.  Errors as
+ * mp_mac_project; MP_ERR_STATE when a uniform spherical mapping's centre is
+ * not the node in the middle of the box (or an extent is odd); the first
+ * call after a spherical mapping builds the radius list (MP_ERR_NOMEM). */
 int mp_mac_project_split(mp_ctx *ctx, double *ux, double *uy, double *uz, const double *S, double *phi,
                          int use_initial_guess, double *sbar, mp_info *info);
 
@@ -254,11 +260,40 @@ int mp_radius_count(const mp_ctx *ctx, long long *nm);
  * Sec. 3.2): avg[m] = (sum of phi over the cells whose centres lie at radius
  * m) / (number of those cells); count[m] = that number.  Radii that no cell
  * centre reaches get 0 and 0.  phi: cells; avg, count: device arrays of
- * mp_radius_count doubles (count may be NULL).  The summation order is fixed,
- * so results are reproducible.  The first call builds the list of cells per
- * radius (host counting sort, 4 bytes per cell of device memory).
- * Errors: MP_ERR_ARG (odd extents, NULL, >= 2^32 cells), MP_ERR_NOMEM. */
+ * mp_radius_count doubles (count may be NULL).  Each cell's eight mirror
+ * images (one per octant about the centre, all at its radius) are summed
+ * first, then each radius in a fixed order, so results are reproducible.  The
+ * first call builds, on the device, the list of octant cells per radius
+ * (12 bytes per eight cells, kept; about as much again of scratch during the
+ * build).  Errors: MP_ERR_ARG (odd extents, NULL), MP_ERR_NOMEM. */
 int mp_average(mp_ctx *ctx, const double *phi, double *avg, double *count);
+
+/* Lateral Average onto a uniform base state (Sec. 3.1, the constant
+ * Delta r = Delta x / 5 spacing of spherical stars before the irregular base
+ * state): the radius averages of mp_average, then quadratic interpolation
+ * onto r_j = (j + 1/2) dr, j < n1d, about the node in the middle of the box:
+ * the parabola through the reached radius (one some cell centre lies at)
+ * nearest r_j and the reached radii just below and above it (shifted inward
+ * at the first and last reached radius); the first and last averages are held
+ * below the smallest and beyond the largest reached radius.  avg: device
+ * array of n1d doubles.  Errors: MP_ERR_ARG (odd extents, NULL, n1d < 1,
+ * dr <= 0), MP_ERR_NOMEM (first call). */
+int mp_average_uniform(mp_ctx *ctx, const double *phi, int n1d, double dr, double *avg);
+
+/* Full velocity of the velocity split (Appendix A): U = U~ + w0 e_r on the
+ * MAC faces, in place on (ux, uy, uz) (face layouts above) holding U~ (e.g.
+ * after mp_mac_project_split).  After an MP_PLANAR mapping e_r = e_z and the
+ * base-state edges are the z faces: z face k (the low face of cell k,
+ * 0 < k < nz) gains w0[k]; ne = nz + 1, re unused (may be NULL); z must be a
+ * Neumann axis (MP_ERR_STATE otherwise).  After a spherical mapping every
+ * face gains w0(r_f) e_r . n_f: r_f the distance of the face centre from the
+ * star centre (the mapping's centre; the middle node for the irregular base
+ * state), e_r . n_f the component of the unit radius vector along the face's
+ * axis (0 at r_f = 0), w0(r) linear between the ne edges re (device array,
+ * increasing; mp_base_radii or r_e = e dr), held outside them.  Wall faces are
+ * left unchanged.  w0: device array of ne doubles (mp_w0).  Returns without
+ * waiting.  Errors: MP_ERR_ARG (NULL, ne), MP_ERR_STATE (no mapping). */
+int mp_add_w0(mp_ctx *ctx, const double *w0, const double *re, long long ne, double *ux, double *uy, double *uz);
 
 /* ---- one-dimensional base state (Sec. 3.2 modules, Appendix A) ----------
  * Arrays are device arrays of doubles owned by the caller; each call is a

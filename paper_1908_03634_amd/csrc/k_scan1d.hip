@@ -280,6 +280,18 @@ struct W0Op {
     __device__ void first() const { w0[0] = 0.0; }
 };
 
+// Offsets of buckets from their counts: offs[j + 1] = the inclusive sum.
+struct OffsetsOp {
+    static constexpr int kExt = EXT_NONE;
+    const double* cnt;
+    long long* offs;
+    __device__ double inc(long long j) const { return cnt[j]; }
+    __device__ double ext(long long) const { return 0.0; }
+    __device__ long long last(const double*, long long n) const { return n - 1; }
+    __device__ void put(long long j, double v) const { offs[j + 1] = (long long)v; }
+    __device__ void first() const { offs[0] = 0; }
+};
+
 template <typename Op>
 void run_scan(long long n, const Op& op, double* work, double* ext_out, hipStream_t s)
 {
@@ -315,6 +327,12 @@ void launch_w0(int spherical, long long n, const double* rc, const double* re, c
 {
     const W0Op op{spherical, n, rc, re, beta0, sbar, psi, w0};
     run_scan(n, op, work, nullptr, s);
+}
+
+void launch_offsets_of_counts(long long nm, const double* cnt, long long* offs, double* work, hipStream_t s)
+{
+    const OffsetsOp op{cnt, offs};
+    run_scan(nm, op, work, nullptr, s);
 }
 
 // ---------------------------------------------------------------------------

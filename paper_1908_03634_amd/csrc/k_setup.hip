@@ -229,6 +229,31 @@ __global__ __launch_bounds__(kBlock) void k_fill(Dims d, int lz, double h, int g
     zpart_store(part, block_sum(bad, sh));
 }
 
+// S - Sbar(cell), Sbar filled from its table like beta0 (the velocity-split
+// source after a uniform spherical mapping, geometry 1 or 3).
+__global__ __launch_bounds__(kBlock) void k_split_fill(Dims d, double h, int geometry, const double* __restrict__ tab,
+                                                       int n1d, double dr, double cx0, double cy0, double cz0,
+                                                       const double* __restrict__ S, double* __restrict__ out)
+{
+    const long long n = d.n();
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(q % d.nx);
+        const long long t = q / d.nx;
+        const int j = (int)(t % d.ny), k = (int)(t / d.ny);
+        out[q] = S[q] - fill_value(geometry, tab, n1d, dr, (i + 0.5) * h - cx0, (j + 0.5) * h - cy0,
+                                   (k + 0.5) * h - cz0, 0);
+    }
+}
+
+void launch_split_fill(const Dims& d, double h, int geometry, const double* tab, int n1d, double dr,
+                       const double* center, const double* S, double* out, hipStream_t s)
+{
+    long long nb = (d.n() + kBlock - 1) / kBlock;
+    nb = nb > 16384 ? 16384 : nb;
+    hipLaunchKernelGGL(k_split_fill, dim3((unsigned)nb), dim3(kBlock), 0, s, d, h, geometry, tab, n1d, dr, center[0],
+                       center[1], center[2], S, out);
+}
+
 void launch_fill(const Dims& d, double h, int geometry, const double* tab, int n1d, double dr, double cx0, double cy0,
                  double cz0, const double* rho, double* beta0, double* ccell, float* ccell32, double* partials,
                  hipStream_t s)

@@ -135,8 +135,14 @@ struct mp_ctx {
     double* sbar = nullptr;             // lateral average of S (velocity-split source)
     long long sbar_n = 0;
     long long nm = 0;                   // radii of the irregular base state (0: odd extents)
-    long long* rad_offs = nullptr;      // cells of radius m: rad_cells[rad_offs[m] .. rad_offs[m+1])
-    unsigned* rad_cells = nullptr;      // built on the first mp_average
+    long long* rad_offs = nullptr;      // octant cells of radius m: rad_list[rad_offs[m] .. rad_offs[m+1])
+    unsigned* rad_list = nullptr;       // built on the device at the first Average
+    double* fold = nullptr;             // one value per octant cell (the eight mirror cells summed)
+    double* avg_irr = nullptr;          // radius averages (the uniform Average interpolates them)
+    double* seff = nullptr;             // S - Sbar on the cells (split source after a uniform spherical mapping)
+    int map_n1d = 0;                    // table of the last mapping: entries, spacing, star centre
+    double map_dr = 0.0;
+    double map_center[3] = {0.0, 0.0, 0.0};
     double* ir_phi = nullptr;     // refinement update fused into the V-cycle's last pass
     const double* ir_s = nullptr;  // (phi += ir_s[0] * e), or nullptr
     bool have_coefs = false, have_base = false;
@@ -228,8 +234,9 @@ void free_all(mp_ctx* c)
     if (c->ccell32) (void)hipFree(c->ccell32);
     if (c->sbar) (void)hipFree(c->sbar);
     if (c->scanw) (void)hipFree(c->scanw);
-    if (c->rad_offs) (void)hipFree(c->rad_offs);
-    if (c->rad_cells) (void)hipFree(c->rad_cells);
+    double* radbufs[] = {(double*)c->rad_offs, (double*)c->rad_list, c->fold, c->avg_irr, c->seff};
+    for (double* p : radbufs)
+        if (p) (void)hipFree(p);
     if (c->hscal) (void)hipHostFree(c->hscal);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -296,48 +303,55 @@ long long radius_count(const Dims& d)
     return (a * a + b * b + e * e - 3) / 8 + 1;
 }
 
-// Cells grouped by radius, each group in memory order (counting sort on the
-// host, once per context), uploaded to the device.
+// The octant list of the lateral Average (cells of the high octant grouped
+// by radius, memory order within a radius) and the folded-value buffer,
+// built on the device at the first Average of a context (the grid does not
+// change).  Its scratch (per-plane counters, ranks, radius counts) is freed
+// afterwards.
 int build_radius_list(mp_ctx* c)
 {
-    if (c->rad_cells) return MP_OK;
+    if (c->rad_list) return MP_OK;
     const Dims& d = c->d0;
     if (c->nm == 0) return fail(c, MP_ERR_ARG, "the irregular base state needs even extents");
-    if (c->n0 >= (1LL << 32)) return fail(c, MP_ERR_ARG, "too many cells for the radius list");
-    std::vector<long long> offs((size_t)c->nm + 1, 0);
-    for (int k = 0; k < d.nz; k++)
-        for (int j = 0; j < d.ny; j++) {
-            const long long bj = 2LL * j + 1 - d.ny, bk = 2LL * k + 1 - d.nz, base = bj * bj + bk * bk - 3;
-            for (int i = 0; i < d.nx; i++) {
-                const long long a = 2LL * i + 1 - d.nx;
-                offs[(size_t)((a * a + base) / 8) + 1]++;
-            }
+    const long long noct = c->n0 / 8;
+    const long long cnt_bytes = mp::oct_count_bytes(d.nx, d.ny, d.nz);
+    const long long wneed = mp::scan_work_doubles(c->nm);
+    void *offs = nullptr, *list = nullptr, *fold = nullptr, *cnt = nullptr, *rank = nullptr, *cntm = nullptr,
+         *work = nullptr;
+    bool ok = hipMalloc(&offs, sizeof(long long) * (size_t)(c->nm + 1)) == hipSuccess;
+    ok = ok && hipMalloc(&list, sizeof(unsigned) * (size_t)noct) == hipSuccess;
+    ok = ok && hipMalloc(&fold, sizeof(double) * (size_t)noct) == hipSuccess;
+    ok = ok && hipMalloc(&cnt, (size_t)cnt_bytes) == hipSuccess;
+    ok = ok && hipMalloc(&rank, sizeof(unsigned) * (size_t)noct) == hipSuccess;
+    ok = ok && hipMalloc(&cntm, sizeof(double) * (size_t)c->nm) == hipSuccess;
+    ok = ok && hipMalloc(&work, sizeof(double) * (size_t)wneed) == hipSuccess;
+    if (test_fail_alloc("radius_list")) ok = false;
+    auto release = [&](bool keep) {
+        void* tmp[] = {cnt, rank, cntm, work};
+        for (void* p : tmp)
+            if (p) (void)hipFree(p);
+        if (!keep) {
+            void* res[] = {offs, list, fold};
+            for (void* p : res)
+                if (p) (void)hipFree(p);
         }
-    for (size_t m = 0; m < (size_t)c->nm; m++) offs[m + 1] += offs[m];
-    std::vector<long long> pos(offs.begin(), offs.end() - 1);
-    std::vector<unsigned> cells((size_t)c->n0);
-    unsigned q = 0;
-    for (int k = 0; k < d.nz; k++)
-        for (int j = 0; j < d.ny; j++) {
-            const long long bj = 2LL * j + 1 - d.ny, bk = 2LL * k + 1 - d.nz, base = bj * bj + bk * bk - 3;
-            for (int i = 0; i < d.nx; i++, q++) {
-                const long long a = 2LL * i + 1 - d.nx;
-                cells[(size_t)pos[(size_t)((a * a + base) / 8)]++] = q;
-            }
-        }
-    hipError_t e1 = hipMalloc((void**)&c->rad_offs, sizeof(long long) * offs.size());
-    hipError_t e2 = hipMalloc((void**)&c->rad_cells, sizeof(unsigned) * cells.size());
-    if (test_fail_alloc("radius_list")) e2 = hipErrorOutOfMemory;
-    if (e1 != hipSuccess || e2 != hipSuccess) {
-        if (c->rad_offs) (void)hipFree(c->rad_offs);
-        if (c->rad_cells) (void)hipFree(c->rad_cells);
-        c->rad_offs = nullptr;
-        c->rad_cells = nullptr;
+    };
+    if (!ok) {
+        release(false);
         (void)hipGetLastError();
         return fail(c, MP_ERR_NOMEM, "no device memory for the radius list");
     }
-    HIPCHK(c, hipMemcpy(c->rad_offs, offs.data(), sizeof(long long) * offs.size(), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->rad_cells, cells.data(), sizeof(unsigned) * cells.size(), hipMemcpyHostToDevice));
+    mp::launch_radius_list(d.nx, d.ny, d.nz, c->nm, (unsigned*)cnt, (unsigned*)rank, (double*)cntm, (long long*)offs,
+                           (unsigned*)list, (double*)work, c->stream);
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        release(false);
+        return fail(c, MP_ERR_DEVICE, "building the radius list failed: %s", hipGetErrorString(e));
+    }
+    release(true);
+    c->rad_offs = (long long*)offs;
+    c->rad_list = (unsigned*)list;
+    c->fold = (double*)fold;
     return MP_OK;
 }
 
@@ -1343,6 +1357,11 @@ int mp_map_base_state(mp_ctx* c, int geometry, const double* beta0_1d, int n1d, 
     }
     c->have_base = c->have_coefs = true;
     c->geometry = geometry;
+    c->map_n1d = n1d;
+    c->map_dr = dr;
+    c->map_center[0] = c0;
+    c->map_center[1] = c1;
+    c->map_center[2] = c2;
     c->map_serial++;
     return MP_OK;
 }
@@ -1467,6 +1486,42 @@ int mp_mac_project(mp_ctx* c, double* ux, double* uy, double* uz, const double* 
     return project(c, ux, uy, uz, S, nullptr, 0, phi, use_initial_guess, info);
 }
 
+// A device buffer of the context holding at least n doubles (grown on demand).
+static int ensure_buffer(mp_ctx* c, double** p, long long* cap, long long n, const char* what)
+{
+    if (*p && *cap >= n) return MP_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (hipMalloc((void**)p, sizeof(double) * (size_t)(n > 0 ? n : 1)) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, MP_ERR_NOMEM, "no device memory for %s", what);
+    }
+    *cap = n;
+    return MP_OK;
+}
+
+// The radius averages of phi into avg_irr (count: optional output).
+static int radius_averages(mp_ctx* c, const double* phi, double* avg, double* count)
+{
+    int st = build_radius_list(c);
+    if (st) return st;
+    mp::launch_average(c->d0, c->nm, c->rad_offs, c->rad_list, phi, c->fold, avg, count, c->stream);
+    return MP_OK;
+}
+
+// The star centre of the last spherical mapping is the node in the middle
+// of the box (what the radii h sqrt(0.75 + 2m) of the Average assume).
+static bool centred_on_middle_node(const mp_ctx* c)
+{
+    const double h = c->cfg.h;
+    const double mid[3] = {0.5 * c->d0.nx * h, 0.5 * c->d0.ny * h, 0.5 * c->d0.nz * h};
+    for (int a = 0; a < 3; a++)
+        if (!(fabs(c->map_center[a] - mid[a]) <= 1e-9 * h)) return false;
+    return c->nm > 0;
+}
+
 int mp_mac_project_split(mp_ctx* c, double* ux, double* uy, double* uz, const double* S, double* phi,
                          int use_initial_guess, double* sbar, mp_info* info)
 {
@@ -1474,31 +1529,42 @@ int mp_mac_project_split(mp_ctx* c, double* ux, double* uy, double* uz, const do
     reset_info(info);
     int st = project_checks(c, ux, uy, uz, S, phi);
     if (st) return st;
-    if (c->geometry != MP_PLANAR && c->geometry != MP_SPHERICAL_IRREGULAR)
-        return fail(c, MP_ERR_STATE, "the split source needs a planar or irregular spherical base state");
+    const int geo = c->geometry;
+    const bool uniform = geo == MP_SPHERICAL || geo == MP_SPHERICAL_QUADRATIC;
+    if (uniform && !centred_on_middle_node(c))
+        return fail(c, MP_ERR_STATE,
+                    "the split source of a uniform spherical base state needs the star centred on the middle node of "
+                    "a box with even extents");
     (void)hipSetDevice(c->cfg.device);
-    const long long ns = c->geometry == MP_PLANAR ? c->d0.nz : c->nm;
+    const long long ns = geo == MP_PLANAR ? c->d0.nz : geo == MP_SPHERICAL_IRREGULAR ? c->nm : c->map_n1d;
     if (!sbar) {
-        if (!c->sbar) {
-            if (hipMalloc((void**)&c->sbar, sizeof(double) * (size_t)ns) != hipSuccess) {
-                c->sbar = nullptr;
-                (void)hipGetLastError();
-                return fail(c, MP_ERR_NOMEM, "no device memory for the lateral average");
-            }
-            c->sbar_n = ns;
-        }
-        if (c->sbar_n < ns) return fail(c, MP_ERR_STATE, "lateral average buffer too small");
+        st = ensure_buffer(c, &c->sbar, &c->sbar_n, ns, "the lateral average");
+        if (st) return st;
         sbar = c->sbar;
     }
     HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-    if (c->geometry == MP_PLANAR) {
+    if (geo == MP_PLANAR) {
         mp::launch_plane_average(c->d0, S, sbar, c->stream);
-    } else {
-        st = build_radius_list(c);
-        if (st) return st;
-        mp::launch_average(c->nm, c->rad_offs, c->rad_cells, S, sbar, nullptr, c->stream);
+        return project(c, ux, uy, uz, S, sbar, 1, phi, use_initial_guess, info);
     }
-    return project(c, ux, uy, uz, S, sbar, c->geometry == MP_PLANAR ? 1 : 2, phi, use_initial_guess, info);
+    if (geo == MP_SPHERICAL_IRREGULAR) {
+        st = radius_averages(c, S, sbar, nullptr);
+        if (st) return st;
+        return project(c, ux, uy, uz, S, sbar, 2, phi, use_initial_guess, info);
+    }
+    // uniform table: the radius averages interpolated onto it, filled back
+    // onto the cells like beta0, S - Sbar formed once
+    long long cap = c->avg_irr ? c->nm : 0;
+    st = ensure_buffer(c, &c->avg_irr, &cap, c->nm, "the radius averages");
+    if (st) return st;
+    long long ncap = c->seff ? c->n0 : 0;
+    st = ensure_buffer(c, &c->seff, &ncap, c->n0, "the split source");
+    if (st) return st;
+    st = radius_averages(c, S, c->avg_irr, nullptr);
+    if (st) return st;
+    mp::launch_average_uniform(c->nm, c->cfg.h, c->avg_irr, c->rad_offs, c->map_n1d, c->map_dr, sbar, c->stream);
+    mp::launch_split_fill(c->d0, c->cfg.h, geo, sbar, c->map_n1d, c->map_dr, c->map_center, S, c->seff, c->stream);
+    return project(c, ux, uy, uz, c->seff, nullptr, 0, phi, use_initial_guess, info);
 }
 
 int mp_solve(mp_ctx* c, const double* rhs, double* x, int use_initial_guess, mp_info* info)
@@ -1706,9 +1772,46 @@ int mp_average(mp_ctx* c, const double* phi, double* avg, double* count)
     if (!phi || !avg) return fail(c, MP_ERR_ARG, "phi and avg are required");
     if (c->nm == 0) return fail(c, MP_ERR_ARG, "the irregular base state needs even extents");
     (void)hipSetDevice(c->cfg.device);
-    int st = build_radius_list(c);
+    int st = radius_averages(c, phi, avg, count);
     if (st) return st;
-    mp::launch_average(c->nm, c->rad_offs, c->rad_cells, phi, avg, count, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MP_OK;
+}
+
+int mp_average_uniform(mp_ctx* c, const double* phi, int n1d, double dr, double* avg)
+{
+    if (!c) return MP_ERR_ARG;
+    if (!phi || !avg) return fail(c, MP_ERR_ARG, "phi and avg are required");
+    if (n1d < 1 || !(dr > 0.0) || !isfinite(dr)) return fail(c, MP_ERR_ARG, "n1d >= 1 and dr > 0 are required");
+    if (c->nm == 0) return fail(c, MP_ERR_ARG, "the lateral average needs even extents");
+    (void)hipSetDevice(c->cfg.device);
+    long long cap = c->avg_irr ? c->nm : 0;
+    int st = ensure_buffer(c, &c->avg_irr, &cap, c->nm, "the radius averages");
+    if (st) return st;
+    st = radius_averages(c, phi, c->avg_irr, nullptr);
+    if (st) return st;
+    mp::launch_average_uniform(c->nm, c->cfg.h, c->avg_irr, c->rad_offs, n1d, dr, avg, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MP_OK;
+}
+
+int mp_add_w0(mp_ctx* c, const double* w0, const double* re, long long ne, double* ux, double* uy, double* uz)
+{
+    if (!c) return MP_ERR_ARG;
+    if (!w0 || !ux || !uy || !uz) return fail(c, MP_ERR_ARG, "w0, ux, uy and uz are required");
+    if (!c->have_base) return fail(c, MP_ERR_STATE, "mp_map_base_state has not succeeded on this context");
+    const bool planar = c->geometry == MP_PLANAR;
+    if (planar) {
+        if (c->d0.pz) return fail(c, MP_ERR_STATE, "w0 of a planar base state needs walls in z");
+        if (ne != (long long)c->d0.nz + 1) return fail(c, MP_ERR_ARG, "planar w0 needs nz + 1 edge values");
+    } else {
+        if (!re || ne < 1) return fail(c, MP_ERR_ARG, "spherical w0 needs its ne >= 1 edges re");
+    }
+    (void)hipSetDevice(c->cfg.device);
+    double center[3] = {c->map_center[0], c->map_center[1], c->map_center[2]};
+    if (c->geometry == MP_SPHERICAL_IRREGULAR)
+        for (int a = 0; a < 3; a++) center[a] = 0.5 * (a == 0 ? c->d0.nx : a == 1 ? c->d0.ny : c->d0.nz) * c->cfg.h;
+    mp::launch_w0_faces(c->d0, planar ? 1 : 0, c->cfg.h, center, w0, re, ne, ux, uy, uz, c->stream);
     HIPCHK(c, hipGetLastError());
     return MP_OK;
 }

@@ -96,7 +96,8 @@ class Info(ctypes.Structure):
 EXPORTS = ["mp_config_default", "mp_init", "mp_map_base_state", "mp_set_coefs", "mp_mac_project", "mp_solve",
            "mp_mac_project_split", "mp_radius_count", "mp_average", "mp_set_kernel_timing", "mp_apply", "mp_coef_grad",
            "mp_nodal_shape", "mp_nodal_project", "mp_nodal_apply", "mp_base_radii", "mp_enforce_hse",
-           "mp_beta0_from_p0", "mp_w0", "mp_enforce_hse_noalloc", "mp_free", "mp_last_error", "mp_version"]
+           "mp_beta0_from_p0", "mp_w0", "mp_enforce_hse_noalloc", "mp_average_uniform", "mp_add_w0", "mp_free",
+           "mp_last_error", "mp_version"]
 
 _lib = None
 
@@ -131,6 +132,10 @@ def load_library(path=None):
     lib.mp_radius_count.restype = I
     lib.mp_average.argtypes = [P, P, P, P]
     lib.mp_average.restype = I
+    lib.mp_average_uniform.argtypes = [P, P, I, D, P]
+    lib.mp_average_uniform.restype = I
+    lib.mp_add_w0.argtypes = [P, P, P, ctypes.c_longlong, P, P, P]
+    lib.mp_add_w0.restype = I
     lib.mp_set_kernel_timing.argtypes = [P, I]
     lib.mp_set_kernel_timing.restype = I
     lib.mp_apply.argtypes = [P, P, P]
@@ -347,6 +352,25 @@ class Context:
         pc = self._ptr(cnt, (nm,), "count") if count else None
         self._check(self._run(self.lib.mp_average, pp, pa, pc), "mp_average")
         return avg, cnt
+
+    def average_uniform(self, phi, n1d, dr, out=None):
+        """Lateral average onto the uniform base state r_j = (j + 1/2) dr
+        (radius averages interpolated quadratically)."""
+        avg = out if out is not None else torch.empty(int(n1d), dtype=torch.float64, device=self.device)
+        self._check(self._run(self.lib.mp_average_uniform, self._ptr(phi, self.shape, "phi"), int(n1d), float(dr),
+                              self._ptr(avg, (int(n1d),), "avg")), "mp_average_uniform")
+        return avg
+
+    def add_w0(self, w0, ux, uy, uz, re=None):
+        """U += w0 e_r on the faces (in place): planar, w0 on the nz + 1 z
+        edges; spherical, w0 on the edges re (linear between them)."""
+        ne = int(w0.shape[0])
+        sx, sy, sz = self.face_shapes()
+        pr = self._ptr(re, (ne,), "re") if re is not None else None
+        code = self._run(self.lib.mp_add_w0, self._ptr(w0, (ne,), "w0"), pr, ne, self._ptr(ux, sx, "ux"),
+                         self._ptr(uy, sy, "uy"), self._ptr(uz, sz, "uz"))
+        self._check(code, "mp_add_w0")
+        return ux, uy, uz
 
     def set_kernel_timing(self, on):
         """Time the finest-level smoother launches of the following calls."""
