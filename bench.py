@@ -319,6 +319,36 @@ def _base1d(dev):
         out[f"{n}^3"] = rec
         _log(f"base1d {n}^3 ({nm} radii): {rec}")
     ctx.close()
+    # the lateral Average of a cell field over the radii of a star (the
+    # device-built octant list, then the fold and per-radius sums per call)
+    for n in (256, 512):
+        c2 = mproj.Context(n, n, n, bc=(1, 1, 1), precision="fp64")
+        nm = c2.radius_count()
+        phi = torch.randn((n, n, n), dtype=torch.float64, device=dev)
+        avg = torch.empty(nm, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c2.average(phi, out=avg, count=False)
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for _ in range(20):
+            c2.average(phi, out=avg, count=False)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / 20
+        n1d = int(np.ceil(5 * np.sqrt(3.0) * n / 2)) + 2
+        avu = torch.empty(n1d, dtype=torch.float64, device=dev)
+        t0 = time.perf_counter()
+        for _ in range(20):
+            c2.average_uniform(phi, n1d, 1.0 / (5 * n), out=avu)
+        torch.cuda.synchronize()
+        peru = (time.perf_counter() - t0) / 20
+        rec = {"radii": nm, "first_call_ms": round(1e3 * first, 2), "average_us": round(1e6 * per, 1),
+               "average_GBps": round(8.0 * n ** 3 / per / 1e9, 1), "uniform_average_us": round(1e6 * peru, 1)}
+        out[f"average {n}^3"] = rec
+        _log(f"average {n}^3: {rec}")
+        c2.close()
+        del phi
     return out
 
 
