@@ -286,14 +286,14 @@ struct FsLds {
         const int ho = ((j + k + 1) & 1) * (NX / 2);
         const bool blk = black_row && k >= g.z0;
         // the black update's neighbour rows first, so that their LDS latency
-        // overlaps the red update (it writes only plane k+1's buffer)
-        H bxlo{}, bxhi{}, bclo{}, bchi{};
-        if (blk) {
-            bxlo = lds_get_half<T, M>(&sx[i0][so + ho - NX]);
-            bxhi = lds_get_half<T, M>(&sx[i0][so + ho + NX]);
-            if constexpr (CELL) bclo = lds_get_half<T, M>(&sc[i0][so + ho - NX]);
-            bchi = lds_get_half<T, M>(&sc[i0][so + ho + NX]);
-        }
+        // overlaps the red update (it writes only plane k+1's buffer).  Every
+        // wavefront reads (rows without a black update read their own row, in
+        // bounds, and drop the values): no branch and no zeroed registers.
+        const int blo = black_row ? so + ho - NX : so + ho, bhi = black_row ? so + ho + NX : so + ho;
+        const H bxlo = lds_get_half<T, M>(&sx[i0][blo]);
+        const H bxhi = lds_get_half<T, M>(&sx[i0][bhi]);
+        const H bclo = CELL ? lds_get_half<T, M>(&sc[i0][blo]) : H{};
+        const H bchi = lds_get_half<T, M>(&sc[i0][bhi]);
         if (red_row) {
             if constexpr (CELL) {
                 x_faces_cell<T, M, PXY>(g, s.c[P1], s.fx[P1]);

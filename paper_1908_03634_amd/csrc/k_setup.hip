@@ -223,7 +223,8 @@ __global__ __launch_bounds__(kBlock) void k_fill(Dims d, int lz, double h, int g
         const double c = b / rq;
         beta0[q] = b;
         ccell[q] = c;
-        if (ccell32) ccell32[q] = (float)c;
+        // FP32 cells as half reciprocals 0.5 / c (the FP32 harmonic mean's input)
+        if (ccell32) ccell32[q] = (float)(0.5 * rq / b);
         if (!(rq > 0.0) || !isfinite(rq) || !isfinite(c) || !(b > 0.0)) bad += 1.0;
     }
     zpart_store(part, block_sum(bad, sh));

@@ -128,7 +128,7 @@ struct mp_ctx {
     int kev_used = 0;
     int nbz = 1;            // partials written by the z-marching reductions
     bool cell_mode = false;  // finest level reads cell values beta0/rho (faces formed on the fly)
-    float* ccell32 = nullptr;  // FP32 copy of the cell values (mixed precision)
+    float* ccell32 = nullptr;  // FP32 half reciprocals 0.5 / c of the cell values (mixed precision)
     int coarse_start = -1;  // first level of the single-workgroup coarse cycle, -1 = off
     bool phi_aligned = true;      // the caller's iterate allows 16-byte accesses
     int geometry = -1;                  // geometry of the last successful mapping

@@ -177,11 +177,14 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
 // the single-workgroup coarse cycle, the fused sweep) evaluates a cell with
 // exactly this arithmetic, so the variants agree bit for bit.
 
-// Harmonic mean 2ab/(a+b).  FP64 uses the same expression as the stored face
-// coefficients (so both modes agree bit for bit); FP32, used only inside the
-// refinement's V-cycles, multiplies by the hardware reciprocal.
+// Harmonic mean 2ab/(a+b) of two cell values.  FP64 takes the values a, b
+// and the same expression as the stored face coefficients (so both modes
+// agree bit for bit).  FP32, used only inside the refinement's V-cycles, holds
+// every cell as its half reciprocal 0.5/c (written by the mapping), so the
+// mean of two cells is the hardware reciprocal of their sum: one add and one
+// reciprocal per face instead of three multiplies more.
 __device__ __forceinline__ double harm(double a, double b) { return 2.0 * a * b / (a + b); }
-__device__ __forceinline__ float harm(float a, float b) { return 2.0f * a * b * __builtin_amdgcn_rcpf(a + b); }
+__device__ __forceinline__ float harm(float ha, float hb) { return __builtin_amdgcn_rcpf(ha + hb); }
 
 // The six face coefficients of cell q in stencil order (x low, x high,
 // y low, y high, z low, z high); walls give 0.
