@@ -233,6 +233,7 @@ struct FsLds {
     const T* __restrict__ ec;
     double* __restrict__ phi;
     const double* __restrict__ irs;
+    bool phi_fresh;  // phi is zero on entry: written, not read
     T h2;
     T (*sx)[NW * NX];
     T (*sc)[NW * NX];
@@ -319,7 +320,7 @@ struct FsLds {
                 double* pp = phi + o;
 #pragma unroll
                 for (int q = 0; q < M; q++) {
-                    const double2 pv = *reinterpret_cast<const double2*>(pp + 2 * q);
+                    const double2 pv = phi_fresh ? make_double2(0.0, 0.0) : *reinterpret_cast<const double2*>(pp + 2 * q);
                     *reinterpret_cast<double2*>(pp + 2 * q) = make_double2(fma(sc0, (double)s.x[P0].v[2 * q], pv.x),
                                                                            fma(sc0, (double)s.x[P0].v[2 * q + 1], pv.y));
                 }
@@ -338,7 +339,7 @@ __global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const
                                                             const T* __restrict__ cc, const T* __restrict__ cxa,
                                                             const T* __restrict__ cza, T h2,
                                                             const T* __restrict__ ec, double* __restrict__ phi,
-                                                            const double* __restrict__ irs)
+                                                            const double* __restrict__ irs, int irf)
 {
     using F = FsLds<T, MODE, M, R, D, IRU, CELL, PXY>;
     constexpr int NS = F::NS;
@@ -378,6 +379,7 @@ __global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const
     f.ec = ec;
     f.phi = phi;
     f.irs = irs;
+    f.phi_fresh = (irf & 1) != 0;
     f.h2 = h2;
     f.sx = sx;
     f.sc = sc;
@@ -454,7 +456,7 @@ __global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const
 // Rows of up to 256 cells: 8 rows, 12 wavefronts, three per SIMD.  Rows of
 // 384 and 512 cells hold 6 or 8 cells per lane in every plane slot: 4 rows,
 // 8 wavefronts, two per SIMD, which the larger strips need for registers.
-template <int M>
+template <int M, int MODE, bool IRU, bool CELL>
 struct FswShape {
     static constexpr int R = M <= 2 ? 8 : 4;
     static constexpr int D = M <= 3 ? 1 : 0;
@@ -474,7 +476,7 @@ constexpr int kFswMinPlanes = 8;
 template <typename T, int MODE, int M, bool IRU, bool CELL, bool PXY>
 static int fsw_chunk(const Dims& d, long long gy)
 {
-    constexpr int R = FswShape<M>::R, D = FswShape<M>::D, NS = D + 4;
+    constexpr int R = FswShape<M, MODE, IRU, CELL>::R, D = FswShape<M, MODE, IRU, CELL>::D, NS = D + 4;
     static int resident = 0;  // workgroups resident on the device at once
     if (resident == 0) {
         int dev = 0, ncu = 0, per_cu = 0;
@@ -503,57 +505,57 @@ static int fsw_chunk(const Dims& d, long long gy)
 
 template <typename T, int MODE, int M, bool IRU, bool CELL, bool PXY>
 static void fsw_launch_p(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, const T* cxa, const T* cza,
-                         T h2, const T* ec, double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1,
+                         T h2, const T* ec, double* phi, const double* irs, int irf, hipEvent_t ev0, hipEvent_t ev1,
                          hipStream_t s)
 {
-    constexpr int R = FswShape<M>::R, D = FswShape<M>::D;
+    constexpr int R = FswShape<M, MODE, IRU, CELL>::R, D = FswShape<M, MODE, IRU, CELL>::D;
     const long long gy = (d.ny + R - 1) / R;
     const int lz = fsw_chunk<T, MODE, M, IRU, CELL, PXY>(d, gy);
     const dim3 grid(1, (unsigned)gy, (unsigned)((d.nz + lz - 1) / lz));
     const dim3 block(kWave * (R + 4));
     if (ev0)
         hipExtLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, D, IRU, CELL, PXY>), grid, block, 0, s, ev0, ev1, 0, d,
-                              lz, xo, xn, b, cc, cxa, cza, h2, ec, phi, irs);
+                              lz, xo, xn, b, cc, cxa, cza, h2, ec, phi, irs, irf);
     else
         hipLaunchKernelGGL((k_fsw_lds<T, MODE, M, R, D, IRU, CELL, PXY>), grid, block, 0, s, d, lz, xo, xn, b,
-                           cc, cxa, cza, h2, ec, phi, irs);
+                           cc, cxa, cza, h2, ec, phi, irs, irf);
 }
 
 // the variant without wall selects when x and y are both periodic
 template <typename T, int MODE, int M, bool IRU, bool CELL>
 static void fsw_launch(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, const T* cxa, const T* cza, T h2,
-                       const T* ec, double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
+                       const T* ec, double* phi, const double* irs, int irf, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
 {
     if (d.px && d.py)
-        fsw_launch_p<T, MODE, M, IRU, CELL, true>(d, xo, xn, b, cc, cxa, cza, h2, ec, phi, irs, ev0, ev1, s);
+        fsw_launch_p<T, MODE, M, IRU, CELL, true>(d, xo, xn, b, cc, cxa, cza, h2, ec, phi, irs, irf, ev0, ev1, s);
     else
-        fsw_launch_p<T, MODE, M, IRU, CELL, false>(d, xo, xn, b, cc, cxa, cza, h2, ec, phi, irs, ev0, ev1, s);
+        fsw_launch_p<T, MODE, M, IRU, CELL, false>(d, xo, xn, b, cc, cxa, cza, h2, ec, phi, irs, irf, ev0, ev1, s);
 }
 
 template <typename T, int M>
 static void fsw_mode(int mode, const Dims& d, const T* xo, T* xn, const T* b, const T* cc, T h2, const T* ec,
-                     double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
+                     double* phi, const double* irs, int irf, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
 {
     if (phi) {
         // the refinement update rides on the last sweep of a V-cycle
         if (mode == FS_PROLONG)
-            fsw_launch<T, FS_PROLONG, M, true, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, phi, irs, ev0, ev1,
+            fsw_launch<T, FS_PROLONG, M, true, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, phi, irs, irf, ev0, ev1,
                                                      s);
         else
-            fsw_launch<T, FS_PLAIN, M, true, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, phi, irs, ev0, ev1, s);
+            fsw_launch<T, FS_PLAIN, M, true, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, phi, irs, irf, ev0, ev1, s);
         return;
     }
     switch (mode) {
     case FS_ZERO:
-        fsw_launch<T, FS_ZERO, M, false, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, nullptr, nullptr, ev0, ev1,
+        fsw_launch<T, FS_ZERO, M, false, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, nullptr, nullptr, 0, ev0, ev1,
                                                s);
         break;
     case FS_PROLONG:
-        fsw_launch<T, FS_PROLONG, M, false, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, nullptr, nullptr, ev0,
+        fsw_launch<T, FS_PROLONG, M, false, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, nullptr, nullptr, 0, ev0,
                                                   ev1, s);
         break;
     default:
-        fsw_launch<T, FS_PLAIN, M, false, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, nullptr, nullptr, ev0, ev1,
+        fsw_launch<T, FS_PLAIN, M, false, true>(d, xo, xn, b, cc, nullptr, nullptr, h2, ec, nullptr, nullptr, 0, ev0, ev1,
                                                 s);
         break;
     }
@@ -561,13 +563,13 @@ static void fsw_mode(int mode, const Dims& d, const T* xo, T* xn, const T* b, co
 
 template <typename T>
 void launch_fsw_blk(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, T h2, int mode, const T* ec,
-                    double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
+                    double* phi, const double* irs, int irf, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
 {
     switch (d.nx) {
-    case 512: fsw_mode<T, 4>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s); break;
-    case 384: fsw_mode<T, 3>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s); break;
-    case 256: fsw_mode<T, 2>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s); break;
-    default: fsw_mode<T, 1>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, ev0, ev1, s); break;
+    case 512: fsw_mode<T, 4>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, irf, ev0, ev1, s); break;
+    case 384: fsw_mode<T, 3>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, irf, ev0, ev1, s); break;
+    case 256: fsw_mode<T, 2>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, irf, ev0, ev1, s); break;
+    default: fsw_mode<T, 1>(mode, d, xo, xn, b, cc, h2, ec, phi, irs, irf, ev0, ev1, s); break;
     }
 }
 
@@ -577,15 +579,15 @@ static void fswf_mode(int mode, const Dims& d, const T* xo, T* xn, const T* b, c
 {
     switch (mode) {
     case FS_ZERO:
-        fsw_launch<T, FS_ZERO, M, false, false>(d, xo, xn, b, c.y, c.x, c.z, h2, ec, nullptr, nullptr, nullptr,
+        fsw_launch<T, FS_ZERO, M, false, false>(d, xo, xn, b, c.y, c.x, c.z, h2, ec, nullptr, nullptr, 0, nullptr,
                                                 nullptr, s);
         break;
     case FS_PROLONG:
-        fsw_launch<T, FS_PROLONG, M, false, false>(d, xo, xn, b, c.y, c.x, c.z, h2, ec, nullptr, nullptr, nullptr,
+        fsw_launch<T, FS_PROLONG, M, false, false>(d, xo, xn, b, c.y, c.x, c.z, h2, ec, nullptr, nullptr, 0, nullptr,
                                                    nullptr, s);
         break;
     default:
-        fsw_launch<T, FS_PLAIN, M, false, false>(d, xo, xn, b, c.y, c.x, c.z, h2, ec, nullptr, nullptr, nullptr,
+        fsw_launch<T, FS_PLAIN, M, false, false>(d, xo, xn, b, c.y, c.x, c.z, h2, ec, nullptr, nullptr, 0, nullptr,
                                                  nullptr, s);
         break;
     }
@@ -604,7 +606,7 @@ void launch_fsw_blkf(const Dims& d, const T* xo, T* xn, const T* b, const Coef<T
 }
 
 template void launch_fsw_blk<float>(const Dims&, const float*, float*, const float*, const float*, float, int,
-                                    const float*, double*, const double*, hipEvent_t, hipEvent_t, hipStream_t);
+                                    const float*, double*, const double*, int, hipEvent_t, hipEvent_t, hipStream_t);
 template void launch_fsw_blkf<float>(const Dims&, const float*, float*, const float*, const Coef<float>&, float, int,
                                      const float*, hipStream_t);
 

@@ -304,14 +304,20 @@ void launch_prolong(const Dims& fine, T* phi, const T* coarse_phi, hipStream_t s
 // registers).  b is made mean-zero first (the system is singular with the
 // constants as null space); the result is returned mean-zero.  With use_x0
 // the iteration starts from the x passed in and stops at rtol times the
-// initial residual; otherwise it starts from zero.  work holds 7 n doubles.
+// initial residual; otherwise it starts from zero.  An unconverged solve
+// returns the iterate of the smallest residual (where the cells are not all
+// coupled and b has a component on another constant mode, the residual
+// stalls above the tolerance while the iterates drift along that mode).
+// work holds 8 n doubles.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ bin, T* __restrict__ xout,
                                                  const T* __restrict__ cx, const T* __restrict__ cy,
                                                  const T* __restrict__ cz, double h2, double rtol, int maxit,
-                                                 int use_x0, double* __restrict__ work, double* __restrict__ iters)
+                                                 int use_x0, double* __restrict__ work, double* __restrict__ iters,
+                                                 const double* __restrict__ skip_if_direct)
 {
     __shared__ double sh[16];
+    if (skip_if_direct && skip_if_direct[0] == 1.0) return;
     const int n = (int)d.n();
     const int tid = threadIdx.x, nt = blockDim.x;
     double* x = work;
@@ -321,6 +327,7 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
     double* v = work + 4 * n;
     double* s = work + 5 * n;
     double* tv = work + 6 * n;
+    double* xb = work + 7 * n;
     const double inv_h2 = 1.0 / h2;
 
     double part = 0.0;
@@ -355,6 +362,9 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
     const double bnorm2 = block_sum(part, sh);
     const double tol2 = rtol * rtol * bnorm2;
     double rho = 1.0, alpha = 1.0, omega = 1.0;
+    // squared residual of the current iterate and of the kept one (xb)
+    double rr_cur = bnorm2, rr_best = bnorm2;
+    for (int q = tid; q < n; q += nt) xb[q] = x[q];
 
     int it = 0;  // iterations begun (each ends in a break or a full step)
     if (bnorm2 > 0.0) {
@@ -380,6 +390,7 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
             const double ss = block_sum(part, sh);
             if (ss <= tol2) {
                 for (int q = tid; q < n; q += nt) x[q] += alpha * p[q];
+                rr_cur = ss;
                 break;
             }
             apply(s, tv);
@@ -392,6 +403,7 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
             const double tt = block_sum(p2, sh);
             if (tt == 0.0) {
                 for (int q = tid; q < n; q += nt) x[q] += alpha * p[q];
+                rr_cur = ss;
                 break;
             }
             omega = ts / tt;
@@ -403,9 +415,18 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
             }
             const double rr = block_sum(part, sh);
             rho = rho1;
+            rr_cur = rr;
             if (rr <= tol2 || omega == 0.0) break;
+            if (rr < rr_best) {
+                rr_best = rr;
+                for (int q = tid; q < n; q += nt) xb[q] = x[q];
+            }
         }
     }
+    // x when converged, else the kept iterate (the threads that wrote xb read
+    // it back, so no barrier is needed before the copy)
+    if (!(rr_cur <= tol2))
+        for (int q = tid; q < n; q += nt) x[q] = xb[q];
     if (iters && tid == 0) iters[0] += (double)(it < maxit ? it + (bnorm2 > 0.0 ? 1 : 0) : it);
     __syncthreads();
     part = 0.0;
@@ -416,13 +437,13 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
 
 template <typename T>
 void launch_bottom(const Dims& d, const T* rhs, T* phi, const T* cx, const T* cy, const T* cz, double h2, double rtol,
-                   int maxit, int use_x0, double* work, double* iters, hipStream_t s)
+                   int maxit, int use_x0, double* work, double* iters, const double* skip_if_direct, hipStream_t s)
 {
     long long n = d.n();
     int nt = (int)((n + 63) / 64) * 64;
     if (nt > 1024) nt = 1024;
     hipLaunchKernelGGL((k_bottom<T>), dim3(1), dim3(nt), 0, s, d, rhs, phi, cx, cy, cz, h2, rtol, maxit, use_x0,
-                       work, iters);
+                       work, iters, skip_if_direct);
 }
 
 // --------------------------------------------------------- FP64 level 0
@@ -583,7 +604,7 @@ void launch_ir_update(long long n, double* phi, const float* e, const double* s,
     template void launch_resid_restrict<T>(const Dims&, const T*, const T*, const Coef<T>&, T, T*, hipStream_t);      \
     template void launch_prolong<T>(const Dims&, T*, const T*, hipStream_t);                                          \
     template void launch_bottom<T>(const Dims&, const T*, T*, const T*, const T*, const T*, double, double, int, int, \
-                                   double*, double*, hipStream_t);
+                                   double*, double*, const double*, hipStream_t);
 MP_INST(float)
 MP_INST(double)
 

@@ -440,6 +440,47 @@ void launch_coef_restrict_cells(const Dims& fine, const double* cc, Tout* cx, To
     hipLaunchKernelGGL((k_coef_restrict_cells<Tout>), sh.grid, sh.block, 0, s, fine, cc, cx, cy, cz);
 }
 
+// FP32 restriction from half reciprocals: each coarse cell's three low faces
+// are the means of the 4 fine faces covering them, a fine face being the
+// FP32 harmonic mean harm(h_a, h_b) of its two cells.
+__global__ __launch_bounds__(kBlock) void k_coef_restrict_cells32(Dims f, const float* __restrict__ hc,
+                                                                  float* __restrict__ cx, float* __restrict__ cy,
+                                                                  float* __restrict__ cz)
+{
+    const int nxc = f.nx / 2, nyc = f.ny / 2, nzc = f.nz / 2;
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (I >= nxc || J >= nyc || K >= nzc) return;
+    const long long q = ((long long)K * nyc + J) * nxc + I;
+    const long long sy = f.nx, sz = (long long)f.nx * f.ny;
+    const long long base = (long long)(2 * K) * sz + (long long)(2 * J) * sy + 2 * I;
+    // the low neighbours of the children on the coarse cell's low faces
+    const long long ox = I > 0 ? -1 : (f.px ? f.nx - 1 : 0);
+    const long long oy = J > 0 ? -sy : (f.py ? (long long)(f.ny - 1) * sy : 0);
+    const long long oz = K > 0 ? -sz : (f.pz ? (long long)(f.nz - 1) * sz : 0);
+    const bool hx = I > 0 || f.px, hy = J > 0 || f.py, hz = K > 0 || f.pz;
+    float ax = 0.0f, ay = 0.0f, az = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            const long long qx = base + a * sz + b * sy, qy = base + a * sz + b, qz = base + a * sy + b;
+            ax += hx ? harm(hc[qx + ox], hc[qx]) : 0.0f;
+            ay += hy ? harm(hc[qy + oy], hc[qy]) : 0.0f;
+            az += hz ? harm(hc[qz + oz], hc[qz]) : 0.0f;
+        }
+    cx[q] = 0.25f * ax;
+    cy[q] = 0.25f * ay;
+    cz[q] = 0.25f * az;
+}
+
+void launch_coef_restrict_cells32(const Dims& fine, const float* hc, float* cx, float* cy, float* cz, hipStream_t s)
+{
+    const Shape3 sh = cells3(fine.nx / 2, fine.ny / 2, fine.nz / 2);
+    hipLaunchKernelGGL(k_coef_restrict_cells32, sh.grid, sh.block, 0, s, fine, hc, cx, cy, cz);
+}
+
 template void launch_coef_restrict_cells<double>(const Dims&, const double*, double*, double*, double*, hipStream_t);
 template void launch_coef_restrict_cells<float>(const Dims&, const double*, float*, float*, float*, hipStream_t);
 

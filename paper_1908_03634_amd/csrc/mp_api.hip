@@ -39,7 +39,8 @@ enum {
     S_ZERO = 6,
     S_NMEAN = 7,
     S_PAIR0 = 8,
-    S_DEF = 12
+    S_DEF = 12,
+    S_BINV = 13  // 1 when the bottom grid's inverse G is usable (read by the kernels)
 };
 
 struct Level {
@@ -69,6 +70,13 @@ constexpr long long kPairMaxCells = 1LL << 18;   // one-launch pair sweeps on le
 inline bool can_coarsen(int nx, int ny, int nz)
 {
     return nx % 2 == 0 && ny % 2 == 0 && nz % 2 == 0 && nx >= 4 && ny >= 4 && nz >= 4;
+}
+
+// The cell-centred hierarchy also stops at a grid small enough for the direct
+// bottom solve (its inverse costs less than the coarser levels' cycles).
+inline bool mac_can_coarsen(int nx, int ny, int nz)
+{
+    return can_coarsen(nx, ny, nz) && (long long)nx * ny * nz > mp::kDirectBottomCells;
 }
 
 // Nodal projection (Sec. 3.2 Step 11): its own node hierarchy, allocated on
@@ -116,6 +124,13 @@ struct mp_ctx {
     double *c64x = nullptr, *c64y = nullptr, *c64z = nullptr;
     double *beta0 = nullptr, *ccell = nullptr, *b64 = nullptr;
     double *partials = nullptr, *dscal = nullptr, *bottom_work = nullptr;
+    double* ginv = nullptr;  // inverse G of the bottom grid (<= kDirectBottomCells cells), or nullptr
+    // G is built on a second stream (it is first needed at the end of the
+    // first V-cycle's descent): ev_coef orders it after the coefficient
+    // pyramid, ev_inv orders the first bottom solve after it
+    hipStream_t side = nullptr;
+    hipEvent_t ev_coef = nullptr, ev_inv = nullptr;
+    bool inv_pending = false;
     long long npartials = 0;     // doubles in partials
     double* scanw = nullptr;     // scratch of the one-dimensional scans when partials is too small
     long long scanw_cap = 0;
@@ -145,6 +160,7 @@ struct mp_ctx {
     double map_center[3] = {0.0, 0.0, 0.0};
     double* ir_phi = nullptr;     // refinement update fused into the V-cycle's last pass
     const double* ir_s = nullptr;  // (phi += ir_s[0] * e), or nullptr
+    bool ir_fresh = false;         // phi is zero before that update (written, not read)
     bool have_coefs = false, have_base = false;
     long long map_serial = 0;  // successful mappings so far
     NodalState* nd = nullptr;
@@ -228,7 +244,8 @@ void free_all(mp_ctx* c)
         }
     }
     c->lv.clear();
-    double* bufs[] = {c->c64x, c->c64y, c->c64z, c->beta0, c->ccell, c->b64, c->partials, c->dscal, c->bottom_work};
+    double* bufs[] = {c->c64x,     c->c64y,   c->c64z,  c->beta0,       c->ccell,
+                      c->b64,      c->partials, c->dscal, c->bottom_work, c->ginv};
     for (double* p : bufs)
         if (p) (void)hipFree(p);
     if (c->ccell32) (void)hipFree(c->ccell32);
@@ -242,6 +259,12 @@ void free_all(mp_ctx* c)
         if (e) (void)hipEventDestroy(e);
     for (auto& e : c->evm)
         if (e) (void)hipEventDestroy(e);
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    if (c->ev_coef) (void)hipEventDestroy(c->ev_coef);
+    if (c->ev_inv) (void)hipEventDestroy(c->ev_inv);
     for (auto& e : c->kev)
         if (e) (void)hipEventDestroy(e);
     c->kev.clear();
@@ -396,8 +419,7 @@ void build_pyramid(mp_ctx* c)
         Level& C = c->lv[l];
         if (l == 1 && c->cell_mode) {
             if (mixed(c))
-                mp::launch_coef_restrict_cells<float>(F.d, c->ccell, (float*)C.cx, (float*)C.cy, (float*)C.cz,
-                                                      c->stream);
+                mp::launch_coef_restrict_cells32(F.d, c->ccell32, (float*)C.cx, (float*)C.cy, (float*)C.cz, c->stream);
             else
                 mp::launch_coef_restrict_cells<double>(F.d, c->ccell, (double*)C.cx, (double*)C.cy, (double*)C.cz,
                                                        c->stream);
@@ -412,6 +434,31 @@ void build_pyramid(mp_ctx* c)
             mp::launch_coef_restrict<double, double>(F.d, (double*)F.cx, (double*)F.cy, (double*)F.cz,
                                                      (double*)C.cx, (double*)C.cy, (double*)C.cz, c->stream);
         }
+    }
+    // inverse of the bottom grid's operator for the direct bottom solve, on
+    // the second stream after the pyramid (S_BINV = 1 when usable; the bottom
+    // kernels read it)
+    if (c->ginv) {
+        const Level& B = c->lv.back();
+        (void)hipEventRecord(c->ev_coef, c->stream);
+        (void)hipStreamWaitEvent(c->side, c->ev_coef, 0);
+        if (mixed(c))
+            mp::launch_bottom_inverse<float>(B.d, (const float*)B.cx, (const float*)B.cy, (const float*)B.cz, c->ginv,
+                                             c->dscal + S_BINV, c->side);
+        else
+            mp::launch_bottom_inverse<double>(B.d, (const double*)B.cx, (const double*)B.cy, (const double*)B.cz,
+                                              c->ginv, c->dscal + S_BINV, c->side);
+        (void)hipEventRecord(c->ev_inv, c->side);
+        c->inv_pending = true;
+    }
+}
+
+// The main stream waits for the bottom inverse once, before its first use.
+void wait_inverse(mp_ctx* c)
+{
+    if (c->inv_pending) {
+        (void)hipStreamWaitEvent(c->stream, c->ev_inv, 0);
+        c->inv_pending = false;
     }
 }
 
@@ -498,12 +545,13 @@ void smooth(mp_ctx* c, int l, bool zero_init, const T* ec, bool last = false)
     if (use_blk(c, l) && L.fsw && sizeof(T) == 4) {
         // one pass for both colours, out of place: x read (not when zero) and
         // written, b and c read, one word each per cell; 1/8 word of coarse
-        // correction after prolongation; 16 bytes per cell (phi in and out)
-        // when the refinement update rides on the sweep
+        // correction after prolongation; 16 bytes per cell (phi in and out;
+        // 8 when phi starts at zero) when the refinement update rides on the
+        // sweep
         const bool iru = last && c->ir_phi != nullptr;
         const int mode = zero_init ? mp::FS_ZERO : ec ? mp::FS_PROLONG : mp::FS_PLAIN;
-        const double bytes =
-            ((zero_init ? 3.0 : 4.0) + (ec ? 0.125 : 0.0)) * sizeof(T) * cells + (iru ? 16.0 * cells : 0.0);
+        const double bytes = ((zero_init ? 3.0 : 4.0) + (ec ? 0.125 : 0.0)) * sizeof(T) * cells +
+                             (iru ? (c->ir_fresh ? 8.0 : 16.0) * cells : 0.0);
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (tm && c->kev_used + 1 < (int)c->kev.size()) {
             e0 = c->kev[c->kev_used];
@@ -513,7 +561,8 @@ void smooth(mp_ctx* c, int l, bool zero_init, const T* ec, bool last = false)
         }
         if constexpr (sizeof(T) == 4)
             mp::launch_fsw_blk<T>(L.d, (const T*)L.x, (T*)L.x2, (const T*)L.b, C.cell, h2, mode, ec,
-                                  iru ? c->ir_phi : nullptr, iru ? c->ir_s : nullptr, e0, e1, c->stream);
+                                  iru ? c->ir_phi : nullptr, iru ? c->ir_s : nullptr, iru && c->ir_fresh ? 1 : 0, e0,
+                                  e1, c->stream);
         std::swap(L.x, L.x2);
         return;
     }
@@ -570,6 +619,9 @@ void coarse_cycle(mp_ctx* c, bool zero_init)
     a.bottom_rtol = c->cfg.bottom_rtol;
     a.bottom_maxit = c->cfg.bottom_max_iter;
     a.bottom_iters = c->dscal + S_BIT;
+    a.bottom_inv = c->ginv;
+    a.bottom_ok = c->dscal + S_BINV;
+    wait_inverse(c);
     for (int q = 0; q < a.nlev; q++) {
         const Level& L = c->lv[l0 + q];
         mp::CoarseLevel<T>& C = a.lv[q];
@@ -598,9 +650,16 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
         return;
     }
     if (l == nlev - 1) {
+        // directly when G is usable, else BiCGStab (each kernel reads S_BINV
+        // and returns at once when the other one applies)
+        const double* ok = c->ginv ? c->dscal + S_BINV : nullptr;
+        if (c->ginv) {
+            wait_inverse(c);
+            mp::launch_bottom_direct<T>(L.d, c->ginv, ok, (const T*)L.b, (T*)L.x, L.h * L.h, c->stream);
+        }
         mp::launch_bottom<T>(L.d, (const T*)L.b, (T*)L.x, (const T*)L.cx, (const T*)L.cy, (const T*)L.cz, L.h * L.h,
                              c->cfg.bottom_rtol, c->cfg.bottom_max_iter, zero_init ? 0 : 1, c->bottom_work,
-                             c->dscal + S_BIT, c->stream);
+                             c->dscal + S_BIT, ok, c->stream);
         return;
     }
     if (zero_init && c->cfg.nu1 == 0) (void)hipMemsetAsync(L.x, 0, sizeof(T) * L.d.n(), c->stream);
@@ -667,9 +726,17 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
         if (info) info->rel_resid = 0.0;
         return MP_OK;
     }
-    if (!use_guess) HIPCHK(c, hipMemsetAsync(phi, 0, sizeof(double) * n, c->stream));
     c->phi_aligned = ((uintptr_t)phi & 15) == 0;
     const bool mx = mixed(c);
+    // from a zero iterate, the first refinement update writes phi without
+    // reading it where it rides on the one-pass finest-level sweep; else phi
+    // is cleared first
+    const bool fresh_ok = mx && use_blk(c, 0) && c->lv[0].fsw && c->cfg.nu2 >= 1;
+    bool phi_set = use_guess != 0;
+    if (!phi_set && !fresh_ok) {
+        HIPCHK(c, hipMemsetAsync(phi, 0, sizeof(double) * n, c->stream));
+        phi_set = true;
+    }
     if (!mx) c->lv[0].x = phi;  // x2 stays the internal second buffer
     int status = MP_ERR_NOT_CONVERGED;
     double rel = 1.0, rel_prev = 1.0;
@@ -728,6 +795,7 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
             // the last V-cycle of the step applies phi += s e in its final
             // smoother pass when the finest level runs blocked kernels
             const bool fuse_ir = use_blk(c, 0) && c->cfg.nu2 >= 1;
+            c->ir_fresh = !phi_set;
             for (int k = 0; k < m; k++) {
                 const bool lastc = k == m - 1;
                 c->ir_phi = fuse_ir && lastc ? phi : nullptr;
@@ -736,6 +804,8 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
                 c->ir_phi = nullptr;
                 vc++;
             }
+            c->ir_fresh = false;
+            phi_set = true;
             if (!fuse_ir) mp::launch_ir_update(n, phi, (const float*)c->lv[0].x, sp, c->stream);
         } else {
             for (int k = 0; k < m; k++) {
@@ -750,6 +820,8 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
             }
         }
     }
+    // no refinement step ran (stopped before the first): phi is zero
+    if (!phi_set) HIPCHK(c, hipMemsetAsync(phi, 0, sizeof(double) * n, c->stream));
     // gauge: mean(phi) = 0
     mp::launch_sum(phi, n, c->partials, nb, c->stream);
     mp::launch_final_sum(c->partials, nb, c->dscal + S_GAUGE, 1.0 / (double)n, nullptr, 0.0, c->stream);
@@ -1122,7 +1194,7 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
     // bottom size check (host only)
     {
         int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
-        while (can_coarsen(nx, ny, nz)) {
+        while (mac_can_coarsen(nx, ny, nz)) {
             nx /= 2;
             ny /= 2;
             nz /= 2;
@@ -1200,11 +1272,13 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
             L.cz = c->c64z;
         }
         c->lv.push_back(L);
-        if (!can_coarsen(d.nx, d.ny, d.nz)) break;
+        if (!mac_can_coarsen(d.nx, d.ny, d.nz)) break;
         d = Dims{d.nx / 2, d.ny / 2, d.nz / 2, d.px, d.py, d.pz};
         h *= 2.0;
     }
-    c->bottom_work = dalloc<double>(7 * c->lv.back().d.n(), e), good &= ok(c->bottom_work);
+    c->bottom_work = dalloc<double>(8 * c->lv.back().d.n(), e), good &= ok(c->bottom_work);
+    if (c->lv.back().d.n() <= mp::kDirectBottomCells)
+        c->ginv = dalloc<double>(mp::kDirectBottomCells * mp::kDirectBottomCells, e), good &= ok(c->ginv);
     // single-workgroup coarse cycle: trailing levels of <= kCoarseCells cells,
     // when the bottom fits one wavefront and there is more than one level
     {
@@ -1269,6 +1343,11 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
         if (good && hipEventCreate(&ev) != hipSuccess) good = false;
     for (auto& ev : c->evm)
         if (good && hipEventCreate(&ev) != hipSuccess) good = false;
+    if (good && c->ginv &&
+        (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+         hipEventCreateWithFlags(&c->ev_coef, hipEventDisableTiming) != hipSuccess ||
+         hipEventCreateWithFlags(&c->ev_inv, hipEventDisableTiming) != hipSuccess))
+        good = false;
     if (good && cfg->kernel_timing && make_timing_events(c) != MP_OK) good = false;
     if (!good) {
         free_all(c);

@@ -220,10 +220,16 @@ __device__ __forceinline__ float gs_div(float n, float d) { return n * __builtin
 //   (h^2 b_q + sum_f c_f x_nb(f)) / sum_f c_f,
 // or the old value when the cell has no coupling.
 template <typename T>
-__device__ __forceinline__ T gs_value(T c0, T c1, T c2, T c3, T c4, T c5, T xm, T xp, T ym, T yp, T zm, T zp, T bq,
-                                      T h2, T old)
+__device__ __forceinline__ T coef_sum(T c0, T c1, T c2, T c3, T c4, T c5)
 {
-    const T csum = ((((c0 + c1) + c2) + c3) + c4) + c5;
+    return ((((c0 + c1) + c2) + c3) + c4) + c5;
+}
+
+// The same with the coefficient sum csum = coef_sum(c0..c5) given.
+template <typename T>
+__device__ __forceinline__ T gs_value_cs(T csum, T c0, T c1, T c2, T c3, T c4, T c5, T xm, T xp, T ym, T yp, T zm,
+                                         T zp, T bq, T h2, T old)
+{
     T s = c0 * xm;
     s = fma(c1, xp, s);
     s = fma(c2, ym, s);
@@ -233,12 +239,20 @@ __device__ __forceinline__ T gs_value(T c0, T c1, T c2, T c3, T c4, T c5, T xm, 
     return csum > T(0) ? gs_div(fma(h2, bq, s), csum) : old;
 }
 
-// Residual b - A x of one cell from its coefficients and neighbour values.
 template <typename T>
-__device__ __forceinline__ T resid_value(T c0, T c1, T c2, T c3, T c4, T c5, T xm, T xp, T ym, T yp, T zm, T zp, T x0,
-                                         T bq, T inv_h2)
+__device__ __forceinline__ T gs_value(T c0, T c1, T c2, T c3, T c4, T c5, T xm, T xp, T ym, T yp, T zm, T zp, T bq,
+                                      T h2, T old)
 {
-    const T csum = ((((c0 + c1) + c2) + c3) + c4) + c5;
+    return gs_value_cs<T>(coef_sum<T>(c0, c1, c2, c3, c4, c5), c0, c1, c2, c3, c4, c5, xm, xp, ym, yp, zm, zp, bq, h2,
+                          old);
+}
+
+// Residual b - A x of one cell from its coefficients (sum csum) and
+// neighbour values.
+template <typename T>
+__device__ __forceinline__ T resid_value_cs(T csum, T c0, T c1, T c2, T c3, T c4, T c5, T xm, T xp, T ym, T yp, T zm,
+                                            T zp, T x0, T bq, T inv_h2)
+{
     T s = c0 * xm;
     s = fma(c1, xp, s);
     s = fma(c2, ym, s);
@@ -246,6 +260,14 @@ __device__ __forceinline__ T resid_value(T c0, T c1, T c2, T c3, T c4, T c5, T x
     s = fma(c4, zm, s);
     s = fma(c5, zp, s);
     return bq - (csum * x0 - s) * inv_h2;
+}
+
+template <typename T>
+__device__ __forceinline__ T resid_value(T c0, T c1, T c2, T c3, T c4, T c5, T xm, T xp, T ym, T yp, T zm, T zp, T x0,
+                                         T bq, T inv_h2)
+{
+    return resid_value_cs<T>(coef_sum<T>(c0, c1, c2, c3, c4, c5), c0, c1, c2, c3, c4, c5, xm, xp, ym, yp, zm, zp, x0,
+                             bq, inv_h2);
 }
 
 // One cell of one colour of red-black Gauss-Seidel on A x = b, in place.

@@ -71,6 +71,9 @@ void launch_coef_restrict(const Dims& fine, const Tin* fx, const Tin* fy, const 
 // The same from fine cell values (fine faces = harmonic means, in FP64).
 template <typename Tout>
 void launch_coef_restrict_cells(const Dims& fine, const double* cc, Tout* cx, Tout* cy, Tout* cz, hipStream_t s);
+// The same in FP32 from the half reciprocals h = 0.5 / c of the fine cell
+// values (fine face = 1 / (h_a + h_b), the FP32 smoother's harmonic mean).
+void launch_coef_restrict_cells32(const Dims& fine, const float* hc, float* cx, float* cy, float* cz, hipStream_t s);
 
 // ---- projection ------------------------------------------------------------
 // b = beta0 S' - D(beta0 U) (= minus the MAC right-hand side); partials
@@ -117,15 +120,41 @@ void launch_resid_restrict(const Dims& fine, const T* phi, const T* rhs, const C
                            hipStream_t s);
 template <typename T>
 void launch_prolong(const Dims& fine, T* phi, const T* coarse_phi, hipStream_t s);
-// BiCGStab in FP64 on the coarsest grid (one workgroup); work = 7 * n doubles.
+// BiCGStab in FP64 on the coarsest grid (one workgroup); work = 8 * n doubles.
 // use_x0: start from phi (tolerance relative to the initial residual).
 // iters: device counter the iterations are added to, or nullptr.
+// skip_if_direct: a device flag (1: the direct bottom solve applies and this
+// kernel returns at once), or nullptr.
 template <typename T>
 void launch_bottom(const Dims& d, const T* rhs, T* phi, const T* cx, const T* cy, const T* cz, double h2, double rtol,
-                   int maxit, int use_x0, double* work, double* iters, hipStream_t s);
+                   int maxit, int use_x0, double* work, double* iters, const double* skip_if_direct, hipStream_t s);
+
+// Direct bottom solve on grids of at most kDirectBottomCells cells.  With L
+// the grid's Laplacian (diagonal: sum of the cell's six face coefficients,
+// off-diagonal: minus the face coefficient; symmetric, positive semidefinite,
+// null space the constants when every cell is coupled), A = L / h^2 and
+// G = (L + alpha 1 1^T)^-1, alpha = trace(L) / n^2, the mean-zero solution of
+// A x = b - mean(b) is
+//   x = h^2 (G b - mean(G b))
+// (G 1 = 1 / (alpha n), so G maps the mean of b onto a constant that the
+// last mean removes).  G is built once per coefficient set by Gauss-Jordan
+// elimination without pivoting (B = L + alpha 1 1^T is symmetric positive
+// definite); a pivot at or below 1e-12 of the largest diagonal entry (a grid
+// whose cells are not all coupled) marks G unusable: *valid = 0, else 1.
+// G: kDirectBottomCells^2 doubles, row-major, zero outside n x n.
+constexpr int kDirectBottomCells = 64;
+template <typename T>
+void launch_bottom_inverse(const Dims& d, const T* cx, const T* cy, const T* cz, double* G, double* valid,
+                           hipStream_t s);
+// x = the direct solution above for right-hand side b on the bottom grid d
+// when *valid == 1 (else the kernel returns at once).
+template <typename T>
+void launch_bottom_direct(const Dims& d, const double* G, const double* valid, const T* b, T* x, double h2,
+                          hipStream_t s);
 
 // The coarse end of a V-cycle in one workgroup (levels lv[0..nlev), the last
-// one solved by one-wavefront conjugate gradients; it must hold <= 256 cells).
+// one solved directly from G when bottom_inv is set, else by one-wavefront
+// conjugate gradients; it must hold <= 256 cells).
 // The five arrays of every level and a residual scratch of the first level's
 // size ((5 * all cells + cells of lv[0]) * sizeof(T) bytes) must fit in
 // kCoarseLdsBytes of LDS.
@@ -151,6 +180,8 @@ struct CoarseArgs {
     double bottom_rtol;
     int bottom_maxit;
     double* bottom_iters;  // device counter the bottom solve adds its iterations to, or nullptr
+    const double* bottom_inv;  // G of the last level, or nullptr (conjugate gradients)
+    const double* bottom_ok;   // device flag: 1 when G is usable (direct bottom)
     CoarseLevel<T> lv[kMaxCoarse];
 };
 template <typename T>
@@ -180,14 +211,15 @@ template <typename T>
 void launch_gs_blk(const Dims& d, T* x, const T* b, const T* cc, T h2, int colour, int mode, const T* ec,
                    double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
 // Both colours of one red-black sweep in one pass, out of place (xo -> xn),
-// in FP32 when fsw_supported(d) (blocked layout, nx = 128 or 256; whole rows
-// per wavefront, rows exchanged through LDS).  Modes:
+// in FP32 when fsw_supported(d) (blocked layout, nx = 128, 256, 384 or 512;
+// whole rows per workgroup, rows exchanged through LDS).  Modes:
 //   FS_PLAIN:   xo as stored;
 //   FS_ZERO:    xo is zero (not read);
 //   FS_PROLONG: xo + e of each cell's parent coarse cell (ec), i.e. the
 //               prolongation applied on the fly.
-// phi != nullptr (FP32): also phi += irs[0] * xn.  Equal bit for bit to two
-// launch_gs_blk colour passes.
+// phi != nullptr (FP32): also phi += irs[0] * xn, or phi = irs[0] * xn when
+// bit 0 of irf is set (phi zero on entry, not read).  Equal bit for bit to
+// two launch_gs_blk colour passes.
 enum { FS_PLAIN = 0, FS_ZERO = 1, FS_PROLONG = 2 };
 // Both colours of one red-black sweep in one launch, out of place (xo -> xn),
 // on a level with stored faces and even extents (rb_pair_supported), in the
@@ -201,7 +233,7 @@ void launch_rb_pair(const Dims& d, const T* xo, T* xn, const T* b, const Coef<T>
 bool fsw_supported(const Dims& d);
 template <typename T>
 void launch_fsw_blk(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, T h2, int mode, const T* ec,
-                    double* phi, const double* irs, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
+                    double* phi, const double* irs, int irf, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
 // The same sweep on a level with stored low-face coefficients c (FP32; equal
 // bit for bit to two launch_gs_blkf colour passes).
 template <typename T>

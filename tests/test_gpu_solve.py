@@ -160,6 +160,54 @@ def test_zero_rhs_gives_zero():
     ctx.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape,bc", [((4, 4, 4), (1, 1, 1)), ((4, 4, 4), (0, 0, 1)), ((2, 4, 8), (1, 0, 1)),
+                                      ((3, 5, 4), (0, 0, 0)), ((8, 8, 8), (1, 1, 0)), ((16, 8, 8), (0, 1, 0))])
+def test_direct_bottom_matches_sparse_lu(precision, shape, bc):
+    """Hierarchies that end on a grid of at most 64 cells solve it directly
+    through the inverse of L + alpha 1 1^T (single-level grids: the whole
+    solve): the answer matches sparse LU and no bottom iteration is counted."""
+    nx, ny, nz = shape
+    say("direct bottom", shape, bc, precision)
+    h = 1.0 / nz
+    cx, cy, cz = W.random_coefs(nx, ny, nz, bc, 311)
+    rhs = W.random_cells(nx, ny, nz, 312)
+    ctx = mproj.Context(nx, ny, nz, h=h, bc=bc, precision=precision, rtol=1e-12)
+    ctx.set_coefs(T(cx), T(cy), T(cz))
+    x, info = ctx.solve(T(rhs))
+    ref = pins.bordered_solve(pins.operator(nx, ny, nz, h, bc, cx, cy, cz), rhs).reshape(nz, ny, nx)
+    assert rel(N(x), ref) < 1e-9
+    assert info["rel_resid"] <= 1e-12
+    assert info["bottom_iters_total"] == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision,coarse_cycle", [("fp64", True), ("fp64", False), ("mixed", True)])
+def test_disconnected_bottom_falls_back_to_conjugate_gradients(precision, coarse_cycle):
+    """Zero x faces on the plane x = 1/2 (walls in x) split every level in
+    two, so L + alpha 1 1^T is singular on the 64-cell bottom grid: its
+    inverse is refused and the bottom runs Krylov iterations instead; the
+    solve still reaches the tolerance (the right-hand side is mean-zero on
+    each half).  Not covered: FP32 V-cycles with one launch per operation
+    (coarse_cycle=False), whose BiCGStab bottom drifts along the second
+    constant mode until FP32 loses the correction."""
+    n = 16
+    bc = (1, 0, 0)
+    cx, cy, cz = W.random_coefs(n, n, n, bc, 321)
+    cx[:, :, n // 2] = 0.0
+    rhs = W.random_cells(n, n, n, 322)
+    for half in (slice(0, n // 2), slice(n // 2, n)):
+        rhs[:, :, half] -= rhs[:, :, half].mean()
+    say("disconnected bottom", precision, coarse_cycle)
+    ctx = mproj.Context(n, n, n, h=1.0 / n, bc=bc, precision=precision, rtol=1e-10, coarse_cycle=coarse_cycle)
+    ctx.set_coefs(T(cx), T(cy), T(cz))
+    x, info = ctx.solve(T(rhs))
+    g = oracle.Grid(n, n, n, 1.0 / n, bc)
+    assert oracle.residual_norm(g, cx, cy, cz, rhs, N(x)) <= 1e-9
+    assert info["bottom_iters_total"] > 0
+    ctx.close()
+
+
 def test_wrong_shapes_are_rejected():
     ctx = mproj.Context(8, 8, 8, precision="fp64")
     with pytest.raises(ValueError):
