@@ -40,18 +40,20 @@ __device__ __forceinline__ double src_of(const Dims& d, double s, const double* 
 
 bool proj_blk_supported(const Dims& d) { return blk_supported(d) && d.px && d.py; }
 
-// b = beta0 S' - D(beta0 U) (shift == nullptr: written, partials = sum b), or
-// the defect sum of (b - shift[0])^2 without a write.
+// b = beta0 S' - D(beta0 U) (shift == nullptr: written, partials = sum b and,
+// when part2 != nullptr, part2 = sum b^2), or the defect sum of
+// (b - shift[0])^2 without a write.
 __global__ __launch_bounds__(BK_T) void k_rhs_blk(Dims d, int lz, double inv_h, const double* __restrict__ beta0,
                                                   const double* __restrict__ ux, const double* __restrict__ uy,
                                                   const double* __restrict__ uz, const double* __restrict__ S,
                                                   const double* __restrict__ sbar, int smode, double* __restrict__ b,
-                                                  double* part, const double* __restrict__ shift)
+                                                  double* part, const double* __restrict__ shift,
+                                                  double* __restrict__ part2)
 {
     constexpr int R = PB_R;
     __shared__ double sh[BK_T / kWave];
     const BlkGeo g = blk_geo<PB_M, R>(d, lz);
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
     const double sh0 = shift ? shift[0] : 0.0;
     if (g.live) {
         const long long sz = (long long)d.nx * d.ny;
@@ -122,6 +124,7 @@ __global__ __launch_bounds__(BK_T) void k_rhs_blk(Dims d, int lz, double inv_h, 
                         acc = fma(e2, e2, acc);
                     } else {
                         acc += v;
+                        acc2 = fma(v, v, acc2);
                     }
                     out.v[c] = v;
                     fzl[t][c] = fzh;
@@ -132,8 +135,13 @@ __global__ __launch_bounds__(BK_T) void k_rhs_blk(Dims d, int lz, double inv_h, 
             for (int t = 0; t < R; t++) bq[t] = bn[t];
         }
     }
+    const long long bid = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) part[bid] = s;
+    if (part2) {
+        const double s2 = block_sum(acc2, sh);
+        if (threadIdx.x == 0) part2[bid] = s2;
+    }
 }
 
 // U <- U - (c / beta0_f) G phi on the low faces of every cell (the cell owns
@@ -224,13 +232,13 @@ __global__ __launch_bounds__(BK_T) void k_vc_blk(Dims d, int lz, double inv_h, c
 
 void launch_rhs_blk(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
                     const double* uz, const double* S, const double* sbar, int smode, double* b, const double* shift,
-                    double* partials, int* nb_out, hipStream_t s)
+                    double* partials, int* nb_out, hipStream_t s, double* partials2)
 {
     int lz = 0;
     const dim3 grid = blk_grid(d, PB_M, PB_R, kBlkMinBlocks, kMaxRedBlocks, lz);
     *nb_out = (int)(grid.x * grid.y * grid.z);
     hipLaunchKernelGGL(k_rhs_blk, grid, dim3(BK_T), 0, s, d, lz, inv_h, beta0, ux, uy, uz, S, sbar, smode, b,
-                       partials, shift);
+                       partials, shift, shift ? nullptr : partials2);
 }
 
 void launch_vc_blk(const Dims& d, double inv_h, const double* cc, const double* beta0, const double* phi, double* ux,

@@ -108,24 +108,59 @@ void launch_sum(const double* x, long long n, double* partials, int nb, hipStrea
 }
 
 __global__ __launch_bounds__(kBlock) void k_sub_mean_sumsq(double* __restrict__ x, long long n,
-                                                           const double* __restrict__ mean, double* part)
+                                                           const double* __restrict__ mean, double* part,
+                                                           float* __restrict__ x32, const double* __restrict__ pair)
 {
     __shared__ double sh[kBlock / kWave];
     const double m = mean[0];
+    const double is = x32 ? pair[1] : 0.0;
     double v = 0.0;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x) {
         double a = x[q] - m;
         x[q] = a;
+        if (x32) x32[q] = (float)(a * is);
         v = fma(a, a, v);
     }
     double s = block_sum(v, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-void launch_sub_mean_sumsq(double* x, long long n, const double* mean, double* partials, int nb, hipStream_t s)
+void launch_sub_mean_sumsq(double* x, long long n, const double* mean, double* partials, int nb, hipStream_t s,
+                           float* x32, const double* pair)
 {
-    hipLaunchKernelGGL(k_sub_mean_sumsq, dim3(nb), dim3(kBlock), 0, s, x, n, mean, partials);
+    hipLaunchKernelGGL(k_sub_mean_sumsq, dim3(nb), dim3(kBlock), 0, s, x, n, mean, partials, x32, pair);
+}
+
+__global__ __launch_bounds__(1024) void k_final_moments(const double* __restrict__ part,
+                                                        const double* __restrict__ part2, int nb, long long n,
+                                                        double* mean_out, double* pair0, double* pair1)
+{
+    __shared__ double sh[16];
+    double v = 0.0, w = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        v += part[b];
+        w += part2[b];
+    }
+    const double s1 = block_sum(v, sh);
+    const double s2 = block_sum(w, sh);
+    if (threadIdx.x == 0) {
+        const double mean = (1.0 / (double)n) * s1;
+        const double raw = s2 / (double)n;
+        const double var = raw - mean * mean;
+        double r = var > 1e-12 * raw ? sqrt(var) : sqrt(raw);
+        if (!(r > 0.0) || !isfinite(r)) r = 1.0;
+        mean_out[0] = mean;
+        pair0[0] = pair1[0] = r;
+        pair0[1] = pair1[1] = 1.0 / r;
+    }
+}
+
+void launch_final_moments(const double* partials, const double* partials2, int nb, long long n, double* mean_out,
+                          double* pair0, double* pair1, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_final_moments, dim3(1), dim3(1024), 0, s, partials, partials2, nb, n, mean_out, pair0,
+                       pair1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_sub_mean(double* __restrict__ x, long long n,
@@ -475,10 +510,78 @@ __global__ __launch_bounds__(kBlock) void k_coef_restrict_cells32(Dims f, const 
     cz[q] = 0.25f * az;
 }
 
+// The same for two x-adjacent coarse cells per thread (nx a multiple of 4):
+// the four fine cells of a row segment as one 16-byte load, the x neighbour
+// below the segment as one word; the same faces summed in the same order.
+__global__ __launch_bounds__(kBlock) void k_coef_restrict_cells32x2(Dims f, const float* __restrict__ hc,
+                                                                    float* __restrict__ cx, float* __restrict__ cy,
+                                                                    float* __restrict__ cz)
+{
+    const int nxc = f.nx / 2, nyc = f.ny / 2, nzc = f.nz / 2;
+    const int I2 = blockIdx.x * blockDim.x + threadIdx.x;  // coarse cells 2 I2, 2 I2 + 1
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    const int K = blockIdx.z * blockDim.z + threadIdx.z;
+    if (2 * I2 >= nxc || J >= nyc || K >= nzc) return;
+    const long long sy = f.nx, sz = (long long)f.nx * f.ny;
+    const long long base = (long long)(2 * K) * sz + (long long)(2 * J) * sy + 4 * I2;
+    const long long ox = I2 > 0 ? -1 : (f.px ? f.nx - 1 : 0);
+    const long long oy = J > 0 ? -sy : (f.py ? (long long)(f.ny - 1) * sy : 0);
+    const long long oz = K > 0 ? -sz : (f.pz ? (long long)(f.nz - 1) * sz : 0);
+    const bool hx = I2 > 0 || f.px, hy = J > 0 || f.py, hz = K > 0 || f.pz;
+    auto ld4 = [&](long long q) { return *reinterpret_cast<const float4*>(hc + q); };
+    // children rows (a = k child, b = j child) and their low neighbours
+    float4 ch[2][2], ny_[2], nz_[2];
+    float nx_[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            ch[a][b] = ld4(base + a * sz + b * sy);
+            nx_[a][b] = hx ? hc[base + a * sz + b * sy + ox] : 0.0f;
+        }
+#pragma unroll
+    for (int a = 0; a < 2; a++) ny_[a] = hy ? ld4(base + a * sz + oy) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int b = 0; b < 2; b++) nz_[b] = hz ? ld4(base + b * sy + oz) : make_float4(0.f, 0.f, 0.f, 0.f);
+    // coarse cell u (0: fine x 0, 1; 1: fine x 2, 3); accumulation order of
+    // k_coef_restrict_cells32: (a, b) = (0,0), (0,1), (1,0), (1,1)
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+        float ax = 0.0f, ay = 0.0f, az = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+                // x face at fine x 2u: neighbour 2u - 1 (the word below the segment for u = 0)
+                const float xo = u == 0 ? nx_[a][b] : ch[a][b].y;
+                const float xi = u == 0 ? ch[a][b].x : ch[a][b].z;
+                ax += (u == 1 || hx) ? harm(xo, xi) : 0.0f;
+                // y face (children k = a, x = 2u + b) and z face (children j = a, x = 2u + b)
+                const float4& cy0 = ch[a][0];
+                const float4& cz0 = ch[0][a];
+                const float yi = b == 0 ? (u == 0 ? cy0.x : cy0.z) : (u == 0 ? cy0.y : cy0.w);
+                const float yo = b == 0 ? (u == 0 ? ny_[a].x : ny_[a].z) : (u == 0 ? ny_[a].y : ny_[a].w);
+                const float zi = b == 0 ? (u == 0 ? cz0.x : cz0.z) : (u == 0 ? cz0.y : cz0.w);
+                const float zo = b == 0 ? (u == 0 ? nz_[a].x : nz_[a].z) : (u == 0 ? nz_[a].y : nz_[a].w);
+                ay += hy ? harm(yo, yi) : 0.0f;
+                az += hz ? harm(zo, zi) : 0.0f;
+            }
+        const long long q = ((long long)K * nyc + J) * nxc + 2 * I2 + u;
+        cx[q] = 0.25f * ax;
+        cy[q] = 0.25f * ay;
+        cz[q] = 0.25f * az;
+    }
+}
+
 void launch_coef_restrict_cells32(const Dims& fine, const float* hc, float* cx, float* cy, float* cz, hipStream_t s)
 {
-    const Shape3 sh = cells3(fine.nx / 2, fine.ny / 2, fine.nz / 2);
-    hipLaunchKernelGGL(k_coef_restrict_cells32, sh.grid, sh.block, 0, s, fine, hc, cx, cy, cz);
+    if (fine.nx % 4 == 0) {
+        const Shape3 sh = cells3(fine.nx / 4, fine.ny / 2, fine.nz / 2);
+        hipLaunchKernelGGL(k_coef_restrict_cells32x2, sh.grid, sh.block, 0, s, fine, hc, cx, cy, cz);
+    } else {
+        const Shape3 sh = cells3(fine.nx / 2, fine.ny / 2, fine.nz / 2);
+        hipLaunchKernelGGL(k_coef_restrict_cells32, sh.grid, sh.block, 0, s, fine, hc, cx, cy, cz);
+    }
 }
 
 template void launch_coef_restrict_cells<double>(const Dims&, const double*, double*, double*, double*, hipStream_t);

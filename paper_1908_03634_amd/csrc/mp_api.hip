@@ -161,6 +161,7 @@ struct mp_ctx {
     double* ir_phi = nullptr;     // refinement update fused into the V-cycle's last pass
     const double* ir_s = nullptr;  // (phi += ir_s[0] * e), or nullptr
     bool ir_fresh = false;         // phi is zero before that update (written, not read)
+    bool b32_ready = false;        // the right-hand side's scaled FP32 copy and its pairs are written
     bool have_coefs = false, have_base = false;
     long long map_serial = 0;  // successful mappings so far
     NodalState* nd = nullptr;
@@ -715,6 +716,9 @@ int cycles_this_step(const mp_ctx* c, int it, double rel, double rel_prev, int m
 // Solve A phi = b64 (b64 mean-zero, ||b64||^2 = nb2 in hscal[S_NB2]).
 int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
 {
+    // the scaled FP32 right-hand side from the mean removal, for this solve only
+    const bool b32_ready = c->b32_ready;
+    c->b32_ready = false;
     const long long n = c->n0;
     const int nb = nblk(c);
     const double nb2 = c->hscal[S_NB2];
@@ -749,8 +753,9 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
         int nbr = 0;
         if (it == 0 && !use_guess) {
             // zero iterate: the residual is b (relative residual 1), so the
-            // residual pass and its read-back are skipped
-            mp::launch_scale32(n, c->b64, mx ? (float*)c->lv[0].b : nullptr, sp, sq, c->stream);
+            // residual pass and its read-back are skipped (and the scaling
+            // too when the mean removal wrote the scaled copy and both pairs)
+            if (!b32_ready) mp::launch_scale32(n, c->b64, mx ? (float*)c->lv[0].b : nullptr, sp, sq, c->stream);
             rel = 1.0;
         } else {
             if (use_blk(c, 0))
@@ -1229,8 +1234,9 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
     {
         int np = c->nbz > mp::kMaxRedBlocks ? c->nbz : mp::kMaxRedBlocks;
         if (mp::blk_supported(c->d0) && mp::blk_reduce_blocks(c->d0) > np) np = mp::blk_reduce_blocks(c->d0);
-        if (mp::proj_blk_supported(c->d0) && mp::proj_blk_reduce_blocks(c->d0) > np)
-            np = mp::proj_blk_reduce_blocks(c->d0);
+        // the blocked right-hand side writes two sets of partials (b, b^2)
+        if (mp::proj_blk_supported(c->d0) && 2 * mp::proj_blk_reduce_blocks(c->d0) > np)
+            np = 2 * mp::proj_blk_reduce_blocks(c->d0);
         c->partials = dalloc<double>(np, e), good &= ok(c->partials);
         c->npartials = np;
     }
@@ -1473,14 +1479,27 @@ int mp_set_coefs(mp_ctx* c, const double* cx, const double* cy, const double* cz
 
 // Prepare b64 from its raw form already in b64 (nb_sum partial sums in
 // partials): mean -> S_MEAN, remove it and ||b||^2 -> S_NB2, rms -> first
-// scale pair (nb: blocks of the grid-stride pass).
-static int finish_rhs(mp_ctx* c, int nb_sum, int nb)
+// scale pair (nb: blocks of the grid-stride pass).  moments: the partials
+// are followed by nb_sum partial sums of b^2, from which the mean and a scale
+// (the rms of b - mean from the two moments) come in one pass, so that the
+// mean removal also writes the first step's scaled FP32 right-hand side.
+static int finish_rhs(mp_ctx* c, int nb_sum, int nb, bool moments = false)
 {
     const long long n = c->n0;
-    mp::launch_final_sum(c->partials, nb_sum, c->dscal + S_MEAN, 1.0 / (double)n, nullptr, 0.0, c->stream);
-    mp::launch_sub_mean_sumsq(c->b64, n, c->dscal + S_MEAN, c->partials, nb, c->stream);
-    mp::launch_final_sum(c->partials, nb, c->dscal + S_NB2, 1.0, c->dscal + S_PAIR0, (double)n, c->stream,
-                         c->dscal + S_BIT);
+    if (moments) {
+        mp::launch_final_moments(c->partials, c->partials + nb_sum, nb_sum, n, c->dscal + S_MEAN, c->dscal + S_PAIR0,
+                                 c->dscal + S_PAIR0 + 2, c->stream);
+        mp::launch_sub_mean_sumsq(c->b64, n, c->dscal + S_MEAN, c->partials, nb, c->stream, (float*)c->lv[0].b,
+                                  c->dscal + S_PAIR0);
+        mp::launch_final_sum(c->partials, nb, c->dscal + S_NB2, 1.0, nullptr, 0.0, c->stream, c->dscal + S_BIT);
+        c->b32_ready = true;
+    } else {
+        c->b32_ready = false;
+        mp::launch_final_sum(c->partials, nb_sum, c->dscal + S_MEAN, 1.0 / (double)n, nullptr, 0.0, c->stream);
+        mp::launch_sub_mean_sumsq(c->b64, n, c->dscal + S_MEAN, c->partials, nb, c->stream);
+        mp::launch_final_sum(c->partials, nb, c->dscal + S_NB2, 1.0, c->dscal + S_PAIR0, (double)n, c->stream,
+                             c->dscal + S_BIT);
+    }
     int st = sync_read(c, S_MEAN, 2);
     if (st) return st;
     if (!isfinite(c->hscal[S_MEAN]) || !isfinite(c->hscal[S_NB2]))
@@ -1508,12 +1527,15 @@ static int project(mp_ctx* c, double* ux, double* uy, double* uz, const double* 
     const bool pblk = c->cfg.blocked && c->cell_mode && mp::proj_blk_supported(c->d0) && aligned16(ux) &&
                       aligned16(uy) && aligned16(uz) && aligned16(S) && aligned16(phi);
     int nbs = c->nbz;
+    // mixed precision with the blocked right-hand side: its second moment
+    // gives the first step's scale, written with the mean removal
+    const bool moments = pblk && mixed(c);
     if (pblk)
         mp::launch_rhs_blk(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->b64, nullptr, c->partials, &nbs,
-                           c->stream);
+                           c->stream, moments ? c->partials + mp::proj_blk_reduce_blocks(c->d0) : nullptr);
     else
         mp::launch_mac_rhs(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->b64, c->partials, c->stream);
-    int st = finish_rhs(c, nbs, nb);
+    int st = finish_rhs(c, nbs, nb, moments);
     if (st) return st;
     if (info) {
         info->rhs_norm = sqrt(c->hscal[S_NB2]);

@@ -39,8 +39,17 @@ void launch_final_sum(const double* partials, int nb, double* out, double scale,
                       hipStream_t s, double* zero_out = nullptr);
 // partials[b] = per-block sum of x (grid-stride, fixed order).
 void launch_sum(const double* x, long long n, double* partials, int nb, hipStream_t s);
-// x[q] -= mean[0]; partials = per-block sum of x^2 after the update.
-void launch_sub_mean_sumsq(double* x, long long n, const double* mean, double* partials, int nb, hipStream_t s);
+// x[q] -= mean[0]; partials = per-block sum of x^2 after the update; when
+// x32 != nullptr also x32[q] = float(x[q] * pair[1]).
+void launch_sub_mean_sumsq(double* x, long long n, const double* mean, double* partials, int nb, hipStream_t s,
+                           float* x32 = nullptr, const double* pair = nullptr);
+// From per-block sums s1 (partials) and s2 (partials2) of b and b^2 over n
+// values: mean_out[0] = s1 / n and a scale for b - mean, the rms
+// r = sqrt(s2 / n - mean^2) (sqrt(s2 / n) where cancellation leaves under
+// 1e-6 of it; 1 for a zero b), written as the pairs (r, 1 / r) at pair0 and
+// pair1.
+void launch_final_moments(const double* partials, const double* partials2, int nb, long long n, double* mean_out,
+                          double* pair0, double* pair1, hipStream_t s);
 // x[q] -= mean[0].
 void launch_sub_mean(double* x, long long n, const double* mean, hipStream_t s);
 // b[q] = -rhs[q]; partials = per-block sum of b.
@@ -257,11 +266,12 @@ void launch_resid64_blk(const Dims& d, const double* x, const double* b, const d
 // launch_vel_correct (cell-value coefficients) when proj_blk_supported(d)
 // and every array is 16-byte aligned.
 bool proj_blk_supported(const Dims& d);
-// shift == nullptr: b written, partials = per-block sums of b; otherwise no
+// shift == nullptr: b written, partials = per-block sums of b (and, when
+// partials2 != nullptr, partials2 = per-block sums of b^2); otherwise no
 // write and partials = per-block sums of (b - shift[0])^2.  *nb_out partials.
 void launch_rhs_blk(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
                     const double* uz, const double* S, const double* sbar, int smode, double* b, const double* shift,
-                    double* partials, int* nb_out, hipStream_t s);
+                    double* partials, int* nb_out, hipStream_t s, double* partials2 = nullptr);
 void launch_vc_blk(const Dims& d, double inv_h, const double* cc, const double* beta0, const double* phi, double* ux,
                    double* uy, double* uz, hipStream_t s);
 int proj_blk_reduce_blocks(const Dims& d);
