@@ -247,6 +247,15 @@ int mp_nodal_project(mp_ctx *ctx, double *ux, double *uy, double *uz, const doub
 /* y = M x on the nodes, FP64, with sigma from the last mapping. */
 int mp_nodal_apply(mp_ctx *ctx, const double *x, double *y);
 
+/* Perturbational pressure from the nodal projection's scalar (Sec. 3.2 Step
+ * 11; Appendix A: the gradient of that scalar updates pi).  The time-step
+ * scaling belongs to an earlier paper, so it is the caller's:
+ *   pi <- a pi + s phi   on every node (a = 0: pi is written, not read),
+ * so that (sigma/beta0) G(pi)/s is the correction the projection applied
+ * when a = 0.  phi, pi: device, nodes (mp_nodal_shape), FP64; may not alias.
+ * Errors: MP_ERR_ARG (NULL or aliased arrays), MP_ERR_NONFINITE (a or s). */
+int mp_nodal_pi(mp_ctx *ctx, const double *phi, double a, double s, double *pi);
+
 /* Solve M x = rhs (rhs mean removed when demean = 1); x mean-zero.  This is
  * also the adjoint solve, M being symmetric. */
 int mp_solve(mp_ctx *ctx, const double *rhs, double *x, int use_initial_guess, mp_info *info);

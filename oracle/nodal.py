@@ -208,3 +208,14 @@ def project(prob, tol=1e-12, maxcycles=200):
     phi, info = solve(g, sigma, R, tol=tol, maxcycles=maxcycles)
     ux, uy, uz = correct(g, sigma, beta0, phi, prob.ux, prob.uy, prob.uz)
     return dict(grid=g, beta0=beta0, sigma=sigma, R=R, mean=m, phi=phi, info=info, ux=ux, uy=uy, uz=uz)
+
+
+def update_pi(phi, s, pi=None, a=0.0):
+    """Perturbational pressure from the nodal scalar (Sec. 3.2 Step 11; Appendix A
+    says the gradient of that scalar updates pi): pi <- a pi + s phi on every
+    node, s the caller's time-step scaling.  With a = 0, (sigma/beta0) G(pi)/s
+    is the correction `correct` applies."""
+    phi = np.asarray(phi, dtype=np.float64)
+    if pi is None:
+        return s * phi
+    return a * np.asarray(pi, dtype=np.float64) + s * phi

@@ -175,6 +175,18 @@ void launch_sub_mean(double* x, long long n, const double* mean, hipStream_t s)
     hipLaunchKernelGGL(k_sub_mean, dim3(grid1(n)), dim3(kBlock), 0, s, x, n, mean);
 }
 
+__global__ __launch_bounds__(kBlock) void k_axpby(long long n, double a, double b, const double* __restrict__ x,
+                                                  double* __restrict__ y)
+{
+    const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (q < n) y[q] = a == 0.0 ? b * x[q] : fma(a, y[q], b * x[q]);
+}
+
+void launch_axpby(long long n, double a, double b, const double* x, double* y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(grid1(n)), dim3(kBlock), 0, s, n, a, b, x, y);
+}
+
 __global__ __launch_bounds__(kBlock) void k_neg_copy_sum(const double* __restrict__ rhs, double* __restrict__ b,
                                                          long long n, double* part)
 {

@@ -1792,6 +1792,19 @@ int mp_nodal_apply(mp_ctx* c, const double* x, double* y)
     return MP_OK;
 }
 
+int mp_nodal_pi(mp_ctx* c, const double* phi, double a, double s, double* pi)
+{
+    if (!c) return MP_ERR_ARG;
+    if (!phi || !pi) return fail(c, MP_ERR_ARG, "phi and pi are required");
+    if (phi == pi) return fail(c, MP_ERR_ARG, "phi and pi may not alias");
+    if (!std::isfinite(a) || !std::isfinite(s)) return fail(c, MP_ERR_NONFINITE, "a and s must be finite");
+    (void)hipSetDevice(c->cfg.device);
+    const mp::NDims d = node_dims(c->d0);
+    mp::launch_axpby((long long)d.mx * d.my * d.mz, a, s, phi, pi, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MP_OK;
+}
+
 int mp_base_radii(mp_ctx* c, double* rc, double* re)
 {
     if (!c) return MP_ERR_ARG;

@@ -52,6 +52,8 @@ void launch_final_moments(const double* partials, const double* partials2, int n
                           double* pair0, double* pair1, hipStream_t s);
 // x[q] -= mean[0].
 void launch_sub_mean(double* x, long long n, const double* mean, hipStream_t s);
+// y[q] = a y[q] + b x[q] (y not read when a == 0).
+void launch_axpby(long long n, double a, double b, const double* x, double* y, hipStream_t s);
 // b[q] = -rhs[q]; partials = per-block sum of b.
 void launch_neg_copy_sum(const double* rhs, double* b, long long n, double* partials, int nb, hipStream_t s);
 

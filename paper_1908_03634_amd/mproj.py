@@ -95,7 +95,7 @@ class Info(ctypes.Structure):
 # Every exported symbol of include/mproj.h.
 EXPORTS = ["mp_config_default", "mp_init", "mp_map_base_state", "mp_set_coefs", "mp_mac_project", "mp_solve",
            "mp_mac_project_split", "mp_radius_count", "mp_average", "mp_set_kernel_timing", "mp_apply", "mp_coef_grad",
-           "mp_nodal_shape", "mp_nodal_project", "mp_nodal_apply", "mp_base_radii", "mp_enforce_hse",
+           "mp_nodal_shape", "mp_nodal_project", "mp_nodal_apply", "mp_nodal_pi", "mp_base_radii", "mp_enforce_hse",
            "mp_beta0_from_p0", "mp_w0", "mp_enforce_hse_noalloc", "mp_average_uniform", "mp_add_w0", "mp_free",
            "mp_last_error", "mp_version"]
 
@@ -148,6 +148,8 @@ def load_library(path=None):
     lib.mp_nodal_project.restype = I
     lib.mp_nodal_apply.argtypes = [P, P, P]
     lib.mp_nodal_apply.restype = I
+    lib.mp_nodal_pi.argtypes = [P, P, D, D, P]
+    lib.mp_nodal_pi.restype = I
     L = ctypes.c_longlong
     lib.mp_base_radii.argtypes = [P, P, P]
     lib.mp_base_radii.restype = I
@@ -426,6 +428,17 @@ class Context:
         ns = self.node_shape
         self._check(self._run(self.lib.mp_nodal_apply, self._ptr(x, ns, "x"), self._ptr(y, ns, "y")), "mp_nodal_apply")
         return y
+
+    def nodal_pi(self, phi, s, pi=None, a=0.0):
+        """pi <- a pi + s phi on the nodes (the perturbational pressure from
+        the nodal projection's scalar; a = 0 writes a new pi)."""
+        ns = self.node_shape
+        if pi is None:
+            pi = self.empty_nodes()
+            a = 0.0
+        self._check(self._run(self.lib.mp_nodal_pi, self._ptr(phi, ns, "phi"), float(a), float(s), self._ptr(pi, ns, "pi")),
+                    "mp_nodal_pi")
+        return pi
 
     # -- one-dimensional base state ----------------------------------------
     def _vec(self, n):

@@ -239,3 +239,36 @@ def test_two_colour_passes_equal_four_colour_passes(shape, bc):
     assert outs[0][3] == outs[1][3] and outs[0][4] <= 1e-11
     for a, b in zip(outs[0][:3], outs[1][:3]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 1), (1, 1, 1)])
+def test_pressure_from_the_nodal_scalar(bc):
+    """pi = s phi bit for bit with the oracle's update; the increment form
+    a pi + s phi likewise (a a power of two, so both sides round once); the
+    gradient of pi / s reproduces the correction the projection applied."""
+    say("nodal pi", bc)
+    p = W.planar_problem(nx=24, ny=20, nz=28, contrast=1e4, bc=bc, seed=7800, velocity="cells")
+    g, b0, sigma = _sigma(p)
+    ctx = _mapped(p, "mixed", rtol=1e-12)
+    ux, uy, uz = T(p.ux), T(p.uy), T(p.uz)
+    phi, _ = ctx.nodal_project(ux, uy, uz, T(p.S))
+    s = 1.0 / 2.5e-3
+    pi = ctx.nodal_pi(phi, s)
+    torch.cuda.synchronize()
+    assert np.array_equal(N(pi), nd.update_pi(N(phi), s))
+    gx, gy, gz = nd.gradient(g, N(pi))
+    w = sigma / b0 / s
+    for new, old, gr in ((ux, p.ux, gx), (uy, p.uy, gy), (uz, p.uz, gz)):
+        assert np.abs((old - N(new)) - w * gr).max() <= 1e-12 * np.abs(old).max()
+    old = np.random.default_rng(11).standard_normal(ctx.node_shape)
+    inc = T(old)
+    ctx.nodal_pi(phi, s, pi=inc, a=0.5)
+    torch.cuda.synchronize()
+    assert np.array_equal(N(inc), nd.update_pi(N(phi), s, pi=old, a=0.5))
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.nodal_pi(phi, s, pi=phi)
+    assert e.value.code == 1
+    with pytest.raises(mproj.MprojError) as e:
+        ctx.nodal_pi(phi, float("nan"), pi=inc)
+    assert e.value.code == 5
+    ctx.close()

@@ -210,3 +210,19 @@ def test_projection_of_a_workload_reaches_the_tolerance():
     w = r["sigma"] / r["beta0"]
     for new, old, gr in ((r["ux"], p.ux, gx), (r["uy"], p.uy, gy), (r["uz"], p.uz, gz)):
         assert np.allclose(old - new, w * gr, rtol=1e-12, atol=1e-14)
+
+
+def test_pressure_update_reproduces_the_applied_correction():
+    """pi = s phi: (sigma/beta0) G(pi) / s is U_dagger - U_new cell by cell,
+    and the increment form adds a multiple of the old pi."""
+    p = W.planar_problem(12, contrast=1e3, seed=71, velocity="cells")
+    r = nd.project(p, tol=1e-12)
+    s = 1.0 / 3.0e-3
+    pi = nd.update_pi(r["phi"], s)
+    gx, gy, gz = nd.gradient(r["grid"], pi)
+    w = r["sigma"] / r["beta0"] / s
+    for new, old, gr in ((r["ux"], p.ux, gx), (r["uy"], p.uy, gy), (r["uz"], p.uz, gz)):
+        assert np.allclose(old - new, w * gr, rtol=1e-11, atol=1e-13)
+    old = np.random.default_rng(3).standard_normal(pi.shape)
+    inc = nd.update_pi(r["phi"], s, pi=old, a=1.0)
+    assert np.allclose(inc, old + pi, rtol=1e-15, atol=1e-15 * np.abs(pi).max())
