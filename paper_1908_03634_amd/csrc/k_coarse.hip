@@ -34,6 +34,14 @@ __device__ __forceinline__ double wave_get(const double (&v)[NS], int nq)
     return r;
 }
 
+// Wavefront minimum broadcast from lane 0.
+__device__ __forceinline__ double wave_min_bcast(double v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+    return __shfl(v, 0, kWave);
+}
+
 template <typename T, int NS>
 __device__ void wave_cg(const Dims& d, const T* __restrict__ bin, T* __restrict__ xout,
                               const T* __restrict__ cx, const T* __restrict__ cy, const T* __restrict__ cz, double h2,
@@ -69,13 +77,62 @@ __device__ void wave_cg(const Dims& d, const T* __restrict__ bin, T* __restrict_
         nbi[u][5] = (int)nb.zp;
         b[u] = live[u] ? (double)bin[qq] : 0.0;
     }
-    double part = 0.0;
+    // Connected parts of the grid: each cell's label becomes the smallest
+    // cell index joined to it through nonzero faces (minimum-label
+    // propagation, settled within a part's diameter).  The constants on each
+    // part span the null space of the operator, so the right-hand side, the
+    // residual and the result are made mean-zero part by part: a right-hand
+    // side left with a component on a part's constant (rounding, where the
+    // cells are not all coupled) would otherwise drive the iterates along
+    // that constant without bound.  With every cell coupled this is the plain
+    // mean removal, in the same operations.
+    double lab[NS];
 #pragma unroll
-    for (int u = 0; u < NS; u++) part += b[u];
-    const double mean = wave_sum_bcast(part) / n;
+    for (int u = 0; u < NS; u++) lab[u] = live[u] ? (double)(lane + kWave * u) : (double)n;
+    for (;;) {
+        double nl[NS];
+        int changed = 0;
+#pragma unroll
+        for (int u = 0; u < NS; u++) {
+            double m = lab[u];
+#pragma unroll
+            for (int f = 0; f < 6; f++) {
+                const double w = wave_get<NS>(lab, nbi[u][f]);
+                if (live[u] && c[u][f] != 0.0 && w < m) m = w;
+            }
+            nl[u] = m;
+            changed |= m != lab[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NS; u++) lab[u] = nl[u];
+        if (wave_sum_bcast((double)changed) == 0.0) break;
+    }
+    auto demean = [&](double (&y)[NS]) {
+        double lo = (double)n;
+#pragma unroll
+        for (int u = 0; u < NS; u++)
+            if (live[u]) lo = fmin(lo, lab[u]);
+        double cur = wave_min_bcast(lo);
+        while (cur < (double)n) {
+            double s = 0.0, cnt = 0.0, nxt = (double)n;
+#pragma unroll
+            for (int u = 0; u < NS; u++) {
+                if (live[u] && lab[u] == cur) {
+                    s += y[u];
+                    cnt += 1.0;
+                }
+                if (live[u] && lab[u] > cur) nxt = fmin(nxt, lab[u]);
+            }
+            const double m = wave_sum_bcast(s) / wave_sum_bcast(cnt);
+#pragma unroll
+            for (int u = 0; u < NS; u++)
+                if (live[u] && lab[u] == cur) y[u] -= m;
+            cur = wave_min_bcast(nxt);
+        }
+    };
+    demean(b);
 #pragma unroll
     for (int u = 0; u < NS; u++) {
-        b[u] = live[u] ? b[u] - mean : 0.0;
         x[u] = 0.0;
         r[u] = b[u];
         p[u] = b[u];
@@ -99,12 +156,10 @@ __device__ void wave_cg(const Dims& d, const T* __restrict__ bin, T* __restrict_
         for (int u = 0; u < NS; u++) acc = fma(a[u], bb[u], acc);
         return wave_sum_bcast(acc);
     };
-    // conjugate gradients: A is symmetric and positive on mean-zero vectors;
-    // the residual is kept mean-zero against rounding.  An unconverged solve
-    // returns the iterate of the smallest residual (where the cells are not
-    // all coupled and b has a component on another constant mode, the
-    // residual stalls above the tolerance while the iterates grow along that
-    // mode); a converged one returns its last iterate.
+    // conjugate gradients: A is symmetric and positive on vectors mean-zero
+    // on every part; the residual is kept so against rounding.  An
+    // unconverged solve returns the iterate of the smallest residual; a
+    // converged one returns its last iterate.
     double rr = dot(r, r);
     const double tol2 = rtol * rtol * rr;
     double rr_best = rr;
@@ -117,16 +172,12 @@ __device__ void wave_cg(const Dims& d, const T* __restrict__ bin, T* __restrict_
         const double pv = dot(p, v);
         if (!(pv > 0.0)) break;
         const double alpha = rr / pv;
-        part = 0.0;
 #pragma unroll
         for (int u = 0; u < NS; u++) {
             x[u] = fma(alpha, p[u], x[u]);
             r[u] = live[u] ? fma(-alpha, v[u], r[u]) : 0.0;
-            part += r[u];
         }
-        const double mr = wave_sum_bcast(part) / n;
-#pragma unroll
-        for (int u = 0; u < NS; u++) r[u] = live[u] ? r[u] - mr : 0.0;
+        demean(r);
         const double rr1 = dot(r, r);
         const double beta = rr1 / rr;
         rr = rr1;
@@ -145,13 +196,10 @@ __device__ void wave_cg(const Dims& d, const T* __restrict__ bin, T* __restrict_
     // iterations of this solve added to the caller's running count (one
     // lane; the solves of a stream run one after another)
     if (iters && lane == 0) iters[0] += (double)it;
-    part = 0.0;
-#pragma unroll
-    for (int u = 0; u < NS; u++) part += live[u] ? xb[u] : 0.0;
-    const double xm = wave_sum_bcast(part) / n;
+    demean(xb);
 #pragma unroll
     for (int u = 0; u < NS; u++)
-        if (live[u]) xout[lane + kWave * u] = (T)(xb[u] - xm);
+        if (live[u]) xout[lane + kWave * u] = (T)xb[u];
 }
 
 // ---- direct bottom solve ----------------------------------------------------
@@ -456,7 +504,7 @@ __device__ void own_smooth(const Owned<T, U>& o, const CoarseLevel<T>& L, bool z
                 const T xm = L.x[n[0]], xp = L.x[n[1]], ym = L.x[n[2]], yp = L.x[n[3]], zm = L.x[n[4]],
                         zp = L.x[n[5]];
                 L.x[q] = gs_value_cs<T>(o.cs[u][s], c[0], c[1], c[2], c[3], c[4], c[5], xm, xp, ym, yp, zm, zp,
-                                        o.b[u][s], L.h2, T(0));
+                                        o.b[u][s], L.h2, L.x[q]);
             }
         }
         __syncthreads();

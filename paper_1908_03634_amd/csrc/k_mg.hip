@@ -299,16 +299,41 @@ void launch_prolong(const Dims& fine, T* phi, const T* coarse_phi, hipStream_t s
 
 // ------------------------------------------------------------ bottom solve
 
+// Block minimum; every thread receives the same value (sh as for block_sum).
+__device__ __forceinline__ double block_min(double v, double* sh)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double m = sh[0];
+    for (int i = 1; i < nw; i++) m = fmin(m, sh[i]);
+    return m;
+}
+
+// The six face coefficients of cell q (stencil order), FP64.
+template <typename T>
+__device__ __forceinline__ void face6(const T* cx, const T* cy, const T* cz, long long q, const Nbr& nb, double (&c)[6])
+{
+    c[0] = (double)cx[q];
+    c[1] = (double)ld_or0(cx, nb.cxp);
+    c[2] = (double)cy[q];
+    c[3] = (double)ld_or0(cy, nb.cyp);
+    c[4] = (double)cz[q];
+    c[5] = (double)ld_or0(cz, nb.czp);
+}
+
 // BiCGStab in FP64 for A x = b on the coarsest grid, run by one workgroup
 // (used when that grid holds more cells than one wavefront solves in
-// registers).  b is made mean-zero first (the system is singular with the
-// constants as null space); the result is returned mean-zero.  With use_x0
-// the iteration starts from the x passed in and stops at rtol times the
-// initial residual; otherwise it starts from zero.  An unconverged solve
-// returns the iterate of the smallest residual (where the cells are not all
-// coupled and b has a component on another constant mode, the residual
-// stalls above the tolerance while the iterates drift along that mode).
-// work holds 8 n doubles.
+// registers).  The constants on each connected part of the grid (cells
+// joined through nonzero faces) span the null space, so b is made mean-zero
+// part by part first and the result is returned so (with every cell coupled:
+// the plain mean removal, in the same operations).  With use_x0 the
+// iteration starts from the x passed in and stops at rtol times the initial
+// residual; otherwise it starts from zero.  An unconverged solve returns the
+// iterate of the smallest residual.  work holds 9 n doubles.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ bin, T* __restrict__ xout,
                                                  const T* __restrict__ cx, const T* __restrict__ cy,
@@ -328,11 +353,58 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
     double* s = work + 5 * n;
     double* tv = work + 6 * n;
     double* xb = work + 7 * n;
+    double* lab = work + 8 * n;  // connected-part label: smallest cell index of the part
     const double inv_h2 = 1.0 / h2;
 
+    // labels by minimum-label propagation (in place: the fixed point, each
+    // part's smallest index, does not depend on the order of the updates)
+    for (int q = tid; q < n; q += nt) lab[q] = (double)q;
+    for (;;) {
+        __syncthreads();
+        double changed = 0.0;
+        for (int q = tid; q < n; q += nt) {
+            int i, j, k;
+            cell_ijk(d, q, i, j, k);
+            const Nbr nb = neighbours(d, q, i, j, k);
+            double c[6];
+            face6<T>(cx, cy, cz, q, nb, c);
+            const long long nq[6] = {nb.xm, nb.xp, nb.ym, nb.yp, nb.zm, nb.zp};
+            double m = lab[q];
+#pragma unroll
+            for (int f = 0; f < 6; f++)
+                if (c[f] != 0.0) m = fmin(m, lab[nq[f]]);
+            if (m < lab[q]) {
+                lab[q] = m;
+                changed = 1.0;
+            }
+        }
+        if (block_sum(changed, sh) == 0.0) break;
+    }
+    // pm[q] = mean of y over the part of cell q (pm may not alias y)
+    auto part_means = [&](const double* y, bool from_bin, double* pm) {
+        double lo = (double)n;
+        for (int q = tid; q < n; q += nt) lo = fmin(lo, lab[q]);
+        double cur = block_min(lo, sh);
+        while (cur < (double)n) {
+            double sum = 0.0, cnt = 0.0, nxt = (double)n;
+            for (int q = tid; q < n; q += nt) {
+                if (lab[q] == cur) {
+                    sum += from_bin ? (double)bin[q] : y[q];
+                    cnt += 1.0;
+                } else if (lab[q] > cur) {
+                    nxt = fmin(nxt, lab[q]);
+                }
+            }
+            const double m = block_sum(sum, sh) / block_sum(cnt, sh);
+            for (int q = tid; q < n; q += nt)
+                if (lab[q] == cur) pm[q] = m;
+            cur = block_min(nxt, sh);
+        }
+        __syncthreads();
+    };
     double part = 0.0;
-    for (int q = tid; q < n; q += nt) part += (double)bin[q];
-    const double mean = block_sum(part, sh) / n;
+    double* bmean = s;  // free until the iteration
+    part_means(nullptr, true, bmean);
     for (int q = tid; q < n; q += nt) x[q] = use_x0 ? (double)xout[q] : 0.0;
 
     // A y for y in work (FP64), coefficients in T.
@@ -352,7 +424,7 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
     if (use_x0) apply(x, tv);
     part = 0.0;
     for (int q = tid; q < n; q += nt) {
-        const double rq = ((double)bin[q] - mean) - (use_x0 ? tv[q] : 0.0);
+        const double rq = ((double)bin[q] - bmean[q]) - (use_x0 ? tv[q] : 0.0);
         r[q] = rq;
         rh[q] = rq;
         p[q] = 0.0;
@@ -429,10 +501,8 @@ __global__ __launch_bounds__(1024) void k_bottom(Dims d, const T* __restrict__ b
         for (int q = tid; q < n; q += nt) x[q] = xb[q];
     if (iters && tid == 0) iters[0] += (double)(it < maxit ? it + (bnorm2 > 0.0 ? 1 : 0) : it);
     __syncthreads();
-    part = 0.0;
-    for (int q = tid; q < n; q += nt) part += x[q];
-    const double xm = block_sum(part, sh) / n;
-    for (int q = tid; q < n; q += nt) xout[q] = (T)(x[q] - xm);
+    part_means(x, false, tv);
+    for (int q = tid; q < n; q += nt) xout[q] = (T)(x[q] - tv[q]);
 }
 
 template <typename T>

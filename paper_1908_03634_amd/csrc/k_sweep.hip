@@ -269,12 +269,11 @@ __global__ __launch_bounds__(SW_THREADS) void k_sweep(Dims d, int lz, int tiles_
             const long long base = (long long)k * sz;
             if (pp.off >= 0) {
                 const int o = (bly + 1) * SW_RX + lxb + 1;
-                // An uncoupled cell keeps its old value.  It is read from
-                // x_old in global memory: the LDS slot of plane k is being
-                // restaged by threads that have moved on to the next step.
+                // The old value is read from x_old in global memory: the LDS
+                // slot of plane k is being restaged by threads that have
+                // moved on to the next step.
                 T old = T(0);
-                const T cs = ((((bcf[0] + bcf[1]) + bcf[2]) + bcf[3]) + bcf[4]) + bcf[5];
-                if (!(cs > T(0)) && !zero_init) {
+                if (!zero_init) {
                     old = xo[base + pp.off];
                     if (ec) old += ec[(long long)(k >> 1) * szc + pp.coff];
                 }

@@ -1282,7 +1282,7 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
         d = Dims{d.nx / 2, d.ny / 2, d.nz / 2, d.px, d.py, d.pz};
         h *= 2.0;
     }
-    c->bottom_work = dalloc<double>(8 * c->lv.back().d.n(), e), good &= ok(c->bottom_work);
+    c->bottom_work = dalloc<double>(9 * c->lv.back().d.n(), e), good &= ok(c->bottom_work);
     if (c->lv.back().d.n() <= mp::kDirectBottomCells)
         c->ginv = dalloc<double>(mp::kDirectBottomCells * mp::kDirectBottomCells, e), good &= ok(c->ginv);
     // single-workgroup coarse cycle: trailing levels of <= kCoarseCells cells,

@@ -182,23 +182,31 @@ def test_direct_bottom_matches_sparse_lu(precision, shape, bc):
     ctx.close()
 
 
-@pytest.mark.parametrize("precision,coarse_cycle", [("fp64", True), ("fp64", False), ("mixed", True)])
-def test_disconnected_bottom_falls_back_to_conjugate_gradients(precision, coarse_cycle):
+@pytest.mark.parametrize("precision,coarse_cycle", [("fp64", True), ("fp64", False), ("mixed", True), ("mixed", False)])
+@pytest.mark.parametrize("n", [16, 32])
+def test_disconnected_bottom_falls_back_to_conjugate_gradients(precision, coarse_cycle, n):
     """Zero x faces on the plane x = 1/2 (walls in x) split every level in
-    two, so L + alpha 1 1^T is singular on the 64-cell bottom grid: its
-    inverse is refused and the bottom runs Krylov iterations instead; the
-    solve still reaches the tolerance (the right-hand side is mean-zero on
-    each half).  Not covered: FP32 V-cycles with one launch per operation
-    (coarse_cycle=False), whose BiCGStab bottom drifts along the second
-    constant mode until FP32 loses the correction."""
-    n = 16
+    two, and one cell has no nonzero face: L + alpha 1 1^T is singular on the
+    64-cell bottom grid, its inverse is refused and the bottom runs Krylov
+    iterations instead, made mean-zero on each connected part (the constants
+    on each part are the null space).  The right-hand side is mean-zero on
+    each part, so the solve reaches the tolerance; without the per-part
+    projection the FP32 V-cycles drift along the second constant."""
     bc = (1, 0, 0)
     cx, cy, cz = W.random_coefs(n, n, n, bc, 321)
     cx[:, :, n // 2] = 0.0
+    i, j, k = 2, 3, 5  # isolated cell
+    cx[k, j, i] = cx[k, j, i + 1] = 0.0
+    cy[k, j, i] = cy[k, (j + 1) % n, i] = 0.0
+    cz[k, j, i] = cz[(k + 1) % n, j, i] = 0.0
     rhs = W.random_cells(n, n, n, 322)
+    rhs[k, j, i] = 0.0
     for half in (slice(0, n // 2), slice(n // 2, n)):
-        rhs[:, :, half] -= rhs[:, :, half].mean()
-    say("disconnected bottom", precision, coarse_cycle)
+        m = np.zeros((n, n, n), dtype=bool)
+        m[:, :, half] = True
+        m[k, j, i] = False
+        rhs[m] -= rhs[m].mean()
+    say("disconnected bottom", n, precision, coarse_cycle)
     ctx = mproj.Context(n, n, n, h=1.0 / n, bc=bc, precision=precision, rtol=1e-10, coarse_cycle=coarse_cycle)
     ctx.set_coefs(T(cx), T(cy), T(cz))
     x, info = ctx.solve(T(rhs))
