@@ -161,6 +161,7 @@ struct mp_ctx {
     double* ir_phi = nullptr;     // refinement update fused into the V-cycle's last pass
     const double* ir_s = nullptr;  // (phi += ir_s[0] * e), or nullptr
     bool ir_fresh = false;         // phi is zero before that update (written, not read)
+    int extra_post = 0;            // finest-level post-smoothing sweeps beyond nu2 in this V-cycle
     bool b32_ready = false;        // the right-hand side's scaled FP32 copy and its pairs are written
     bool have_coefs = false, have_base = false;
     long long map_serial = 0;  // successful mappings so far
@@ -680,8 +681,8 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
         mp::launch_prolong<T>(L.d, (T*)L.x, (const T*)C.x, c->stream);
         return;
     }
-    for (int s = 0; s < c->cfg.nu2; s++)
-        smooth<T>(c, l, false, s == 0 ? (const T*)C.x : (const T*)nullptr, s == c->cfg.nu2 - 1);
+    const int nu2 = c->cfg.nu2 + (l == 0 ? c->extra_post : 0);
+    for (int s = 0; s < nu2; s++) smooth<T>(c, l, false, s == 0 ? (const T*)C.x : (const T*)nullptr, s == nu2 - 1);
 }
 
 // V-cycles before the next residual check.  cycles_per_outer > 0 fixes the
@@ -692,25 +693,40 @@ void vcycle(mp_ctx* c, int l, bool zero_init)
 // one measuring cycle: the first cycle contracts most (~1e-2), so 4 cycles
 // end near 1e-6, still above the FP32 floor.  The mean rate of such a step
 // includes that first cycle, so the prediction aims at half the tolerance:
-// the MAC and nodal solves at 256^3 then reach 1e-10 in two steps (4 + 4 and
-// 4 + 3 cycles) instead of three.
+// the MAC and nodal solves at 256^3 then reach 1e-10 in two steps instead of
+// three.
 // The contraction per cycle weakens as the smooth error components remain
 // (on the stratified workloads ~0.03 for the second cycle, ~0.08 for the
 // eighth), so the mean rate of the last step is discounted by a fifth: a
 // prediction one cycle short costs a whole refinement step (an FP64 residual
 // and a read-back) to run the missing cycle.
+// Those two allowances make the predicted count about 0.4 cycle larger than
+// what the workloads need: where the last predicted cycle would be used for
+// at most kLastFraction of it, the step runs one cycle fewer and its last
+// cycle one more finest-level post-smoothing sweep (*extra_post = 1), which
+// buys ~0.1 cycle for a tenth of the cost.  The MAC solves at 256^3 to 512^3
+// then take 4 cycles, and 2 cycles plus a sweep (end residual 5e-11 to
+// 7e-11 against 1e-10), instead of 4 + 3.
 constexpr int kFirstCycles = 4;
+constexpr double kLastFraction = 0.45;
 
-int cycles_this_step(const mp_ctx* c, int it, double rel, double rel_prev, int m_prev, bool from_zero)
+int cycles_this_step(const mp_ctx* c, int it, double rel, double rel_prev, int m_prev, bool from_zero,
+                     int* extra_post = nullptr)
 {
+    if (extra_post) *extra_post = 0;
     if (c->cfg.cycles_per_outer > 0) return c->cfg.cycles_per_outer;
     if (it == 0) return from_zero ? kFirstCycles : 1;
     if (!(rel_prev > 0.0) || !(rel > 0.0)) return 1;
     const double rho = pow(rel / rel_prev, 1.0 / m_prev);
     if (!(rho > 0.0) || rho >= 0.5) return 1;
     const double need = log(0.5 * c->cfg.rtol / rel) / (0.8 * log(rho));
-    const int m = (int)ceil(need - 0.25);
-    return m < 1 ? 1 : m > 4 ? 4 : m;
+    int m = (int)ceil(need - 0.25);
+    m = m < 1 ? 1 : m > 4 ? 4 : m;
+    if (extra_post && c->cfg.nu2 >= 1 && m >= 2 && need - (m - 1) <= kLastFraction) {
+        m -= 1;
+        *extra_post = 1;
+    }
+    return m;
 }
 
 // Solve A phi = b64 (b64 mean-zero, ||b64||^2 = nb2 in hscal[S_NB2]).
@@ -793,7 +809,8 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
             fail(c, MP_ERR_NOT_CONVERGED, "stagnated at step %d (rel. residual %.3e)", it, rel);
             break;
         }
-        const int m = cycles_this_step(c, it, rel, rel_prev, m_prev, it == 0 && !use_guess);
+        int extra = 0;
+        const int m = cycles_this_step(c, it, rel, rel_prev, m_prev, it == 0 && !use_guess, &extra);
         rel_prev = rel;
         m_prev = m;
         if (mx) {
@@ -805,8 +822,10 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
                 const bool lastc = k == m - 1;
                 c->ir_phi = fuse_ir && lastc ? phi : nullptr;
                 c->ir_s = sp;
+                c->extra_post = lastc ? extra : 0;
                 vcycle<float>(c, 0, k == 0);
                 c->ir_phi = nullptr;
+                c->extra_post = 0;
                 vc++;
             }
             c->ir_fresh = false;
@@ -814,7 +833,9 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
             if (!fuse_ir) mp::launch_ir_update(n, phi, (const float*)c->lv[0].x, sp, c->stream);
         } else {
             for (int k = 0; k < m; k++) {
+                c->extra_post = k == m - 1 ? extra : 0;
                 vcycle<double>(c, 0, it == 0 && k == 0 && !use_guess);
+                c->extra_post = 0;
                 vc++;
                 // out-of-place sweeps may leave the iterate in the second buffer
                 if (c->lv[0].x != (void*)phi) {
