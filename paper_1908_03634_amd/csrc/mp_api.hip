@@ -1037,7 +1037,8 @@ void nd_vcycle(mp_ctx* c, int l)
     if (l + 1 < nlev - 1 && l + 1 != N.coarse_start) (void)hipMemsetAsync(C.x, 0, sizeof(T) * C.nn, c->stream);
     nd_vcycle<T>(c, l + 1);
     mp::launch_nd_prolong<T>(L.d, C.d, (T*)L.x, (const T*)C.x, L.col ? 1 : 0, c->stream);
-    for (int s = 0; s < c->cfg.nu2; s++) sweep(false);
+    const int nu2 = c->cfg.nu2 + (l == 0 ? c->extra_post : 0);
+    for (int s = 0; s < nu2; s++) sweep(false);
 }
 
 // Solve A phi = N.b64 on the nodes (||b||^2 in hscal[S_NB2], its rms pair in
@@ -1110,19 +1111,24 @@ int nd_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
             fail(c, MP_ERR_NOT_CONVERGED, "nodal solve stagnated at step %d (rel. residual %.3e)", it, rel);
             break;
         }
-        const int m = cycles_this_step(c, it, rel, rel_prev, m_prev, it == 0 && !use_guess);
+        int extra = 0;
+        const int m = cycles_this_step(c, it, rel, rel_prev, m_prev, it == 0 && !use_guess, &extra);
         rel_prev = rel;
         m_prev = m;
         if (mx) {
             HIPCHK(c, hipMemsetAsync(L0.x, 0, sizeof(float) * n, c->stream));
             for (int k = 0; k < m; k++) {
+                c->extra_post = k == m - 1 ? extra : 0;
                 nd_vcycle<float>(c, 0);
+                c->extra_post = 0;
                 vc++;
             }
             mp::launch_ir_update(n, phi, (const float*)L0.x, sp, c->stream);
         } else {
             for (int k = 0; k < m; k++) {
+                c->extra_post = k == m - 1 ? extra : 0;
                 nd_vcycle<double>(c, 0);
+                c->extra_post = 0;
                 vc++;
             }
         }
