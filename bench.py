@@ -220,7 +220,10 @@ def _large(name, args, dev):
         err = float(np.linalg.norm(phi.cpu().numpy() - ref["phi"]) / np.linalg.norm(ref["phi"]))
         out["phi_error_vs_oracle"] = {"value": err, "gpu_rtol": 1e-10, "oracle_rtol": 1e-12,
                                       "oracle_seconds": round(time.perf_counter() - t0, 1),
-                                      "note": "relative L2 error of the benchmarked mixed solve's phi"}
+                                      "rel_resid": out.get("rel_resid"),
+                                      "note": "relative L2 error of the benchmarked mixed solve's phi; it follows "
+                                              "the residual the solve stops at (at most the condition number times "
+                                              "it); solved to 1e-12 the tests hold phi within 1e-9"}
         _log(f"{name}: phi error vs the oracle {err:.3e}")
     return out
 

@@ -131,7 +131,8 @@ void launch_resid_restrict(const Dims& fine, const T* phi, const T* rhs, const C
                            hipStream_t s);
 template <typename T>
 void launch_prolong(const Dims& fine, T* phi, const T* coarse_phi, hipStream_t s);
-// BiCGStab in FP64 on the coarsest grid (one workgroup); work = 8 * n doubles.
+// BiCGStab in FP64 on the coarsest grid (one workgroup), made mean-zero on
+// each connected part of the grid; work = 9 * n doubles.
 // use_x0: start from phi (tolerance relative to the initial residual).
 // iters: device counter the iterations are added to, or nullptr.
 // skip_if_direct: a device flag (1: the direct bottom solve applies and this

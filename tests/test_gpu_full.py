@@ -61,9 +61,13 @@ def _phi_parity(name):
     e = _check_projection(p, r, full_phi_ref=ref["phi"], tol=1e-12)
     assert e < 1e-9
     r["ctx"].close()
-    r = gpu_project(p, "mixed", rtol=1e-10)
-    say(f"  phi error at rtol 1e-10 (reported): {rel(N(r['phi']), ref['phi']):.3e}")
-    r["ctx"].close()
+    # at the production tolerance the error follows the residual reached
+    # (bounded by the condition number times it), for either precision
+    for prec in ("mixed", "fp64"):
+        r = gpu_project(p, prec, rtol=1e-10)
+        say(f"  {prec} at rtol 1e-10 (reported): residual {r['info']['rel_resid']:.3e}, "
+            f"phi error {rel(N(r['phi']), ref['phi']):.3e}")
+        r["ctx"].close()
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
