@@ -321,3 +321,22 @@ def test_cell_and_face_coefficient_modes_agree(precision):
         assert rel(N(xa), N(xb)) < 1e-9
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("rtol", [1e-6, 1e-8, 1e-9, 1e-11])
+def test_tolerances_are_reached(precision, rtol):
+    """The refinement schedule (predicted cycles per step, a last cycle traded
+    for one more finest-level sweep where the prediction leaves room) reaches
+    any tolerance: the residual of the GPU phi, evaluated by the oracle's
+    operator, is within the requested tolerance, and phi lies within the
+    tolerance times a conditioning margin of the oracle's solve at 1e-12."""
+    say("tolerance", rtol, precision)
+    p = W.planar_problem(64, contrast=1e4, seed=808)
+    ref = oracle.mac_project(p, tol=1e-12)
+    r = gpu_project(p, precision, rtol=rtol)
+    phi = N(r["phi"])
+    assert r["info"]["rel_resid"] <= rtol
+    assert oracle.residual_norm(ref["grid"], ref["cx"], ref["cy"], ref["cz"], ref["rhs"], phi) <= 1.05 * rtol
+    assert rel(phi, ref["phi"]) <= 1e3 * rtol
+    r["ctx"].close()
