@@ -75,14 +75,21 @@ typedef struct mp_config {
     double rtol;             /* stop when ||rhs - M phi||_2 <= rtol ||rhs||_2 (FP64) */
     int max_outer;           /* max residual checks: refinement steps (MIXED)
                                 or groups of V-cycles (FP64) */
-    int nu1, nu2;            /* red-black Gauss-Seidel sweeps before / after */
+    int nu1, nu2;            /* red-black Gauss-Seidel sweeps (over-relaxed,
+                                omega = 1.08) before / after */
     int cycles_per_outer;    /* V-cycles between residual checks (FP32
                                 V-cycles per refinement step in MIXED);
                                 0: predicted from the last step's
-                                contraction (1 to 4) */
+                                contraction (1 to 4; a last cycle the
+                                prediction would use for <= 0.45 of it is
+                                replaced by one more finest-level
+                                post-smoothing sweep) */
     double bottom_rtol;      /* bottom-solver tolerance on the coarsest grid
-                                (conjugate gradients in one wavefront up to
-                                256 cells, BiCGStab in one workgroup above) */
+                                where it is not solved directly (<= 64 cells,
+                                all coupled): conjugate gradients in one
+                                wavefront up to 256 cells, BiCGStab in one
+                                workgroup above, mean-zero on each connected
+                                part of the grid */
     int bottom_max_iter;     /* bottom-solver iteration cap */
     int demean;              /* 1: remove the mean of the rhs; 0: require mean ~ 0 */
     int kernel_timing;       /* 1: time the finest-level smoother launches with
