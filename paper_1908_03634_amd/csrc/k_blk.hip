@@ -357,13 +357,15 @@ __global__ __launch_bounds__(BK_T) void k_rr_blk(Dims d, int lz, const T* __rest
     }
 }
 
-// FP64 refinement residual r = b - A x, its scaled FP32 copy
-// r32 = float(r * inv_s[0]) (when r32 != nullptr) and per-block sums of r^2.
+// FP64 refinement residual r = (b - shift[0]) - A x (shift == nullptr: b as
+// stored), its scaled FP32 copy r32 = float(r * inv_s[0]) (when r32 !=
+// nullptr) and per-block sums of r^2.
 template <int M, int R>
 __global__ __launch_bounds__(BK_T) void k_resid64_blk(Dims d, int lz, const double* __restrict__ x,
                                                      const double* __restrict__ b, const double* __restrict__ cc,
                                                      double inv_h2, float* __restrict__ r32,
-                                                     const double* __restrict__ inv_s, double* partials)
+                                                     const double* __restrict__ inv_s, double* partials,
+                                                     const double* __restrict__ shift)
 {
     using S = Strip<double, M>;
     __shared__ double sh[BK_W];
@@ -371,6 +373,7 @@ __global__ __launch_bounds__(BK_T) void k_resid64_blk(Dims d, int lz, const doub
     double acc = 0.0;
     if (g.live) {
         const double is = r32 ? inv_s[0] : 0.0;
+        const double m = shift ? shift[0] : 0.0;
         const long long sz = (long long)d.nx * d.ny;
         long long roff[R + 2];
 #pragma unroll
@@ -386,6 +389,11 @@ __global__ __launch_bounds__(BK_T) void k_resid64_blk(Dims d, int lz, const doub
             if (k + 1 < g.z1)
                 load_plane<double, M, R>(g, x, b, cc, roff, (long long)(k + 1) * sz, (long long)wrap_plane(d, k + 2) * sz,
                                          nxt);
+            // b - m: the bits of a right-hand side stored with its mean removed
+#pragma unroll
+            for (int t = 0; t < R; t++)
+#pragma unroll
+                for (int c = 0; c < 2 * M; c++) q.bq[t].v[c] = q.bq[t].v[c] - m;
             S r[R];
             plane_resid<double, M, R>(g, hzm, hzp, xm, x0, cm, c0, q, inv_h2, r);
 #pragma unroll
@@ -512,14 +520,14 @@ void launch_rr_blk(const Dims& d, const T* x, const T* b, const T* cc, T inv_h2,
 }
 
 void launch_resid64_blk(const Dims& d, const double* x, const double* b, const double* cc, double inv_h2, float* r32,
-                        const double* inv_s, double* partials, int* nb_out, hipStream_t s)
+                        const double* inv_s, double* partials, int* nb_out, hipStream_t s, const double* shift)
 {
     constexpr int R = rows_for<double>(kResidPairs);
     int lz;
     const dim3 grid = blk_grid(d, kResidPairs, R, kBlkMinBlocks, kMaxRedBlocks, lz);
     *nb_out = (int)(grid.x * grid.y * grid.z);
     hipLaunchKernelGGL((k_resid64_blk<kResidPairs, R>), grid, dim3(BK_T), 0, s, d, lz, x, b, cc, inv_h2, r32, inv_s,
-                       partials);
+                       partials, shift);
 }
 
 template void launch_gs_blk<float>(const Dims&, float*, const float*, const float*, float, int, int, const float*,

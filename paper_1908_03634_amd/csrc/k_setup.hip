@@ -109,7 +109,8 @@ void launch_sum(const double* x, long long n, double* partials, int nb, hipStrea
 
 __global__ __launch_bounds__(kBlock) void k_sub_mean_sumsq(double* __restrict__ x, long long n,
                                                            const double* __restrict__ mean, double* part,
-                                                           float* __restrict__ x32, const double* __restrict__ pair)
+                                                           float* __restrict__ x32, const double* __restrict__ pair,
+                                                           int keep)
 {
     __shared__ double sh[kBlock / kWave];
     const double m = mean[0];
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_sub_mean_sumsq(double* __restrict__ 
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n;
          q += (long long)gridDim.x * blockDim.x) {
         double a = x[q] - m;
-        x[q] = a;
+        if (!keep) x[q] = a;
         if (x32) x32[q] = (float)(a * is);
         v = fma(a, a, v);
     }
@@ -127,9 +128,9 @@ __global__ __launch_bounds__(kBlock) void k_sub_mean_sumsq(double* __restrict__ 
 }
 
 void launch_sub_mean_sumsq(double* x, long long n, const double* mean, double* partials, int nb, hipStream_t s,
-                           float* x32, const double* pair)
+                           float* x32, const double* pair, bool keep)
 {
-    hipLaunchKernelGGL(k_sub_mean_sumsq, dim3(nb), dim3(kBlock), 0, s, x, n, mean, partials, x32, pair);
+    hipLaunchKernelGGL(k_sub_mean_sumsq, dim3(nb), dim3(kBlock), 0, s, x, n, mean, partials, x32, pair, keep ? 1 : 0);
 }
 
 __global__ __launch_bounds__(1024) void k_final_moments(const double* __restrict__ part,

@@ -124,6 +124,9 @@ struct mp_ctx {
     double *c64x = nullptr, *c64y = nullptr, *c64z = nullptr;
     double *beta0 = nullptr, *ccell = nullptr, *b64 = nullptr;
     double *partials = nullptr, *dscal = nullptr, *bottom_work = nullptr;
+    // b64 holds the raw right-hand side and its mean is *b_shift (subtracted
+    // by the residual), or b64 is mean-zero (nullptr)
+    const double* b_shift = nullptr;
     double* ginv = nullptr;  // inverse G of the bottom grid (<= kDirectBottomCells cells), or nullptr
     // G is built on a second stream (it is first needed at the end of the
     // first V-cycle's descent): ev_coef orders it after the coefficient
@@ -747,6 +750,11 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
         return MP_OK;
     }
     c->phi_aligned = ((uintptr_t)phi & 15) == 0;
+    // a raw right-hand side is read through the blocked residual only
+    if (c->b_shift && !use_blk(c, 0)) {
+        mp::launch_sub_mean(c->b64, n, c->b_shift, c->stream);
+        c->b_shift = nullptr;
+    }
     const bool mx = mixed(c);
     // from a zero iterate, the first refinement update writes phi without
     // reading it where it rides on the one-pass finest-level sweep; else phi
@@ -776,7 +784,7 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
         } else {
             if (use_blk(c, 0))
                 mp::launch_resid64_blk(c->d0, phi, c->b64, c->ccell, inv_h2, mx ? (float*)c->lv[0].b : nullptr,
-                                       sp + 1, c->partials, &nbr, c->stream);
+                                       sp + 1, c->partials, &nbr, c->stream, c->b_shift);
             else
                 mp::launch_resid64(c->d0, phi, c->b64, coef64(c), inv_h2, mx ? (float*)c->lv[0].b : nullptr, sp + 1,
                                    c->partials, &nbr, c->stream);
@@ -848,7 +856,8 @@ int run_solve(mp_ctx* c, double* phi, int use_guess, mp_info* info)
     }
     // no refinement step ran (stopped before the first): phi is zero
     if (!phi_set) HIPCHK(c, hipMemsetAsync(phi, 0, sizeof(double) * n, c->stream));
-    // gauge: mean(phi) = 0
+    // gauge: mean(phi) = 0 (one reduction for every residual kernel, so that
+    // the blocked and one-cell paths return the same bits)
     mp::launch_sum(phi, n, c->partials, nb, c->stream);
     mp::launch_final_sum(c->partials, nb, c->dscal + S_GAUGE, 1.0 / (double)n, nullptr, 0.0, c->stream);
     mp::launch_sub_mean(phi, n, c->dscal + S_GAUGE, c->stream);
@@ -1510,14 +1519,18 @@ int mp_set_coefs(mp_ctx* c, const double* cx, const double* cy, const double* cz
 // are followed by nb_sum partial sums of b^2, from which the mean and a scale
 // (the rms of b - mean from the two moments) come in one pass, so that the
 // mean removal also writes the first step's scaled FP32 right-hand side.
-static int finish_rhs(mp_ctx* c, int nb_sum, int nb, bool moments = false)
+// keep_raw (with moments): b64 keeps the raw right-hand side and the blocked
+// FP64 residual subtracts the mean as it reads it, saving the write-back.
+static int finish_rhs(mp_ctx* c, int nb_sum, int nb, bool moments = false, bool keep_raw = false)
 {
     const long long n = c->n0;
+    c->b_shift = nullptr;
     if (moments) {
         mp::launch_final_moments(c->partials, c->partials + nb_sum, nb_sum, n, c->dscal + S_MEAN, c->dscal + S_PAIR0,
                                  c->dscal + S_PAIR0 + 2, c->stream);
         mp::launch_sub_mean_sumsq(c->b64, n, c->dscal + S_MEAN, c->partials, nb, c->stream, (float*)c->lv[0].b,
-                                  c->dscal + S_PAIR0);
+                                  c->dscal + S_PAIR0, keep_raw);
+        if (keep_raw) c->b_shift = c->dscal + S_MEAN;
         mp::launch_final_sum(c->partials, nb, c->dscal + S_NB2, 1.0, nullptr, 0.0, c->stream, c->dscal + S_BIT);
         c->b32_ready = true;
     } else {
@@ -1562,7 +1575,7 @@ static int project(mp_ctx* c, double* ux, double* uy, double* uz, const double* 
                            c->stream, moments ? c->partials + mp::proj_blk_reduce_blocks(c->d0) : nullptr);
     else
         mp::launch_mac_rhs(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->b64, c->partials, c->stream);
-    int st = finish_rhs(c, nbs, nb, moments);
+    int st = finish_rhs(c, nbs, nb, moments, moments && c->lv[0].blk);
     if (st) return st;
     if (info) {
         info->rhs_norm = sqrt(c->hscal[S_NB2]);

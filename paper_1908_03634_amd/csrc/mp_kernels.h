@@ -40,9 +40,10 @@ void launch_final_sum(const double* partials, int nb, double* out, double scale,
 // partials[b] = per-block sum of x (grid-stride, fixed order).
 void launch_sum(const double* x, long long n, double* partials, int nb, hipStream_t s);
 // x[q] -= mean[0]; partials = per-block sum of x^2 after the update; when
-// x32 != nullptr also x32[q] = float(x[q] * pair[1]).
+// x32 != nullptr also x32[q] = float(x[q] * pair[1]).  keep: x is left as it
+// was (the sums and x32 as if updated).
 void launch_sub_mean_sumsq(double* x, long long n, const double* mean, double* partials, int nb, hipStream_t s,
-                           float* x32 = nullptr, const double* pair = nullptr);
+                           float* x32 = nullptr, const double* pair = nullptr, bool keep = false);
 // From per-block sums s1 (partials) and s2 (partials2) of b and b^2 over n
 // values: mean_out[0] = s1 / n and a scale for b - mean, the rms
 // r = sqrt(s2 / n - mean^2) (sqrt(s2 / n) where cancellation leaves under
@@ -260,9 +261,11 @@ void launch_rr_blkf(const Dims& d, const T* x, const T* b, const Coef<T>& c, T i
 // Coarse rhs = mean of the 8 fine residuals b - A x (as launch_resid_restrict).
 template <typename T>
 void launch_rr_blk(const Dims& d, const T* x, const T* b, const T* cc, T inv_h2, T* bc, hipStream_t s);
-// As launch_resid64 with cell-value coefficients cc.
+// As launch_resid64 with cell-value coefficients cc; shift != nullptr: b is
+// taken as b - shift[0] (the same bits as b stored with the mean removed).
 void launch_resid64_blk(const Dims& d, const double* x, const double* b, const double* cc, double inv_h2, float* r32,
-                        const double* inv_s, double* partials, int* nb_out, hipStream_t s);
+                        const double* inv_s, double* partials, int* nb_out, hipStream_t s,
+                        const double* shift = nullptr);
 
 // ---- register-blocked projection kernels (finest level, periodic x and y) --
 // Same results, bit for bit, as launch_mac_rhs / launch_rhs_defect /
