@@ -340,3 +340,44 @@ def test_tolerances_are_reached(precision, rtol):
     assert oracle.residual_norm(ref["grid"], ref["cx"], ref["cy"], ref["cz"], ref["rhs"], phi) <= 1.05 * rtol
     assert rel(phi, ref["phi"]) <= 1e3 * rtol
     r["ctx"].close()
+
+
+@pytest.mark.parametrize("case", ["nonfinite", "zero", "singular"])
+def test_rhs_checks_on_the_blocked_path(case):
+    """With the blocked projection kernels in mixed precision (the right-hand
+    side kept raw, its mean subtracted by the residual): a non-finite source,
+    a zero right-hand side and (demean off) a right-hand side with a mean are
+    reported as on the other paths."""
+    say("blocked rhs checks", case)
+    p = W.planar_problem(nx=128, ny=16, nz=16, contrast=1e3, seed=8100)
+    S = p.S.copy()
+    kw = {}
+    ux, uy, uz = p.ux, p.uy, p.uz
+    if case == "nonfinite":
+        S[3, 5, 7] = np.inf
+    elif case == "zero":
+        S = np.zeros_like(S)
+        ux, uy, uz = (np.zeros_like(u) for u in (ux, uy, uz))
+    else:
+        S = S + 1.0
+        kw["demean"] = False
+    ctx = context_for(p, "mixed", **kw)
+    ctx.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center)
+    U = [T(u) for u in (ux, uy, uz)]
+    if case == "zero":
+        phi, info = ctx.mac_project(*U, T(S))
+        assert not N(phi).any() and info["rel_resid"] == 0.0 and info["rhs_norm"] == 0.0
+        assert all(not N(u).any() for u in U)
+    else:
+        with pytest.raises(mproj.MprojError) as e:
+            ctx.mac_project(*U, T(S))
+        assert e.value.code == (5 if case == "nonfinite" else 6)
+    # the context still projects a regular right-hand side afterwards
+    ref = oracle.mac_project(p, tol=1e-12)
+    ctx2 = context_for(p, "mixed", rtol=1e-10)
+    ctx2.map_base_state(p.geometry, T(p.beta0_1d), T(p.rho), p.dr, p.center)
+    phi2, info2 = ctx2.mac_project(T(p.ux), T(p.uy), T(p.uz), T(p.S))
+    assert info2["rel_resid"] <= 1e-10
+    assert info2["rhs_mean"] == pytest.approx(ref["mean"], rel=1e-9, abs=1e-14)
+    ctx.close()
+    ctx2.close()
