@@ -43,6 +43,14 @@ bool fsw_supported(const Dims& d)
     return blk_supported(d) && (d.nx == 128 || d.nx == 256 || d.nx == 384 || d.nx == 512);
 }
 
+// Rows of 192 cells between walls in x (the 384^3 box's second level): the
+// strips of 256-cell rows, lanes 48-63 past the row's end idle (they load the
+// row's first cells, and store nothing).
+bool fsw_narrow_supported(const Dims& d)
+{
+    return d.nx == 192 && !d.px && d.ny % 4 == 0 && d.nz >= 4 && d.nz % 2 == 0;
+}
+
 // The M cells of one parity (q even or q odd) of a lane's strip.
 template <typename T, int M>
 struct Half {
@@ -234,6 +242,8 @@ struct FsLds {
     double* __restrict__ phi;
     const double* __restrict__ irs;
     bool phi_fresh;  // phi is zero on entry: written, not read
+    bool lane_live;  // the lane's strip lies in the row (rows narrower than 2 M x 64 cells)
+    int xe;          // the strip's first column, 0 for a lane past the row's end
     T h2;
     T (*sx)[NW * NX];
     T (*sc)[NW * NX];
@@ -245,7 +255,7 @@ struct FsLds {
         } else {
             S v = ld_strip<T, M>(xo, (long long)kk * sz + roff);
             if constexpr (MODE == FS_PROLONG) {
-                const long long o = (long long)(kk >> 1) * szc + (long long)(jw >> 1) * nxc + (g.xi >> 1);
+                const long long o = (long long)(kk >> 1) * szc + (long long)(jw >> 1) * nxc + (xe >> 1);
 #pragma unroll
                 for (int q = 0; q < 2 * M; q++) v.v[q] = v.v[q] + ec[o + (q >> 1)];
             }
@@ -314,15 +324,18 @@ struct FsLds {
             fs_row<T, M, CELL, PXY>(d, g, j, k, 1, h2, s.x[P0], bxlo, bxhi, s.x[PM], s.x[P1], s.fx[P0], s.c[P0], bclo,
                                bchi, CELL ? s.fz[PM] : s.cz[P0], CELL ? s.fz[P0] : s.cz[P1], s.b[P0]);
             const long long o = (long long)k * sz + roff;
-            st_strip<T, M>(xn, o, s.x[P0]);
+            if (lane_live) st_strip<T, M>(xn, o, s.x[P0]);
             if constexpr (IRU) {
-                const double sc0 = irs[0];
-                double* pp = phi + o;
+                if (lane_live) {
+                    const double sc0 = irs[0];
+                    double* pp = phi + o;
 #pragma unroll
-                for (int q = 0; q < M; q++) {
-                    const double2 pv = phi_fresh ? make_double2(0.0, 0.0) : *reinterpret_cast<const double2*>(pp + 2 * q);
-                    *reinterpret_cast<double2*>(pp + 2 * q) = make_double2(fma(sc0, (double)s.x[P0].v[2 * q], pv.x),
-                                                                           fma(sc0, (double)s.x[P0].v[2 * q + 1], pv.y));
+                    for (int q = 0; q < M; q++) {
+                        const double2 pv =
+                            phi_fresh ? make_double2(0.0, 0.0) : *reinterpret_cast<const double2*>(pp + 2 * q);
+                        *reinterpret_cast<double2*>(pp + 2 * q) = make_double2(
+                            fma(sc0, (double)s.x[P0].v[2 * q], pv.x), fma(sc0, (double)s.x[P0].v[2 * q + 1], pv.y));
+                    }
                 }
             }
         }
@@ -366,7 +379,9 @@ __global__ __launch_bounds__(kWave*(R + 4)) void k_fsw_lds(Dims d, int lz, const
     f.red_row = t >= 1 && t <= R + 2;
     f.black_row = t >= 2 && t <= R + 1 && f.j < d.ny;
     f.sz = (long long)d.nx * d.ny;
-    f.roff = (long long)f.jw * d.nx + g.xi;
+    f.lane_live = g.xi < d.nx;
+    f.xe = f.lane_live ? g.xi : 0;
+    f.roff = (long long)f.jw * d.nx + f.xe;
     f.nxc = d.nx >> 1;
     f.szc = (long long)f.nxc * (d.ny >> 1);
     f.so = t * F::NX + M * g.lane;  // the lane's words in row t of a buffer
@@ -600,7 +615,8 @@ void launch_fsw_blkf(const Dims& d, const T* xo, T* xn, const T* b, const Coef<T
     switch (d.nx) {
     case 512: fswf_mode<T, 4>(mode, d, xo, xn, b, c, h2, ec, s); break;
     case 384: fswf_mode<T, 3>(mode, d, xo, xn, b, c, h2, ec, s); break;
-    case 256: fswf_mode<T, 2>(mode, d, xo, xn, b, c, h2, ec, s); break;
+    case 256:
+    case 192: fswf_mode<T, 2>(mode, d, xo, xn, b, c, h2, ec, s); break;
     default: fswf_mode<T, 1>(mode, d, xo, xn, b, c, h2, ec, s); break;
     }
 }

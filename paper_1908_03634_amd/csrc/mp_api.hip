@@ -526,6 +526,17 @@ void smooth(mp_ctx* c, int l, bool zero_init, const T* ec, bool last = false)
         }
         return;
     }
+    if (L.fsw && !C.cell && !use_blkf(c, l)) {
+        // rows of 192 cells: the one-pass sweep on 256-cell strips
+        const double words = (zero_init ? 5.0 : 6.0) + (ec ? 0.125 : 0.0);
+        timed_begin(c, tm);
+        if constexpr (sizeof(T) == 4)
+            mp::launch_fsw_blkf<T>(L.d, (const T*)L.x, (T*)L.x2, (const T*)L.b, C, h2,
+                                   zero_init ? mp::FS_ZERO : ec ? mp::FS_PROLONG : mp::FS_PLAIN, ec, c->stream);
+        timed_end(c, tm, words * sizeof(T) * cells);
+        std::swap(L.x, L.x2);
+        return;
+    }
     if (L.pair && !C.cell) {
         // words per cell: x_old (unless zero), b, 3 coefficients, x_new, 1/8
         // coarse e; the red neighbours evaluated again are read from cache
@@ -1356,8 +1367,11 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
             if (c->coarse_start >= 0 && l >= c->coarse_start) break;
             // FP32 levels only: the FP64 variants need too many registers
             L.blkf = cfg->blocked && mx && mp::blk_supported(L.d);
-            // both colours of a sweep in one pass where rows are 128 or 256 cells
-            if (l > 0) L.fsw = L.blkf && mp::fsw_supported(L.d) && cfg->smoother != MP_SMOOTH_PER_COLOUR;
+            // both colours of a sweep in one pass where rows are 128 to 512
+            // cells, or 192 between walls in x
+            if (l > 0)
+                L.fsw = ((L.blkf && mp::fsw_supported(L.d)) || (mx && mp::fsw_narrow_supported(L.d))) &&
+                        cfg->smoother != MP_SMOOTH_PER_COLOUR;
             L.fused = !L.blkf && mp::sweep_supported(L.d) &&
                       (cfg->smoother == MP_SMOOTH_FUSED ||
                        (cfg->smoother == MP_SMOOTH_AUTO && L.d.n() >= kFusedMinCells));

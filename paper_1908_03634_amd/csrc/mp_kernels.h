@@ -244,6 +244,9 @@ template <typename T>
 void launch_rb_pair(const Dims& d, const T* xo, T* xn, const T* b, const Coef<T>& c, T h2, int mode, const T* ec,
                     hipStream_t s);
 bool fsw_supported(const Dims& d);
+// Rows of 192 cells with walls in x: the stored-face sweep below on 256-cell
+// strips, the lanes past the row's end idle.
+bool fsw_narrow_supported(const Dims& d);
 template <typename T>
 void launch_fsw_blk(const Dims& d, const T* xo, T* xn, const T* b, const T* cc, T h2, int mode, const T* ec,
                     double* phi, const double* irs, int irf, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
