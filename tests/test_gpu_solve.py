@@ -277,7 +277,8 @@ def test_coarse_cycle_kernel_matches_per_level_launches(precision):
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 @pytest.mark.parametrize("shape,bc", [((64, 64, 64), (0, 0, 1)), ((128, 32, 48), (1, 1, 1)), ((40, 24, 16), (0, 1, 0)),
-                                      ((384, 16, 12), (1, 1, 1)), ((512, 12, 10), (0, 0, 1)), ((512, 8, 8), (0, 1, 0))])
+                                      ((384, 16, 12), (1, 1, 1)), ((512, 12, 10), (0, 0, 1)), ((512, 8, 8), (0, 1, 0)),
+                                      ((192, 8, 8), (1, 0, 1)), ((192, 24, 16), (1, 1, 1))])
 def test_fused_sweep_bitwise_with_face_coefficients(precision, shape, bc):
     """Caller face coefficients (face mode on every level): the fused sweeps
     ("fused", and "auto" with its one-launch sweep on the coarser levels)
