@@ -631,14 +631,15 @@ __global__ __launch_bounds__(kBlock) void k_mac_rhs(Dims d, int lz, double inv_h
                                                     const double* __restrict__ uz, const double* __restrict__ S,
                                                     const double* __restrict__ sbar, int smode,
                                                     double* __restrict__ b, double* part,
-                                                    const double* __restrict__ shift)
+                                                    const double* __restrict__ shift, double* part2)
 {
-    // shift == nullptr: write b, partials = sum b.
+    // shift == nullptr: write b, partials = sum b (and part2 = sum b^2 when
+    // part2 != nullptr).
     // shift != nullptr: no write, partials = sum (b - shift[0])^2.
     const double sh0 = shift ? shift[0] : 0.0;
     __shared__ double sh[kBlock / kWave];
     MP_ZCOL
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
     // the z flux through the low face of plane k; the high face's flux of
     // plane k is carried to plane k+1 (same operands, same value)
     double fzl = 0.0, b0 = 0.0;
@@ -674,20 +675,22 @@ __global__ __launch_bounds__(kBlock) void k_mac_rhs(Dims d, int lz, double inv_h
         } else {
             b[q] = v;
             acc += v;
+            acc2 = fma(v, v, acc2);
         }
         fzl = fzh;
         b0 = bzp;
     }
     zpart_store(part, block_sum(acc, sh));
+    if (part2) zpart_store(part2, block_sum(acc2, sh));
 }
 
 void launch_mac_rhs(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
                     const double* uz, const double* S, const double* sbar, int smode, double* b, double* partials,
-                    hipStream_t s)
+                    hipStream_t s, double* partials2)
 {
     const ShapeZ sh = zmarch(d.nx, d.ny, d.nz, kZBlocks);
     hipLaunchKernelGGL(k_mac_rhs, sh.grid, sh.block, 0, s, d, sh.lz, inv_h, beta0, ux, uy, uz, S, sbar, smode, b,
-                       partials, (const double*)nullptr);
+                       partials, (const double*)nullptr, partials2);
 }
 
 void launch_rhs_defect(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
@@ -696,7 +699,7 @@ void launch_rhs_defect(const Dims& d, double inv_h, const double* beta0, const d
 {
     const ShapeZ sh = zmarch(d.nx, d.ny, d.nz, kZBlocks);
     hipLaunchKernelGGL(k_mac_rhs, sh.grid, sh.block, 0, s, d, sh.lz, inv_h, beta0, ux, uy, uz, S, sbar, smode,
-                       (double*)nullptr, partials, shift);
+                       (double*)nullptr, partials, shift, (double*)nullptr);
 }
 
 // Lateral average of a planar atmosphere (Sec. 3.1): one block per plane,

@@ -1284,6 +1284,8 @@ int mp_init(const mp_config* cfg, mp_ctx** out)
         // the blocked right-hand side writes two sets of partials (b, b^2)
         if (mp::proj_blk_supported(c->d0) && 2 * mp::proj_blk_reduce_blocks(c->d0) > np)
             np = 2 * mp::proj_blk_reduce_blocks(c->d0);
+        // and so does the one-cell right-hand side (b, b^2 per z-column block)
+        if (2 * c->nbz > np) np = 2 * c->nbz;
         c->partials = dalloc<double>(np, e), good &= ok(c->partials);
         c->npartials = np;
     }
@@ -1581,14 +1583,15 @@ static int project(mp_ctx* c, double* ux, double* uy, double* uz, const double* 
     const bool pblk = c->cfg.blocked && c->cell_mode && mp::proj_blk_supported(c->d0) && aligned16(ux) &&
                       aligned16(uy) && aligned16(uz) && aligned16(S) && aligned16(phi);
     int nbs = c->nbz;
-    // mixed precision with the blocked right-hand side: its second moment
-    // gives the first step's scale, written with the mean removal
-    const bool moments = pblk && mixed(c);
+    // mixed precision: the right-hand side's second moment gives the first
+    // step's scale, written with the mean removal
+    const bool moments = mixed(c);
     if (pblk)
         mp::launch_rhs_blk(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->b64, nullptr, c->partials, &nbs,
                            c->stream, moments ? c->partials + mp::proj_blk_reduce_blocks(c->d0) : nullptr);
     else
-        mp::launch_mac_rhs(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->b64, c->partials, c->stream);
+        mp::launch_mac_rhs(c->d0, inv_h, c->beta0, ux, uy, uz, S, sbar, smode, c->b64, c->partials, c->stream,
+                           moments ? c->partials + c->nbz : nullptr);
     int st = finish_rhs(c, nbs, nb, moments, moments && c->lv[0].blk);
     if (st) return st;
     if (info) {

@@ -89,11 +89,12 @@ void launch_coef_restrict_cells32(const Dims& fine, const float* hc, float* cx, 
 
 // ---- projection ------------------------------------------------------------
 // b = beta0 S' - D(beta0 U) (= minus the MAC right-hand side); partials
-// (zred_blocks) = sum b.  S' = S (smode 0), or S - Sbar with Sbar per plane
-// (smode 1) or per irregular radius (smode 2): the velocity-split source.
+// (zred_blocks) = sum b, and partials2 = sum b^2 when given.  S' = S (smode
+// 0), or S - Sbar with Sbar per plane (smode 1) or per irregular radius
+// (smode 2): the velocity-split source.
 void launch_mac_rhs(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
                     const double* uz, const double* S, const double* sbar, int smode, double* b, double* partials,
-                    hipStream_t s);
+                    hipStream_t s, double* partials2 = nullptr);
 // partials (zred_blocks) = per-block sum of (beta0 S' - D(beta0 U) - shift[0])^2
 // (no write): the divergence defect of a projected velocity.
 void launch_rhs_defect(const Dims& d, double inv_h, const double* beta0, const double* ux, const double* uy,
