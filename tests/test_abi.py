@@ -17,7 +17,7 @@ def declared():
     return sorted(set(re.findall(r"^\s*(?:int|void|const char\s*\*)\s*\*?\s*(mp_\w+)\s*\(", txt, re.M)))
 
 
-def test_header_declares_the_north_star_entry_points():
+def test_header_declares_the_four_named_entry_points():
     names = declared()
     for n in ("mp_init", "mp_map_base_state", "mp_mac_project", "mp_free"):
         assert n in names
